@@ -1,0 +1,114 @@
+"""Write the stored expected proofs under tests/golden/ by running the CPU oracle.
+
+Only ``oracle`` and ``workloads`` are used: every stored value is what the
+oracle computes for the seeded synthetic inputs.  Usage:
+
+    python tests/golden/make_golden.py [cfg1 tiny cfg2 cfg3 cfg4] [--procs N]
+
+Each config file lists, per group: name, group id, shapes, the SHA-256 of the
+proof bytes and the final transcript state; small configs also keep the full
+proof in hex.
+"""
+import argparse
+import hashlib
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from oracle.zkmat import prove_workload_group  # noqa: E402
+import workloads  # noqa: E402
+
+_W = None
+
+
+def _prove(i):
+    g = _W.groups[i]
+    t = time.time()
+    proof, state, det = prove_workload_group(g, _W.seed)
+    return i, proof, state, time.time() - t
+
+
+def record(w, keep_hex: bool, procs: int):
+    global _W
+    _W = w
+    idx = list(range(len(w.groups)))
+    # largest groups first so the pool's tail is short
+    idx.sort(key=lambda i: -sum(d0 * d1 + d1 * d2 for d0, d1, d2 in w.groups[i].shapes))
+    if procs > 1:
+        with mp.get_context("fork").Pool(procs) as pool:
+            res = pool.map(_prove, idx, chunksize=1)
+    else:
+        res = [_prove(i) for i in idx]
+    res.sort()
+    out = []
+    for i, proof, state, dt in res:
+        g = w.groups[i]
+        e = dict(name=g.name, group_id=g.group_id, shapes=[list(s) for s in g.shapes],
+                 proof_sha256=hashlib.sha256(proof).hexdigest(), state=state.hex(),
+                 proof_len=len(proof))
+        if keep_hex:
+            e["proof_hex"] = proof.hex()
+        out.append(e)
+        print(f"  {g.name:28s} {g.shapes} {dt:7.1f}s", flush=True)
+    return dict(workload=w.name, seed=w.seed, groups=out)
+
+
+TINY = [
+    # (seed, dims list, dtype, trans, value_bits)
+    (11, [(1, 1, 1)], "int16", (False, False), None),
+    (12, [(3, 5, 7)], "int16", (False, False), None),
+    (13, [(5, 1, 3)], "int16", (True, False), None),
+    (14, [(1, 300, 1)], "int16", (False, True), None),
+    (15, [(70, 33, 130)], "int16", (True, True), None),
+    (16, [(17, 64, 9), (17, 3, 9)], "int16", (False, True), None),
+    (17, [(40, 257, 65)], "int32", (False, False), 20),
+    (18, [(33, 19, 47)], "int64", (True, False), 24),
+    (19, [(300, 520, 129)], "int16", (False, False), None),
+]
+
+
+def tiny_groups():
+    import numpy as np
+    out = []
+    for k, (seed, dims, dt, trans, vb) in enumerate(TINY):
+        g = workloads.tiny_random_group(seed, dims, dtype=getattr(np, dt), trans=trans,
+                                        value_bits=vb, name=f"tiny{k}")
+        g.group_id = k
+        out.append(g)
+    return workloads.Workload("tiny parity cases", 1234, out)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("configs", nargs="*", default=["cfg1", "tiny", "cfg2", "cfg3"])
+    ap.add_argument("--procs", type=int, default=os.cpu_count())
+    args = ap.parse_args()
+    for name in args.configs:
+        t = time.time()
+        print(f"{name}: generating", flush=True)
+        if name == "tiny":
+            w = tiny_groups()
+        elif name == "cfg1_sweep":
+            data = [record(workloads.config1(seed=s), True, 1) for s in range(1, 17)]
+            with open(os.path.join(HERE, "cfg1_sweep.json"), "w") as f:
+                json.dump(data, f, indent=1)
+            continue
+        else:
+            w = workloads.make_config(name)
+        print(f"{name}: proving {len(w.groups)} groups", flush=True)
+        data = record(w, keep_hex=name in ("cfg1", "tiny"), procs=args.procs)
+        data["tiny_spec"] = TINY if name == "tiny" else None
+        with open(os.path.join(HERE, f"{name}.json"), "w") as f:
+            json.dump(data, f, indent=1)
+        print(f"{name}: done in {time.time() - t:.1f}s", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,14 @@
+"""Seeded synthetic workloads for the matmul-sumcheck prover.
+
+This package only draws integer tensors and forms the witness products that a
+prover is asked to prove; it holds none of the proof system's arithmetic (no
+field, no multilinear extension, no transcript).  Both the CPU oracle
+(``oracle/``) and the device library's tests and benchmark take their inputs
+from here, so the two sides see identical bytes.
+"""
+from .gen import (  # noqa: F401
+    Product, Group, Workload,
+    quantize_gaussian, requant, exact_matmul,
+    config1, lora_forward, lora_backward_update, config2, config3, config4,
+    serving_request, serving_stream, tiny_random_group, CONFIG_NAMES, make_config,
+)

@@ -1,0 +1,340 @@
+"""Seeded synthetic inputs shaped like the paper's LoRA fine-tuning matmuls.
+
+The paper proves every matrix product of a LoRA step (forward, backward and
+the LoRA update) with its matmul sumcheck (Sections III-IV).  It trains on real
+LLaMA/OPT weights and C4 text, neither of which is used here: these generators
+draw fixed-point int16 tensors with the shapes of a 7B-class (hidden 4096,
+FFN 11008) and a 13B-class (hidden 5120, FFN 13824) decoder layer instead.
+
+Conventions (all integers, nothing here touches a field):
+  * Gaussian tensors are quantised as clip(rint(N(0, sigma^2) * 2^12)) to int16;
+    sigma = 0.02 for weights (W, LoRA A, LoRA B) and 1 for activations and dY.
+  * LoRA layer:  Y = X W + (X A) B,  X: T x d_in, W: d_in x d_out,
+    A: d_in x r, B: r x d_out.  Chained operands are re-quantised with
+    ``requant`` (round half up at scale 2^12, saturating to int16).
+  * Backward and update:  G = requant(dY B^T), dA = X^T G, dB = H^T dY,
+    dX = dY W^T + G A^T (a two-product sum group), H = requant(X A).
+  * The witness C of a group is the exact integer sum of its products.
+
+Tensors are drawn with ``numpy.random.default_rng(seed)`` in the order each
+constructor lists, so a (config, seed) pair always yields the same bytes.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, List, Optional
+
+import numpy as np
+
+SCALE_BITS = 12
+I16_MIN, I16_MAX = -(1 << 15), (1 << 15) - 1
+
+
+# --------------------------------------------------------------------------
+# data model
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class Product:
+    """One product op(A) @ op(B); op is the identity or a transposed view.
+
+    ``A`` and ``B`` are the stored (row-major, C-contiguous) tensors.  The
+    mathematical left factor is ``A.T`` when ``transA`` is set, likewise for B.
+    """
+    name: str
+    A: np.ndarray
+    B: np.ndarray
+    transA: bool = False
+    transB: bool = False
+
+    def opA(self) -> np.ndarray:
+        return self.A.T if self.transA else self.A
+
+    def opB(self) -> np.ndarray:
+        return self.B.T if self.transB else self.B
+
+    @property
+    def dims(self):
+        a, b = self.opA(), self.opB()
+        assert a.shape[1] == b.shape[0], (self.name, a.shape, b.shape)
+        return (int(a.shape[0]), int(a.shape[1]), int(b.shape[1]))
+
+
+@dataclasses.dataclass
+class Group:
+    """Products that share the output C (C = sum of the products)."""
+    name: str
+    products: List[Product]
+    C: np.ndarray
+    group_id: int = 0
+
+    @property
+    def shapes(self):
+        return [p.dims for p in self.products]
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    seed: int
+    groups: List[Group]
+
+    def n_products(self) -> int:
+        return sum(len(g.products) for g in self.groups)
+
+
+# --------------------------------------------------------------------------
+# integer helpers (witness generation only)
+# --------------------------------------------------------------------------
+def quantize_gaussian(rng: np.random.Generator, shape, sigma: float) -> np.ndarray:
+    x = rng.standard_normal(shape) * (sigma * (1 << SCALE_BITS))
+    return np.clip(np.rint(x), I16_MIN, I16_MAX).astype(np.int16)
+
+
+def requant(z: np.ndarray) -> np.ndarray:
+    """Round-half-up rescale by 2^12 with int16 saturation (chained operands)."""
+    z = np.asarray(z, dtype=np.int64)
+    q = (z + (1 << (SCALE_BITS - 1))) >> SCALE_BITS
+    return np.clip(q, I16_MIN, I16_MAX).astype(np.int16)
+
+
+def exact_matmul(a: np.ndarray, b: np.ndarray, device: Optional[str] = None) -> np.ndarray:
+    """Exact integer product as int64.
+
+    Large products go through float64 GEMM, which is exact here: every product
+    of two entries and every partial sum is an integer of magnitude below 2^53
+    (checked from the operand bounds), so no rounding can occur in any order.
+    ``device="cuda"`` runs that float64 GEMM with torch on the GPU (witness
+    generation for benchmarks); small products use int64 matmul on the host.
+    """
+    a = np.asarray(a)
+    b = np.asarray(b)
+    k = a.shape[1]
+    amax = int(np.abs(a.astype(np.int64)).max(initial=0))
+    bmax = int(np.abs(b.astype(np.int64)).max(initial=0))
+    bound = amax * bmax * max(k, 1)
+    if bound >= (1 << 53):
+        if bound >= (1 << 62):
+            raise ValueError("product would overflow int64")
+        return a.astype(np.int64) @ b.astype(np.int64)
+    if a.shape[0] * k * b.shape[1] <= (1 << 22):
+        return a.astype(np.int64) @ b.astype(np.int64)
+    if device is not None and device != "cpu":
+        import torch
+        ta = torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=torch.float64)
+        tb = torch.from_numpy(np.ascontiguousarray(b)).to(device=device, dtype=torch.float64)
+        out = (ta @ tb).to(torch.int64).cpu().numpy()
+        return out
+    return (a.astype(np.float64) @ b.astype(np.float64)).astype(np.int64)
+
+
+def _group(name, prods, device=None) -> Group:
+    C = None
+    for p in prods:
+        t = exact_matmul(p.opA(), p.opB(), device=device)
+        C = t if C is None else C + t
+    return Group(name, prods, C)
+
+
+def _number(groups: List[Group]) -> List[Group]:
+    for i, g in enumerate(groups):
+        g.group_id = i
+    return groups
+
+
+# --------------------------------------------------------------------------
+# configurations
+# --------------------------------------------------------------------------
+def config1(seed: int = 1) -> Workload:
+    """Single product: A 64x128 and B 128x32, int16 uniform in [-2^15, 2^15)."""
+    rng = np.random.default_rng(seed)
+    A = rng.integers(I16_MIN, I16_MAX + 1, size=(64, 128), dtype=np.int16)
+    B = rng.integers(I16_MIN, I16_MAX + 1, size=(128, 32), dtype=np.int16)
+    g = _group("A@B", [Product("A@B", A, B)])
+    return Workload("single 64x128x32 int16", seed, _number([g]))
+
+
+class LoraLayer:
+    """Draws one LoRA-adapted linear layer: X, W, A, B (and dY on demand)."""
+
+    def __init__(self, rng, T, d_in, d_out, r, with_dy: bool, X: Optional[np.ndarray] = None):
+        self.T, self.d_in, self.d_out, self.r = T, d_in, d_out, r
+        self.X = quantize_gaussian(rng, (T, d_in), 1.0) if X is None else X
+        self.W = quantize_gaussian(rng, (d_in, d_out), 0.02)
+        self.A = quantize_gaussian(rng, (d_in, r), 0.02)
+        self.B = quantize_gaussian(rng, (r, d_out), 0.02)
+        self.dY = quantize_gaussian(rng, (T, d_out), 1.0) if with_dy else None
+        self._H = None
+        self._G = None
+
+    @property
+    def H(self):
+        if self._H is None:
+            self._H = requant(exact_matmul(self.X, self.A))
+        return self._H
+
+    @property
+    def G(self):
+        if self._G is None:
+            self._G = requant(exact_matmul(self.dY, self.B.T))
+        return self._G
+
+
+def lora_forward(L: LoraLayer, tag: str = "", device=None) -> List[Group]:
+    """P1 X.W, P2 X.A, P3 H.B."""
+    return [
+        _group(f"{tag}P1 X.W", [Product(f"{tag}P1 X.W", L.X, L.W)], device),
+        _group(f"{tag}P2 X.A", [Product(f"{tag}P2 X.A", L.X, L.A)], device),
+        _group(f"{tag}P3 H.B", [Product(f"{tag}P3 H.B", L.H, L.B)], device),
+    ]
+
+
+def lora_backward_update(L: LoraLayer, tag: str = "", device=None) -> List[Group]:
+    """P4 G=dY.B^T, P5 dA=X^T.G, P6 dB=H^T.dY, dX = P7 dY.W^T + P8 G.A^T."""
+    return [
+        _group(f"{tag}P4 dY.B^T", [Product(f"{tag}P4 dY.B^T", L.dY, L.B, transB=True)], device),
+        _group(f"{tag}P5 X^T.G", [Product(f"{tag}P5 X^T.G", L.X, L.G, transA=True)], device),
+        _group(f"{tag}P6 H^T.dY", [Product(f"{tag}P6 H^T.dY", L.H, L.dY, transA=True)], device),
+        _group(f"{tag}dX", [Product(f"{tag}P7 dY.W^T", L.dY, L.W, transB=True),
+                            Product(f"{tag}P8 G.A^T", L.G, L.A, transB=True)], device),
+    ]
+
+
+def config2(seed: int = 2, T: int = 512, device=None) -> Workload:
+    """LoRA forward of a 4096x4096 layer, rank 16, T tokens: 3 products."""
+    rng = np.random.default_rng(seed)
+    L = LoraLayer(rng, T, 4096, 4096, 16, with_dy=False)
+    return Workload(f"lora fwd T={T} 4096x4096 r16", seed, _number(lora_forward(L, device=device)))
+
+
+def config3(seed: int = 3, T: int = 512, device=None) -> Workload:
+    """Backward + update of the 4096x4096 layer (P4..P8) and the full FFN-up
+    layer 4096->11008 (P1..P8), rank 16, T tokens."""
+    rng = np.random.default_rng(seed)
+    L1 = LoraLayer(rng, T, 4096, 4096, 16, with_dy=True)
+    L2 = LoraLayer(rng, T, 4096, 11008, 16, with_dy=True)
+    groups = lora_backward_update(L1, "attn:", device) + lora_forward(L2, "up:", device) \
+        + lora_backward_update(L2, "up:", device)
+    return Workload(f"lora bwd+upd T={T} 4096x4096 + ffn-up 4096x11008 r16", seed, _number(groups))
+
+
+BLOCK_7B = dict(hidden=4096, ffn=11008, r=16)
+
+
+def config4(seed: int = 4, T: int = 2048, hidden: int = 4096, ffn: int = 11008, r: int = 16,
+            device=None) -> Workload:
+    """One decoder block, LoRA rank r on q, k, v, o, gate, up, down; all
+    forward, backward and update products (7 targets x 8 products)."""
+    rng = np.random.default_rng(seed)
+    x_attn = quantize_gaussian(rng, (T, hidden), 1.0)
+    x_o = quantize_gaussian(rng, (T, hidden), 1.0)
+    x_mlp = quantize_gaussian(rng, (T, hidden), 1.0)
+    x_down = quantize_gaussian(rng, (T, ffn), 1.0)
+    targets = [("q", x_attn, hidden, hidden), ("k", x_attn, hidden, hidden),
+               ("v", x_attn, hidden, hidden), ("o", x_o, hidden, hidden),
+               ("gate", x_mlp, hidden, ffn), ("up", x_mlp, hidden, ffn),
+               ("down", x_down, ffn, hidden)]
+    groups: List[Group] = []
+    for name, X, d_in, d_out in targets:
+        L = LoraLayer(rng, T, d_in, d_out, r, with_dy=True, X=X)
+        groups += lora_forward(L, f"{name}:", device) + lora_backward_update(L, f"{name}:", device)
+    return Workload(f"7B block T={T} h{hidden} ffn{ffn} r{r}", seed, _number(groups))
+
+
+# --------------------------------------------------------------------------
+# serving requests (13B-class shapes)
+# --------------------------------------------------------------------------
+SERVE_13B = dict(hidden=5120, ffn=13824)
+SERVE_TARGETS = ("q", "k", "v", "o", "gate", "up", "down")
+SERVE_T = (128, 512, 2048)
+SERVE_RANKS = (8, 16, 64)
+SERVE_TYPES = ("fwd", "bwd", "upd")
+
+
+def serve_dims(target: str, hidden: int = 5120, ffn: int = 13824):
+    if target in ("q", "k", "v", "o"):
+        return hidden, hidden
+    if target in ("gate", "up"):
+        return hidden, ffn
+    return ffn, hidden
+
+
+def frozen_weight(target: str, seed: int = 5, hidden: int = 5120, ffn: int = 13824) -> np.ndarray:
+    """The frozen W of one target; shared by every request on that target."""
+    d_in, d_out = serve_dims(target, hidden, ffn)
+    rng = np.random.default_rng([seed, SERVE_TARGETS.index(target)])
+    return quantize_gaussian(rng, (d_in, d_out), 0.02)
+
+
+def serving_request(req_id: int, target: str, T: int, r: int, kind: str, W: np.ndarray,
+                    seed: int = 5, device=None) -> Workload:
+    """One proof request: fwd -> P1..P3, bwd -> P4 + dX group, upd -> P5, P6."""
+    d_in, d_out = W.shape
+    rng = np.random.default_rng([seed, 1000 + req_id])
+    X = quantize_gaussian(rng, (T, d_in), 1.0)
+    L = LoraLayer.__new__(LoraLayer)
+    L.T, L.d_in, L.d_out, L.r = T, d_in, d_out, r
+    L.X, L.W = X, W
+    L.A = quantize_gaussian(rng, (d_in, r), 0.02)
+    L.B = quantize_gaussian(rng, (r, d_out), 0.02)
+    L.dY = quantize_gaussian(rng, (T, d_out), 1.0) if kind != "fwd" else None
+    L._H = None
+    L._G = None
+    tag = f"req{req_id}:{target}:"
+    if kind == "fwd":
+        groups = lora_forward(L, tag, device)
+    else:
+        bu = lora_backward_update(L, tag, device)
+        groups = [bu[0], bu[3]] if kind == "bwd" else [bu[1], bu[2]]
+    return Workload(f"request {req_id} {kind} {target} T={T} r={r}", seed, _number(groups))
+
+
+def serving_stream(n: int, rate_per_s: float, seed: int = 5):
+    """Poisson arrival times and request types: list of (t_arrive, target, T, r, kind)."""
+    rng = np.random.default_rng([seed, 7])
+    gaps = rng.exponential(1.0 / rate_per_s, size=n)
+    t = np.cumsum(gaps)
+    out = []
+    for i in range(n):
+        out.append((float(t[i]), SERVE_TARGETS[rng.integers(len(SERVE_TARGETS))],
+                    SERVE_T[rng.integers(len(SERVE_T))], SERVE_RANKS[rng.integers(len(SERVE_RANKS))],
+                    SERVE_TYPES[rng.integers(len(SERVE_TYPES))]))
+    return out
+
+
+# --------------------------------------------------------------------------
+# small random groups for parity tests
+# --------------------------------------------------------------------------
+_DTYPE_RANGE = {np.int16: (I16_MIN, I16_MAX), np.int32: (-(1 << 31), (1 << 31) - 1),
+                np.int64: (-(1 << 62), (1 << 62) - 1)}
+
+
+def tiny_random_group(seed: int, dims_list, dtype=np.int16, trans=(False, False),
+                      value_bits: Optional[int] = None, name: str = "rand") -> Group:
+    """A group of products with the given (D0, D1, D2) dims (shared D0, D2).
+
+    Entries are uniform over the dtype (or over +-2^value_bits if given).  The
+    stored tensors are transposed when the matching flag is set, so that the
+    product is formed through a transposed view.
+    """
+    rng = np.random.default_rng(seed)
+    lo, hi = _DTYPE_RANGE[dtype]
+    if value_bits is not None:
+        lo, hi = -(1 << value_bits), (1 << value_bits) - 1
+    prods = []
+    for k, (d0, d1, d2) in enumerate(dims_list):
+        a = rng.integers(lo, hi + 1, size=(d0, d1), dtype=np.int64).astype(dtype)
+        b = rng.integers(lo, hi + 1, size=(d1, d2), dtype=np.int64).astype(dtype)
+        A = np.ascontiguousarray(a.T) if trans[0] else a
+        B = np.ascontiguousarray(b.T) if trans[1] else b
+        prods.append(Product(f"{name}{k}", A, B, transA=trans[0], transB=trans[1]))
+    g = _group(name, prods)
+    return g
+
+
+CONFIG_NAMES = ("cfg1", "cfg2", "cfg3", "cfg4")
+
+
+def make_config(name: str, **kw) -> Workload:
+    fn: Callable[..., Workload] = {"cfg1": config1, "cfg2": config2, "cfg3": config3,
+                                   "cfg4": config4}[name]
+    return fn(**kw)
