@@ -1,0 +1,184 @@
+/*
+ * verilora.h -- C ABI of the MI355X matmul-sumcheck prover.
+ *
+ * The library proves matrix-product claims C = A.B (and sums of products)
+ * with the sumcheck protocol over the BLS12-381 scalar field Fr.  The field is
+ * this library's choice; the paper asks only for |F| ~ 2^254 (Sec. V).  The
+ * statement is Sec. II-C: with every dimension zero padded to a power of two,
+ *     C~(u, v) = sum_{w in {0,1}^{n1}} A~(u, w) * B~(w, v)            (zk-mle-matmul)
+ * for random u, v, where X~ is the multilinear extension of eq. (MLE).  zkMat
+ * (Sec. IV-B) applies this to every matrix product of a LoRA step, given the
+ * input matrices and the claimed output.
+ *
+ * Conventions shared by every entry point
+ *   - Integer matrices are row-major with a leading dimension "ld" counted in
+ *     elements (ld >= number of columns).  Signed integers enter the field as
+ *     x mod p, so x < 0 becomes p - |x|.
+ *   - A vl_fr_vec is a device vector of Fr elements in Montgomery form
+ *     (x * 2^256 mod p) stored as structure-of-limbs: 32-bit limb j
+ *     (little-endian, j = 0..7) of element k is at base[j * ld + k].
+ *   - A vl_fr passed to or from the host is canonical (< p), little-endian.
+ *   - Index bits are read most-significant first: index i of a length-2^n
+ *     vector is the point (b_1, ..., b_n) with b_1 the top bit.
+ *   - "stream" is a hipStream_t (NULL for the default stream).  Device
+ *     calls are asynchronous on that stream unless stated otherwise.
+ *   - The caller owns every buffer.  No entry point allocates device memory;
+ *     scratch space comes from a caller-provided workspace.
+ *   - Every call returns a vl_status; on failure vl_last_error() gives a
+ *     message (thread-local, valid until the next call on that thread).
+ */
+#ifndef VERILORA_H
+#define VERILORA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VL_OK = 0,
+  VL_ERR_INVALID_ARG = 1,      /* null pointer, bad enum, inconsistent sizes   */
+  VL_ERR_SHAPE = 2,            /* a dimension is 0, too large, or mismatched   */
+  VL_ERR_DTYPE = 3,            /* unsupported element type                     */
+  VL_ERR_WORKSPACE = 4,        /* workspace smaller than the size query says   */
+  VL_ERR_HIP = 5,              /* a HIP runtime call failed                    */
+  VL_ERR_FALSE_STATEMENT = 6,  /* the products do not sum to C: no proof       */
+  VL_ERR_REJECT = 7,           /* verification failed                          */
+  VL_ERR_BUFFER_TOO_SMALL = 8, /* an output buffer is too small                */
+  VL_ERR_RANGE = 9             /* an int32/int64 entry is outside the range the
+                                  contraction digits represent (|x| >= 2^63 for
+                                  int64 with four digits, 2^47 with three)     */
+} vl_status;
+
+typedef enum { VL_I16 = 1, VL_I32 = 2, VL_I64 = 3 } vl_dtype;
+
+enum { VL_CONTRACT_ROWS = 0, VL_CONTRACT_COLS = 1 };
+enum { VL_MODE_PER_INSTANCE = 0, VL_MODE_BATCHED = 1, VL_MODE_PERSISTENT = 2 };
+
+typedef struct { uint32_t w[8]; } vl_fr;
+
+typedef struct {
+  uint32_t* base;
+  uint64_t n;   /* number of elements                          */
+  uint64_t ld;  /* plane stride in 32-bit words, ld >= n        */
+} vl_fr_vec;
+
+/* One product op(A) . op(B).  Without transposition A is D0 x D1 (lda >= D1)
+ * and B is D1 x D2 (ldb >= D2).  With trans_a the stored A is D1 x D0
+ * (lda >= D0) and op(A) is its transpose; likewise trans_b stores B as
+ * D2 x D1 (ldb >= D1).  A and B are device pointers for proving and host
+ * pointers (or NULL) for verification. */
+typedef struct {
+  const void* A;
+  const void* B;
+  int32_t dtype_a, dtype_b;
+  uint32_t D0, D1, D2;
+  uint64_t lda, ldb;
+  int32_t trans_a, trans_b;
+} vl_product;
+
+/* A group: products sharing D0 and D2 whose sum is the claimed C (D0 x D2,
+ * ldc >= D2).  A group of one product is a plain matmul; more products prove
+ * a sum of products (zkMat covers additions, Sec. IV-B).  group_id and the
+ * seed key the group's own Fiat-Shamir transcript. */
+typedef struct {
+  const vl_product* prods;
+  uint32_t n_prods;      /* 1 .. VL_MAX_PRODS */
+  uint32_t group_id;
+  const void* C;
+  int32_t dtype_c;
+  uint64_t ldc;
+} vl_group;
+
+#define VL_MAX_PRODS 8
+#define VL_MAX_DIM (1u << 20)
+
+typedef struct {
+  int32_t mode;            /* VL_MODE_*; every mode yields identical bytes            */
+  int32_t async;           /* 0: proofs/digests are host buffers and the call returns
+                              after they are written; 1: they are device buffers, the
+                              call only enqueues work, and per-group status codes land
+                              in status[]                                             */
+  void* workspace;         /* device memory, >= vl_workspace_size() bytes             */
+  uint64_t workspace_bytes;
+  int32_t* status;         /* async only: device int32[n_groups], VL_OK / VL_ERR_*     */
+  const void* plan;        /* reserved, must be NULL                                  */
+} vl_prove_opts;
+
+/* Lift n signed integers (dtype) at device pointer src into Fr (Montgomery,
+ * structure-of-limbs) at dst (dst.n >= n).  Negative x becomes p - |x|. */
+vl_status vl_fr_lift(const void* src, int32_t dtype, uint64_t n, vl_fr_vec dst, void* stream);
+
+/* Convert n elements of a device vl_fr_vec to canonical form, written
+ * element-major to the device array dst (8 words per element). */
+vl_status vl_fr_export(vl_fr_vec src, uint64_t n, uint32_t* dst, void* stream);
+
+/* eq table of eq. (MLE): out[i] = prod_j (x_j b_j(i) + (1 - x_j)(1 - b_j(i)))
+ * for i < 2^nvars (b_1 = top bit).  point: host array of nvars canonical
+ * elements; out.n must be >= 2^nvars.  nvars <= 20. */
+vl_status vl_eq_table(const vl_fr* point, uint32_t nvars, vl_fr_vec out, void* stream);
+
+/* Workspace bytes needed by vl_mle_partial_eval for this shape. */
+uint64_t vl_partial_eval_workspace_size(uint32_t rows, uint32_t cols, int32_t contract, int32_t dtype);
+
+/* Partial evaluation of a matrix MLE (the A~(u, .) and B~(., v) of
+ * eq. (zk-mle-matmul)).  M: device rows x cols integers (dtype), row-major,
+ * leading dimension ld.
+ *   VL_CONTRACT_ROWS: out[c] = sum_r eq[r] M[r][c]   (needs eq.n >= rows)
+ *   VL_CONTRACT_COLS: out[r] = sum_c M[r][c] eq[c]   (needs eq.n >= cols)
+ * Entries of out beyond the result length (cols resp. rows) up to out.n are
+ * set to zero, so out is the zero-padded table of a multilinear function. */
+vl_status vl_mle_partial_eval(const void* M, int32_t dtype, uint32_t rows, uint32_t cols,
+                              uint64_t ld, int32_t contract, vl_fr_vec eq, vl_fr_vec out,
+                              void* workspace, uint64_t workspace_bytes, void* stream);
+
+/* Bytes of one group's proof:
+ * 32 * (1 + (n_prods - 1) + sum over products of (3 * n1 + 2)),
+ * n1 = ceil(log2 D1).  Layout: c || part claims || per product the round
+ * values g(0), g(1), g(2) per round || a_final || b_final, each a canonical
+ * 32-byte little-endian field element. */
+uint64_t vl_proof_size(const vl_group* group);
+
+/* Device workspace needed to prove these groups with these options. */
+uint64_t vl_workspace_size(const vl_group* groups, uint64_t n_groups, const vl_prove_opts* opts);
+
+/* Prove every group (the matmul sumcheck of eq. (zk-mle-matmul), Sec. II-C,
+ * run by zkMat for each product of a LoRA step, Sec. IV-B).
+ *   proofs   : host (async = 0) or device (async = 1) buffer of proofs_len
+ *              bytes; group g's proof starts at offsets[g]
+ *   offsets  : host uint64[n_groups + 1], filled by the call
+ *   digests  : optional (NULL) 32 bytes per group, the final transcript
+ *              state; host or device like proofs
+ * The proof of a group depends only on (its matrices, seed, group_id); the
+ * mode, the batching and other groups never change a byte.  Returns
+ * VL_ERR_FALSE_STATEMENT (async = 0) if some group's products do not sum to
+ * its C; in async mode that code lands in status[g] instead. */
+vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n_groups, uint64_t seed,
+                                   const vl_prove_opts* opts, uint8_t* proofs, uint64_t proofs_len,
+                                   uint64_t* offsets, uint8_t* digests, void* stream);
+
+/* Host-side verifier (CPU only).  Replays the transcript for (shape, seed,
+ * group_id), checks g(0) + g(1) against the running claim in every round,
+ * moves the claim to g(r) by interpolation on {0, 1, 2}, and checks the last
+ * claim against a_final * b_final.  If the group's A, B (every product) and C
+ * pointers are all non-NULL they are read as HOST matrices and c = C~(u, v),
+ * a_final = A~(u, r), b_final = B~(r, v) are also checked by direct
+ * evaluation (commitment openings are out of scope).
+ *   reduced : optional host output of the reduced claims, canonical:
+ *             c, u[n0], v[n2], then per product r[n1], a_final, b_final
+ *   reduced_len : elements written (or needed, on VL_ERR_BUFFER_TOO_SMALL)
+ *   fail_round  : 1-based round of the group that failed, 0 for a length or
+ *                 encoding error or a failed final or witness check, -1 on VL_OK
+ * Returns VL_OK or VL_ERR_REJECT. */
+vl_status vl_verify_transcript(const uint8_t* proof, uint64_t len, const vl_group* group,
+                               uint64_t seed, vl_fr* reduced, uint64_t reduced_cap,
+                               uint64_t* reduced_len, int32_t* fail_round);
+
+/* Message for the last non-OK status on this thread. */
+const char* vl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VERILORA_H */

@@ -1,0 +1,269 @@
+"""ctypes binding of libverilora.so (argument marshalling only).
+
+The functions below carry the C ABI's names (without the ``vl_`` prefix) and
+pass raw pointers through; every step of the prover runs in the library's
+HIP kernels.  PyTorch supplies device memory and the current HIP stream.  If
+the library has not been built the first call raises: there is no fallback.
+"""
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libverilora.so")
+
+VL_OK, VL_ERR_INVALID_ARG, VL_ERR_SHAPE, VL_ERR_DTYPE, VL_ERR_WORKSPACE, VL_ERR_HIP, \
+    VL_ERR_FALSE_STATEMENT, VL_ERR_REJECT, VL_ERR_BUFFER_TOO_SMALL, VL_ERR_RANGE = range(10)
+VL_I16, VL_I32, VL_I64 = 1, 2, 3
+VL_CONTRACT_ROWS, VL_CONTRACT_COLS = 0, 1
+VL_MODE_PER_INSTANCE, VL_MODE_BATCHED, VL_MODE_PERSISTENT = 0, 1, 2
+VL_MAX_PRODS = 8
+
+STATUS_NAMES = {0: "VL_OK", 1: "VL_ERR_INVALID_ARG", 2: "VL_ERR_SHAPE", 3: "VL_ERR_DTYPE",
+                4: "VL_ERR_WORKSPACE", 5: "VL_ERR_HIP", 6: "VL_ERR_FALSE_STATEMENT",
+                7: "VL_ERR_REJECT", 8: "VL_ERR_BUFFER_TOO_SMALL", 9: "VL_ERR_RANGE"}
+
+EXPORTED = ("vl_fr_lift", "vl_fr_export", "vl_eq_table", "vl_partial_eval_workspace_size",
+            "vl_mle_partial_eval", "vl_proof_size", "vl_workspace_size",
+            "vl_sumcheck_matmul_prove", "vl_verify_transcript", "vl_last_error")
+
+c_u32, c_u64, c_i32, c_vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p
+
+
+class vl_fr(ctypes.Structure):
+    _fields_ = [("w", c_u32 * 8)]
+
+
+class vl_fr_vec(ctypes.Structure):
+    _fields_ = [("base", c_vp), ("n", c_u64), ("ld", c_u64)]
+
+
+class vl_product(ctypes.Structure):
+    _fields_ = [("A", c_vp), ("B", c_vp), ("dtype_a", c_i32), ("dtype_b", c_i32),
+                ("D0", c_u32), ("D1", c_u32), ("D2", c_u32), ("lda", c_u64), ("ldb", c_u64),
+                ("trans_a", c_i32), ("trans_b", c_i32)]
+
+
+class vl_group(ctypes.Structure):
+    _fields_ = [("prods", ctypes.POINTER(vl_product)), ("n_prods", c_u32), ("group_id", c_u32),
+                ("C", c_vp), ("dtype_c", c_i32), ("ldc", c_u64)]
+
+
+class vl_prove_opts(ctypes.Structure):
+    _fields_ = [("mode", c_i32), ("async_", c_i32), ("workspace", c_vp), ("workspace_bytes", c_u64),
+                ("status", c_vp), ("plan", c_vp)]
+
+
+class VLError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2508_21393_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.vl_fr_lift.argtypes = [c_vp, c_i32, c_u64, vl_fr_vec, c_vp]
+        L.vl_fr_export.argtypes = [vl_fr_vec, c_u64, c_vp, c_vp]
+        L.vl_eq_table.argtypes = [ctypes.POINTER(vl_fr), c_u32, vl_fr_vec, c_vp]
+        L.vl_partial_eval_workspace_size.argtypes = [c_u32, c_u32, c_i32, c_i32]
+        L.vl_partial_eval_workspace_size.restype = c_u64
+        L.vl_mle_partial_eval.argtypes = [c_vp, c_i32, c_u32, c_u32, c_u64, c_i32, vl_fr_vec, vl_fr_vec,
+                                          c_vp, c_u64, c_vp]
+        L.vl_proof_size.argtypes = [ctypes.POINTER(vl_group)]
+        L.vl_proof_size.restype = c_u64
+        L.vl_workspace_size.argtypes = [ctypes.POINTER(vl_group), c_u64, ctypes.POINTER(vl_prove_opts)]
+        L.vl_workspace_size.restype = c_u64
+        L.vl_sumcheck_matmul_prove.argtypes = [ctypes.POINTER(vl_group), c_u64, c_u64,
+                                               ctypes.POINTER(vl_prove_opts), c_vp, c_u64,
+                                               ctypes.POINTER(c_u64), c_vp, c_vp]
+        L.vl_verify_transcript.argtypes = [c_vp, c_u64, ctypes.POINTER(vl_group), c_u64,
+                                           ctypes.POINTER(vl_fr), c_u64, ctypes.POINTER(c_u64),
+                                           ctypes.POINTER(c_i32)]
+        L.vl_last_error.restype = ctypes.c_char_p
+        for f in ("vl_fr_lift", "vl_fr_export", "vl_eq_table", "vl_mle_partial_eval",
+                  "vl_sumcheck_matmul_prove", "vl_verify_transcript"):
+            getattr(L, f).restype = c_i32
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().vl_last_error().decode()
+
+
+def _check(status: int):
+    if status != VL_OK:
+        raise VLError(status, last_error())
+
+
+# ---------------------------------------------------------------- helpers ----
+def dtype_code(dt) -> int:
+    s = str(dt).replace("torch.", "")
+    return {"int16": VL_I16, "int32": VL_I32, "int64": VL_I64}[s]
+
+
+def _ptr(x) -> int:
+    """Raw pointer of a torch tensor (device or host) or a numpy array (host)."""
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    return x.ctypes.data
+
+
+def _row_stride(x) -> int:
+    """Leading dimension in elements (a single row may report any stride)."""
+    rows, cols = x.shape
+    if hasattr(x, "stride") and callable(x.stride):
+        assert cols <= 1 or x.stride(1) == 1, "matrices must be row-major"
+        ld = x.stride(0)
+    else:
+        assert cols <= 1 or x.strides[1] == x.itemsize, "matrices must be row-major"
+        ld = x.strides[0] // x.itemsize
+    return ld if rows > 1 else max(ld, cols, 1)
+
+
+def fr_to_int(f: vl_fr) -> int:
+    return sum(int(f.w[i]) << (32 * i) for i in range(8))
+
+
+def int_to_fr(x: int) -> vl_fr:
+    f = vl_fr()
+    for i in range(8):
+        f.w[i] = (x >> (32 * i)) & 0xFFFFFFFF
+    return f
+
+
+def fr_vec(t, n: Optional[int] = None) -> vl_fr_vec:
+    """A (8, ld) uint32/int32 device tensor viewed as a structure-of-limbs vector."""
+    assert t.dim() == 2 and t.shape[0] == 8 and t.stride(1) == 1
+    return vl_fr_vec(t.data_ptr(), t.shape[1] if n is None else n, t.stride(0))
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+class GroupArgs:
+    """vl_group built from (A, B, transA, transB) operands and C; keeps the
+    Python objects alive as long as the structure is used."""
+
+    def __init__(self, group_id: int, prods: Sequence[Tuple[object, object, bool, bool]], C):
+        self.keep = [C] + [x for p in prods for x in p[:2]]
+        arr = (vl_product * len(prods))()
+        for k, (A, B, ta, tb) in enumerate(prods):
+            a_rows, a_cols = A.shape
+            b_rows, b_cols = B.shape
+            D0, D1 = (a_cols, a_rows) if ta else (a_rows, a_cols)
+            D1b, D2 = (b_cols, b_rows) if tb else (b_rows, b_cols)
+            assert D1 == D1b, "inner dimensions differ"
+            arr[k] = vl_product(_ptr(A), _ptr(B), dtype_code(A.dtype), dtype_code(B.dtype), D0, D1, D2,
+                                _row_stride(A), _row_stride(B), int(ta), int(tb))
+        self.prods = arr
+        self.struct = vl_group(arr, len(prods), group_id, _ptr(C), dtype_code(C.dtype), _row_stride(C))
+
+    @property
+    def shapes(self):
+        return [(p.D0, p.D1, p.D2) for p in self.prods]
+
+
+def group_array(groups: Sequence[GroupArgs]):
+    arr = (vl_group * len(groups))()
+    for i, g in enumerate(groups):
+        arr[i] = g.struct
+    return arr
+
+
+# ---------------------------------------------------------------- the ABI ----
+def fr_lift(src, n: int, dst: vl_fr_vec, stream=None):
+    _check(lib().vl_fr_lift(_ptr(src), dtype_code(src.dtype), n, dst, _stream(stream)))
+
+
+def fr_export(src: vl_fr_vec, n: int, dst, stream=None):
+    _check(lib().vl_fr_export(src, n, _ptr(dst), _stream(stream)))
+
+
+def eq_table(point: Sequence[int], out: vl_fr_vec, stream=None):
+    arr = (vl_fr * max(1, len(point)))(*[int_to_fr(x) for x in point])
+    _check(lib().vl_eq_table(arr, len(point), out, _stream(stream)))
+
+
+def partial_eval_workspace_size(rows: int, cols: int, contract: int, dtype) -> int:
+    return lib().vl_partial_eval_workspace_size(rows, cols, contract, dtype_code(dtype))
+
+
+def mle_partial_eval(M, contract: int, eq: vl_fr_vec, out: vl_fr_vec, workspace, stream=None):
+    rows, cols = M.shape
+    _check(lib().vl_mle_partial_eval(_ptr(M), dtype_code(M.dtype), rows, cols, _row_stride(M), contract,
+                                     eq, out, _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                     _stream(stream)))
+
+
+def proof_size(group: GroupArgs) -> int:
+    return lib().vl_proof_size(ctypes.byref(group.struct))
+
+
+def workspace_size(groups: Sequence[GroupArgs], mode: int = VL_MODE_BATCHED, async_: bool = False) -> int:
+    arr = group_array(groups)
+    opts = vl_prove_opts(mode, int(async_), None, 0, None, None)
+    return lib().vl_workspace_size(arr, len(groups), ctypes.byref(opts))
+
+
+def sumcheck_matmul_prove(groups: Sequence[GroupArgs], seed: int, mode: int = VL_MODE_BATCHED,
+                          workspace=None, stream=None, with_digests: bool = True):
+    """Blocking prove: returns (list of proof bytes, list of 32-byte digests)."""
+    import torch
+    arr = group_array(groups)
+    n = len(groups)
+    ws_bytes = workspace_size(groups, mode)
+    if workspace is None:
+        workspace = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device="cuda")
+    opts = vl_prove_opts(mode, 0, workspace.data_ptr(), workspace.numel(), None, None)
+    total = sum(proof_size(g) for g in groups)
+    buf = ctypes.create_string_buffer(max(total, 1))
+    offs = (c_u64 * (n + 1))()
+    dig = ctypes.create_string_buffer(32 * n) if with_digests else None
+    _check(lib().vl_sumcheck_matmul_prove(arr, n, seed, ctypes.byref(opts), ctypes.addressof(buf), total,
+                                          offs, ctypes.addressof(dig) if dig is not None else None,
+                                          _stream(stream)))
+    raw = buf.raw
+    proofs = [raw[offs[i]:offs[i + 1]] for i in range(n)]
+    digests = [dig.raw[32 * i:32 * i + 32] for i in range(n)] if dig is not None else None
+    return proofs, digests
+
+
+def sumcheck_matmul_prove_async(groups: Sequence[GroupArgs], seed: int, proofs_dev, status_dev,
+                                workspace, mode: int = VL_MODE_BATCHED, digests_dev=None, stream=None):
+    """Enqueue a prove on the stream; proofs/status/digests land in device
+    buffers.  Returns the host offsets of each group's proof."""
+    arr = group_array(groups)
+    n = len(groups)
+    opts = vl_prove_opts(mode, 1, workspace.data_ptr(), workspace.numel(), status_dev.data_ptr(), None)
+    offs = (c_u64 * (n + 1))()
+    _check(lib().vl_sumcheck_matmul_prove(arr, n, seed, ctypes.byref(opts), proofs_dev.data_ptr(),
+                                          proofs_dev.numel(), offs,
+                                          digests_dev.data_ptr() if digests_dev is not None else None,
+                                          _stream(stream)))
+    return [int(offs[i]) for i in range(n + 1)]
+
+
+def verify_transcript(proof: bytes, group: GroupArgs, seed: int):
+    """Host verifier.  Returns (ok, fail_round, reduced claims as ints)."""
+    cap = 4096
+    red = (vl_fr * cap)()
+    rlen = c_u64(0)
+    fr_ = c_i32(0)
+    buf = ctypes.create_string_buffer(proof, max(len(proof), 1))
+    st = lib().vl_verify_transcript(ctypes.addressof(buf), len(proof), ctypes.byref(group.struct), seed,
+                                    red, cap, ctypes.byref(rlen), ctypes.byref(fr_))
+    if st not in (VL_OK, VL_ERR_REJECT):
+        _check(st)
+    return st == VL_OK, fr_.value, [fr_to_int(red[i]) for i in range(rlen.value)] if st == VL_OK else []

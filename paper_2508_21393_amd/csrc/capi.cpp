@@ -1,0 +1,571 @@
+// Host orchestration and the C ABI of the prover (see include/verilora.h).
+//
+// A prove call turns each group into device jobs:
+//   1. host: transcript init, squeeze u (n0 values) and v (n2 values)
+//   2. eq jobs: eq(u, .) as a table and in pack form; eq(v, .) in pack form
+//   3. contraction jobs: a_p = A_p~(u, .), b_p = B_p~(., v) for every product,
+//      t = C eq(v, .) for the claim (eq. (zk-mle-matmul), Sec. II-C)
+//   4. finish jobs: add split contractions, zero pad to powers of two
+//   5. one rounds job per group: c = eq(u, .) . t, prover guard, sumcheck
+// Per-instance mode runs these launches group by group with a host wait per
+// group; batched mode runs each stage once for all groups (one launch per
+// stage and contraction kind); both write identical bytes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "plan.hpp"
+#include "sha256.hpp"
+
+namespace vl {
+
+thread_local std::string g_err;
+
+vl_status fail(vl_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+uint32_t nvars_of(uint64_t d) {
+  uint32_t n = 0;
+  while ((1ull << n) < d) ++n;
+  return n;
+}
+
+uint64_t esize(int dt) {
+  switch (dt) {
+    case VL_I16: return 2;
+    case VL_I32: return 4;
+    case VL_I64: return 8;
+    default: return 0;
+  }
+}
+
+// ---------------------------------------------------------------- checks ----
+vl_status check_group(const vl_group& g, bool need_ptrs) {
+  if (!g.prods || g.n_prods == 0 || g.n_prods > VL_MAX_PRODS)
+    return fail(VL_ERR_INVALID_ARG, "group %u: n_prods must be 1..%d", g.group_id, VL_MAX_PRODS);
+  const vl_product& p0 = g.prods[0];
+  for (uint32_t k = 0; k < g.n_prods; ++k) {
+    const vl_product& p = g.prods[k];
+    if (p.D0 == 0 || p.D1 == 0 || p.D2 == 0 || p.D0 > VL_MAX_DIM || p.D1 > VL_MAX_DIM ||
+        p.D2 > VL_MAX_DIM)
+      return fail(VL_ERR_SHAPE, "group %u product %u: dims must be 1..2^20", g.group_id, k);
+    if (p.D0 != p0.D0 || p.D2 != p0.D2)
+      return fail(VL_ERR_SHAPE, "group %u: products must share D0 and D2", g.group_id);
+    if (!esize(p.dtype_a) || !esize(p.dtype_b))
+      return fail(VL_ERR_DTYPE, "group %u product %u: dtype must be VL_I16/I32/I64", g.group_id, k);
+    const uint64_t acols = p.trans_a ? p.D0 : p.D1, bcols = p.trans_b ? p.D1 : p.D2;
+    if (p.lda < acols || p.ldb < bcols)
+      return fail(VL_ERR_SHAPE, "group %u product %u: leading dimension too small", g.group_id, k);
+    if (need_ptrs && (!p.A || !p.B))
+      return fail(VL_ERR_INVALID_ARG, "group %u product %u: null matrix", g.group_id, k);
+  }
+  if (!esize(g.dtype_c)) return fail(VL_ERR_DTYPE, "group %u: dtype_c must be VL_I16/I32/I64", g.group_id);
+  if (g.ldc < p0.D2) return fail(VL_ERR_SHAPE, "group %u: ldc < D2", g.group_id);
+  if (need_ptrs && !g.C) return fail(VL_ERR_INVALID_ARG, "group %u: null C", g.group_id);
+  return VL_OK;
+}
+
+uint64_t proof_elems(const vl_group& g) {
+  uint64_t n = g.n_prods;  // c and the part claims
+  for (uint32_t k = 0; k < g.n_prods; ++k) n += 3ull * nvars_of(g.prods[k].D1) + 2;
+  return n;
+}
+
+void group_challenges(const vl_group& g, uint64_t seed, Transcript& tr, std::vector<Fr>& u,
+                      std::vector<Fr>& v) {
+  std::vector<uint32_t> dims;
+  for (uint32_t k = 0; k < g.n_prods; ++k) {
+    dims.push_back(g.prods[k].D0);
+    dims.push_back(g.prods[k].D1);
+    dims.push_back(g.prods[k].D2);
+  }
+  tr_init(tr, seed, g.group_id, g.n_prods, dims.data());
+  const uint32_t n0 = nvars_of(g.prods[0].D0), n2 = nvars_of(g.prods[0].D2);
+  u.resize(n0);
+  v.resize(n2);
+  for (uint32_t i = 0; i < n0; ++i) u[i] = tr_squeeze(tr, VL_LBL_U);
+  for (uint32_t i = 0; i < n2; ++i) v[i] = tr_squeeze(tr, VL_LBL_V);
+}
+
+// ---------------------------------------------------------------- planning --
+static int contract_kind(int dtype, int nd, bool rows, bool vec) {
+  int base;
+  if (dtype == VL_I16) base = CK_I16_ROWS;
+  else if (dtype == VL_I32) base = CK_I32_ROWS;
+  else base = nd == 3 ? CK_I64N3_ROWS : CK_I64N4_ROWS;
+  return base + (rows ? 0 : (vec ? 2 : 1));
+}
+
+int digits_for(int dtype) { return dtype == VL_I16 ? 1 : (dtype == VL_I32 ? 3 : 4); }
+
+void Builder::contract(const void* M, int dtype, int nd, uint64_t ld, bool rows, uint32_t n_out,
+                       uint32_t len, const uint32_t* pack, uint32_t* dst, uint64_t dst_ld,
+                       uint64_t n_total, int32_t* err) {
+  ContractJob j{};
+  const uint64_t es = esize(dtype);
+  const bool vec = !rows && (reinterpret_cast<uintptr_t>(M) % 16 == 0) && ((ld * es) % 16 == 0);
+  const int kind = contract_kind(dtype, nd, rows, vec);
+  const uint32_t out_waves = (n_out + 63) / 64;
+  uint64_t chunk = std::max<uint64_t>(256, T.chunk_target / (uint32_t)nd);
+  chunk = std::min<uint64_t>(chunk, align_up(len, kChunkAlign));
+  chunk = align_up(chunk, kChunkAlign);
+  while (T.min_tasks > 1 && chunk > 256 &&
+         (uint64_t)out_waves * ((len + chunk - 1) / chunk) < T.min_tasks)
+    chunk = align_up(chunk / 2, kChunkAlign);
+  const uint32_t n_chunks = (uint32_t)((len + chunk - 1) / chunk);
+  j.M = M;
+  j.ld = ld;
+  j.n_out = n_out;
+  j.len = len;
+  j.chunk = (uint32_t)chunk;
+  j.n_chunks = n_chunks;
+  j.out_waves = out_waves;
+  j.task_begin = P.cj_tasks[kind];
+  j.pack = pack;
+  j.err = nd > 1 ? err : nullptr;
+  FinishJob f{};
+  f.n_valid = n_out;
+  f.n_total = (uint32_t)n_total;
+  f.out = dst;
+  f.out_ld = dst_ld;
+  f.n_chunks = n_chunks;
+  if (n_chunks == 1) {
+    j.dst = dst;
+    j.dst_ld = dst_ld;
+    j.chunk_stride = 0;
+    f.part = nullptr;
+  } else {
+    const uint64_t pld = align_up(n_out, 64);
+    uint32_t* part = dev<uint32_t>(take((uint64_t)n_chunks * 8 * pld * 4));
+    j.dst = part;
+    j.dst_ld = pld;
+    j.chunk_stride = 8 * pld;
+    f.part = part;
+    f.part_ld = pld;
+    f.chunk_stride = 8 * pld;
+  }
+  P.cj_tasks[kind] += out_waves * n_chunks;
+  P.cj[kind].push_back(j);
+  if (f.part || f.n_total > f.n_valid) {
+    f.thread_begin = P.fin_threads;
+    P.fin_threads += f.n_total;
+    P.fin.push_back(f);
+  }
+}
+
+void Builder::eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_pairs) {
+  EqJob e{};
+  e.nvars = (uint32_t)x.size();
+  e.pack_pairs = pack_pairs;
+  e.thread_begin = P.eq_threads;
+  e.eq = eq;
+  e.eq_ld = 1ull << x.size();
+  e.pack = pack;
+  std::vector<uint32_t> pts;
+  for (const Fr& xi : x) {
+    const Fr xm = fr_to_mont(xi);
+    const Fr om = fr_sub(fr_R(), xm);
+    pts.insert(pts.end(), xm.w, xm.w + 8);
+    pts.insert(pts.end(), om.w, om.w + 8);
+  }
+  P.points.push_back(pts);
+  const uint32_t threads = std::max<uint32_t>(1, (uint32_t)((1ull << x.size()) / 2));
+  P.eq_threads += std::max(threads, pack_pairs);
+  P.eq.push_back(e);
+}
+
+void Builder::group(const vl_group& g, uint64_t seed, uint8_t* proof_dev, int32_t* status_dev,
+                    uint8_t* digest_dev, int32_t* err) {
+  Transcript tr;
+  std::vector<Fr> u, v;
+  group_challenges(g, seed, tr, u, v);
+  const vl_product& p0 = g.prods[0];
+  const uint32_t D0 = p0.D0, D2 = p0.D2, n0 = (uint32_t)u.size();
+  const uint64_t L0 = 1ull << n0;
+  uint32_t* eqU = dev<uint32_t>(take(8 * L0 * 4));
+  uint32_t* packU = dev<uint32_t>(take((uint64_t)((D0 + 1) / 2) * 128));
+  uint32_t* packV = dev<uint32_t>(take((uint64_t)((D2 + 1) / 2) * 128));
+  uint32_t* tvec = dev<uint32_t>(take(8 * L0 * 4));
+  eq_job(u, eqU, packU, (D0 + 1) / 2);
+  eq_job(v, nullptr, packV, (D2 + 1) / 2);
+
+  // claim contraction: t[i] = sum_j C[i][j] eq(v, j).  Three 16-bit digits
+  // cover |C| < 2^47 - 2^31, enough for sums of int16 products with a total
+  // inner dimension <= 2^16; wider C uses four (an out-of-range entry makes
+  // the prover refuse with VL_ERR_RANGE rather than prove a wrong claim).
+  int ndc = 4;
+  if (g.dtype_c == VL_I16) ndc = 1;
+  else if (g.dtype_c == VL_I32) ndc = 3;
+  else {
+    uint64_t sum_d1 = 0;
+    bool small = true;
+    for (uint32_t k = 0; k < g.n_prods; ++k) {
+      sum_d1 += g.prods[k].D1;
+      small &= g.prods[k].dtype_a == VL_I16 && g.prods[k].dtype_b == VL_I16;
+    }
+    if (small && sum_d1 <= (1u << 16)) ndc = 3;
+  }
+  contract(g.C, g.dtype_c, ndc, g.ldc, false, D0, D2, packV, tvec, L0, L0, err);
+
+  RoundsJob rj{};
+  memcpy(rj.st, tr.st, 32);
+  rj.n_prods = g.n_prods;
+  rj.n0 = n0;
+  rj.eqU = eqU;
+  rj.eqU_ld = L0;
+  rj.t = tvec;
+  rj.t_ld = L0;
+  rj.proof = proof_dev;
+  rj.status = status_dev;
+  rj.digest = digest_dev;
+  rj.err = err;
+  for (uint32_t k = 0; k < g.n_prods; ++k) {
+    const vl_product& p = g.prods[k];
+    const uint32_t n1 = nvars_of(p.D1);
+    const uint64_t L1 = 1ull << n1;
+    uint32_t* a = dev<uint32_t>(take(8 * L1 * 4));
+    uint32_t* b = dev<uint32_t>(take(8 * L1 * 4));
+    // a[w] = sum_i eq(u, i) op(A)[i][w]: rows of stored A, or columns of stored A^T
+    contract(p.A, p.dtype_a, digits_for(p.dtype_a), p.lda, !p.trans_a, p.D1, D0, packU, a, L1, L1, err);
+    // b[w] = sum_j op(B)[w][j] eq(v, j): columns of stored B, or rows of stored B^T
+    contract(p.B, p.dtype_b, digits_for(p.dtype_b), p.ldb, p.trans_b != 0, p.D1, D2, packV, b, L1, L1, err);
+    rj.prods[k].a = a;
+    rj.prods[k].b = b;
+    rj.prods[k].ld = L1;
+    rj.prods[k].n1 = n1;
+  }
+  P.rounds.push_back(rj);
+}
+
+BlobLayout blob_layout(const Plan& P) {
+  BlobLayout L{};
+  uint64_t o = 0;
+  L.err = o;
+  o = align_up(o + 4ull * std::max<uint32_t>(P.n_err, 1), 64);
+  L.eq = o;
+  o = align_up(o + P.eq.size() * sizeof(EqJob), 64);
+  for (int k = 0; k < CK_COUNT; ++k) {
+    L.cj[k] = o;
+    o = align_up(o + P.cj[k].size() * sizeof(ContractJob), 64);
+  }
+  L.fin = o;
+  o = align_up(o + P.fin.size() * sizeof(FinishJob), 64);
+  L.rounds = o;
+  o = align_up(o + P.rounds.size() * sizeof(RoundsJob), 64);
+  L.points = o;
+  for (const auto& pt : P.points) o = align_up(o + pt.size() * 4, 64);
+  L.total = align_up(o, 256);
+  return L;
+}
+
+uint64_t blob_bound(const vl_group* groups, uint64_t n) {
+  uint64_t cj = 0, pts = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    cj += 1 + 2ull * groups[i].n_prods;
+    pts += 2ull * (nvars_of(groups[i].prods[0].D0) + nvars_of(groups[i].prods[0].D2)) * 32 + 128;
+  }
+  return align_up(4 * n + 64 + 2 * n * (sizeof(EqJob) + 64) +
+                      cj * (sizeof(ContractJob) + sizeof(FinishJob) + 128) +
+                      n * (sizeof(RoundsJob) + 64) + pts + 64 * CK_COUNT + 1024,
+                  256);
+}
+
+// fills the blob (descriptor pointers patched to the workspace copy)
+void fill_blob(Plan& P, const BlobLayout& L, uint8_t* dblob) {
+  P.blob.assign(L.total, 0);
+  uint64_t po = L.points;
+  for (size_t i = 0; i < P.eq.size(); ++i) {
+    P.eq[i].point = reinterpret_cast<const uint32_t*>(dblob + po);
+    memcpy(P.blob.data() + po, P.points[i].data(), P.points[i].size() * 4);
+    po = align_up(po + P.points[i].size() * 4, 64);
+  }
+  memcpy(P.blob.data() + L.eq, P.eq.data(), P.eq.size() * sizeof(EqJob));
+  for (int k = 0; k < CK_COUNT; ++k)
+    if (!P.cj[k].empty())
+      memcpy(P.blob.data() + L.cj[k], P.cj[k].data(), P.cj[k].size() * sizeof(ContractJob));
+  if (!P.fin.empty()) memcpy(P.blob.data() + L.fin, P.fin.data(), P.fin.size() * sizeof(FinishJob));
+  if (!P.rounds.empty())
+    memcpy(P.blob.data() + L.rounds, P.rounds.data(), P.rounds.size() * sizeof(RoundsJob));
+}
+
+hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipStream_t s) {
+  hipError_t e = launch_upload(dblob, P.blob.data(), L.total, s);
+  if (e != hipSuccess) return e;
+  e = launch_eq(reinterpret_cast<const EqJob*>(dblob + L.eq), (uint32_t)P.eq.size(), P.eq_threads, s);
+  if (e != hipSuccess) return e;
+  for (int k = 0; k < CK_COUNT; ++k) {
+    if (P.cj[k].empty()) continue;
+    e = launch_contract(k, reinterpret_cast<const ContractJob*>(dblob + L.cj[k]),
+                        (uint32_t)P.cj[k].size(), P.cj_tasks[k], s);
+    if (e != hipSuccess) return e;
+  }
+  if (!P.fin.empty()) {
+    e = launch_finish(reinterpret_cast<const FinishJob*>(dblob + L.fin), (uint32_t)P.fin.size(),
+                      P.fin_threads, s);
+    if (e != hipSuccess) return e;
+  }
+  return launch_rounds(reinterpret_cast<const RoundsJob*>(dblob + L.rounds), (uint32_t)P.rounds.size(), s);
+}
+
+Tuning tuning_for(const vl_prove_opts* o) {
+  Tuning t;
+  t.per_instance = !o || o->mode == VL_MODE_PER_INSTANCE;
+  t.min_tasks = t.per_instance ? 1024 : 1;
+  return t;
+}
+
+uint64_t out_bytes(const vl_group& g) { return align_up(proof_elems(g) * 32, 256) + 512; }
+
+// Plans groups [g0, g1) with the blob at workspace offset 0 and data after it.
+// ws == nullptr plans for sizing only.
+void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, uint64_t g1,
+                 uint64_t seed, uint8_t* ws, bool async, uint8_t* proofs_dev, const uint64_t* offsets,
+                 int32_t* status_dev, uint8_t* digests_dev) {
+  P = Plan();
+  const uint64_t blob = blob_bound(groups + g0, g1 - g0);
+  Builder B(P, T, reinterpret_cast<uint64_t>(ws), blob);
+  P.n_err = (uint32_t)(g1 - g0);
+  for (uint64_t i = g0; i < g1; ++i) {
+    uint8_t* pd;
+    int32_t* sd;
+    uint8_t* dd;
+    if (async) {
+      pd = proofs_dev ? proofs_dev + offsets[i] : nullptr;
+      sd = status_dev ? status_dev + i : nullptr;
+      dd = digests_dev ? digests_dev + 32 * i : nullptr;
+    } else {
+      const uint64_t o = B.take(out_bytes(groups[i]));
+      pd = ws + o;
+      sd = reinterpret_cast<int32_t*>(pd + align_up(proof_elems(groups[i]) * 32, 256));
+      dd = reinterpret_cast<uint8_t*>(sd) + 256;
+      P.proof_off.push_back(o);
+    }
+    int32_t* err = reinterpret_cast<int32_t*>(ws + 4 * (i - g0));  // blob starts with the flags
+    B.group(groups[i], seed, pd, sd, dd, err);
+  }
+  P.data_end = B.off;
+}
+
+}  // namespace vl
+
+using namespace vl;
+
+extern "C" {
+
+const char* vl_last_error(void) { return g_err.c_str(); }
+
+uint64_t vl_proof_size(const vl_group* g) {
+  if (!g || check_group(*g, false) != VL_OK) return 0;
+  return 32 * proof_elems(*g);
+}
+
+uint64_t vl_workspace_size(const vl_group* groups, uint64_t n, const vl_prove_opts* o) {
+  if (!groups || n == 0) return 0;
+  for (uint64_t i = 0; i < n; ++i)
+    if (check_group(groups[i], false) != VL_OK) return 0;
+  const Tuning T = tuning_for(o);
+  const bool async = o && o->async;
+  std::vector<uint64_t> offs(n + 1, 0);
+  Plan P;
+  if (T.per_instance) {
+    uint64_t mx = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+      plan_groups(P, T, groups, i, i + 1, 0, nullptr, async, nullptr, offs.data(), nullptr, nullptr);
+      mx = std::max(mx, P.data_end);
+    }
+    return align_up(mx, 256);
+  }
+  plan_groups(P, T, groups, 0, n, 0, nullptr, async, nullptr, offs.data(), nullptr, nullptr);
+  return align_up(P.data_end, 256);
+}
+
+vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t seed,
+                                   const vl_prove_opts* o, uint8_t* proofs, uint64_t proofs_len,
+                                   uint64_t* offsets, uint8_t* digests, void* stream) {
+  if (!groups || n == 0 || !o || !proofs || !offsets)
+    return fail(VL_ERR_INVALID_ARG, "null argument");
+  if (o->plan) return fail(VL_ERR_INVALID_ARG, "plan must be NULL");
+  if (o->mode < VL_MODE_PER_INSTANCE || o->mode > VL_MODE_PERSISTENT)
+    return fail(VL_ERR_INVALID_ARG, "unknown mode %d", o->mode);
+  if (o->async && !o->status) return fail(VL_ERR_INVALID_ARG, "async mode needs a status array");
+  for (uint64_t i = 0; i < n; ++i) {
+    const vl_status st = check_group(groups[i], true);
+    if (st != VL_OK) return st;
+  }
+  uint64_t tot = 0;
+  for (uint64_t i = 0; i < n; ++i) {
+    offsets[i] = tot;
+    tot += 32 * proof_elems(groups[i]);
+  }
+  offsets[n] = tot;
+  if (proofs_len < tot)
+    return fail(VL_ERR_BUFFER_TOO_SMALL, "proof buffer holds %llu bytes, %llu needed",
+                (unsigned long long)proofs_len, (unsigned long long)tot);
+  const uint64_t need = vl_workspace_size(groups, n, o);
+  if (!o->workspace || o->workspace_bytes < need)
+    return fail(VL_ERR_WORKSPACE, "workspace of %llu bytes, %llu needed",
+                (unsigned long long)o->workspace_bytes, (unsigned long long)need);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  uint8_t* ws = reinterpret_cast<uint8_t*>(o->workspace);
+  const Tuning T = tuning_for(o);
+  const bool async = o->async != 0;
+  Plan P;
+
+  // blocking mode: copy proofs, digests and status back, wait, report
+  auto fetch = [&](uint64_t g0, uint64_t g1) -> vl_status {
+    std::vector<int32_t> status(g1 - g0, -1);
+    for (uint64_t i = g0; i < g1; ++i) {
+      const uint8_t* pd = ws + P.proof_off[i - g0];
+      const uint64_t pb = 32 * proof_elems(groups[i]);
+      const uint8_t* sd = pd + align_up(pb, 256);
+      hipError_t e = hipMemcpyAsync(proofs + offsets[i], pd, pb, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(&status[i - g0], sd, 4, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess && digests)
+        e = hipMemcpyAsync(digests + 32 * i, sd + 256, 32, hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) return fail(VL_ERR_HIP, "copy back: %s", hipGetErrorString(e));
+    }
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(VL_ERR_HIP, "prove: %s", hipGetErrorString(e));
+    for (uint64_t i = g0; i < g1; ++i) {
+      const int32_t st = status[i - g0];
+      if (st == VL_ERR_FALSE_STATEMENT)
+        return fail(VL_ERR_FALSE_STATEMENT, "group %u: the products do not sum to C", groups[i].group_id);
+      if (st == VL_ERR_RANGE)
+        return fail(VL_ERR_RANGE, "group %u: an entry exceeds the contraction digit range",
+                    groups[i].group_id);
+      if (st != VL_OK) return fail(VL_ERR_HIP, "group %u: prover status %d", groups[i].group_id, st);
+    }
+    return VL_OK;
+  };
+  auto run = [&](uint64_t g0, uint64_t g1) -> vl_status {
+    plan_groups(P, T, groups, g0, g1, seed, ws, async, proofs, offsets, o->status, digests);
+    const BlobLayout L = blob_layout(P);
+    fill_blob(P, L, ws);
+    const hipError_t e = enqueue_plan(P, L, ws, s);
+    if (e != hipSuccess) return fail(VL_ERR_HIP, "launch: %s", hipGetErrorString(e));
+    return async ? VL_OK : fetch(g0, g1);
+  };
+  if (T.per_instance) {
+    for (uint64_t i = 0; i < n; ++i) {
+      const vl_status st = run(i, i + 1);
+      if (st != VL_OK) return st;
+    }
+    return VL_OK;
+  }
+  return run(0, n);
+}
+
+vl_status vl_fr_lift(const void* src, int32_t dtype, uint64_t n, vl_fr_vec dst, void* stream) {
+  if (!src || !dst.base) return fail(VL_ERR_INVALID_ARG, "null pointer");
+  if (!esize(dtype)) return fail(VL_ERR_DTYPE, "dtype must be VL_I16/I32/I64");
+  if (dst.n < n || dst.ld < dst.n) return fail(VL_ERR_SHAPE, "destination too small");
+  const hipError_t e = launch_lift(src, dtype, n, dst.base, dst.ld, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(VL_ERR_HIP, "lift: %s", hipGetErrorString(e));
+  return VL_OK;
+}
+
+vl_status vl_fr_export(vl_fr_vec src, uint64_t n, uint32_t* dst, void* stream) {
+  if (!src.base || !dst) return fail(VL_ERR_INVALID_ARG, "null pointer");
+  if (src.n < n || src.ld < src.n) return fail(VL_ERR_SHAPE, "source too small");
+  const hipError_t e = launch_export(src.base, src.ld, n, dst, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(VL_ERR_HIP, "export: %s", hipGetErrorString(e));
+  return VL_OK;
+}
+
+vl_status vl_eq_table(const vl_fr* point, uint32_t nvars, vl_fr_vec out, void* stream) {
+  if ((!point && nvars) || !out.base) return fail(VL_ERR_INVALID_ARG, "null pointer");
+  if (nvars > 20) return fail(VL_ERR_SHAPE, "nvars must be <= 20");
+  if (out.n < (1ull << nvars) || out.ld < out.n) return fail(VL_ERR_SHAPE, "out.n < 2^nvars");
+  EqPointArgs a{};
+  a.nvars = nvars;
+  a.out = out.base;
+  a.ld = out.ld;
+  for (uint32_t i = 0; i < nvars; ++i) {
+    Fr x;
+    memcpy(x.w, point[i].w, 32);
+    if (!fr_lt_p(x)) return fail(VL_ERR_INVALID_ARG, "point[%u] is not canonical", i);
+    const Fr xm = fr_to_mont(x), om = fr_sub(fr_R(), xm);
+    memcpy(a.pt[i][0], xm.w, 32);
+    memcpy(a.pt[i][1], om.w, 32);
+  }
+  const hipError_t e = launch_eq_point(a, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(VL_ERR_HIP, "eq_table: %s", hipGetErrorString(e));
+  return VL_OK;
+}
+
+// layout of the partial-eval workspace: [pack][job blob][split partials]
+static uint64_t pe_pack_bytes(uint64_t len) { return align_up(((len + 1) / 2) * 128, 256); }
+static constexpr uint64_t kPeBlob = 1024;
+
+uint64_t vl_partial_eval_workspace_size(uint32_t rows, uint32_t cols, int32_t contract, int32_t dtype) {
+  if (rows == 0 || cols == 0 || !esize(dtype) ||
+      (contract != VL_CONTRACT_ROWS && contract != VL_CONTRACT_COLS))
+    return 0;
+  const bool rws = contract == VL_CONTRACT_ROWS;
+  const uint64_t len = rws ? rows : cols, n_out = rws ? cols : rows;
+  Plan P;
+  Tuning T;
+  T.min_tasks = 1024;
+  Builder B(P, T, 0, pe_pack_bytes(len) + kPeBlob);
+  // alignment of M is unknown here; the plan's size does not depend on it
+  B.contract(nullptr, dtype, digits_for(dtype), cols, rws, (uint32_t)n_out, (uint32_t)len, nullptr,
+             nullptr, 1, n_out, nullptr);
+  return align_up(B.off, 256);
+}
+
+vl_status vl_mle_partial_eval(const void* M, int32_t dtype, uint32_t rows, uint32_t cols, uint64_t ld,
+                              int32_t contract, vl_fr_vec eq, vl_fr_vec out, void* workspace,
+                              uint64_t workspace_bytes, void* stream) {
+  if (!M || !eq.base || !out.base || !workspace) return fail(VL_ERR_INVALID_ARG, "null pointer");
+  if (!esize(dtype)) return fail(VL_ERR_DTYPE, "dtype must be VL_I16/I32/I64");
+  if (contract != VL_CONTRACT_ROWS && contract != VL_CONTRACT_COLS)
+    return fail(VL_ERR_INVALID_ARG, "contract must be VL_CONTRACT_ROWS or VL_CONTRACT_COLS");
+  if (rows == 0 || cols == 0 || rows > VL_MAX_DIM || cols > VL_MAX_DIM || ld < cols)
+    return fail(VL_ERR_SHAPE, "bad matrix shape");
+  const bool rws = contract == VL_CONTRACT_ROWS;
+  const uint32_t len = rws ? rows : cols, n_out = rws ? cols : rows;
+  if (eq.n < len || eq.ld < eq.n) return fail(VL_ERR_SHAPE, "eq vector shorter than the contraction");
+  if (out.n < n_out || out.ld < out.n) return fail(VL_ERR_SHAPE, "out vector too short");
+  if (workspace_bytes < vl_partial_eval_workspace_size(rows, cols, contract, dtype))
+    return fail(VL_ERR_WORKSPACE, "workspace too small");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  uint8_t* ws = reinterpret_cast<uint8_t*>(workspace);
+  uint32_t* pack = reinterpret_cast<uint32_t*>(ws);
+  uint8_t* dblob = ws + pe_pack_bytes(len);
+  Plan P;
+  Tuning T;
+  T.min_tasks = 1024;
+  Builder B(P, T, reinterpret_cast<uint64_t>(ws), pe_pack_bytes(len) + kPeBlob);
+  B.contract(M, dtype, digits_for(dtype), ld, rws, n_out, len, pack, out.base, out.ld, out.n,
+             reinterpret_cast<int32_t*>(dblob));
+  int kind = -1;
+  for (int k = 0; k < CK_COUNT; ++k)
+    if (!P.cj[k].empty()) kind = k;
+  std::vector<uint8_t> blob(kPeBlob, 0);   // [err flag][contract job][finish job]
+  const uint64_t jo = 64, fo = 64 + align_up(sizeof(ContractJob), 64);
+  memcpy(blob.data() + jo, &P.cj[kind][0], sizeof(ContractJob));
+  if (!P.fin.empty()) memcpy(blob.data() + fo, &P.fin[0], sizeof(FinishJob));
+  hipError_t e = launch_upload(dblob, blob.data(), blob.size(), s);
+  if (e == hipSuccess) e = launch_pack(eq.base, eq.ld, len, pack, s);
+  if (e == hipSuccess)
+    e = launch_contract(kind, reinterpret_cast<const ContractJob*>(dblob + jo), 1, P.cj_tasks[kind], s);
+  if (e == hipSuccess && !P.fin.empty())
+    e = launch_finish(reinterpret_cast<const FinishJob*>(dblob + fo), 1, P.fin_threads, s);
+  if (e != hipSuccess) return fail(VL_ERR_HIP, "partial_eval: %s", hipGetErrorString(e));
+  return VL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,224 @@
+// Arithmetic in Fr, the BLS12-381 scalar field (host and device).
+//
+// The paper only asks for a field of about 2^254 elements "such as" the
+// BLS12-381 one (Sec. V); this library fixes that field.
+//   p = 0x73eda753299d7d483339d80809a1d80553bda402fffe5bfeffffffff00000001
+// Elements are 8 little-endian 32-bit limbs.  Inside the library they are kept
+// in Montgomery form x*R mod p with R = 2^256; on the wire (proof bytes, host
+// API) they are canonical.  Multiplication is CIOS Montgomery multiplication
+// (Koc, Acar, Kaliski, IEEE Micro 1996).  Because the top limb of p is below
+// 2^31 - 1, the running value of each CIOS step fits in 8 limbs plus one carry
+// word, so no ninth limb is kept.  -p^-1 mod 2^32 = 0xFFFFFFFF, so the
+// Montgomery quotient digit of a step is simply -t0.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIPCC__) || defined(__HIP__)
+#include <hip/hip_runtime.h>
+#define VL_HD __host__ __device__ __forceinline__
+#else
+#define VL_HD inline
+#endif
+
+namespace vl {
+
+struct Fr {
+  uint32_t w[8];
+};
+
+// p, R mod p, R^2 mod p, and 2^80 * p as a 12-limb integer (the offset that
+// makes a signed contraction result nonnegative before Montgomery reduction).
+#define VL_P_LIMBS 0x00000001u, 0xffffffffu, 0xfffe5bfeu, 0x53bda402u, \
+                   0x09a1d805u, 0x3339d808u, 0x299d7d48u, 0x73eda753u
+#define VL_R_LIMBS 0xfffffffeu, 0x00000001u, 0x00034802u, 0x5884b7fau, \
+                   0xecbc4ff5u, 0x998c4fefu, 0xacc5056fu, 0x1824b159u
+#define VL_R2_LIMBS 0xf3f29c6du, 0xc999e990u, 0x87925c23u, 0x2b6cedcbu, \
+                    0x7254398fu, 0x05d31496u, 0x9f59ff11u, 0x0748d9d9u
+#define VL_KP_LIMBS 0x00000000u, 0x00000000u, 0x00010000u, 0xffff0000u, \
+                    0x5bfeffffu, 0xa402fffeu, 0xd80553bdu, 0xd80809a1u, \
+                    0x7d483339u, 0xa753299du, 0x000073edu, 0x00000000u
+
+VL_HD uint32_t p_limb(int i) {
+  // switch keeps the constant in the instruction stream on the device
+  switch (i) {
+    case 0: return 0x00000001u; case 1: return 0xffffffffu;
+    case 2: return 0xfffe5bfeu; case 3: return 0x53bda402u;
+    case 4: return 0x09a1d805u; case 5: return 0x3339d808u;
+    case 6: return 0x299d7d48u; default: return 0x73eda753u;
+  }
+}
+
+VL_HD Fr fr_zero() { Fr r; for (int i = 0; i < 8; ++i) r.w[i] = 0; return r; }
+VL_HD Fr fr_from_limbs(uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, uint32_t a4,
+                       uint32_t a5, uint32_t a6, uint32_t a7) {
+  Fr r; r.w[0] = a0; r.w[1] = a1; r.w[2] = a2; r.w[3] = a3;
+  r.w[4] = a4; r.w[5] = a5; r.w[6] = a6; r.w[7] = a7; return r;
+}
+VL_HD Fr fr_R() { return fr_from_limbs(VL_R_LIMBS); }     // Montgomery form of 1
+VL_HD Fr fr_R2() { return fr_from_limbs(VL_R2_LIMBS); }
+VL_HD Fr fr_one_raw() { return fr_from_limbs(1, 0, 0, 0, 0, 0, 0, 0); }
+
+VL_HD bool fr_eq(const Fr& a, const Fr& b) {
+  uint32_t d = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) d |= a.w[i] ^ b.w[i];
+  return d == 0;
+}
+
+VL_HD bool fr_is_zero(const Fr& a) {
+  uint32_t d = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) d |= a.w[i];
+  return d == 0;
+}
+
+// a < p ?
+VL_HD bool fr_lt_p(const Fr& a) {
+  uint32_t borrow = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    uint64_t d = (uint64_t)a.w[i] - p_limb(i) - borrow;
+    borrow = (uint32_t)(d >> 63);
+  }
+  return borrow != 0;
+}
+
+// r = a - p if a >= p else a   (a < 2p)
+VL_HD Fr fr_reduce_once(const Fr& a) {
+  Fr t;
+  uint32_t borrow = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    uint64_t d = (uint64_t)a.w[i] - p_limb(i) - borrow;
+    t.w[i] = (uint32_t)d;
+    borrow = (uint32_t)(d >> 63);
+  }
+  Fr r;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r.w[i] = borrow ? a.w[i] : t.w[i];
+  return r;
+}
+
+VL_HD Fr fr_add(const Fr& a, const Fr& b) {
+  Fr s;
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    uint64_t t = (uint64_t)a.w[i] + b.w[i] + c;
+    s.w[i] = (uint32_t)t;
+    c = (uint32_t)(t >> 32);
+  }
+  return fr_reduce_once(s);   // a + b < 2p < 2^256: no carry out
+}
+
+VL_HD Fr fr_sub(const Fr& a, const Fr& b) {
+  Fr d;
+  uint32_t borrow = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    uint64_t t = (uint64_t)a.w[i] - b.w[i] - borrow;
+    d.w[i] = (uint32_t)t;
+    borrow = (uint32_t)(t >> 63);
+  }
+  // if it went negative add p back
+  uint32_t mask = 0u - borrow;
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    uint64_t t = (uint64_t)d.w[i] + (p_limb(i) & mask) + c;
+    d.w[i] = (uint32_t)t;
+    c = (uint32_t)(t >> 32);
+  }
+  return d;
+}
+
+VL_HD Fr fr_neg(const Fr& a) { return fr_sub(fr_zero(), a); }
+VL_HD Fr fr_double(const Fr& a) { return fr_add(a, a); }
+
+// Montgomery product a*b*R^-1 mod p (inputs < p, output < p).
+VL_HD Fr fr_mul(const Fr& a, const Fr& b) {
+  uint32_t t[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) t[j] = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const uint32_t bi = b.w[i];
+    // t += a * b_i, keeping the carry word A
+    uint64_t s = (uint64_t)a.w[0] * bi + t[0];
+    uint32_t A = (uint32_t)(s >> 32);
+    t[0] = (uint32_t)s;
+    const uint32_t m = 0u - t[0];          // m = t0 * (-p^-1) mod 2^32
+    // t0 + m * p0 = t0 + m: low word is 0, carry is (t0 != 0)
+    uint32_t C = t[0] != 0u ? 1u : 0u;
+#pragma unroll
+    for (int j = 1; j < 8; ++j) {
+      uint64_t s1 = (uint64_t)a.w[j] * bi + t[j] + A;
+      A = (uint32_t)(s1 >> 32);
+      uint64_t s2 = (uint64_t)m * p_limb(j) + (uint32_t)s1 + C;
+      C = (uint32_t)(s2 >> 32);
+      t[j - 1] = (uint32_t)s2;
+    }
+    t[7] = A + C;
+  }
+  Fr r;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) r.w[j] = t[j];
+  return fr_reduce_once(r);
+}
+
+VL_HD Fr fr_to_mont(const Fr& a) { return fr_mul(a, fr_R2()); }
+VL_HD Fr fr_from_mont(const Fr& a) { return fr_mul(a, fr_one_raw()); }
+
+// Montgomery reduction of a nonnegative 12-limb integer X < p * 2^256:
+// returns X * R^-1 mod p (fully reduced).
+VL_HD Fr fr_redc12(const uint32_t x_in[12]) {
+  uint32_t x[16];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) x[i] = x_in[i];
+#pragma unroll
+  for (int i = 12; i < 16; ++i) x[i] = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const uint32_t m = 0u - x[i];
+    uint32_t c = x[i] != 0u ? 1u : 0u;   // x_i + m * p0 = 0 mod 2^32
+#pragma unroll
+    for (int j = 1; j < 8; ++j) {
+      uint64_t s = (uint64_t)m * p_limb(j) + x[i + j] + c;
+      x[i + j] = (uint32_t)s;
+      c = (uint32_t)(s >> 32);
+    }
+#pragma unroll
+    for (int k = i + 8; k < 16; ++k) {
+      uint64_t s = (uint64_t)x[k] + c;
+      x[k] = (uint32_t)s;
+      c = (uint32_t)(s >> 32);
+    }
+  }
+  Fr r;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) r.w[j] = x[8 + j];
+  // (X + M p) / R < X / R + p < 2^81 + p < 2p for X < 2^337: one subtraction
+  return fr_reduce_once(r);
+}
+
+// canonical little-endian 32-byte encoding
+VL_HD void fr_to_bytes(const Fr& a, uint8_t* out) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    out[4 * i + 0] = (uint8_t)(a.w[i]);
+    out[4 * i + 1] = (uint8_t)(a.w[i] >> 8);
+    out[4 * i + 2] = (uint8_t)(a.w[i] >> 16);
+    out[4 * i + 3] = (uint8_t)(a.w[i] >> 24);
+  }
+}
+
+VL_HD Fr fr_from_bytes(const uint8_t* in) {
+  Fr a;
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    a.w[i] = (uint32_t)in[4 * i] | ((uint32_t)in[4 * i + 1] << 8) |
+             ((uint32_t)in[4 * i + 2] << 16) | ((uint32_t)in[4 * i + 3] << 24);
+  return a;
+}
+
+}  // namespace vl

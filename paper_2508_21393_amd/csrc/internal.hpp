@@ -1,0 +1,126 @@
+// Internal job descriptors shared by the kernels and the host orchestration.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/verilora.h"
+#include "fr.hpp"
+
+namespace vl {
+
+constexpr int kWave = 64;
+constexpr int kContractBlock = 256;            // 4 waves, one task per wave
+constexpr uint32_t kFlushPairs = 128;          // int32 accumulator bound (see contract kernel)
+constexpr uint32_t kChunkAlign = 32;           // contraction chunks start at multiples of 32
+constexpr int kRoundsBlock = 512;
+
+// An eq table to build: out[i] = prod_j (x_j or 1 - x_j), i < 2^nvars, plus
+// its "pack" form used by the integer contractions (see contract kernel).
+struct EqJob {
+  uint32_t nvars;
+  uint32_t pack_pairs;        // pairs to emit into pack (ceil(len / 2))
+  uint32_t thread_begin;      // prefix sum of threads over jobs in a launch
+  uint32_t pad_;
+  const uint32_t* point;      // device: 2 * nvars Montgomery elements, AoS (x_j, 1 - x_j)
+  uint32_t* eq;               // SoL Montgomery output, may be null
+  uint64_t eq_ld;
+  uint32_t* pack;             // pack_pairs * 32 words, may be null
+};
+
+// eq table of a point passed by value (at most 20 variables)
+struct EqPointArgs {
+  uint32_t nvars;
+  uint32_t pad_;
+  uint32_t* out;
+  uint64_t ld;
+  uint32_t pt[20][2][8];      // Montgomery (x_j, 1 - x_j)
+};
+
+// A slice of a host image copied to device memory by a kernel launch.
+constexpr uint32_t kUploadBytes = 3072;   // multiple of 4 (blob sizes are multiples of 256)
+struct UploadArgs {
+  void* dst;
+  uint32_t bytes;
+  uint32_t pad_;
+  uint32_t words[kUploadBytes / 4];
+};
+
+// One integer contraction: for each output n < n_out and each chunk of the
+// contraction index m, sum_m eq[m] * M(m, n), where M(m, n) is the stored
+// matrix at [m * ld + n] (rows kernel) or [n * ld + m] (cols kernel).
+struct ContractJob {
+  const void* M;
+  uint64_t ld;
+  uint32_t n_out;             // outputs (stored columns for rows, stored rows for cols)
+  uint32_t len;               // contraction length
+  uint32_t chunk;             // chunk length, multiple of kChunkAlign
+  uint32_t n_chunks;
+  uint32_t out_waves;         // ceil(n_out / 64)
+  uint32_t task_begin;        // prefix sum of tasks (out_waves * n_chunks) within a launch
+  const uint32_t* pack;       // eq pack table of the contraction index
+  uint32_t* dst;              // n_chunks == 1: final SoL vector; else partial SoL slot 0
+  uint64_t dst_ld;            // plane stride of dst (final vector or one partial)
+  uint64_t chunk_stride;      // words between consecutive chunk partials
+  int32_t* err;               // set to 1 if an entry cannot be represented (int32/int64)
+};
+
+// Sum chunk partials into the final SoL vector and zero its padding.
+struct FinishJob {
+  const uint32_t* part;       // SoL partial 0 (null if the contraction wrote dst directly)
+  uint64_t part_ld;
+  uint64_t chunk_stride;
+  uint32_t n_chunks;
+  uint32_t n_valid;           // outputs written by the contraction
+  uint32_t n_total;           // padded length (power of two)
+  uint32_t thread_begin;
+  uint32_t* out;
+  uint64_t out_ld;
+};
+
+struct RoundsProd {
+  uint32_t* a;
+  uint32_t* b;
+  uint64_t ld;
+  uint32_t n1;
+  uint32_t pad_;
+};
+
+// The sumcheck rounds of one group, run by one workgroup.
+struct RoundsJob {
+  uint8_t st[32];             // transcript state after squeezing u and v
+  uint32_t n_prods;
+  uint32_t n0;
+  const uint32_t* eqU;        // SoL eq(u, .), length 2^n0
+  uint64_t eqU_ld;
+  const uint32_t* t;          // SoL t[i] = sum_j C[i][j] eq(v, j), length 2^n0
+  uint64_t t_ld;
+  uint8_t* proof;             // device proof bytes of this group
+  int32_t* status;            // device status word of this group
+  uint8_t* digest;            // device 32 bytes or null
+  const int32_t* err;         // range flag of this group's contractions
+  RoundsProd prods[VL_MAX_PRODS];
+};
+
+// host launchers (kernels.hip)
+hipError_t launch_eq(const EqJob* jobs_dev, uint32_t n_jobs, uint32_t n_threads, hipStream_t s);
+hipError_t launch_contract(int kind, const ContractJob* jobs_dev, uint32_t n_jobs, uint32_t n_tasks,
+                           hipStream_t s);
+hipError_t launch_finish(const FinishJob* jobs_dev, uint32_t n_jobs, uint32_t n_threads, hipStream_t s);
+hipError_t launch_rounds(const RoundsJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
+hipError_t launch_lift(const void* src, int dtype, uint64_t n, uint32_t* dst, uint64_t ld, hipStream_t s);
+hipError_t launch_export(const uint32_t* src, uint64_t ld, uint64_t n, uint32_t* dst, hipStream_t s);
+hipError_t launch_eq_point(const EqPointArgs& a, hipStream_t s);
+hipError_t launch_pack(const uint32_t* eq, uint64_t ld, uint64_t len, uint32_t* pack, hipStream_t s);
+hipError_t launch_upload(void* dst, const void* src, uint64_t bytes, hipStream_t s);
+hipError_t launch_zero_words(uint32_t* p, uint64_t n_words, hipStream_t s);
+
+// contraction kernel variants (index = kind)
+enum ContractKind {
+  CK_I16_ROWS = 0, CK_I16_COLS = 1, CK_I16_COLS_VEC = 2,
+  CK_I32_ROWS = 3, CK_I32_COLS = 4, CK_I32_COLS_VEC = 5,
+  CK_I64N3_ROWS = 6, CK_I64N3_COLS = 7, CK_I64N3_COLS_VEC = 8,
+  CK_I64N4_ROWS = 9, CK_I64N4_COLS = 10, CK_I64N4_COLS_VEC = 11,
+  CK_COUNT = 12
+};
+
+}  // namespace vl

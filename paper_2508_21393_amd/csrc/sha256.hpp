@@ -1,0 +1,191 @@
+// SHA-256 (FIPS 180-4) and the Fiat-Shamir transcript, host and device.
+//
+// The paper turns its interactive protocols non-interactive by hashing every
+// earlier public message into each verifier challenge (Fiat-Shamir; Sec. IV-A
+// footnote, Sec. V).  It names no hash or byte layout; this library fixes:
+//   init:    st = H("VeriLoRA-zkMat-v1" || u64 seed || u32 group_id
+//                   || u32 n_products || (u32 D0, D1, D2) per product)
+//   absorb:  st = H(st || label || data)
+//   squeeze: for ctr = 0, 1, ...: h = H(st || label || u32 ctr);
+//            x = LE(h) mod 2^255; if x < p { st = h; return x }
+// with little-endian integers and canonical 32-byte field elements.
+#pragma once
+#include <stdint.h>
+
+#include "fr.hpp"
+
+namespace vl {
+
+VL_HD uint32_t rotr32(uint32_t x, int n) { return (x >> n) | (x << (32 - n)); }
+
+VL_HD void sha256_compress(uint32_t h[8], const uint8_t blk[64]) {
+  const uint32_t K[64] = {
+      0x428a2f98u, 0x71374491u, 0xb5c0fbcfu, 0xe9b5dba5u, 0x3956c25bu, 0x59f111f1u, 0x923f82a4u,
+      0xab1c5ed5u, 0xd807aa98u, 0x12835b01u, 0x243185beu, 0x550c7dc3u, 0x72be5d74u, 0x80deb1feu,
+      0x9bdc06a7u, 0xc19bf174u, 0xe49b69c1u, 0xefbe4786u, 0x0fc19dc6u, 0x240ca1ccu, 0x2de92c6fu,
+      0x4a7484aau, 0x5cb0a9dcu, 0x76f988dau, 0x983e5152u, 0xa831c66du, 0xb00327c8u, 0xbf597fc7u,
+      0xc6e00bf3u, 0xd5a79147u, 0x06ca6351u, 0x14292967u, 0x27b70a85u, 0x2e1b2138u, 0x4d2c6dfcu,
+      0x53380d13u, 0x650a7354u, 0x766a0abbu, 0x81c2c92eu, 0x92722c85u, 0xa2bfe8a1u, 0xa81a664bu,
+      0xc24b8b70u, 0xc76c51a3u, 0xd192e819u, 0xd6990624u, 0xf40e3585u, 0x106aa070u, 0x19a4c116u,
+      0x1e376c08u, 0x2748774cu, 0x34b0bcb5u, 0x391c0cb3u, 0x4ed8aa4au, 0x5b9cca4fu, 0x682e6ff3u,
+      0x748f82eeu, 0x78a5636fu, 0x84c87814u, 0x8cc70208u, 0x90befffau, 0xa4506cebu, 0xbef9a3f7u,
+      0xc67178f2u};
+  uint32_t w[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i)
+    w[i] = ((uint32_t)blk[4 * i] << 24) | ((uint32_t)blk[4 * i + 1] << 16) |
+           ((uint32_t)blk[4 * i + 2] << 8) | (uint32_t)blk[4 * i + 3];
+  uint32_t a = h[0], b = h[1], c = h[2], d = h[3], e = h[4], f = h[5], g = h[6], hh = h[7];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    uint32_t wi;
+    if (i < 16) {
+      wi = w[i];
+    } else {
+      const uint32_t w15 = w[(i - 15) & 15], w2 = w[(i - 2) & 15];
+      const uint32_t s0 = rotr32(w15, 7) ^ rotr32(w15, 18) ^ (w15 >> 3);
+      const uint32_t s1 = rotr32(w2, 17) ^ rotr32(w2, 19) ^ (w2 >> 10);
+      wi = w[i & 15] + s0 + w[(i - 7) & 15] + s1;
+      w[i & 15] = wi;
+    }
+    const uint32_t S1 = rotr32(e, 6) ^ rotr32(e, 11) ^ rotr32(e, 25);
+    const uint32_t ch = (e & f) ^ (~e & g);
+    const uint32_t t1 = hh + S1 + ch + K[i] + wi;
+    const uint32_t S0 = rotr32(a, 2) ^ rotr32(a, 13) ^ rotr32(a, 22);
+    const uint32_t mj = (a & b) ^ (a & c) ^ (b & c);
+    const uint32_t t2 = S0 + mj;
+    hh = g; g = f; f = e; e = d + t1; d = c; c = b; b = a; a = t1 + t2;
+  }
+  h[0] += a; h[1] += b; h[2] += c; h[3] += d; h[4] += e; h[5] += f; h[6] += g; h[7] += hh;
+}
+
+// Streaming hasher for short messages.
+struct Sha256 {
+  uint32_t h[8];
+  uint8_t buf[64];
+  uint32_t fill;
+  uint64_t total;
+};
+
+VL_HD void sha256_init(Sha256& s) {
+  s.h[0] = 0x6a09e667u; s.h[1] = 0xbb67ae85u; s.h[2] = 0x3c6ef372u; s.h[3] = 0xa54ff53au;
+  s.h[4] = 0x510e527fu; s.h[5] = 0x9b05688cu; s.h[6] = 0x1f83d9abu; s.h[7] = 0x5be0cd19u;
+  s.fill = 0;
+  s.total = 0;
+}
+
+VL_HD void sha256_update(Sha256& s, const uint8_t* p, uint32_t n) {
+  for (uint32_t i = 0; i < n; ++i) {
+    s.buf[s.fill++] = p[i];
+    if (s.fill == 64) {
+      sha256_compress(s.h, s.buf);
+      s.fill = 0;
+    }
+  }
+  s.total += n;
+}
+
+VL_HD void sha256_final(Sha256& s, uint8_t out[32]) {
+  const uint64_t bits = s.total * 8;
+  uint8_t one = 0x80;
+  sha256_update(s, &one, 1);
+  uint8_t z = 0;
+  while (s.fill != 56) sha256_update(s, &z, 1);
+  uint8_t len[8];
+  for (int i = 0; i < 8; ++i) len[i] = (uint8_t)(bits >> (56 - 8 * i));
+  sha256_update(s, len, 8);
+  for (int i = 0; i < 8; ++i) {
+    out[4 * i] = (uint8_t)(s.h[i] >> 24);
+    out[4 * i + 1] = (uint8_t)(s.h[i] >> 16);
+    out[4 * i + 2] = (uint8_t)(s.h[i] >> 8);
+    out[4 * i + 3] = (uint8_t)(s.h[i]);
+  }
+}
+
+VL_HD void put_u32le(uint8_t* o, uint32_t v) {
+  o[0] = (uint8_t)v; o[1] = (uint8_t)(v >> 8); o[2] = (uint8_t)(v >> 16); o[3] = (uint8_t)(v >> 24);
+}
+
+struct Transcript {
+  uint8_t st[32];
+};
+
+// labels used by the protocol
+#define VL_LBL_U "u"
+#define VL_LBL_V "v"
+#define VL_LBL_CLAIM "claim"
+#define VL_LBL_PART "part"
+#define VL_LBL_ROUND "round"
+#define VL_LBL_R "r"
+#define VL_LBL_FINAL "final"
+
+VL_HD uint32_t lbl_len(const char* l) {
+  uint32_t n = 0;
+  while (l[n]) ++n;
+  return n;
+}
+
+VL_HD void tr_init(Transcript& t, uint64_t seed, uint32_t group_id, uint32_t n_prods,
+                   const uint32_t* dims /* 3 per product */) {
+  Sha256 s;
+  sha256_init(s);
+  const char dom[] = "VeriLoRA-zkMat-v1";
+  sha256_update(s, (const uint8_t*)dom, 17);
+  uint8_t b[8];
+  for (int i = 0; i < 8; ++i) b[i] = (uint8_t)(seed >> (8 * i));
+  sha256_update(s, b, 8);
+  put_u32le(b, group_id);
+  sha256_update(s, b, 4);
+  put_u32le(b, n_prods);
+  sha256_update(s, b, 4);
+  for (uint32_t k = 0; k < 3 * n_prods; ++k) {
+    put_u32le(b, dims[k]);
+    sha256_update(s, b, 4);
+  }
+  sha256_final(s, t.st);
+}
+
+VL_HD void tr_absorb(Transcript& t, const char* label, const uint8_t* data, uint32_t n) {
+  Sha256 s;
+  sha256_init(s);
+  sha256_update(s, t.st, 32);
+  sha256_update(s, (const uint8_t*)label, lbl_len(label));
+  sha256_update(s, data, n);
+  sha256_final(s, t.st);
+}
+
+VL_HD void tr_absorb_fr(Transcript& t, const char* label, const Fr* xs, uint32_t k) {
+  Sha256 s;
+  sha256_init(s);
+  sha256_update(s, t.st, 32);
+  sha256_update(s, (const uint8_t*)label, lbl_len(label));
+  for (uint32_t i = 0; i < k; ++i) {
+    uint8_t e[32];
+    fr_to_bytes(xs[i], e);
+    sha256_update(s, e, 32);
+  }
+  sha256_final(s, t.st);
+}
+
+// returns a canonical (not Montgomery) field element
+VL_HD Fr tr_squeeze(Transcript& t, const char* label) {
+  for (uint32_t ctr = 0;; ++ctr) {
+    Sha256 s;
+    sha256_init(s);
+    sha256_update(s, t.st, 32);
+    sha256_update(s, (const uint8_t*)label, lbl_len(label));
+    uint8_t c[4];
+    put_u32le(c, ctr);
+    sha256_update(s, c, 4);
+    uint8_t h[32];
+    sha256_final(s, h);
+    Fr x = fr_from_bytes(h);
+    x.w[7] &= 0x7fffffffu;
+    if (fr_lt_p(x)) {
+      for (int i = 0; i < 32; ++i) t.st[i] = h[i];
+      return x;
+    }
+  }
+}
+
+}  // namespace vl

@@ -1,0 +1,110 @@
+"""Host-side checks of the C ABI (no GPU): exports and the CPU verifier.
+
+The library's host verifier (C++ SHA-256 transcript, Montgomery arithmetic,
+interpolation and witness MLE evaluation) must accept every proof the oracle
+writes and reject every single-element tamper, and its reduced claims must
+equal the oracle's challenges and final values.
+"""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.zkmat import prove_group, verify_group, Reject
+import workloads
+from paper_2508_21393_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLD = os.path.join(ROOT, "tests", "golden")
+
+
+def _lib_or_skip():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.skip("libverilora.so not built")
+    return B.lib()
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib_or_skip()
+    header = open(os.path.join(ROOT, "include", "verilora.h")).read()
+    declared = set(re.findall(r"\b(vl_[a-z_0-9]+)\s*\(", header))
+    assert declared == set(B.EXPORTED)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def host_group(g: workloads.Group) -> B.GroupArgs:
+    prods = [(p.A, p.B, p.transA, p.transB) for p in g.products]
+    return B.GroupArgs(g.group_id, prods, g.C)
+
+
+def _tiny_groups():
+    spec = json.load(open(os.path.join(GOLD, "tiny.json")))
+    out = []
+    for k, (seed, dims, dt, trans, vb) in enumerate(spec["tiny_spec"]):
+        g = workloads.tiny_random_group(seed, [tuple(d) for d in dims], dtype=getattr(np, dt),
+                                        trans=tuple(trans), value_bits=vb, name=f"tiny{k}")
+        g.group_id = k
+        out.append((g, bytes.fromhex(spec["groups"][k]["proof_hex"]), spec["seed"]))
+    return out
+
+
+def test_host_verifier_accepts_golden_proofs_with_witness():
+    _lib_or_skip()
+    cases = _tiny_groups()
+    w = workloads.config1()
+    cfg1 = json.load(open(os.path.join(GOLD, "cfg1.json")))
+    cases.append((w.groups[0], bytes.fromhex(cfg1["groups"][0]["proof_hex"]), w.seed))
+    for g, proof, seed in cases:
+        ga = host_group(g)
+        assert B.proof_size(ga) == len(proof)
+        ok, fr, red = B.verify_transcript(proof, ga, seed)
+        assert ok, (g.name, B.last_error())
+        assert fr == -1
+        # reduced claims: c, u, v, then per product r..., a_final, b_final
+        res = verify_group(proof, g.shapes, seed, g.group_id)
+        expect = [res["c"]] + res["u"] + res["v"]
+        for rvec, (af, bf) in zip(res["r"], res["finals"]):
+            expect += rvec + [af, bf]
+        assert red == expect
+
+
+def test_host_verifier_rejects_tampering_and_wrong_witness():
+    _lib_or_skip()
+    g = workloads.tiny_random_group(31, [(6, 10, 5), (6, 3, 5)], trans=(True, False))
+    prods = [(p.opA(), p.opB()) for p in g.products]
+    proof, _, _ = prove_group(prods, g.C, 77, 0)
+    ga = host_group(g)
+    assert B.verify_transcript(proof, ga, 77)[0]
+    n_el = len(proof) // 32
+    for i in range(n_el):
+        x = int.from_bytes(proof[32 * i:32 * i + 32], "little")
+        bad = proof[:32 * i] + ((x + 1) % oracle.P).to_bytes(32, "little") + proof[32 * i + 32:]
+        ok, fr, _ = B.verify_transcript(bad, ga, 77)
+        assert not ok, i
+        with pytest.raises(Reject):
+            verify_group(bad, g.shapes, 77, 0)
+    assert not B.verify_transcript(proof, ga, 78)[0]
+    assert not B.verify_transcript(proof[:-1], ga, 77)[0]
+    assert not B.verify_transcript(proof[:-32] + oracle.P.to_bytes(32, "little"), ga, 77)[0]
+    # witness mismatch: same shapes, one entry of C changed
+    g2 = workloads.Group(g.name, g.products, g.C.copy(), g.group_id)
+    g2.C[0, 0] += 1
+    assert not B.verify_transcript(proof, host_group(g2), 77)[0]
+
+
+def test_round_failure_reports_round_index():
+    _lib_or_skip()
+    g = workloads.tiny_random_group(5, [(4, 16, 4)])
+    prods = [(p.opA(), p.opB()) for p in g.products]
+    proof, _, _ = prove_group(prods, g.C, 1, 0)
+    ga = B.GroupArgs(0, [(p.A, p.B, p.transA, p.transB) for p in g.products], g.C)
+    # change g(0) of round 3 (element 1 + 3*2): rounds 1, 2 pass, round 3 fails
+    i = 1 + 3 * 2
+    x = int.from_bytes(proof[32 * i:32 * i + 32], "little")
+    bad = proof[:32 * i] + ((x + 5) % oracle.P).to_bytes(32, "little") + proof[32 * i + 32:]
+    ok, fr, _ = B.verify_transcript(bad, ga, 1)
+    assert not ok and fr == 3
