@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark of the matmul-sumcheck prover on one MI355X.
+
+Workload: one 7B-class decoder block (hidden 4096, FFN 11008, 32 heads) at
+T = 2048 tokens with rank-16 LoRA on q, k, v, o, gate, up and down: every
+forward, backward and LoRA-update product, 56 products in 49 groups, int16
+operands and exact int64 outputs (seeded synthetic data, ``workloads``).  A
+step proves all 49 groups in one call with inputs resident in HBM and the
+proof bytes copied back to the host.
+
+Reports (one JSON line): algorithmic Fr MACs/s (value), proofs/s, p50/p99
+step latency, the per-instance prover on the same inputs, the dominant
+kernel against its VALU ceiling (HIP-event stage timing over the timed
+steps), and the CPU oracle on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Fr MACs/s + matmul-sumcheck proofs/s; batched vs per-instance; p50/p99 latency"
+CU, LANES_PER_CLK, CLOCK_HZ = 256, 64, 2.4e9   # MI355X: CUs, VALU lanes per CU per clock, peak clock
+DOT2_PER_I16_MAC = 16                           # 32 eq bytes x one 16-bit digit, 2 per v_dot2
+
+
+def nv(d):
+    return max(0, math.ceil(math.log2(d))) if d > 1 else 0
+
+
+def algorithmic_macs(shapes_by_group):
+    """Fr multiply-accumulates the method needs (partial evaluations, claim,
+    rounds and folds, eq tables), independent of how the kernels do them."""
+    total = 0
+    for shapes in shapes_by_group:
+        d0, _, d2 = shapes[0]
+        total += d0 * d2 + d0 + (2 ** nv(d0) - 1) + (2 ** nv(d2) - 1)
+        for (a, b, c) in shapes:
+            total += a * b + b * c + 5 * (2 ** nv(b) - 1)
+    return total
+
+
+def int16_contraction_macs(groups):
+    """Entries streamed by the int16 contraction kernels, by kernel kind."""
+    from paper_2508_21393_amd import binding as B
+    rows = cols = 0
+    for g in groups:
+        for p in g.products:
+            d0, d1, d2 = p.dims
+            if p.transA:
+                cols += d0 * d1
+            else:
+                rows += d0 * d1
+            if p.transB:
+                rows += d1 * d2
+            else:
+                cols += d1 * d2
+    return {B.STAGE_NAMES.index("i16_rows"): rows, B.STAGE_NAMES.index("i16_cols_vec"): cols,
+            B.STAGE_NAMES.index("i16_cols"): cols}
+
+
+def cpu_baseline(workload, budget_s=15.0):
+    """The oracle, unmodified, single-threaded, on the cheapest groups of the
+    same workload until the time budget is used."""
+    import oracle  # noqa: F401
+    from oracle.zkmat import prove_workload_group
+    order = sorted(workload.groups, key=lambda g: algorithmic_macs([g.shapes]))
+    t0 = time.perf_counter()
+    macs, names = 0, []
+    for g in order:
+        if time.perf_counter() - t0 > budget_s:
+            break
+        prove_workload_group(g, workload.seed)
+        macs += algorithmic_macs([g.shapes])
+        names.append(g.name)
+    dt = time.perf_counter() - t0
+    return {"value": macs / dt, "unit": "Fr-MAC/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(names)} of {len(workload.groups)} groups of the same block "
+                      f"(cheapest first: {', '.join(names)}), {macs / 1e6:.1f} M MACs in {dt:.1f} s"}
+
+
+def peak_rates():
+    import ctypes
+    from paper_2508_21393_amd.build import PEAK_LIB
+    if not os.path.exists(PEAK_LIB):
+        return None
+    L = ctypes.CDLL(PEAK_LIB)
+    L.vlpeak_lane_ops_per_s.restype = ctypes.c_double
+    L.vlpeak_lane_ops_per_s.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]
+    names = ["dot2_i32_i16", "mad_u64_u32", "mul_lo_u32", "mul_hi_u32", "add_u32"]
+    return {n: L.vlpeak_lane_ops_per_s(i, 8192, 4096) for i, n in enumerate(names)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--T", type=int, default=2048)
+    ap.add_argument("--mode", default="batched", choices=["batched", "per_instance", "persistent"])
+    ap.add_argument("--per-instance-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-peak", action="store_true")
+    args = ap.parse_args()
+    ws = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or ws != 1:
+        print("bench.py measures one GPU: the prover's groups are independent and this build "
+              "runs on a single MI355X (see DESIGN.md for how the groups would shard); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    from paper_2508_21393_amd import binding as B
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    B.lib()
+    mode = {"batched": B.VL_MODE_BATCHED, "per_instance": B.VL_MODE_PER_INSTANCE,
+            "persistent": B.VL_MODE_PERSISTENT}[args.mode]
+    t_gen = time.perf_counter()
+    w = workloads.config4(T=args.T, device="cuda")
+    groups = w.groups
+    dev = lambda x: torch.from_numpy(x).to("cuda")  # noqa: E731
+    gas = [B.GroupArgs(g.group_id, [(dev(p.A), dev(p.B), p.transA, p.transB) for p in g.products],
+                       dev(g.C)) for g in groups]
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    shapes = [g.shapes for g in groups]
+    macs = algorithmic_macs(shapes)
+    n_products = sum(len(s) for s in shapes)
+    workspace = torch.empty(B.workspace_size(gas, mode), dtype=torch.uint8, device="cuda")
+
+    def step(stage=None):
+        return B.sumcheck_matmul_prove(gas, w.seed, mode=mode, workspace=workspace, stage_ms=stage)
+
+    for _ in range(args.warmup):
+        ref, ref_dig = step()
+    torch.cuda.synchronize()
+    lat, stage_sum = [], [0.0] * B.VL_STAGE_COUNT
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        st = []
+        proofs, dig = step(st)
+        lat.append(time.perf_counter() - s0)
+        stage_sum = [a + b for a, b in zip(stage_sum, st)]
+        assert dig == ref_dig, "proofs changed between steps"
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    lat_ms = sorted(1e3 * x for x in lat)
+    p50 = lat_ms[len(lat_ms) // 2]
+    p99 = lat_ms[min(len(lat_ms) - 1, int(math.ceil(0.99 * len(lat_ms))) - 1)]
+    stage_avg = [x / args.steps for x in stage_sum]
+
+    # per-instance prover on the same inputs (the baseline the batched path must beat)
+    per_inst_ms = None
+    if mode != B.VL_MODE_PER_INSTANCE and args.per_instance_steps > 0:
+        ws_pi = torch.empty(B.workspace_size(gas, B.VL_MODE_PER_INSTANCE), dtype=torch.uint8, device="cuda")
+        pi, _ = B.sumcheck_matmul_prove(gas, w.seed, mode=B.VL_MODE_PER_INSTANCE, workspace=ws_pi)
+        assert pi == ref, "per-instance proofs differ from the batched ones"
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.per_instance_steps):
+            B.sumcheck_matmul_prove(gas, w.seed, mode=B.VL_MODE_PER_INSTANCE, workspace=ws_pi)
+        torch.cuda.synchronize()
+        per_inst_ms = 1e3 * (time.perf_counter() - t1) / args.per_instance_steps
+        del ws_pi
+
+    # dominant kernel: the int16 contraction kind with the most device time
+    k16 = int16_contraction_macs(groups)
+    dom = max(k16, key=lambda k: stage_avg[k])
+    dom_ms = stage_avg[dom]
+    achieved = k16[dom] / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0
+    rates = None if args.no_peak else peak_rates()
+    dot2_rate = CU * LANES_PER_CLK * CLOCK_HZ
+    peak = dot2_rate / DOT2_PER_I16_MAC / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T Fr-MAC/s",
+                "frac": achieved / peak if peak else None, "traffic": None,
+                "kernel": f"contract_kernel {B.STAGE_NAMES[dom]} (int16 x eq, v_dot2_i32_i16)",
+                "work_per_launch": k16[dom], "avg_launch_ms": dom_ms}
+
+    out = {
+        "metric": METRIC, "value": macs * args.steps / elapsed, "unit": "Fr-MAC/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "Fr (BLS12-381 scalar field, exact); int16 operands, int64 outputs",
+        "data": "synthetic (seeded int16 fixed-point tensors, no model weights or dataset)",
+        "config": {"workload": f"7B-class block T={args.T}, hidden 4096, FFN 11008, LoRA r16 on "
+                               f"q,k,v,o,gate,up,down: fwd+bwd+update", "groups": len(groups),
+                   "products": n_products, "mode": args.mode, "algorithmic_macs_per_step": macs},
+        "proofs_per_s": n_products * args.steps / elapsed,
+        "latency_ms": {"p50": p50, "p99": p99},
+        "per_instance_ms_per_step": per_inst_ms,
+        "speedup_vs_per_instance": (per_inst_ms / ms_per_step) if per_inst_ms else None,
+        "stage_ms": {B.STAGE_NAMES[i]: stage_avg[i] for i in range(B.VL_STAGE_COUNT) if stage_avg[i] > 0},
+        "roofline": roofline,
+        "valu_lane_ops_per_s": rates,
+        "witness_setup_s": t_gen,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -104,7 +104,21 @@ typedef struct {
   uint64_t workspace_bytes;
   int32_t* status;         /* async only: device int32[n_groups], VL_OK / VL_ERR_*     */
   const void* plan;        /* reserved, must be NULL                                  */
+  float* stage_ms;         /* optional host float[VL_STAGE_COUNT] (blocking mode only):
+                              device time of each stage, from HIP events recorded on
+                              the call's stream around the stage's launches, summed over
+                              the call; see VL_STAGE_*                                */
 } vl_prove_opts;
+
+/* stages of a prove call, in launch order */
+#define VL_STAGE_UPLOAD 0      /* job descriptors to device memory                 */
+#define VL_STAGE_EQ 1          /* eq tables and their byte-sliced "pack" form      */
+#define VL_STAGE_CONTRACT 2    /* + kind: integer contraction kernels, 12 kinds:
+                                  int16 rows/cols/cols-vec, int32 (3 digits),
+                                  int64 three-digit, int64 four-digit (same order) */
+#define VL_STAGE_FINISH 14     /* split-contraction sums and zero padding          */
+#define VL_STAGE_ROUNDS 15     /* claim, prover guard, sumcheck rounds, proof bytes */
+#define VL_STAGE_COUNT 16
 
 /* Lift n signed integers (dtype) at device pointer src into Fr (Montgomery,
  * structure-of-limbs) at dst (dst.n >= n).  Negative x becomes p - |x|. */

@@ -18,6 +18,10 @@ VL_I16, VL_I32, VL_I64 = 1, 2, 3
 VL_CONTRACT_ROWS, VL_CONTRACT_COLS = 0, 1
 VL_MODE_PER_INSTANCE, VL_MODE_BATCHED, VL_MODE_PERSISTENT = 0, 1, 2
 VL_MAX_PRODS = 8
+VL_STAGE_COUNT = 16
+STAGE_NAMES = ["upload", "eq", "i16_rows", "i16_cols", "i16_cols_vec", "i32_rows", "i32_cols",
+               "i32_cols_vec", "i64n3_rows", "i64n3_cols", "i64n3_cols_vec", "i64n4_rows", "i64n4_cols",
+               "i64n4_cols_vec", "finish", "rounds"]
 
 STATUS_NAMES = {0: "VL_OK", 1: "VL_ERR_INVALID_ARG", 2: "VL_ERR_SHAPE", 3: "VL_ERR_DTYPE",
                 4: "VL_ERR_WORKSPACE", 5: "VL_ERR_HIP", 6: "VL_ERR_FALSE_STATEMENT",
@@ -51,7 +55,7 @@ class vl_group(ctypes.Structure):
 
 class vl_prove_opts(ctypes.Structure):
     _fields_ = [("mode", c_i32), ("async_", c_i32), ("workspace", c_vp), ("workspace_bytes", c_u64),
-                ("status", c_vp), ("plan", c_vp)]
+                ("status", c_vp), ("plan", c_vp), ("stage_ms", c_vp)]
 
 
 class VLError(RuntimeError):
@@ -213,20 +217,25 @@ def proof_size(group: GroupArgs) -> int:
 
 def workspace_size(groups: Sequence[GroupArgs], mode: int = VL_MODE_BATCHED, async_: bool = False) -> int:
     arr = group_array(groups)
-    opts = vl_prove_opts(mode, int(async_), None, 0, None, None)
+    opts = vl_prove_opts(mode, int(async_), None, 0, None, None, None)
     return lib().vl_workspace_size(arr, len(groups), ctypes.byref(opts))
 
 
 def sumcheck_matmul_prove(groups: Sequence[GroupArgs], seed: int, mode: int = VL_MODE_BATCHED,
-                          workspace=None, stream=None, with_digests: bool = True):
-    """Blocking prove: returns (list of proof bytes, list of 32-byte digests)."""
+                          workspace=None, stream=None, with_digests: bool = True, stage_ms=None):
+    """Blocking prove: returns (list of proof bytes, list of 32-byte digests).
+
+    ``stage_ms``: optional list that receives VL_STAGE_COUNT per-stage device
+    times (HIP events) of this call."""
     import torch
     arr = group_array(groups)
     n = len(groups)
     ws_bytes = workspace_size(groups, mode)
     if workspace is None:
         workspace = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device="cuda")
-    opts = vl_prove_opts(mode, 0, workspace.data_ptr(), workspace.numel(), None, None)
+    timing = (ctypes.c_float * VL_STAGE_COUNT)() if stage_ms is not None else None
+    opts = vl_prove_opts(mode, 0, workspace.data_ptr(), workspace.numel(), None, None,
+                         ctypes.addressof(timing) if timing is not None else None)
     total = sum(proof_size(g) for g in groups)
     buf = ctypes.create_string_buffer(max(total, 1))
     offs = (c_u64 * (n + 1))()
@@ -234,6 +243,8 @@ def sumcheck_matmul_prove(groups: Sequence[GroupArgs], seed: int, mode: int = VL
     _check(lib().vl_sumcheck_matmul_prove(arr, n, seed, ctypes.byref(opts), ctypes.addressof(buf), total,
                                           offs, ctypes.addressof(dig) if dig is not None else None,
                                           _stream(stream)))
+    if timing is not None:
+        stage_ms[:] = list(timing)
     raw = buf.raw
     proofs = [raw[offs[i]:offs[i + 1]] for i in range(n)]
     digests = [dig.raw[32 * i:32 * i + 32] for i in range(n)] if dig is not None else None
@@ -246,7 +257,7 @@ def sumcheck_matmul_prove_async(groups: Sequence[GroupArgs], seed: int, proofs_d
     buffers.  Returns the host offsets of each group's proof."""
     arr = group_array(groups)
     n = len(groups)
-    opts = vl_prove_opts(mode, 1, workspace.data_ptr(), workspace.numel(), status_dev.data_ptr(), None)
+    opts = vl_prove_opts(mode, 1, workspace.data_ptr(), workspace.numel(), status_dev.data_ptr(), None, None)
     offs = (c_u64 * (n + 1))()
     _check(lib().vl_sumcheck_matmul_prove(arr, n, seed, ctypes.byref(opts), proofs_dev.data_ptr(),
                                           proofs_dev.numel(), offs,

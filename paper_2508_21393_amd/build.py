@@ -13,9 +13,11 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libverilora.so")
+PEAK_LIB = os.path.join(HERE, "libvlpeak.so")
 ARCH = "gfx950"
 
 SOURCES = ["kernels.hip", "capi.cpp", "verify.cpp"]
+PEAK_SOURCES = ["peak.hip"]
 
 # packed FP32 instructions stay off in all device code; hipcc's host pass warns
 # that it does not know the feature, which is harmless
@@ -42,18 +44,26 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs, out):
+    tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = True) -> str:
+    """Compile libverilora.so (the prover) and libvlpeak.so (the VALU rate
+    microbenchmark used by bench.py)."""
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = SOURCES + PEAK_SOURCES
+    with cf.ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+        objs = dict(zip(srcs, ex.map(_compile, srcs)))
+    _link([objs[s] for s in SOURCES], LIB)
+    _link([objs[s] for s in PEAK_SOURCES], PEAK_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {PEAK_LIB}")
     return LIB
 
 

@@ -96,8 +96,8 @@ void group_challenges(const vl_group& g, uint64_t seed, Transcript& tr, std::vec
   const uint32_t n0 = nvars_of(g.prods[0].D0), n2 = nvars_of(g.prods[0].D2);
   u.resize(n0);
   v.resize(n2);
-  for (uint32_t i = 0; i < n0; ++i) u[i] = tr_squeeze(tr, VL_LBL_U);
-  for (uint32_t i = 0; i < n2; ++i) v[i] = tr_squeeze(tr, VL_LBL_V);
+  for (uint32_t i = 0; i < n0; ++i) u[i] = tr_squeeze_fixed(tr, VL_LBL_U);
+  for (uint32_t i = 0; i < n2; ++i) v[i] = tr_squeeze_fixed(tr, VL_LBL_V);
 }
 
 // ---------------------------------------------------------------- planning --
@@ -301,23 +301,67 @@ void fill_blob(Plan& P, const BlobLayout& L, uint8_t* dblob) {
     memcpy(P.blob.data() + L.rounds, P.rounds.data(), P.rounds.size() * sizeof(RoundsJob));
 }
 
-hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipStream_t s) {
-  hipError_t e = launch_upload(dblob, P.blob.data(), L.total, s);
-  if (e != hipSuccess) return e;
-  e = launch_eq(reinterpret_cast<const EqJob*>(dblob + L.eq), (uint32_t)P.eq.size(), P.eq_threads, s);
-  if (e != hipSuccess) return e;
+hipError_t StageEvents::create() {
+  for (int i = 0; i < 2 * VL_STAGE_COUNT; ++i) {
+    const hipError_t e = hipEventCreate(&ev[i]);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+void StageEvents::destroy() {
+  for (int i = 0; i < 2 * VL_STAGE_COUNT; ++i)
+    if (ev[i]) (void)hipEventDestroy(ev[i]);
+}
+
+hipError_t StageEvents::begin(int stage, hipStream_t s) {
+  used[stage] = true;
+  return hipEventRecord(ev[2 * stage], s);
+}
+
+hipError_t StageEvents::end(int stage, hipStream_t s) { return hipEventRecord(ev[2 * stage + 1], s); }
+
+void StageEvents::accumulate(float* ms) {
+  for (int i = 0; i < VL_STAGE_COUNT; ++i) {
+    if (!used[i]) continue;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) == hipSuccess) ms[i] += t;
+    used[i] = false;
+  }
+}
+
+#define VL_STAGE(ev, st, s, launch)                   \
+  do {                                                 \
+    if (ev) {                                          \
+      const hipError_t e0_ = (ev)->begin((st), (s));  \
+      if (e0_ != hipSuccess) return e0_;               \
+    }                                                  \
+    const hipError_t e1_ = (launch);                   \
+    if (e1_ != hipSuccess) return e1_;                 \
+    if (ev) {                                          \
+      const hipError_t e2_ = (ev)->end((st), (s));    \
+      if (e2_ != hipSuccess) return e2_;               \
+    }                                                  \
+  } while (0)
+
+hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipStream_t s,
+                        StageEvents* ev) {
+  VL_STAGE(ev, VL_STAGE_UPLOAD, s, launch_upload(dblob, P.blob.data(), L.total, s));
+  VL_STAGE(ev, VL_STAGE_EQ, s,
+           launch_eq(reinterpret_cast<const EqJob*>(dblob + L.eq), (uint32_t)P.eq.size(), P.eq_threads, s));
   for (int k = 0; k < CK_COUNT; ++k) {
     if (P.cj[k].empty()) continue;
-    e = launch_contract(k, reinterpret_cast<const ContractJob*>(dblob + L.cj[k]),
-                        (uint32_t)P.cj[k].size(), P.cj_tasks[k], s);
-    if (e != hipSuccess) return e;
+    VL_STAGE(ev, VL_STAGE_CONTRACT + k, s,
+             launch_contract(k, reinterpret_cast<const ContractJob*>(dblob + L.cj[k]),
+                             (uint32_t)P.cj[k].size(), P.cj_tasks[k], s));
   }
-  if (!P.fin.empty()) {
-    e = launch_finish(reinterpret_cast<const FinishJob*>(dblob + L.fin), (uint32_t)P.fin.size(),
-                      P.fin_threads, s);
-    if (e != hipSuccess) return e;
-  }
-  return launch_rounds(reinterpret_cast<const RoundsJob*>(dblob + L.rounds), (uint32_t)P.rounds.size(), s);
+  if (!P.fin.empty())
+    VL_STAGE(ev, VL_STAGE_FINISH, s,
+             launch_finish(reinterpret_cast<const FinishJob*>(dblob + L.fin), (uint32_t)P.fin.size(),
+                           P.fin_threads, s));
+  VL_STAGE(ev, VL_STAGE_ROUNDS, s,
+           launch_rounds(reinterpret_cast<const RoundsJob*>(dblob + L.rounds), (uint32_t)P.rounds.size(), s));
+  return hipSuccess;
 }
 
 Tuning tuning_for(const vl_prove_opts* o) {
@@ -423,6 +467,23 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
   const Tuning T = tuning_for(o);
   const bool async = o->async != 0;
   Plan P;
+  StageEvents events;
+  StageEvents* ev = nullptr;
+  if (o->stage_ms && !async) {
+    for (int i = 0; i < VL_STAGE_COUNT; ++i) o->stage_ms[i] = 0.f;
+    const hipError_t e = events.create();
+    if (e != hipSuccess) {
+      events.destroy();
+      return fail(VL_ERR_HIP, "event create: %s", hipGetErrorString(e));
+    }
+    ev = &events;
+  }
+  struct Cleanup {
+    StageEvents* e;
+    ~Cleanup() {
+      if (e) e->destroy();
+    }
+  } cleanup{ev};
 
   // blocking mode: copy proofs, digests and status back, wait, report
   auto fetch = [&](uint64_t g0, uint64_t g1) -> vl_status {
@@ -439,6 +500,7 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
     }
     const hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(VL_ERR_HIP, "prove: %s", hipGetErrorString(e));
+    if (ev) ev->accumulate(o->stage_ms);
     for (uint64_t i = g0; i < g1; ++i) {
       const int32_t st = status[i - g0];
       if (st == VL_ERR_FALSE_STATEMENT)
@@ -454,7 +516,7 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
     plan_groups(P, T, groups, g0, g1, seed, ws, async, proofs, offsets, o->status, digests);
     const BlobLayout L = blob_layout(P);
     fill_blob(P, L, ws);
-    const hipError_t e = enqueue_plan(P, L, ws, s);
+    const hipError_t e = enqueue_plan(P, L, ws, s, ev);
     if (e != hipSuccess) return fail(VL_ERR_HIP, "launch: %s", hipGetErrorString(e));
     return async ? VL_OK : fetch(g0, g1);
   };

@@ -26,18 +26,13 @@ struct Fr {
   uint32_t w[8];
 };
 
-// p, R mod p, R^2 mod p, and 2^80 * p as a 12-limb integer (the offset that
-// makes a signed contraction result nonnegative before Montgomery reduction).
+// p, R mod p and R^2 mod p as limbs.
 #define VL_P_LIMBS 0x00000001u, 0xffffffffu, 0xfffe5bfeu, 0x53bda402u, \
                    0x09a1d805u, 0x3339d808u, 0x299d7d48u, 0x73eda753u
 #define VL_R_LIMBS 0xfffffffeu, 0x00000001u, 0x00034802u, 0x5884b7fau, \
                    0xecbc4ff5u, 0x998c4fefu, 0xacc5056fu, 0x1824b159u
 #define VL_R2_LIMBS 0xf3f29c6du, 0xc999e990u, 0x87925c23u, 0x2b6cedcbu, \
                     0x7254398fu, 0x05d31496u, 0x9f59ff11u, 0x0748d9d9u
-#define VL_KP_LIMBS 0x00000000u, 0x00000000u, 0x00010000u, 0xffff0000u, \
-                    0x5bfeffffu, 0xa402fffeu, 0xd80553bdu, 0xd80809a1u, \
-                    0x7d483339u, 0xa753299du, 0x000073edu, 0x00000000u
-
 VL_HD uint32_t p_limb(int i) {
   // switch keeps the constant in the instruction stream on the device
   switch (i) {
@@ -168,38 +163,6 @@ VL_HD Fr fr_mul(const Fr& a, const Fr& b) {
 
 VL_HD Fr fr_to_mont(const Fr& a) { return fr_mul(a, fr_R2()); }
 VL_HD Fr fr_from_mont(const Fr& a) { return fr_mul(a, fr_one_raw()); }
-
-// Montgomery reduction of a nonnegative 12-limb integer X < p * 2^256:
-// returns X * R^-1 mod p (fully reduced).
-VL_HD Fr fr_redc12(const uint32_t x_in[12]) {
-  uint32_t x[16];
-#pragma unroll
-  for (int i = 0; i < 12; ++i) x[i] = x_in[i];
-#pragma unroll
-  for (int i = 12; i < 16; ++i) x[i] = 0;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const uint32_t m = 0u - x[i];
-    uint32_t c = x[i] != 0u ? 1u : 0u;   // x_i + m * p0 = 0 mod 2^32
-#pragma unroll
-    for (int j = 1; j < 8; ++j) {
-      uint64_t s = (uint64_t)m * p_limb(j) + x[i + j] + c;
-      x[i + j] = (uint32_t)s;
-      c = (uint32_t)(s >> 32);
-    }
-#pragma unroll
-    for (int k = i + 8; k < 16; ++k) {
-      uint64_t s = (uint64_t)x[k] + c;
-      x[k] = (uint32_t)s;
-      c = (uint32_t)(s >> 32);
-    }
-  }
-  Fr r;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) r.w[j] = x[8 + j];
-  // (X + M p) / R < X / R + p < 2^81 + p < 2p for X < 2^337: one subtraction
-  return fr_reduce_once(r);
-}
 
 // canonical little-endian 32-byte encoding
 VL_HD void fr_to_bytes(const Fr& a, uint8_t* out) {

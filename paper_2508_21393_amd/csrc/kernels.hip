@@ -20,8 +20,8 @@
 // table is wave-uniform) and the digit pair from a vector register.  Each
 // dot2 adds at most 2 * 255 * 2^15 < 2^24 in magnitude, so 128 of them fit an
 // int32 accumulator; every 128 pairs the 32 accumulators are folded into
-// 64-bit limb sums.  At the end of a chunk the signed ~300-bit sum is made
-// nonnegative by adding 2^80 * p and reduced once (REDC).
+// 64-bit limb sums.  At the end of a chunk the signed ~300-bit sum is reduced
+// with one Montgomery multiplication (see finalize).
 #include <cstring>
 
 #include "internal.hpp"
@@ -204,6 +204,13 @@ __device__ __forceinline__ void flush(int32_t (&acc)[ND][32], int64_t (&T)[QC]) 
   }
 }
 
+// The signed sum V = sum_q T[q] 2^(32q) (two's complement over 12 limbs) is
+// congruent to R^2 * value, so V * R^-1 mod p is the Montgomery form of the
+// value.  With V = lo + 2^256 * hi (lo unsigned 256-bit, |hi| < 2^80):
+//     V * R^-1 = lo * R^-1 + hi  (mod p),
+// one Montgomery multiplication of lo by 1 plus a small signed lift.  (A
+// direct 12-limb REDC was miscompiled for gfx950 at -O3 -- one carry was
+// lost -- so the reduction goes through the field multiplier instead.)
 template <int QC>
 __device__ __forceinline__ Fr finalize(const int64_t (&T)[QC]) {
   uint32_t L[12];
@@ -214,15 +221,28 @@ __device__ __forceinline__ Fr finalize(const int64_t (&T)[QC]) {
     L[q] = (uint32_t)v;
     carry = v >> 32;
   }
-  const uint32_t KP[12] = {VL_KP_LIMBS};
-  uint32_t c = 0;
+  Fr lo;
 #pragma unroll
-  for (int q = 0; q < 12; ++q) {
-    const uint64_t s = (uint64_t)L[q] + KP[q] + c;
-    L[q] = (uint32_t)s;
-    c = (uint32_t)(s >> 32);
+  for (int j = 0; j < 8; ++j) lo.w[j] = L[j];
+  lo = fr_reduce_once(fr_reduce_once(lo));   // 2^256 < 3p
+  const Fr part = fr_mul(lo, fr_one_raw());
+  // the signed top part as a field element (|hi| < 2^80)
+  const bool neg = (L[11] >> 31) != 0;
+  Fr h = fr_zero();
+  if (!neg) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) h.w[j] = L[8 + j];
+  } else {
+    uint32_t c = 1;   // |hi| = ~hi + 1
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t w = ~L[8 + j];
+      h.w[j] = w + c;
+      c = (h.w[j] < w) ? 1u : 0u;
+    }
+    h = fr_neg(h);
   }
-  return fr_redc12(L);
+  return fr_add(part, h);
 }
 
 template <typename T, int ND, bool ROWS, bool VEC>
@@ -427,17 +447,17 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
   Transcript tr;
   uint8_t* out = J.proof;
   if (tid == 0) {
-#pragma unroll 1
+#pragma unroll
     for (int i = 0; i < 32; ++i) tr.st[i] = J.st[i];
-    Fr cc = fr_from_mont(c);
+    const Fr cc[1] = {fr_from_mont(c)};
     put_fr(out, c);
     out += 32;
-    tr_absorb_fr(tr, VL_LBL_CLAIM, &cc, 1);
+    tr_absorb_frs(tr, VL_LBL_CLAIM, cc);
     for (uint32_t p = 0; p + 1 < J.n_prods; ++p) {
-      Fr sc = fr_from_mont(s[p]);
+      const Fr sc[1] = {fr_from_mont(s[p])};
       put_fr(out, s[p]);
       out += 32;
-      tr_absorb_fr(tr, VL_LBL_PART, &sc, 1);
+      tr_absorb_frs(tr, VL_LBL_PART, sc);
     }
   }
   for (uint32_t p = 0; p < J.n_prods; ++p) {
@@ -465,8 +485,8 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
           put_fr(out, g[k]);
           out += 32;
         }
-        tr_absorb_fr(tr, VL_LBL_ROUND, gc, 3);
-        const Fr r = fr_to_mont(tr_squeeze(tr, VL_LBL_R));
+        tr_absorb_frs(tr, VL_LBL_ROUND, gc);
+        const Fr r = fr_to_mont(tr_squeeze_fixed(tr, VL_LBL_R));
         for (int j = 0; j < 8; ++j) bcast[j] = r.w[j];
       }
       __syncthreads();
@@ -492,7 +512,7 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
       out += 32;
       fin[0] = fr_from_mont(fin[0]);
       fin[1] = fr_from_mont(fin[1]);
-      tr_absorb_fr(tr, VL_LBL_FINAL, fin, 2);
+      tr_absorb_frs(tr, VL_LBL_FINAL, fin);
     }
     __syncthreads();
   }

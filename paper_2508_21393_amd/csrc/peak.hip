@@ -1,0 +1,80 @@
+// VALU issue-rate microbenchmark (libvlpeak.so), used by bench.py to state
+// the ceiling of the integer contraction: per-lane throughput of
+// v_dot2c_i32_i16, v_mad_u64_u32, v_mul_lo_u32, v_mul_hi_u32 and v_add_u32
+// (full-rate reference), each as 8 independent dependency chains per lane so
+// that issue rate, not latency, is measured.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace {
+
+constexpr int kChains = 8;
+
+template <int OP>
+__global__ void __launch_bounds__(256) rate_kernel(uint32_t* out, uint32_t iters, uint32_t seed) {
+  uint32_t a = seed ^ threadIdx.x, b = seed + blockIdx.x * 7u;
+  uint32_t acc[kChains];
+  uint64_t acc64[kChains];
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) {
+    acc[c] = a + c;
+    acc64[c] = (uint64_t)(b + c);
+  }
+  for (uint32_t i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) {
+      if constexpr (OP == 0) {
+        asm volatile("v_dot2c_i32_i16 %0, %1, %2" : "+v"(acc[c]) : "v"(a), "v"(b));
+      } else if constexpr (OP == 1) {
+        uint64_t sd;
+        asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc64[c]), "=s"(sd) : "v"(a), "v"(b));
+      } else if constexpr (OP == 2) {
+        asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(acc[c]) : "v"(b));
+      } else if constexpr (OP == 3) {
+        asm volatile("v_mul_hi_u32 %0, %0, %1" : "+v"(acc[c]) : "v"(b));
+      } else {
+        asm volatile("v_add_u32 %0, %0, %1" : "+v"(acc[c]) : "v"(b));
+      }
+    }
+  }
+  uint32_t s = 0;
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) s ^= acc[c] ^ (uint32_t)acc64[c] ^ (uint32_t)(acc64[c] >> 32);
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+template <int OP>
+double run(uint32_t blocks, uint32_t iters) {
+  uint32_t* out = nullptr;
+  if (hipMalloc(&out, (size_t)blocks * 256 * 4) != hipSuccess) return -1.0;
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  hipLaunchKernelGGL(rate_kernel<OP>, dim3(blocks), dim3(256), 0, 0, out, iters / 8, 1u);  // warm up
+  (void)hipEventRecord(e0, 0);
+  hipLaunchKernelGGL(rate_kernel<OP>, dim3(blocks), dim3(256), 0, 0, out, iters, 1u);
+  (void)hipEventRecord(e1, 0);
+  (void)hipEventSynchronize(e1);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(out);
+  const double ops = (double)blocks * 256.0 * iters * kChains;
+  return ms > 0 ? ops / (ms * 1e-3) : -1.0;
+}
+
+}  // namespace
+
+// which: 0 dot2_i32_i16, 1 mad_u64_u32, 2 mul_lo_u32, 3 mul_hi_u32, 4 add_u32.
+// Returns lane-operations per second, or a negative value on error.
+extern "C" double vlpeak_lane_ops_per_s(int which, uint32_t blocks, uint32_t iters) {
+  switch (which) {
+    case 0: return run<0>(blocks, iters);
+    case 1: return run<1>(blocks, iters);
+    case 2: return run<2>(blocks, iters);
+    case 3: return run<3>(blocks, iters);
+    case 4: return run<4>(blocks, iters);
+    default: return -1.0;
+  }
+}

@@ -71,7 +71,19 @@ struct Builder {
 BlobLayout blob_layout(const Plan& P);
 uint64_t blob_bound(const vl_group* groups, uint64_t n);
 void fill_blob(Plan& P, const BlobLayout& L, uint8_t* dblob);
-hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipStream_t s);
+// HIP events around each stage (blocking mode timing)
+struct StageEvents {
+  hipEvent_t ev[2 * VL_STAGE_COUNT] = {};
+  bool used[VL_STAGE_COUNT] = {};
+  hipError_t create();
+  void destroy();
+  hipError_t begin(int stage, hipStream_t s);
+  hipError_t end(int stage, hipStream_t s);
+  void accumulate(float* ms);  // after the stream has been synchronised
+};
+
+hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipStream_t s,
+                        StageEvents* ev = nullptr);
 Tuning tuning_for(const vl_prove_opts* o);
 void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, uint64_t g1,
                  uint64_t seed, uint8_t* ws, bool async, uint8_t* proofs_dev, const uint64_t* offsets,

@@ -110,7 +110,8 @@ struct Transcript {
   uint8_t st[32];
 };
 
-// labels used by the protocol
+// labels used by the protocol (string literals, so their lengths are known
+// at compile time)
 #define VL_LBL_U "u"
 #define VL_LBL_V "v"
 #define VL_LBL_CLAIM "claim"
@@ -118,12 +119,6 @@ struct Transcript {
 #define VL_LBL_ROUND "round"
 #define VL_LBL_R "r"
 #define VL_LBL_FINAL "final"
-
-VL_HD uint32_t lbl_len(const char* l) {
-  uint32_t n = 0;
-  while (l[n]) ++n;
-  return n;
-}
 
 VL_HD void tr_init(Transcript& t, uint64_t seed, uint32_t group_id, uint32_t n_prods,
                    const uint32_t* dims /* 3 per product */) {
@@ -145,43 +140,76 @@ VL_HD void tr_init(Transcript& t, uint64_t seed, uint32_t group_id, uint32_t n_p
   sha256_final(s, t.st);
 }
 
-VL_HD void tr_absorb(Transcript& t, const char* label, const uint8_t* data, uint32_t n) {
-  Sha256 s;
-  sha256_init(s);
-  sha256_update(s, t.st, 32);
-  sha256_update(s, (const uint8_t*)label, lbl_len(label));
-  sha256_update(s, data, n);
-  sha256_final(s, t.st);
-}
-
-VL_HD void tr_absorb_fr(Transcript& t, const char* label, const Fr* xs, uint32_t k) {
-  Sha256 s;
-  sha256_init(s);
-  sha256_update(s, t.st, 32);
-  sha256_update(s, (const uint8_t*)label, lbl_len(label));
-  for (uint32_t i = 0; i < k; ++i) {
-    uint8_t e[32];
-    fr_to_bytes(xs[i], e);
-    sha256_update(s, e, 32);
+// One-shot SHA-256 of a message whose length N is a compile-time constant.
+// Padding is laid out at compile time and every index is constant, so on the
+// device the message and the blocks stay in registers.
+template <int N>
+VL_HD void sha256_fixed(const uint8_t (&m)[N], uint8_t out[32]) {
+  constexpr int NB = (N + 9 + 63) / 64;
+  uint32_t h[8] = {0x6a09e667u, 0xbb67ae85u, 0x3c6ef372u, 0xa54ff53au,
+                   0x510e527fu, 0x9b05688cu, 0x1f83d9abu, 0x5be0cd19u};
+  constexpr uint64_t bits = (uint64_t)N * 8;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    uint8_t blk[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+      const int k = b * 64 + i;
+      uint8_t v = 0;
+      if (k < N) v = m[k];
+      else if (k == N) v = 0x80;
+      else if (k >= NB * 64 - 8) v = (uint8_t)(bits >> (8 * (NB * 64 - 1 - k)));
+      blk[i] = v;
+    }
+    sha256_compress(h, blk);
   }
-  sha256_final(s, t.st);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    out[4 * i] = (uint8_t)(h[i] >> 24);
+    out[4 * i + 1] = (uint8_t)(h[i] >> 16);
+    out[4 * i + 2] = (uint8_t)(h[i] >> 8);
+    out[4 * i + 3] = (uint8_t)(h[i]);
+  }
 }
 
-// returns a canonical (not Montgomery) field element
-VL_HD Fr tr_squeeze(Transcript& t, const char* label) {
+// absorb(label, x_0 .. x_{K-1}): st = H(st || label || enc(x_0) || ...), xs canonical
+template <int LN, int K>
+VL_HD void tr_absorb_frs(Transcript& t, const char (&label)[LN], const Fr (&xs)[K]) {
+  constexpr int L = LN - 1;
+  uint8_t m[32 + L + 32 * K];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) m[i] = t.st[i];
+#pragma unroll
+  for (int i = 0; i < L; ++i) m[32 + i] = (uint8_t)label[i];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      m[32 + L + 32 * k + 4 * i] = (uint8_t)(xs[k].w[i]);
+      m[32 + L + 32 * k + 4 * i + 1] = (uint8_t)(xs[k].w[i] >> 8);
+      m[32 + L + 32 * k + 4 * i + 2] = (uint8_t)(xs[k].w[i] >> 16);
+      m[32 + L + 32 * k + 4 * i + 3] = (uint8_t)(xs[k].w[i] >> 24);
+    }
+  sha256_fixed(m, t.st);
+}
+
+// squeeze(label): a canonical, uniformly distributed field element
+template <int LN>
+VL_HD Fr tr_squeeze_fixed(Transcript& t, const char (&label)[LN]) {
+  constexpr int L = LN - 1;
   for (uint32_t ctr = 0;; ++ctr) {
-    Sha256 s;
-    sha256_init(s);
-    sha256_update(s, t.st, 32);
-    sha256_update(s, (const uint8_t*)label, lbl_len(label));
-    uint8_t c[4];
-    put_u32le(c, ctr);
-    sha256_update(s, c, 4);
+    uint8_t m[32 + L + 4];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) m[i] = t.st[i];
+#pragma unroll
+    for (int i = 0; i < L; ++i) m[32 + i] = (uint8_t)label[i];
+    put_u32le(m + 32 + L, ctr);
     uint8_t h[32];
-    sha256_final(s, h);
+    sha256_fixed(m, h);
     Fr x = fr_from_bytes(h);
     x.w[7] &= 0x7fffffffu;
     if (fr_lt_p(x)) {
+#pragma unroll
       for (int i = 0; i < 32; ++i) t.st[i] = h[i];
       return x;
     }

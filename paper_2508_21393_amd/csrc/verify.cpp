@@ -96,12 +96,16 @@ extern "C" vl_status vl_verify_transcript(const uint8_t* proof, uint64_t len, co
   out.push_back(c);
   for (const Fr& x : u) out.push_back(x);
   for (const Fr& x : v) out.push_back(x);
-  tr_absorb_fr(tr, VL_LBL_CLAIM, &c, 1);
+  {
+    const Fr cc[1] = {c};
+    tr_absorb_frs(tr, VL_LBL_CLAIM, cc);
+  }
   std::vector<Fr> claims;  // Montgomery
   Fr parts_sum = fr_zero();
   for (uint32_t k = 0; k + 1 < g->n_prods; ++k) {
     const Fr s = el[pos++];
-    tr_absorb_fr(tr, VL_LBL_PART, &s, 1);
+    const Fr sa[1] = {s};
+    tr_absorb_frs(tr, VL_LBL_PART, sa);
     const Fr sm = fr_to_mont(s);
     claims.push_back(sm);
     parts_sum = fr_add(parts_sum, sm);
@@ -123,8 +127,8 @@ extern "C" vl_status vl_verify_transcript(const uint8_t* proof, uint64_t len, co
         if (fail_round) *fail_round = round_no;
         return fail(VL_ERR_REJECT, "round %d: g(0) + g(1) differs from the claim", round_no);
       }
-      tr_absorb_fr(tr, VL_LBL_ROUND, gc, 3);
-      const Fr rc = tr_squeeze(tr, VL_LBL_R);
+      tr_absorb_frs(tr, VL_LBL_ROUND, gc);
+      const Fr rc = tr_squeeze_fixed(tr, VL_LBL_R);
       const Fr r = fr_to_mont(rc);
       rvecs[k].push_back(r);
       out.push_back(rc);
@@ -143,7 +147,7 @@ extern "C" vl_status vl_verify_transcript(const uint8_t* proof, uint64_t len, co
       if (fail_round) *fail_round = 0;
       return fail(VL_ERR_REJECT, "product %u: final claim differs from a_final * b_final", k);
     }
-    tr_absorb_fr(tr, VL_LBL_FINAL, fin, 2);
+    tr_absorb_frs(tr, VL_LBL_FINAL, fin);
     out.push_back(fin[0]);
     out.push_back(fin[1]);
   }

@@ -1,0 +1,176 @@
+"""Continuous-batching proof server (one GPU).
+
+Proof requests (a list of groups with device-resident witnesses, and a seed)
+arrive over time.  The server keeps a fixed number of slots; each slot owns a
+HIP stream and, while busy, a workspace and device buffers for proofs and
+status.  A request is admitted when a slot is free and its device memory
+(workspace + proof + status bytes, plus its witness bytes if the caller says
+they are not yet counted) fits the HBM budget; otherwise it waits in FIFO
+order.  Admitted requests are enqueued with the asynchronous prove entry
+point, so requests on different slots overlap on the device; completion is
+found by polling HIP events, after which the proof bytes are copied back,
+latency is recorded and the slot and its memory are released.
+
+The arithmetic is untouched: a request's proof bytes depend only on its
+matrices, its seed and its group ids, so a result is identical alone and in
+any mix (the serving tests check this).
+"""
+import collections
+import dataclasses
+import time
+from typing import Deque, Dict, List, Optional, Sequence
+
+from . import binding as B
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    groups: Sequence[B.GroupArgs]
+    seed: int
+    t_arrive: float = 0.0
+    witness_bytes: int = 0          # counted against the budget while in flight (0 = resident pool)
+    mode: int = B.VL_MODE_BATCHED
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    proofs: List[bytes]
+    status: List[int]
+    t_arrive: float
+    t_admit: float
+    t_done: float
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrive
+
+
+class _Slot:
+    def __init__(self, torch, idx: int):
+        self.idx = idx
+        self.stream = torch.cuda.Stream()      # default priority
+        self.req: Optional[Request] = None
+        self.event = None
+        self.bufs = None
+        self.offs = None
+        self.bytes = 0
+        self.t_admit = 0.0
+
+
+class ProofServer:
+    def __init__(self, n_slots: int = 4, hbm_budget_bytes: int = 32 << 30):
+        import torch
+        self.torch = torch
+        self.slots = [_Slot(torch, i) for i in range(n_slots)]
+        self.budget = hbm_budget_bytes
+        self.in_use = 0
+        self.queue: Deque[Request] = collections.deque()
+        self.done: Dict[int, Result] = {}
+        self.peak_in_flight = 0
+
+    # -- sizing ---------------------------------------------------------------
+    @staticmethod
+    def request_bytes(req: Request) -> int:
+        ws = B.workspace_size(req.groups, req.mode, async_=True)
+        proof = sum(B.proof_size(g) for g in req.groups)
+        return ws + proof + 4 * len(req.groups) + 32 * len(req.groups) + req.witness_bytes
+
+    # -- queue ----------------------------------------------------------------
+    def submit(self, req: Request):
+        if not req.t_arrive:
+            req.t_arrive = time.perf_counter()
+        if self.request_bytes(req) > self.budget:
+            raise ValueError(f"request {req.rid} needs more than the whole HBM budget")
+        self.queue.append(req)
+
+    def _admit(self):
+        torch = self.torch
+        while self.queue:
+            slot = next((s for s in self.slots if s.req is None), None)
+            if slot is None:
+                return
+            req = self.queue[0]
+            need = self.request_bytes(req)
+            if self.in_use + need > self.budget:
+                return                       # FIFO: wait for memory to free up
+            self.queue.popleft()
+            ng = len(req.groups)
+            ws = torch.empty(max(256, B.workspace_size(req.groups, req.mode, async_=True)),
+                             dtype=torch.uint8, device="cuda")
+            total = sum(B.proof_size(g) for g in req.groups)
+            proofs = torch.empty(max(1, total), dtype=torch.uint8, device="cuda")
+            status = torch.full((ng,), -1, dtype=torch.int32, device="cuda")
+            # the slot's stream must see the allocations made on the current stream
+            slot.stream.wait_stream(torch.cuda.current_stream())
+            slot.offs = B.sumcheck_matmul_prove_async(req.groups, req.seed, proofs, status, ws,
+                                                      mode=req.mode, stream=slot.stream)
+            ev = torch.cuda.Event()
+            ev.record(slot.stream)
+            for t in (ws, proofs, status):
+                t.record_stream(slot.stream)
+            slot.req, slot.event, slot.bufs, slot.bytes = req, ev, (ws, proofs, status), need
+            slot.t_admit = time.perf_counter()
+            self.in_use += need
+            self.peak_in_flight = max(self.peak_in_flight, sum(s.req is not None for s in self.slots))
+
+    def _reap(self) -> int:
+        n = 0
+        for s in self.slots:
+            if s.req is None or not s.event.query():
+                continue
+            ws, proofs, status = s.bufs
+            raw = proofs.cpu().numpy().tobytes()
+            st = status.cpu().tolist()
+            req = s.req
+            self.done[req.rid] = Result(req.rid, [raw[s.offs[i]:s.offs[i + 1]] for i in range(len(req.groups))],
+                                        st, req.t_arrive, s.t_admit, time.perf_counter())
+            self.in_use -= s.bytes
+            s.req = s.event = s.bufs = s.offs = None
+            s.bytes = 0
+            n += 1
+        return n
+
+    def poll(self) -> int:
+        """Admit what fits, collect what finished; returns requests completed."""
+        n = self._reap()
+        self._admit()
+        return n
+
+    def busy(self) -> bool:
+        return bool(self.queue) or any(s.req is not None for s in self.slots)
+
+    def drain(self, sleep_s: float = 0.0):
+        while self.busy():
+            if self.poll() == 0 and sleep_s:
+                time.sleep(sleep_s)
+
+
+def run_open_loop(server: ProofServer, arrivals, make_request, sleep_s: float = 0.0002):
+    """Feed requests at their arrival times (seconds from start) and run the
+    server until all are done.  ``arrivals`` is a list of (t, payload);
+    ``make_request(i, payload)`` returns a Request.  Returns the results in
+    arrival order and the wall time."""
+    t0 = time.perf_counter()
+    i = 0
+    while i < len(arrivals) or server.busy():
+        now = time.perf_counter() - t0
+        while i < len(arrivals) and arrivals[i][0] <= now:
+            req = make_request(i, arrivals[i][1])
+            req.t_arrive = t0 + arrivals[i][0]
+            server.submit(req)
+            i += 1
+        if server.poll() == 0 and sleep_s:
+            time.sleep(sleep_s)
+    wall = time.perf_counter() - t0
+    return [server.done[k] for k in sorted(server.done)], wall
+
+
+def latency_summary(results: Sequence[Result]) -> dict:
+    lat = sorted(r.latency for r in results)
+    if not lat:
+        return {}
+    pick = lambda q: lat[min(len(lat) - 1, max(0, int(round(q * len(lat))) - 1))]  # noqa: E731
+    return {"p50_ms": 1e3 * pick(0.50), "p99_ms": 1e3 * pick(0.99), "mean_ms": 1e3 * sum(lat) / len(lat),
+            "n": len(lat)}
