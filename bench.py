@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Fr MACs/s + matmul-sumcheck proofs/s; batched vs per-instance; p50/p99 latency"
 CU, LANES_PER_CLK, CLOCK_HZ = 256, 64, 2.4e9   # MI355X: CUs, VALU lanes per CU per clock, peak clock
-DOT2_PER_I16_MAC = 16                           # 32 eq bytes x one 16-bit digit, 2 per v_dot2
+MAD_PER_I16_MAC = 8                             # 8 signed 32-bit eq digits x one int16 entry
 
 
 def nv(d):
@@ -45,22 +45,27 @@ def algorithmic_macs(shapes_by_group):
 
 
 def int16_contraction_macs(groups):
-    """Entries streamed by the int16 contraction kernels, by kernel kind."""
+    """Entries streamed by the int16 contraction kernels, by stage (kernel
+    kind), following the library's planning rule: a row contraction with at
+    least 256 outputs runs 4 columns per lane with 8-byte loads; the column
+    kernels read 16-byte aligned rows with vector loads (all operands here are
+    aligned)."""
     from paper_2508_21393_amd import binding as B
-    rows = cols = 0
+    k = {n: 0 for n in ("i16_rows", "i16_rows4_vec", "i16_cols_vec")}
     for g in groups:
         for p in g.products:
             d0, d1, d2 = p.dims
+            # A side: outputs are the D1 columns of op(A)
             if p.transA:
-                cols += d0 * d1
+                k["i16_cols_vec"] += d0 * d1
             else:
-                rows += d0 * d1
+                k["i16_rows4_vec" if d1 >= 256 else "i16_rows"] += d0 * d1
+            # B side: outputs are the D1 rows of op(B)
             if p.transB:
-                rows += d1 * d2
+                k["i16_rows4_vec" if d1 >= 256 else "i16_rows"] += d1 * d2
             else:
-                cols += d1 * d2
-    return {B.STAGE_NAMES.index("i16_rows"): rows, B.STAGE_NAMES.index("i16_cols_vec"): cols,
-            B.STAGE_NAMES.index("i16_cols"): cols}
+                k["i16_cols_vec"] += d1 * d2
+    return {B.STAGE_NAMES.index(n): v for n, v in k.items()}
 
 
 def cpu_baseline(workload, budget_s=15.0):
@@ -91,7 +96,7 @@ def peak_rates():
     L = ctypes.CDLL(PEAK_LIB)
     L.vlpeak_lane_ops_per_s.restype = ctypes.c_double
     L.vlpeak_lane_ops_per_s.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]
-    names = ["dot2_i32_i16", "mad_u64_u32", "mul_lo_u32", "mul_hi_u32", "add_u32"]
+    names = ["dot2_i32_i16", "mad_u64_u32", "mul_lo_u32", "mul_hi_u32", "add_u32", "mad_i64_i32"]
     return {n: L.vlpeak_lane_ops_per_s(i, 8192, 4096) for i, n in enumerate(names)}
 
 
@@ -177,11 +182,11 @@ def main():
     dom_ms = stage_avg[dom]
     achieved = k16[dom] / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0
     rates = None if args.no_peak else peak_rates()
-    dot2_rate = CU * LANES_PER_CLK * CLOCK_HZ
-    peak = dot2_rate / DOT2_PER_I16_MAC / 1e12
+    mad_rate = CU * LANES_PER_CLK * CLOCK_HZ
+    peak = mad_rate / MAD_PER_I16_MAC / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T Fr-MAC/s",
                 "frac": achieved / peak if peak else None, "traffic": None,
-                "kernel": f"contract_kernel {B.STAGE_NAMES[dom]} (int16 x eq, v_dot2_i32_i16)",
+                "kernel": f"contract_kernel {B.STAGE_NAMES[dom]} (int16 x eq digits, v_mad_i64_i32)",
                 "work_per_launch": k16[dom], "avg_launch_ms": dom_ms}
 
     out = {

@@ -46,9 +46,9 @@ typedef enum {
   VL_ERR_FALSE_STATEMENT = 6,  /* the products do not sum to C: no proof       */
   VL_ERR_REJECT = 7,           /* verification failed                          */
   VL_ERR_BUFFER_TOO_SMALL = 8, /* an output buffer is too small                */
-  VL_ERR_RANGE = 9             /* an int32/int64 entry is outside the range the
-                                  contraction digits represent (|x| >= 2^63 for
-                                  int64 with four digits, 2^47 with three)     */
+  VL_ERR_RANGE = 9             /* a claimed C entry is outside the range the
+                                  planned contraction digits represent (about
+                                  |C| >= 2^47 for int64 C of int16 products)   */
 } vl_status;
 
 typedef enum { VL_I16 = 1, VL_I32 = 2, VL_I64 = 3 } vl_dtype;
@@ -113,12 +113,15 @@ typedef struct {
 /* stages of a prove call, in launch order */
 #define VL_STAGE_UPLOAD 0      /* job descriptors to device memory                 */
 #define VL_STAGE_EQ 1          /* eq tables and their byte-sliced "pack" form      */
-#define VL_STAGE_CONTRACT 2    /* + kind: integer contraction kernels, 12 kinds:
-                                  int16 rows/cols/cols-vec, int32 (3 digits),
-                                  int64 three-digit, int64 four-digit (same order) */
-#define VL_STAGE_FINISH 14     /* split-contraction sums and zero padding          */
-#define VL_STAGE_ROUNDS 15     /* claim, prover guard, sumcheck rounds, proof bytes */
-#define VL_STAGE_COUNT 16
+#define VL_STAGE_CONTRACT 2    /* + kind: integer contraction kernels, 14 kinds:
+                                  int16 rows (1 column per lane; 4 columns with
+                                  element loads; 4 columns with 8-byte loads),
+                                  int16 cols (element loads; 16-byte row loads);
+                                  then rows, cols, cols-vec for int32, int64 with
+                                  |x| < 2^47, and int64                            */
+#define VL_STAGE_FINISH 16     /* split-contraction sums and zero padding          */
+#define VL_STAGE_ROUNDS 17     /* claim, prover guard, sumcheck rounds, proof bytes */
+#define VL_STAGE_COUNT 18
 
 /* Lift n signed integers (dtype) at device pointer src into Fr (Montgomery,
  * structure-of-limbs) at dst (dst.n >= n).  Negative x becomes p - |x|. */

@@ -18,10 +18,10 @@ VL_I16, VL_I32, VL_I64 = 1, 2, 3
 VL_CONTRACT_ROWS, VL_CONTRACT_COLS = 0, 1
 VL_MODE_PER_INSTANCE, VL_MODE_BATCHED, VL_MODE_PERSISTENT = 0, 1, 2
 VL_MAX_PRODS = 8
-VL_STAGE_COUNT = 16
-STAGE_NAMES = ["upload", "eq", "i16_rows", "i16_cols", "i16_cols_vec", "i32_rows", "i32_cols",
-               "i32_cols_vec", "i64n3_rows", "i64n3_cols", "i64n3_cols_vec", "i64n4_rows", "i64n4_cols",
-               "i64n4_cols_vec", "finish", "rounds"]
+VL_STAGE_COUNT = 18
+STAGE_NAMES = ["upload", "eq", "i16_rows", "i16_rows4", "i16_rows4_vec", "i16_cols", "i16_cols_vec", "i32_rows",
+               "i32_cols", "i32_cols_vec", "i64s_rows", "i64s_cols", "i64s_cols_vec", "i64_rows",
+               "i64_cols", "i64_cols_vec", "finish", "rounds"]
 
 STATUS_NAMES = {0: "VL_OK", 1: "VL_ERR_INVALID_ARG", 2: "VL_ERR_SHAPE", 3: "VL_ERR_DTYPE",
                 4: "VL_ERR_WORKSPACE", 5: "VL_ERR_HIP", 6: "VL_ERR_FALSE_STATEMENT",

@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
@@ -100,26 +101,62 @@ void group_challenges(const vl_group& g, uint64_t seed, Transcript& tr, std::vec
   for (uint32_t i = 0; i < n2; ++i) v[i] = tr_squeeze_fixed(tr, VL_LBL_V);
 }
 
-// ---------------------------------------------------------------- planning --
-static int contract_kind(int dtype, int nd, bool rows, bool vec) {
-  int base;
-  if (dtype == VL_I16) base = CK_I16_ROWS;
-  else if (dtype == VL_I32) base = CK_I32_ROWS;
-  else base = nd == 3 ? CK_I64N3_ROWS : CK_I64N4_ROWS;
-  return base + (rows ? 0 : (vec ? 2 : 1));
+// Challenges of groups [g0, g1): transcript state after u and v.  Each group
+// is independent (its own transcript), so large calls split the hashing over
+// a few host threads.
+void all_challenges(const vl_group* groups, uint64_t g0, uint64_t g1, uint64_t seed,
+                    std::vector<Challenges>& out) {
+  const uint64_t n = g1 - g0;
+  out.assign(n, Challenges());
+  auto work = [&](uint64_t lo, uint64_t hi) {
+    for (uint64_t i = lo; i < hi; ++i) group_challenges(groups[g0 + i], seed, out[i].tr, out[i].u, out[i].v);
+  };
+  const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+  const uint64_t nt = std::min<uint64_t>(hw, n / 4);
+  if (nt <= 1) {
+    work(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const uint64_t per = (n + nt - 1) / nt;
+  for (uint64_t t = 0; t < nt; ++t) {
+    const uint64_t lo = t * per, hi = std::min(n, lo + per);
+    if (lo < hi) th.emplace_back(work, lo, hi);
+  }
+  for (auto& x : th) x.join();
 }
 
-int digits_for(int dtype) { return dtype == VL_I16 ? 1 : (dtype == VL_I32 ? 3 : 4); }
+// ---------------------------------------------------------------- planning --
+// Digit layout of an entry type: int16 entries are one 16-bit digit; int32
+// and int64 use 24-bit digits (two cover |x| < 2^47, three any int64).
+int digits_for(int dtype) { return dtype == VL_I16 ? 1 : (dtype == VL_I32 ? 2 : 3); }
+
+static int contract_kind(int dtype, int nd, bool rows, bool vec, int opl) {
+  if (dtype == VL_I16) {
+    if (rows) return opl == 4 ? (vec ? CK_I16_ROWS4_VEC : CK_I16_ROWS4) : CK_I16_ROWS;
+    return vec ? CK_I16_COLS_VEC : CK_I16_COLS;
+  }
+  const int base = dtype == VL_I32 ? CK_I32_ROWS : (nd == 2 ? CK_I64S_ROWS : CK_I64_ROWS);
+  return base + (rows ? 0 : (vec ? 2 : 1));
+}
 
 void Builder::contract(const void* M, int dtype, int nd, uint64_t ld, bool rows, uint32_t n_out,
                        uint32_t len, const uint32_t* pack, uint32_t* dst, uint64_t dst_ld,
                        uint64_t n_total, int32_t* err) {
   ContractJob j{};
   const uint64_t es = esize(dtype);
-  const bool vec = !rows && (reinterpret_cast<uintptr_t>(M) % 16 == 0) && ((ld * es) % 16 == 0);
-  const int kind = contract_kind(dtype, nd, rows, vec);
-  const uint32_t out_waves = (n_out + 63) / 64;
-  uint64_t chunk = std::max<uint64_t>(256, T.chunk_target / (uint32_t)nd);
+  // vector loads: 16-byte aligned rows (cols kernels), 8-byte aligned groups
+  // of four columns (int16 rows kernel)
+  const bool vec = rows ? ((reinterpret_cast<uintptr_t>(M) % 8 == 0) && ((ld * es) % 8 == 0))
+                        : ((reinterpret_cast<uintptr_t>(M) % 16 == 0) && ((ld * es) % 16 == 0));
+  // four adjacent columns per lane for wide int16 row contractions: one
+  // scalar load of the eq digits then feeds 32 multiply-adds
+  const int opl = (rows && dtype == VL_I16 && n_out >= 256) ? 4 : 1;
+  const int kind = contract_kind(dtype, nd, rows, vec, opl);
+  const uint32_t out_waves = (n_out + 64 * opl - 1) / (64 * opl);
+  // chunk: about T.lane_macs multiply-adds per lane and task
+  uint64_t chunk = std::max<uint64_t>(64, T.lane_macs / (8ull * nd * opl));
+  chunk = std::min<uint64_t>(chunk, kMaxChunk);
   chunk = std::min<uint64_t>(chunk, align_up(len, kChunkAlign));
   chunk = align_up(chunk, kChunkAlign);
   while (T.min_tasks > 1 && chunk > 256 &&
@@ -135,7 +172,7 @@ void Builder::contract(const void* M, int dtype, int nd, uint64_t ld, bool rows,
   j.out_waves = out_waves;
   j.task_begin = P.cj_tasks[kind];
   j.pack = pack;
-  j.err = nd > 1 ? err : nullptr;
+  j.err = err;
   FinishJob f{};
   f.n_valid = n_out;
   f.n_total = (uint32_t)n_total;
@@ -166,10 +203,10 @@ void Builder::contract(const void* M, int dtype, int nd, uint64_t ld, bool rows,
   }
 }
 
-void Builder::eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_pairs) {
+void Builder::eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_len) {
   EqJob e{};
   e.nvars = (uint32_t)x.size();
-  e.pack_pairs = pack_pairs;
+  e.pack_len = pack_len;
   e.thread_begin = P.eq_threads;
   e.eq = eq;
   e.eq_ld = 1ull << x.size();
@@ -183,45 +220,43 @@ void Builder::eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uin
   }
   P.points.push_back(pts);
   const uint32_t threads = std::max<uint32_t>(1, (uint32_t)((1ull << x.size()) / 2));
-  P.eq_threads += std::max(threads, pack_pairs);
+  P.eq_threads += std::max(threads, (pack_len + 1) / 2);
   P.eq.push_back(e);
 }
 
-void Builder::group(const vl_group& g, uint64_t seed, uint8_t* proof_dev, int32_t* status_dev,
+void Builder::group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev, int32_t* status_dev,
                     uint8_t* digest_dev, int32_t* err) {
-  Transcript tr;
-  std::vector<Fr> u, v;
-  group_challenges(g, seed, tr, u, v);
+  const Transcript& tr = ch.tr;
+  const std::vector<Fr>& u = ch.u;
+  const std::vector<Fr>& v = ch.v;
   const vl_product& p0 = g.prods[0];
   const uint32_t D0 = p0.D0, D2 = p0.D2, n0 = (uint32_t)u.size();
   const uint64_t L0 = 1ull << n0;
   uint32_t* eqU = dev<uint32_t>(take(8 * L0 * 4));
-  uint32_t* packU = dev<uint32_t>(take((uint64_t)((D0 + 1) / 2) * 128));
-  uint32_t* packV = dev<uint32_t>(take((uint64_t)((D2 + 1) / 2) * 128));
+  uint32_t* packU = dev<uint32_t>(take((uint64_t)D0 * 32));
+  uint32_t* packV = dev<uint32_t>(take((uint64_t)D2 * 32));
   uint32_t* tvec = dev<uint32_t>(take(8 * L0 * 4));
-  eq_job(u, eqU, packU, (D0 + 1) / 2);
-  eq_job(v, nullptr, packV, (D2 + 1) / 2);
+  eq_job(u, eqU, packU, D0);
+  eq_job(v, nullptr, packV, D2);
 
-  // claim contraction: t[i] = sum_j C[i][j] eq(v, j).  Three 16-bit digits
-  // cover |C| < 2^47 - 2^31, enough for sums of int16 products with a total
-  // inner dimension <= 2^16; wider C uses four (an out-of-range entry makes
+  // claim contraction: t[i] = sum_j C[i][j] eq(v, j).  Two 24-bit digits
+  // cover |C| < 2^47 - 2^23, enough for sums of int16 products with a total
+  // inner dimension <= 2^16; wider C uses three (an out-of-range entry makes
   // the prover refuse with VL_ERR_RANGE rather than prove a wrong claim).
-  int ndc = 4;
-  if (g.dtype_c == VL_I16) ndc = 1;
-  else if (g.dtype_c == VL_I32) ndc = 3;
-  else {
+  int ndc = digits_for(g.dtype_c);
+  if (g.dtype_c == VL_I64) {
     uint64_t sum_d1 = 0;
     bool small = true;
     for (uint32_t k = 0; k < g.n_prods; ++k) {
       sum_d1 += g.prods[k].D1;
       small &= g.prods[k].dtype_a == VL_I16 && g.prods[k].dtype_b == VL_I16;
     }
-    if (small && sum_d1 <= (1u << 16)) ndc = 3;
+    if (small && sum_d1 <= (1u << 16)) ndc = 2;
   }
   contract(g.C, g.dtype_c, ndc, g.ldc, false, D0, D2, packV, tvec, L0, L0, err);
 
   RoundsJob rj{};
-  memcpy(rj.st, tr.st, 32);
+  memcpy(rj.st, tr.h, 32);
   rj.n_prods = g.n_prods;
   rj.n0 = n0;
   rj.eqU = eqU;
@@ -371,10 +406,10 @@ Tuning tuning_for(const vl_prove_opts* o) {
   return t;
 }
 
-uint64_t out_bytes(const vl_group& g) { return align_up(proof_elems(g) * 32, 256) + 512; }
-
 // Plans groups [g0, g1) with the blob at workspace offset 0 and data after it.
-// ws == nullptr plans for sizing only.
+// Blocking mode gathers every proof, status word and digest of the call in
+// one region (proofs at their final offsets, then statuses, then digests) so
+// that one copy brings them back.  ws == nullptr plans for sizing only.
 void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, uint64_t g1,
                  uint64_t seed, uint8_t* ws, bool async, uint8_t* proofs_dev, const uint64_t* offsets,
                  int32_t* status_dev, uint8_t* digests_dev) {
@@ -382,6 +417,25 @@ void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, 
   const uint64_t blob = blob_bound(groups + g0, g1 - g0);
   Builder B(P, T, reinterpret_cast<uint64_t>(ws), blob);
   P.n_err = (uint32_t)(g1 - g0);
+  const uint64_t n = g1 - g0;
+  std::vector<Challenges> ch;
+  if (ws) {
+    all_challenges(groups, g0, g1, seed, ch);
+  } else {
+    // sizing: the challenges do not change any size, only their count matters
+    ch.assign(n, Challenges());
+    for (uint64_t i = 0; i < n; ++i) {
+      ch[i].u.assign(nvars_of(groups[g0 + i].prods[0].D0), fr_zero());
+      ch[i].v.assign(nvars_of(groups[g0 + i].prods[0].D2), fr_zero());
+    }
+  }
+  uint64_t proof_total = 0;
+  for (uint64_t i = g0; i < g1; ++i) proof_total += 32 * proof_elems(groups[i]);
+  if (!async) {
+    P.out_proof_bytes = proof_total;
+    P.out_off = B.take(align_up(proof_total, 256) + align_up(4 * n, 256) + 32 * n);
+  }
+  uint64_t rel = 0;
   for (uint64_t i = g0; i < g1; ++i) {
     uint8_t* pd;
     int32_t* sd;
@@ -391,14 +445,14 @@ void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, 
       sd = status_dev ? status_dev + i : nullptr;
       dd = digests_dev ? digests_dev + 32 * i : nullptr;
     } else {
-      const uint64_t o = B.take(out_bytes(groups[i]));
-      pd = ws + o;
-      sd = reinterpret_cast<int32_t*>(pd + align_up(proof_elems(groups[i]) * 32, 256));
-      dd = reinterpret_cast<uint8_t*>(sd) + 256;
-      P.proof_off.push_back(o);
+      uint8_t* base = ws + P.out_off;
+      pd = base + rel;
+      sd = reinterpret_cast<int32_t*>(base + align_up(proof_total, 256)) + (i - g0);
+      dd = base + align_up(proof_total, 256) + align_up(4 * n, 256) + 32 * (i - g0);
     }
+    rel += 32 * proof_elems(groups[i]);
     int32_t* err = reinterpret_cast<int32_t*>(ws + 4 * (i - g0));  // blob starts with the flags
-    B.group(groups[i], seed, pd, sd, dd, err);
+    B.group(groups[i], ch[i - g0], pd, sd, dd, err);
   }
   P.data_end = B.off;
 }
@@ -458,10 +512,7 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
   if (proofs_len < tot)
     return fail(VL_ERR_BUFFER_TOO_SMALL, "proof buffer holds %llu bytes, %llu needed",
                 (unsigned long long)proofs_len, (unsigned long long)tot);
-  const uint64_t need = vl_workspace_size(groups, n, o);
-  if (!o->workspace || o->workspace_bytes < need)
-    return fail(VL_ERR_WORKSPACE, "workspace of %llu bytes, %llu needed",
-                (unsigned long long)o->workspace_bytes, (unsigned long long)need);
+  if (!o->workspace) return fail(VL_ERR_WORKSPACE, "no workspace");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   uint8_t* ws = reinterpret_cast<uint8_t*>(o->workspace);
   const Tuning T = tuning_for(o);
@@ -485,28 +536,25 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
     }
   } cleanup{ev};
 
-  // blocking mode: copy proofs, digests and status back, wait, report
+  // blocking mode: one copy of the gathered proofs, statuses and digests
   auto fetch = [&](uint64_t g0, uint64_t g1) -> vl_status {
-    std::vector<int32_t> status(g1 - g0, -1);
-    for (uint64_t i = g0; i < g1; ++i) {
-      const uint8_t* pd = ws + P.proof_off[i - g0];
-      const uint64_t pb = 32 * proof_elems(groups[i]);
-      const uint8_t* sd = pd + align_up(pb, 256);
-      hipError_t e = hipMemcpyAsync(proofs + offsets[i], pd, pb, hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess) e = hipMemcpyAsync(&status[i - g0], sd, 4, hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess && digests)
-        e = hipMemcpyAsync(digests + 32 * i, sd + 256, 32, hipMemcpyDeviceToHost, s);
-      if (e != hipSuccess) return fail(VL_ERR_HIP, "copy back: %s", hipGetErrorString(e));
-    }
-    const hipError_t e = hipStreamSynchronize(s);
+    const uint64_t n = g1 - g0;
+    const uint64_t pa = align_up(P.out_proof_bytes, 256), sa = align_up(4 * n, 256);
+    std::vector<uint8_t> host(pa + sa + 32 * n);
+    hipError_t e = hipMemcpyAsync(host.data(), ws + P.out_off, host.size(), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return fail(VL_ERR_HIP, "copy back: %s", hipGetErrorString(e));
+    e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(VL_ERR_HIP, "prove: %s", hipGetErrorString(e));
     if (ev) ev->accumulate(o->stage_ms);
+    memcpy(proofs + offsets[g0], host.data(), P.out_proof_bytes);
+    if (digests) memcpy(digests + 32 * g0, host.data() + pa + sa, 32 * n);
     for (uint64_t i = g0; i < g1; ++i) {
-      const int32_t st = status[i - g0];
+      int32_t st;
+      memcpy(&st, host.data() + pa + 4 * (i - g0), 4);
       if (st == VL_ERR_FALSE_STATEMENT)
         return fail(VL_ERR_FALSE_STATEMENT, "group %u: the products do not sum to C", groups[i].group_id);
       if (st == VL_ERR_RANGE)
-        return fail(VL_ERR_RANGE, "group %u: an entry exceeds the contraction digit range",
+        return fail(VL_ERR_RANGE, "group %u: an entry of C exceeds the contraction digit range",
                     groups[i].group_id);
       if (st != VL_OK) return fail(VL_ERR_HIP, "group %u: prover status %d", groups[i].group_id, st);
     }
@@ -514,6 +562,9 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
   };
   auto run = [&](uint64_t g0, uint64_t g1) -> vl_status {
     plan_groups(P, T, groups, g0, g1, seed, ws, async, proofs, offsets, o->status, digests);
+    if (P.data_end > o->workspace_bytes)
+      return fail(VL_ERR_WORKSPACE, "workspace of %llu bytes, %llu needed",
+                  (unsigned long long)o->workspace_bytes, (unsigned long long)align_up(P.data_end, 256));
     const BlobLayout L = blob_layout(P);
     fill_blob(P, L, ws);
     const hipError_t e = enqueue_plan(P, L, ws, s, ev);
@@ -569,7 +620,7 @@ vl_status vl_eq_table(const vl_fr* point, uint32_t nvars, vl_fr_vec out, void* s
 }
 
 // layout of the partial-eval workspace: [pack][job blob][split partials]
-static uint64_t pe_pack_bytes(uint64_t len) { return align_up(((len + 1) / 2) * 128, 256); }
+static uint64_t pe_pack_bytes(uint64_t len) { return align_up(len * 32, 256); }
 static constexpr uint64_t kPeBlob = 1024;
 
 uint64_t vl_partial_eval_workspace_size(uint32_t rows, uint32_t cols, int32_t contract, int32_t dtype) {

@@ -130,8 +130,67 @@ VL_HD Fr fr_sub(const Fr& a, const Fr& b) {
 VL_HD Fr fr_neg(const Fr& a) { return fr_sub(fr_zero(), a); }
 VL_HD Fr fr_double(const Fr& a) { return fr_add(a, a); }
 
-// Montgomery product a*b*R^-1 mod p (inputs < p, output < p).
+#if defined(__HIP_DEVICE_COMPILE__)
+// Device Montgomery product by product scanning with the reduction folded in
+// (Koc, Acar, Kaliski's finely integrated product scanning).  Column k sums
+// a_i b_{k-i} and m_i p_{k-i} (i < k); for k < 8 the digit m_k = -t0 (as
+// -p^-1 = 0xFFFFFFFF mod 2^32) clears the column's low word, for k >= 8 the
+// low word is result word k - 8.  The column sum is kept as a 64-bit pair
+// (low, middle word) that each partial product is multiply-added into with
+// v_mad_u64_u32, plus a top word that takes its carry-out through
+// v_addc_co_u32: two instructions per partial product.  Carries go through
+// scalar registers the compiler picks, so independent products interleave.
+__device__ __forceinline__ void fr_mac96(uint64_t& acc, uint32_t& top, uint32_t x, uint32_t y) {
+  uint64_t c, dummy;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc), "=s"(c) : "v"(x), "v"(y));
+  asm("v_addc_co_u32 %0, %1, %0, 0, %2" : "+v"(top), "=s"(dummy) : "s"(c));
+}
+
+__device__ __forceinline__ void fr_mac96s(uint64_t& acc, uint32_t& top, uint32_t x, uint32_t ys) {
+  uint64_t c, dummy;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc), "=s"(c) : "v"(x), "s"(ys));
+  asm("v_addc_co_u32 %0, %1, %0, 0, %2" : "+v"(top), "=s"(dummy) : "s"(c));
+}
+
+#endif
+
+// Montgomery product a*b*R^-1 mod p (inputs < p, output < p).  The device
+// build uses the product-scanning form above; the host build uses CIOS.
 VL_HD Fr fr_mul(const Fr& a, const Fr& b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  uint32_t m[8], u[8];
+  uint64_t acc = 0;
+  uint32_t top = 0;
+#pragma unroll
+  for (int k = 0; k < 15; ++k) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int j = k - i;
+      if (j >= 0 && j < 8) fr_mac96(acc, top, a.w[i], b.w[j]);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int j = k - i;
+      if (i < k && j >= 1 && j < 8) fr_mac96s(acc, top, m[i], p_limb(j));
+    }
+    const uint32_t t0 = (uint32_t)acc;
+    // a column sum stays below 2^69, so the shifted value is below 2^37 and
+    // the +1 below cannot carry out of 64 bits
+    acc = (acc >> 32) | ((uint64_t)top << 32);
+    top = 0;
+    if (k < 8) {
+      m[k] = 0u - t0;
+      acc += t0 != 0u ? 1u : 0u;            // t0 + m_k * p_0 = t0 + m_k = 0 or 2^32
+    } else {
+      u[k - 8] = t0;
+    }
+  }
+  u[7] = (uint32_t)acc;                      // the result is below 2p < 2^256
+  Fr r;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) r.w[j] = u[j];
+  return fr_reduce_once(r);
+#else
   uint32_t t[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) t[j] = 0;
@@ -159,6 +218,7 @@ VL_HD Fr fr_mul(const Fr& a, const Fr& b) {
 #pragma unroll
   for (int j = 0; j < 8; ++j) r.w[j] = t[j];
   return fr_reduce_once(r);
+#endif
 }
 
 VL_HD Fr fr_to_mont(const Fr& a) { return fr_mul(a, fr_R2()); }

@@ -10,21 +10,21 @@ namespace vl {
 
 constexpr int kWave = 64;
 constexpr int kContractBlock = 256;            // 4 waves, one task per wave
-constexpr uint32_t kFlushPairs = 128;          // int32 accumulator bound (see contract kernel)
 constexpr uint32_t kChunkAlign = 32;           // contraction chunks start at multiples of 32
+constexpr uint32_t kMaxChunk = 1u << 16;       // int64 accumulators of int16 digits hold 2^16 entries
 constexpr int kRoundsBlock = 512;
 
 // An eq table to build: out[i] = prod_j (x_j or 1 - x_j), i < 2^nvars, plus
 // its "pack" form used by the integer contractions (see contract kernel).
 struct EqJob {
   uint32_t nvars;
-  uint32_t pack_pairs;        // pairs to emit into pack (ceil(len / 2))
+  uint32_t pack_len;          // entries to emit into pack (8 signed digits each)
   uint32_t thread_begin;      // prefix sum of threads over jobs in a launch
   uint32_t pad_;
   const uint32_t* point;      // device: 2 * nvars Montgomery elements, AoS (x_j, 1 - x_j)
   uint32_t* eq;               // SoL Montgomery output, may be null
   uint64_t eq_ld;
-  uint32_t* pack;             // pack_pairs * 32 words, may be null
+  uint32_t* pack;             // pack_len * 8 words, may be null
 };
 
 // eq table of a point passed by value (at most 20 variables)
@@ -87,7 +87,7 @@ struct RoundsProd {
 
 // The sumcheck rounds of one group, run by one workgroup.
 struct RoundsJob {
-  uint8_t st[32];             // transcript state after squeezing u and v
+  uint32_t st[8];             // transcript state (digest words) after squeezing u and v
   uint32_t n_prods;
   uint32_t n0;
   const uint32_t* eqU;        // SoL eq(u, .), length 2^n0
@@ -115,12 +115,17 @@ hipError_t launch_upload(void* dst, const void* src, uint64_t bytes, hipStream_t
 hipError_t launch_zero_words(uint32_t* p, uint64_t n_words, hipStream_t s);
 
 // contraction kernel variants (index = kind)
+// (entry type, digits x digit bits, orientation, outputs per lane)
 enum ContractKind {
-  CK_I16_ROWS = 0, CK_I16_COLS = 1, CK_I16_COLS_VEC = 2,
-  CK_I32_ROWS = 3, CK_I32_COLS = 4, CK_I32_COLS_VEC = 5,
-  CK_I64N3_ROWS = 6, CK_I64N3_COLS = 7, CK_I64N3_COLS_VEC = 8,
-  CK_I64N4_ROWS = 9, CK_I64N4_COLS = 10, CK_I64N4_COLS_VEC = 11,
-  CK_COUNT = 12
+  CK_I16_ROWS = 0,       // int16, 1 x 16, rows, 1
+  CK_I16_ROWS4 = 1,      // int16, 1 x 16, rows, 4 (element loads)
+  CK_I16_ROWS4_VEC = 2,  // int16, 1 x 16, rows, 4 (8-byte loads)
+  CK_I16_COLS = 3,       // int16, cols, element loads
+  CK_I16_COLS_VEC = 4,   // int16, cols, 16-byte row loads
+  CK_I32_ROWS = 5, CK_I32_COLS = 6, CK_I32_COLS_VEC = 7,        // int32, 2 x 24
+  CK_I64S_ROWS = 8, CK_I64S_COLS = 9, CK_I64S_COLS_VEC = 10,    // int64 with |x| < 2^47, 2 x 24
+  CK_I64_ROWS = 11, CK_I64_COLS = 12, CK_I64_COLS_VEC = 13,     // int64, 3 x 24
+  CK_COUNT = 14
 };
 
 }  // namespace vl

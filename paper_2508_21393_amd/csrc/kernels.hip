@@ -31,6 +31,22 @@ namespace vl {
 
 typedef short v2i16 __attribute__((ext_vector_type(2)));
 typedef const __attribute__((address_space(4))) uint32_t* cu32_ptr;
+typedef const __attribute__((address_space(4))) int32_t* ci32_ptr;
+
+// e (canonical, < p < 2^255) as 8 signed 32-bit digits, e = sum_j d_j 2^(32 j),
+// d_j in [-2^31, 2^31); the top limb of p is below 2^31 - 1, so d_7 never
+// carries into a ninth digit
+__device__ __forceinline__ void signed_digits(const Fr& e, uint32_t* out) {
+  uint32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const uint32_t v = e.w[j] + c;        // e.w[j] + c <= 2^32 - 1 + 1: v == 0 means wrap
+    const bool wrap = c && v == 0;
+    const bool up = j < 7 && (wrap || v >= 0x80000000u);
+    out[j] = v;                           // as int32: v - 2^32 when up
+    c = up ? 1u : 0u;
+  }
+}
 
 __device__ __forceinline__ int32_t sdot2(uint32_t e, uint32_t x, int32_t acc) {
   return __builtin_amdgcn_sdot2(__builtin_bit_cast(v2i16, e), __builtin_bit_cast(v2i16, x), acc,
@@ -90,16 +106,10 @@ __global__ void __launch_bounds__(256) eq_kernel(const EqJob* __restrict__ jobs,
     if (2ull * t < len) store_sol(J.eq, J.eq_ld, 2ull * t, e0);
     if (2ull * t + 1 < len) store_sol(J.eq, J.eq_ld, 2ull * t + 1, e1);
   }
-  if (J.pack && t < J.pack_pairs) {
-    const Fr p0 = fr_to_mont(e0);   // e * R^2 mod p
-    const Fr p1 = fr_to_mont(e1);
-    uint32_t* out = J.pack + (uint64_t)t * 32;
-#pragma unroll
-    for (int k = 0; k < 32; ++k) {
-      const uint32_t b0 = (p0.w[k >> 2] >> (8 * (k & 3))) & 0xffu;
-      const uint32_t b1 = (p1.w[k >> 2] >> (8 * (k & 3))) & 0xffu;
-      out[k] = b0 | (b1 << 16);
-    }
+  if (J.pack) {
+    // pack: e * R^2 mod p as signed digits, 8 words per entry
+    if (2 * t < J.pack_len) signed_digits(fr_to_mont(e0), J.pack + (uint64_t)(2 * t) * 8);
+    if (2 * t + 1 < J.pack_len) signed_digits(fr_to_mont(e1), J.pack + (uint64_t)(2 * t + 1) * 8);
   }
 }
 
@@ -138,86 +148,91 @@ __global__ void __launch_bounds__(256) eq_point_kernel(EqPointArgs a) {
 // pack form of a caller-provided eq vector (vl_mle_partial_eval)
 __global__ void __launch_bounds__(256) pack_kernel(const uint32_t* __restrict__ eq, uint64_t ld,
                                                    uint64_t len, uint32_t* __restrict__ pack) {
-  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (2 * t >= len) return;
-  const Fr p0 = fr_to_mont(load_sol(eq, ld, 2 * t));
-  const Fr p1 = (2 * t + 1 < len) ? fr_to_mont(load_sol(eq, ld, 2 * t + 1)) : fr_zero();
-  uint32_t* out = pack + t * 32;
-#pragma unroll
-  for (int k = 0; k < 32; ++k) {
-    const uint32_t b0 = (p0.w[k >> 2] >> (8 * (k & 3))) & 0xffu;
-    const uint32_t b1 = (p1.w[k >> 2] >> (8 * (k & 3))) & 0xffu;
-    out[k] = b0 | (b1 << 16);
-  }
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  signed_digits(fr_to_mont(load_sol(eq, ld, i)), pack + i * 8);
 }
 
 // ---------------------------------------------------------------- contract --
-constexpr int q_count(int nd) { return (8 * 31 + 16 * (nd - 1)) / 32 + 1; }
-
-// signed 16-bit digits of a pair of entries, packed per digit as (x0 | x1 << 16)
-template <int ND, typename T>
-__device__ __forceinline__ void pair_digits(T x0, T x1, uint32_t (&w)[ND], uint32_t& bad) {
-  if constexpr (ND == 1) {
-    w[0] = (uint32_t)(uint16_t)x0 | ((uint32_t)(uint16_t)x1 << 16);
+// Signed digits of an entry for v_mad_i64_i32: x = sum_t d_t 2^(DB t) with
+// d_t in [-2^(DB-1), 2^(DB-1)).  int16 entries are their own single digit.
+template <typename T, int ND, int DB>
+__device__ __forceinline__ void entry_digits(T x, int32_t (&d)[ND], uint32_t& bad) {
+  if constexpr (ND == 1 && sizeof(T) == 2) {
+    d[0] = (int32_t)x;
   } else {
-    int64_t r0 = (int64_t)x0, r1 = (int64_t)x1;
+    int64_t r = (int64_t)x;
 #pragma unroll
     for (int t = 0; t < ND; ++t) {
-      const uint32_t d0 = (uint32_t)r0 & 0xffffu, d1 = (uint32_t)r1 & 0xffffu;
-      w[t] = d0 | (d1 << 16);
-      // r <- (r - sext16(d)) / 2^16 without overflow
-      r0 = (r0 >> 16) + ((r0 >> 15) & 1);
-      r1 = (r1 >> 16) + ((r1 >> 15) & 1);
+      d[t] = (int32_t)((uint32_t)r << (32 - DB)) >> (32 - DB);
+      // r <- (r - d_t) / 2^DB, written so that it cannot overflow
+      r = (r >> DB) + ((r >> (DB - 1)) & 1);
     }
-    bad |= (uint32_t)((r0 | r1) != 0);
+    bad |= (uint32_t)(r != 0);
   }
 }
 
-template <int ND>
-__device__ __forceinline__ void dot_pair(cu32_ptr e, const uint32_t (&w)[ND],
-                                         int32_t (&acc)[ND][32]) {
+// acc[o][t][j] += e_j * d[o][t] for the 8 signed eq digits e_j (wave-uniform,
+// scalar registers); one v_mad_i64_i32 each
+template <int OPL, int ND>
+__device__ __forceinline__ void mac8(ci32_ptr e, const int32_t (&d)[OPL][ND],
+                                     int64_t (&acc)[OPL][ND][8]) {
 #pragma unroll
-  for (int k = 0; k < 32; ++k) {
-    const uint32_t ev = e[k];
+  for (int j = 0; j < 8; ++j) {
+    const int32_t ev = e[j];
 #pragma unroll
-    for (int t = 0; t < ND; ++t) acc[t][k] = sdot2(ev, w[t], acc[t][k]);
+    for (int o = 0; o < OPL; ++o)
+#pragma unroll
+      for (int t = 0; t < ND; ++t) acc[o][t][j] += (int64_t)ev * (int64_t)d[o][t];
   }
 }
 
-template <int ND, int QC>
-__device__ __forceinline__ void flush(int32_t (&acc)[ND][32], int64_t (&T)[QC]) {
+// wide digits (DB = 24): move the high words out before an int64 can overflow
+template <int OPL, int ND>
+__device__ __forceinline__ void spill_high(int64_t (&acc)[OPL][ND][8], int64_t (&hi)[OPL][ND][8]) {
+#pragma unroll
+  for (int o = 0; o < OPL; ++o)
+#pragma unroll
+    for (int t = 0; t < ND; ++t)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t h = acc[o][t][j] >> 32;
+        hi[o][t][j] += h;
+        acc[o][t][j] -= (int64_t)((uint64_t)h << 32);
+      }
+}
+
+// V = sum_{t,j} (acc + 2^32 hi) 2^(DB t + 32 j), congruent to R^2 * value
+// (the eq digits hold e * R^2 mod p).  With V = lo + 2^256 hi (lo unsigned
+// 256-bit, |hi| < 2^80): V * R^-1 = lo * R^-1 + hi (mod p), i.e. one
+// Montgomery multiplication by 1 plus a small signed lift.  (A direct
+// 12-limb REDC written with 64-bit adds lost a carry when compiled for gfx950
+// at -O3, so the reduction goes through the field multiplier.)
+template <int ND, int DB>
+__device__ __forceinline__ Fr finalize_digits(const int64_t (&acc)[ND][8], const int64_t (&hi)[ND][8]) {
+  int64_t S[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) S[q] = 0;
 #pragma unroll
   for (int t = 0; t < ND; ++t) {
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-      const int bit = 8 * k + 16 * t;
-      T[bit >> 5] += (int64_t)((uint64_t)(int64_t)acc[t][k] << (bit & 31));
-      acc[t][k] = 0;
+    for (int j = 0; j < 8; ++j) {
+      const int bit = DB * t;
+      const int b = j + bit / 32, sh = bit % 32;
+      const int64_t a = acc[t][j];
+      const int64_t H = (a >> 32) + hi[t][j];
+      const uint64_t lo = (uint64_t)(uint32_t)a << sh;
+      S[b] += (int64_t)(lo & 0xffffffffu);
+      S[b + 1] += (int64_t)(lo >> 32);
+      S[b + 1] += (int64_t)(uint32_t)((uint64_t)H << sh);
+      S[b + 2] += sh == 0 ? (H >> 32) : (H >> (32 - sh));
     }
   }
-  // keep all but the top limb sum in [0, 2^32)
-#pragma unroll
-  for (int q = 0; q + 1 < QC; ++q) {
-    const int64_t c = T[q] >> 32;
-    T[q] -= (int64_t)((uint64_t)c << 32);
-    T[q + 1] += c;
-  }
-}
-
-// The signed sum V = sum_q T[q] 2^(32q) (two's complement over 12 limbs) is
-// congruent to R^2 * value, so V * R^-1 mod p is the Montgomery form of the
-// value.  With V = lo + 2^256 * hi (lo unsigned 256-bit, |hi| < 2^80):
-//     V * R^-1 = lo * R^-1 + hi  (mod p),
-// one Montgomery multiplication of lo by 1 plus a small signed lift.  (A
-// direct 12-limb REDC was miscompiled for gfx950 at -O3 -- one carry was
-// lost -- so the reduction goes through the field multiplier instead.)
-template <int QC>
-__device__ __forceinline__ Fr finalize(const int64_t (&T)[QC]) {
   uint32_t L[12];
   int64_t carry = 0;
 #pragma unroll
   for (int q = 0; q < 12; ++q) {
-    const int64_t v = (q < QC ? T[q] : 0) + carry;
+    const int64_t v = S[q] + carry;
     L[q] = (uint32_t)v;
     carry = v >> 32;
   }
@@ -226,7 +241,6 @@ __device__ __forceinline__ Fr finalize(const int64_t (&T)[QC]) {
   for (int j = 0; j < 8; ++j) lo.w[j] = L[j];
   lo = fr_reduce_once(fr_reduce_once(lo));   // 2^256 < 3p
   const Fr part = fr_mul(lo, fr_one_raw());
-  // the signed top part as a field element (|hi| < 2^80)
   const bool neg = (L[11] >> 31) != 0;
   Fr h = fr_zero();
   if (!neg) {
@@ -245,101 +259,144 @@ __device__ __forceinline__ Fr finalize(const int64_t (&T)[QC]) {
   return fr_add(part, h);
 }
 
-template <typename T, int ND, bool ROWS, bool VEC>
+// One wave per task: OPL consecutive outputs per lane (rows kernel: columns
+// of the stored matrix; cols kernel: its rows), one chunk of the contraction
+// index.  DB = 16 (int16 entries): products < 2^46, so int64 accumulators
+// hold 2^16 entries (chunks never exceed that).  DB = 24: products < 2^54,
+// high words are moved out every 256 entries.
+template <typename T, int ND, int DB, bool ROWS, bool VEC, int OPL>
 __global__ void __launch_bounds__(kContractBlock)
 contract_kernel(const ContractJob* __restrict__ jobs, uint32_t n_jobs, uint32_t n_tasks) {
-  constexpr int QC = q_count(ND);
+  constexpr bool WIDE = DB > 16;
+  constexpr uint32_t kSpill = 256;
   const uint32_t task = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (task >= n_tasks) return;
-  uint32_t lo = 0, hi = n_jobs;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (jobs[mid].task_begin <= task) lo = mid; else hi = mid;
+  uint32_t lo = 0, hi_i = n_jobs;
+  while (hi_i - lo > 1) {
+    const uint32_t mid = (lo + hi_i) >> 1;
+    if (jobs[mid].task_begin <= task) lo = mid; else hi_i = mid;
   }
   const ContractJob& J = jobs[lo];
   const uint32_t local = task - J.task_begin;
   const uint32_t chunk = local % J.n_chunks;
   const uint32_t owave = local / J.n_chunks;
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t n = owave * 64u + lane;
-  const bool valid = n < J.n_out;
+  const uint32_t n0 = (owave * 64u + lane) * OPL;
   const uint32_t m0 = chunk * J.chunk;
   const uint32_t m1 = min(m0 + J.chunk, J.len);
   const T* __restrict__ M = (const T*)J.M;
   const uint64_t ld = J.ld;
-  cu32_ptr pack = (cu32_ptr)J.pack;
+  const uint32_t n_out = J.n_out;
+  cu32_ptr pk32 = (cu32_ptr)J.pack;
+  ci32_ptr pack = (ci32_ptr)pk32;
 
-  int32_t acc[ND][32];
+  int64_t acc[OPL][ND][8];
+  int64_t hi[OPL][ND][8];
 #pragma unroll
-  for (int t = 0; t < ND; ++t)
+  for (int o = 0; o < OPL; ++o)
 #pragma unroll
-    for (int k = 0; k < 32; ++k) acc[t][k] = 0;
-  int64_t Tq[QC];
+    for (int t = 0; t < ND; ++t)
 #pragma unroll
-  for (int q = 0; q < QC; ++q) Tq[q] = 0;
+      for (int j = 0; j < 8; ++j) acc[o][t][j] = hi[o][t][j] = 0;
   uint32_t bad = 0;
 
-  auto elem = [&](uint32_t m) -> T {
-    return ROWS ? M[(uint64_t)m * ld + n] : M[(uint64_t)n * ld + m];
-  };
-
   uint32_t m = m0;
-  if constexpr (VEC) {
-    // cols layout, 16-byte aligned rows: 64 bytes of the lane's row per step
-    constexpr uint32_t BE = 64 / sizeof(T);
-    const T* row = M + (uint64_t)(valid ? n : 0u) * ld;
+  if constexpr (VEC && !ROWS) {
+    // cols layout, 16-byte aligned rows: each lane streams its own row 16
+    // bytes at a time, the next 16 bytes in flight while these are used
+    static_assert(OPL == 1, "vector cols kernel has one row per lane");
+    constexpr uint32_t BE = 16 / sizeof(T);
+    const bool valid = n0 < n_out;
+    const uint4* row = (const uint4*)(M + (uint64_t)(valid ? n0 : 0u) * ld);
     const uint32_t mv = m0 + ((m1 - m0) / BE) * BE;
-    while (m < mv) {
-      const uint32_t bend = min(m + 2 * kFlushPairs, mv);
-      for (; m < bend; m += BE) {
-        uint4 buf[4];
-        if (valid) {
-          const uint4* src = (const uint4*)(row + m);
+    if (m < mv) {
+      uint4 cur = valid ? row[m / BE] : make_uint4(0, 0, 0, 0);
+      while (m < mv) {
+        const uint32_t bend = WIDE ? min(m + kSpill, mv) : mv;
+        for (; m < bend; m += BE) {
+          uint4 nxt = make_uint4(0, 0, 0, 0);
+          if (valid && m + BE < mv) nxt = row[m / BE + 1];
+          const T* x = (const T*)&cur;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) buf[i] = src[i];
+          for (uint32_t q = 0; q < BE; ++q) {
+            int32_t d[1][ND];
+            entry_digits<T, ND, DB>(x[q], d[0], bad);
+            mac8<1, ND>(pack + (uint64_t)(m + q) * 8, d, acc);
+          }
+          cur = nxt;
+        }
+        if constexpr (WIDE) spill_high<OPL, ND>(acc, hi);
+      }
+    }
+  }
+  if constexpr (VEC && ROWS) {
+    // rows layout, four int16 columns per lane read as one 8-byte load;
+    // batches of four rows, the next batch in flight while this one is used
+    static_assert(OPL == 4 && sizeof(T) == 2 && !WIDE, "vector rows kernel: int16, 4 columns");
+    constexpr uint32_t BR = 4;
+    const bool full = n0 + 3 < n_out;
+    auto load4 = [&](uint32_t mm) -> uint2 {
+      uint2 v = make_uint2(0, 0);
+      if (mm < m1) {
+        if (full) {
+          v = *(const uint2*)(M + (uint64_t)mm * ld + n0);
         } else {
+          uint16_t e[4] = {0, 0, 0, 0};
 #pragma unroll
-          for (int i = 0; i < 4; ++i) buf[i] = make_uint4(0, 0, 0, 0);
-        }
-        const T* x = (const T*)buf;
-#pragma unroll
-        for (uint32_t q = 0; q < BE / 2; ++q) {
-          uint32_t w[ND];
-          pair_digits<ND, T>(x[2 * q], x[2 * q + 1], w, bad);
-          dot_pair<ND>(pack + ((m >> 1) + q) * 32, w, acc);
+          for (int o = 0; o < 4; ++o)
+            if (n0 + o < n_out) e[o] = (uint16_t)M[(uint64_t)mm * ld + n0 + o];
+          v = make_uint2(e[0] | ((uint32_t)e[1] << 16), e[2] | ((uint32_t)e[3] << 16));
         }
       }
-      flush<ND, QC>(acc, Tq);
-    }
-  }
-  {
-    const uint32_t m1e = m + ((m1 - m) & ~1u);
-    while (m < m1e) {
-      const uint32_t bend = min(m + 2 * kFlushPairs, m1e);
-#pragma unroll 2
-      for (; m < bend; m += 2) {
-        T x0 = 0, x1 = 0;
-        if (valid) {
-          x0 = elem(m);
-          x1 = elem(m + 1);
+      return v;
+    };
+    uint2 cur[BR];
+#pragma unroll
+    for (uint32_t r = 0; r < BR; ++r) cur[r] = load4(m + r);
+    for (; m < m1; m += BR) {
+      uint2 nxt[BR];
+#pragma unroll
+      for (uint32_t r = 0; r < BR; ++r) nxt[r] = load4(m + BR + r);
+#pragma unroll
+      for (uint32_t r = 0; r < BR; ++r) {
+        if (m + r < m1) {
+          int32_t d[OPL][ND];
+          d[0][0] = (int32_t)(int16_t)(cur[r].x & 0xffffu);
+          d[1][0] = (int32_t)(int16_t)(cur[r].x >> 16);
+          d[2][0] = (int32_t)(int16_t)(cur[r].y & 0xffffu);
+          d[3][0] = (int32_t)(int16_t)(cur[r].y >> 16);
+          mac8<OPL, ND>(pack + (uint64_t)(m + r) * 8, d, acc);
         }
-        uint32_t w[ND];
-        pair_digits<ND, T>(x0, x1, w, bad);
-        dot_pair<ND>(pack + (m >> 1) * 32, w, acc);
       }
-      flush<ND, QC>(acc, Tq);
-    }
-    if (m < m1) {  // odd contraction length: last entry pairs with zero
-      T x0 = valid ? elem(m) : (T)0;
-      uint32_t w[ND];
-      pair_digits<ND, T>(x0, (T)0, w, bad);
-      dot_pair<ND>(pack + (m >> 1) * 32, w, acc);
-      flush<ND, QC>(acc, Tq);
+#pragma unroll
+      for (uint32_t r = 0; r < BR; ++r) cur[r] = nxt[r];
     }
   }
-  if (ND > 1 && valid && bad && J.err) atomicOr(J.err, 1);
-  const Fr r = finalize<QC>(Tq);
-  if (valid) store_sol(J.dst + (uint64_t)chunk * J.chunk_stride, J.dst_ld, n, r);
+  while (m < m1) {
+    const uint32_t bend = WIDE ? min(m + kSpill, m1) : m1;
+#pragma unroll 4
+    for (; m < bend; ++m) {
+      int32_t d[OPL][ND];
+#pragma unroll
+      for (int o = 0; o < OPL; ++o) {
+        const uint32_t n = n0 + o;
+        T x = 0;
+        if (n < n_out) x = ROWS ? M[(uint64_t)m * ld + n] : M[(uint64_t)n * ld + m];
+        entry_digits<T, ND, DB>(x, d[o], bad);
+      }
+      mac8<OPL, ND>(pack + (uint64_t)m * 8, d, acc);
+    }
+    if constexpr (WIDE) spill_high<OPL, ND>(acc, hi);
+  }
+  if constexpr (ND > 1 || sizeof(T) > 2) {
+    if (bad && J.err) atomicOr(J.err, 1);
+  }
+#pragma unroll
+  for (int o = 0; o < OPL; ++o) {
+    const Fr r = finalize_digits<ND, DB>(acc[o], hi[o]);
+    const uint32_t n = n0 + o;
+    if (n < n_out) store_sol(J.dst + (uint64_t)chunk * J.chunk_stride, J.dst_ld, n, r);
+  }
 }
 
 // ---------------------------------------------------------------- finish ----
@@ -408,10 +465,30 @@ __device__ __forceinline__ void put_fr(uint8_t* dst, const Fr& mont) {
   for (int i = 0; i < 32; ++i) dst[i] = b[i];
 }
 
+__device__ __forceinline__ void lds_put(uint32_t* dst, const Fr& v) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) dst[j] = v.w[j];
+}
+__device__ __forceinline__ Fr lds_get(const uint32_t* src) {
+  Fr v;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v.w[j] = src[j];
+  return v;
+}
+
+// (2 b - a) for the evaluation at X = 2 of the line through (0, a), (1, b)
+__device__ __forceinline__ Fr at_two(const Fr& a, const Fr& b) { return fr_sub(fr_double(b), a); }
+
+// One workgroup per group.  Round 1 of every product is computed in a first
+// pass (its g(0) + g(1) is the product's sum, so the prover guard needs no
+// extra pass); later rounds compute g(0) and g(2) and take g(1) = claim - g(0),
+// the claim moving to g(r) by interpolation on {0, 1, 2}.  All of it leaves
+// the proof bytes unchanged.
 __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* __restrict__ jobs) {
   const RoundsJob& J = jobs[blockIdx.x];
   __shared__ uint32_t red[3 * 8 * (kRoundsBlock / kWave)];
-  __shared__ uint32_t bcast[8];
+  __shared__ uint32_t first[VL_MAX_PRODS][3][8];   // round-1 values per product
+  __shared__ uint32_t bcast[2][8];                 // r and the next claim
   const uint32_t tid = threadIdx.x, NT = blockDim.x;
 
   if (J.err && *(volatile const int32_t*)J.err) {
@@ -426,58 +503,83 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
     v1[0] = fr_add(v1[0], fr_mul(load_sol(J.eqU, J.eqU_ld, i), load_sol(J.t, J.t_ld, i)));
   block_sum<1>(v1, red);
   const Fr c = v1[0];
-  // s_p = sum_w a_p[w] b_p[w]; the products must sum to c
-  Fr s[VL_MAX_PRODS];
+
+  // round 1 of every product; its g(0) + g(1) = sum_w a_p[w] b_p[w]
   Fr total = fr_zero();
   for (uint32_t p = 0; p < J.n_prods; ++p) {
     const RoundsProd& P = J.prods[p];
-    v1[0] = fr_zero();
-    const uint32_t len1 = 1u << P.n1;
-    for (uint32_t k = tid; k < len1; k += NT)
-      v1[0] = fr_add(v1[0], fr_mul(load_sol(P.a, P.ld, k), load_sol(P.b, P.ld, k)));
-    block_sum<1>(v1, red);
-    s[p] = v1[0];
-    total = fr_add(total, s[p]);
+    Fr g[3];
+    g[0] = g[1] = g[2] = fr_zero();
+    if (P.n1 == 0) {
+      if (tid == 0) g[0] = fr_mul(load_sol(P.a, P.ld, 0), load_sol(P.b, P.ld, 0));
+    } else {
+      const uint32_t h = 1u << (P.n1 - 1);
+      for (uint32_t t = tid; t < h; t += NT) {
+        const Fr a0 = load_sol(P.a, P.ld, t), a1 = load_sol(P.a, P.ld, t + h);
+        const Fr b0 = load_sol(P.b, P.ld, t), b1 = load_sol(P.b, P.ld, t + h);
+        g[0] = fr_add(g[0], fr_mul(a0, b0));
+        g[1] = fr_add(g[1], fr_mul(a1, b1));
+        g[2] = fr_add(g[2], fr_mul(at_two(a0, a1), at_two(b0, b1)));
+      }
+    }
+    block_sum<3>(g, red);
+    if (tid == 0)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) lds_put(first[p][k], g[k]);
+    total = fr_add(total, fr_add(g[0], g[1]));
   }
   if (!fr_eq(total, c)) {
     if (tid == 0) *J.status = VL_ERR_FALSE_STATEMENT;
     return;
   }
+  __syncthreads();
 
   Transcript tr;
   uint8_t* out = J.proof;
   if (tid == 0) {
 #pragma unroll
-    for (int i = 0; i < 32; ++i) tr.st[i] = J.st[i];
+    for (int i = 0; i < 8; ++i) tr.h[i] = J.st[i];
     const Fr cc[1] = {fr_from_mont(c)};
     put_fr(out, c);
     out += 32;
     tr_absorb_frs(tr, VL_LBL_CLAIM, cc);
     for (uint32_t p = 0; p + 1 < J.n_prods; ++p) {
-      const Fr sc[1] = {fr_from_mont(s[p])};
-      put_fr(out, s[p]);
+      const Fr sp = fr_add(lds_get(first[p][0]), lds_get(first[p][1]));
+      const Fr sc[1] = {fr_from_mont(sp)};
+      put_fr(out, sp);
       out += 32;
       tr_absorb_frs(tr, VL_LBL_PART, sc);
     }
   }
+  const Fr one = fr_R(), two = fr_double(fr_R());
+  const Fr inv2 = fr_from_limbs(0xffffffffu, 0x00000000u, 0x0001a401u, 0xac425bfdu, 0xf65e27fau,
+                                0xccc627f7u, 0xd66282b7u, 0x0c1258acu);  // 2^-1 R mod p
   for (uint32_t p = 0; p < J.n_prods; ++p) {
     const RoundsProd& P = J.prods[p];
     uint32_t* a = P.a;
     uint32_t* b = P.b;
     const uint64_t ld = P.ld;
+    Fr claim = fr_add(lds_get(first[p][0]), lds_get(first[p][1]));
     for (uint32_t rd = 0; rd < P.n1; ++rd) {
       const uint32_t h = 1u << (P.n1 - 1 - rd);
       Fr g[3];
-      g[0] = g[1] = g[2] = fr_zero();
-      for (uint32_t t = tid; t < h; t += NT) {
-        const Fr a0 = load_sol(a, ld, t), a1 = load_sol(a, ld, t + h);
-        const Fr b0 = load_sol(b, ld, t), b1 = load_sol(b, ld, t + h);
-        g[0] = fr_add(g[0], fr_mul(a0, b0));
-        g[1] = fr_add(g[1], fr_mul(a1, b1));
-        const Fr da = fr_sub(fr_double(a1), a0), db = fr_sub(fr_double(b1), b0);
-        g[2] = fr_add(g[2], fr_mul(da, db));
+      if (rd == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g[k] = lds_get(first[p][k]);
+      } else {
+        Fr q[2];
+        q[0] = q[1] = fr_zero();
+        for (uint32_t t = tid; t < h; t += NT) {
+          const Fr a0 = load_sol(a, ld, t), a1 = load_sol(a, ld, t + h);
+          const Fr b0 = load_sol(b, ld, t), b1 = load_sol(b, ld, t + h);
+          q[0] = fr_add(q[0], fr_mul(a0, b0));
+          q[1] = fr_add(q[1], fr_mul(at_two(a0, a1), at_two(b0, b1)));
+        }
+        block_sum<2>(q, red);
+        g[0] = q[0];
+        g[1] = fr_sub(claim, q[0]);
+        g[2] = q[1];
       }
-      block_sum<3>(g, red);
       if (tid == 0) {
         Fr gc[3];
         for (int k = 0; k < 3; ++k) {
@@ -487,12 +589,18 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
         }
         tr_absorb_frs(tr, VL_LBL_ROUND, gc);
         const Fr r = fr_to_mont(tr_squeeze_fixed(tr, VL_LBL_R));
-        for (int j = 0; j < 8; ++j) bcast[j] = r.w[j];
+        // g(r) = g0 (r-1)(r-2)/2 - g1 r (r-2) + g2 r (r-1)/2
+        const Fr rm1 = fr_sub(r, one), rm2 = fr_sub(r, two);
+        const Fr l0 = fr_mul(fr_mul(rm1, rm2), inv2);
+        const Fr l1 = fr_neg(fr_mul(r, rm2));
+        const Fr l2 = fr_mul(fr_mul(r, rm1), inv2);
+        const Fr next = fr_add(fr_add(fr_mul(g[0], l0), fr_mul(g[1], l1)), fr_mul(g[2], l2));
+        lds_put(bcast[0], r);
+        lds_put(bcast[1], next);
       }
       __syncthreads();
-      Fr r;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) r.w[j] = bcast[j];
+      const Fr r = lds_get(bcast[0]);
+      claim = lds_get(bcast[1]);
       for (uint32_t t = tid; t < h; t += NT) {
         const Fr a0 = load_sol(a, ld, t), a1 = load_sol(a, ld, t + h);
         const Fr b0 = load_sol(b, ld, t), b1 = load_sol(b, ld, t + h);
@@ -517,8 +625,11 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
     __syncthreads();
   }
   if (tid == 0) {
-    if (J.digest)
-      for (int i = 0; i < 32; ++i) J.digest[i] = tr.st[i];
+    if (J.digest) {
+      uint8_t d[32];
+      tr_to_bytes(tr, d);
+      for (int i = 0; i < 32; ++i) J.digest[i] = d[i];
+    }
     *J.status = VL_OK;
   }
 }
@@ -580,16 +691,15 @@ hipError_t launch_eq_point(const EqPointArgs& a, hipStream_t s) {
 
 hipError_t launch_pack(const uint32_t* eq, uint64_t ld, uint64_t len, uint32_t* pack,
                        hipStream_t s) {
-  const uint64_t pairs = (len + 1) / 2;
-  if (pairs == 0) return hipSuccess;
-  hipLaunchKernelGGL(pack_kernel, dim3(blocks_for(pairs, 256)), dim3(256), 0, s, eq, ld, len, pack);
+  if (len == 0) return hipSuccess;
+  hipLaunchKernelGGL(pack_kernel, dim3(blocks_for(len, 256)), dim3(256), 0, s, eq, ld, len, pack);
   return hipGetLastError();
 }
 
-template <typename T, int ND, bool ROWS, bool VEC>
+template <typename T, int ND, int DB, bool ROWS, bool VEC, int OPL>
 static hipError_t launch_contract_t(const ContractJob* jobs, uint32_t n_jobs, uint32_t n_tasks,
                                     hipStream_t s) {
-  hipLaunchKernelGGL((contract_kernel<T, ND, ROWS, VEC>), dim3(blocks_for(n_tasks, 4)),
+  hipLaunchKernelGGL((contract_kernel<T, ND, DB, ROWS, VEC, OPL>), dim3(blocks_for(n_tasks, 4)),
                      dim3(kContractBlock), 0, s, jobs, n_jobs, n_tasks);
   return hipGetLastError();
 }
@@ -597,23 +707,26 @@ static hipError_t launch_contract_t(const ContractJob* jobs, uint32_t n_jobs, ui
 hipError_t launch_contract(int kind, const ContractJob* jobs, uint32_t n_jobs, uint32_t n_tasks,
                            hipStream_t s) {
   if (n_tasks == 0) return hipSuccess;
+#define VL_CK(K, T, ND, DB, R, V, O) \
+  case K: return launch_contract_t<T, ND, DB, R, V, O>(jobs, n_jobs, n_tasks, s);
   switch (kind) {
-    case CK_I16_ROWS: return launch_contract_t<int16_t, 1, true, false>(jobs, n_jobs, n_tasks, s);
-    case CK_I16_COLS: return launch_contract_t<int16_t, 1, false, false>(jobs, n_jobs, n_tasks, s);
-    case CK_I16_COLS_VEC: return launch_contract_t<int16_t, 1, false, true>(jobs, n_jobs, n_tasks, s);
-    case CK_I32_ROWS: return launch_contract_t<int32_t, 3, true, false>(jobs, n_jobs, n_tasks, s);
-    case CK_I32_COLS: return launch_contract_t<int32_t, 3, false, false>(jobs, n_jobs, n_tasks, s);
-    case CK_I32_COLS_VEC: return launch_contract_t<int32_t, 3, false, true>(jobs, n_jobs, n_tasks, s);
-    case CK_I64N3_ROWS: return launch_contract_t<int64_t, 3, true, false>(jobs, n_jobs, n_tasks, s);
-    case CK_I64N3_COLS: return launch_contract_t<int64_t, 3, false, false>(jobs, n_jobs, n_tasks, s);
-    case CK_I64N3_COLS_VEC:
-      return launch_contract_t<int64_t, 3, false, true>(jobs, n_jobs, n_tasks, s);
-    case CK_I64N4_ROWS: return launch_contract_t<int64_t, 4, true, false>(jobs, n_jobs, n_tasks, s);
-    case CK_I64N4_COLS: return launch_contract_t<int64_t, 4, false, false>(jobs, n_jobs, n_tasks, s);
-    case CK_I64N4_COLS_VEC:
-      return launch_contract_t<int64_t, 4, false, true>(jobs, n_jobs, n_tasks, s);
+    VL_CK(CK_I16_ROWS, int16_t, 1, 16, true, false, 1)
+    VL_CK(CK_I16_ROWS4, int16_t, 1, 16, true, false, 4)
+    VL_CK(CK_I16_ROWS4_VEC, int16_t, 1, 16, true, true, 4)
+    VL_CK(CK_I16_COLS, int16_t, 1, 16, false, false, 1)
+    VL_CK(CK_I16_COLS_VEC, int16_t, 1, 16, false, true, 1)
+    VL_CK(CK_I32_ROWS, int32_t, 2, 24, true, false, 1)
+    VL_CK(CK_I32_COLS, int32_t, 2, 24, false, false, 1)
+    VL_CK(CK_I32_COLS_VEC, int32_t, 2, 24, false, true, 1)
+    VL_CK(CK_I64S_ROWS, int64_t, 2, 24, true, false, 1)
+    VL_CK(CK_I64S_COLS, int64_t, 2, 24, false, false, 1)
+    VL_CK(CK_I64S_COLS_VEC, int64_t, 2, 24, false, true, 1)
+    VL_CK(CK_I64_ROWS, int64_t, 3, 24, true, false, 1)
+    VL_CK(CK_I64_COLS, int64_t, 3, 24, false, false, 1)
+    VL_CK(CK_I64_COLS_VEC, int64_t, 3, 24, false, true, 1)
     default: return hipErrorInvalidValue;
   }
+#undef VL_CK
 }
 
 hipError_t launch_finish(const FinishJob* jobs, uint32_t n_jobs, uint32_t n_threads, hipStream_t s) {

@@ -1,7 +1,7 @@
 // VALU issue-rate microbenchmark (libvlpeak.so), used by bench.py to state
 // the ceiling of the integer contraction: per-lane throughput of
-// v_dot2c_i32_i16, v_mad_u64_u32, v_mul_lo_u32, v_mul_hi_u32 and v_add_u32
-// (full-rate reference), each as 8 independent dependency chains per lane so
+// v_dot2c_i32_i16, v_mad_u64_u32, v_mad_i64_i32, v_mul_lo_u32, v_mul_hi_u32
+// and v_add_u32, each as 8 independent dependency chains per lane so
 // that issue rate, not latency, is measured.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -28,6 +28,9 @@ __global__ void __launch_bounds__(256) rate_kernel(uint32_t* out, uint32_t iters
       } else if constexpr (OP == 1) {
         uint64_t sd;
         asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(acc64[c]), "=s"(sd) : "v"(a), "v"(b));
+      } else if constexpr (OP == 5) {
+        uint64_t sd;
+        asm volatile("v_mad_i64_i32 %0, %1, %2, %3, %0" : "+v"(acc64[c]), "=s"(sd) : "v"(a), "v"(b));
       } else if constexpr (OP == 2) {
         asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(acc[c]) : "v"(b));
       } else if constexpr (OP == 3) {
@@ -66,7 +69,8 @@ double run(uint32_t blocks, uint32_t iters) {
 
 }  // namespace
 
-// which: 0 dot2_i32_i16, 1 mad_u64_u32, 2 mul_lo_u32, 3 mul_hi_u32, 4 add_u32.
+// which: 0 dot2_i32_i16, 1 mad_u64_u32, 2 mul_lo_u32, 3 mul_hi_u32, 4 add_u32,
+// 5 mad_i64_i32.
 // Returns lane-operations per second, or a negative value on error.
 extern "C" double vlpeak_lane_ops_per_s(int which, uint32_t blocks, uint32_t iters) {
   switch (which) {
@@ -75,6 +79,7 @@ extern "C" double vlpeak_lane_ops_per_s(int which, uint32_t blocks, uint32_t ite
     case 2: return run<2>(blocks, iters);
     case 3: return run<3>(blocks, iters);
     case 4: return run<4>(blocks, iters);
+    case 5: return run<5>(blocks, iters);
     default: return -1.0;
   }
 }

@@ -21,9 +21,15 @@ uint64_t proof_elems(const vl_group& g);
 void group_challenges(const vl_group& g, uint64_t seed, Transcript& tr, std::vector<Fr>& u,
                       std::vector<Fr>& v);
 
+// a group's transcript after squeezing u (n0 values) and v (n2 values)
+struct Challenges {
+  Transcript tr;
+  std::vector<Fr> u, v;
+};
+
 struct Tuning {
   bool per_instance = false;
-  uint32_t chunk_target = 1024;   // contraction elements per task for one digit
+  uint32_t lane_macs = 16384;     // multiply-adds per lane and contraction task
   uint32_t min_tasks = 1;         // split a contraction until it has this many tasks
 };
 
@@ -39,7 +45,8 @@ struct Plan {
   std::vector<RoundsJob> rounds;
   std::vector<std::vector<uint32_t>> points;  // per eq job: (x_j, 1 - x_j) Montgomery
   uint32_t n_err = 0;
-  std::vector<uint64_t> proof_off;            // blocking mode: workspace offset of each proof
+  uint64_t out_off = 0;                       // blocking mode: gathered proofs|status|digests
+  uint64_t out_proof_bytes = 0;
 };
 
 struct BlobLayout {
@@ -63,8 +70,8 @@ struct Builder {
   X* dev(uint64_t o) const { return reinterpret_cast<X*>(base + o); }
   void contract(const void* M, int dtype, int nd, uint64_t ld, bool rows, uint32_t n_out, uint32_t len,
                 const uint32_t* pack, uint32_t* dst, uint64_t dst_ld, uint64_t n_total, int32_t* err);
-  void eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_pairs);
-  void group(const vl_group& g, uint64_t seed, uint8_t* proof_dev, int32_t* status_dev,
+  void eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_len);
+  void group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev, int32_t* status_dev,
              uint8_t* digest_dev, int32_t* err);
 };
 

@@ -18,7 +18,8 @@ namespace vl {
 
 VL_HD uint32_t rotr32(uint32_t x, int n) { return (x >> n) | (x << (32 - n)); }
 
-VL_HD void sha256_compress(uint32_t h[8], const uint8_t blk[64]) {
+// FIPS 180-4 compression of one block given as 16 big-endian message words
+VL_HD void sha256_compress_w(uint32_t h[8], const uint32_t (&win)[16]) {
   const uint32_t K[64] = {
       0x428a2f98u, 0x71374491u, 0xb5c0fbcfu, 0xe9b5dba5u, 0x3956c25bu, 0x59f111f1u, 0x923f82a4u,
       0xab1c5ed5u, 0xd807aa98u, 0x12835b01u, 0x243185beu, 0x550c7dc3u, 0x72be5d74u, 0x80deb1feu,
@@ -32,9 +33,7 @@ VL_HD void sha256_compress(uint32_t h[8], const uint8_t blk[64]) {
       0xc67178f2u};
   uint32_t w[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i)
-    w[i] = ((uint32_t)blk[4 * i] << 24) | ((uint32_t)blk[4 * i + 1] << 16) |
-           ((uint32_t)blk[4 * i + 2] << 8) | (uint32_t)blk[4 * i + 3];
+  for (int i = 0; i < 16; ++i) w[i] = win[i];
   uint32_t a = h[0], b = h[1], c = h[2], d = h[3], e = h[4], f = h[5], g = h[6], hh = h[7];
 #pragma unroll
   for (int i = 0; i < 64; ++i) {
@@ -57,6 +56,14 @@ VL_HD void sha256_compress(uint32_t h[8], const uint8_t blk[64]) {
     hh = g; g = f; f = e; e = d + t1; d = c; c = b; b = a; a = t1 + t2;
   }
   h[0] += a; h[1] += b; h[2] += c; h[3] += d; h[4] += e; h[5] += f; h[6] += g; h[7] += hh;
+}
+
+VL_HD void sha256_compress(uint32_t h[8], const uint8_t blk[64]) {
+  uint32_t w[16];
+  for (int i = 0; i < 16; ++i)
+    w[i] = ((uint32_t)blk[4 * i] << 24) | ((uint32_t)blk[4 * i + 1] << 16) |
+           ((uint32_t)blk[4 * i + 2] << 8) | (uint32_t)blk[4 * i + 3];
+  sha256_compress_w(h, w);
 }
 
 // Streaming hasher for short messages.
@@ -106,9 +113,26 @@ VL_HD void put_u32le(uint8_t* o, uint32_t v) {
   o[0] = (uint8_t)v; o[1] = (uint8_t)(v >> 8); o[2] = (uint8_t)(v >> 16); o[3] = (uint8_t)(v >> 24);
 }
 
+// The transcript state is the last digest, kept as its 8 big-endian words
+// (digest byte i is byte 3 - i % 4 of word i / 4).
 struct Transcript {
-  uint8_t st[32];
+  uint32_t h[8];
 };
+
+VL_HD void tr_to_bytes(const Transcript& t, uint8_t out[32]) {
+  for (int i = 0; i < 8; ++i) {
+    out[4 * i] = (uint8_t)(t.h[i] >> 24);
+    out[4 * i + 1] = (uint8_t)(t.h[i] >> 16);
+    out[4 * i + 2] = (uint8_t)(t.h[i] >> 8);
+    out[4 * i + 3] = (uint8_t)(t.h[i]);
+  }
+}
+
+VL_HD void tr_from_bytes(Transcript& t, const uint8_t in[32]) {
+  for (int i = 0; i < 8; ++i)
+    t.h[i] = ((uint32_t)in[4 * i] << 24) | ((uint32_t)in[4 * i + 1] << 16) |
+             ((uint32_t)in[4 * i + 2] << 8) | (uint32_t)in[4 * i + 3];
+}
 
 // labels used by the protocol (string literals, so their lengths are known
 // at compile time)
@@ -137,60 +161,56 @@ VL_HD void tr_init(Transcript& t, uint64_t seed, uint32_t group_id, uint32_t n_p
     put_u32le(b, dims[k]);
     sha256_update(s, b, 4);
   }
-  sha256_final(s, t.st);
+  uint8_t st[32];
+  sha256_final(s, st);
+  tr_from_bytes(t, st);
 }
 
-// One-shot SHA-256 of a message whose length N is a compile-time constant.
-// Padding is laid out at compile time and every index is constant, so on the
-// device the message and the blocks stay in registers.
-template <int N>
-VL_HD void sha256_fixed(const uint8_t (&m)[N], uint8_t out[32]) {
+// One-shot SHA-256 of an N-byte message, N a compile-time constant, whose
+// byte k is byte_at(k).  Every loop is unrolled, so k is a constant at each
+// call of byte_at and the message words are assembled in registers (no byte
+// arrays, hence no scratch memory on the device).
+template <int N, typename ByteAt>
+VL_HD void sha256_gen(uint32_t (&h)[8], ByteAt byte_at) {
   constexpr int NB = (N + 9 + 63) / 64;
-  uint32_t h[8] = {0x6a09e667u, 0xbb67ae85u, 0x3c6ef372u, 0xa54ff53au,
-                   0x510e527fu, 0x9b05688cu, 0x1f83d9abu, 0x5be0cd19u};
   constexpr uint64_t bits = (uint64_t)N * 8;
+  h[0] = 0x6a09e667u; h[1] = 0xbb67ae85u; h[2] = 0x3c6ef372u; h[3] = 0xa54ff53au;
+  h[4] = 0x510e527fu; h[5] = 0x9b05688cu; h[6] = 0x1f83d9abu; h[7] = 0x5be0cd19u;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    uint8_t blk[64];
+    uint32_t w[16];
 #pragma unroll
-    for (int i = 0; i < 64; ++i) {
-      const int k = b * 64 + i;
-      uint8_t v = 0;
-      if (k < N) v = m[k];
-      else if (k == N) v = 0x80;
-      else if (k >= NB * 64 - 8) v = (uint8_t)(bits >> (8 * (NB * 64 - 1 - k)));
-      blk[i] = v;
+    for (int i = 0; i < 16; ++i) {
+      uint32_t v = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = b * 64 + 4 * i + q;
+        uint32_t byte = 0;
+        if (k < N) byte = byte_at(k);
+        else if (k == N) byte = 0x80u;
+        else if (k >= NB * 64 - 8) byte = (uint32_t)(bits >> (8 * (NB * 64 - 1 - k))) & 0xffu;
+        v |= byte << (24 - 8 * q);
+      }
+      w[i] = v;
     }
-    sha256_compress(h, blk);
-  }
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    out[4 * i] = (uint8_t)(h[i] >> 24);
-    out[4 * i + 1] = (uint8_t)(h[i] >> 16);
-    out[4 * i + 2] = (uint8_t)(h[i] >> 8);
-    out[4 * i + 3] = (uint8_t)(h[i]);
+    sha256_compress_w(h, w);
   }
 }
+
+VL_HD uint32_t state_byte(const Transcript& t, int k) { return (t.h[k >> 2] >> (24 - 8 * (k & 3))) & 0xffu; }
+VL_HD uint32_t fr_byte(const Fr& x, int b) { return (x.w[b >> 2] >> (8 * (b & 3))) & 0xffu; }
 
 // absorb(label, x_0 .. x_{K-1}): st = H(st || label || enc(x_0) || ...), xs canonical
 template <int LN, int K>
 VL_HD void tr_absorb_frs(Transcript& t, const char (&label)[LN], const Fr (&xs)[K]) {
   constexpr int L = LN - 1;
-  uint8_t m[32 + L + 32 * K];
-#pragma unroll
-  for (int i = 0; i < 32; ++i) m[i] = t.st[i];
-#pragma unroll
-  for (int i = 0; i < L; ++i) m[32 + i] = (uint8_t)label[i];
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      m[32 + L + 32 * k + 4 * i] = (uint8_t)(xs[k].w[i]);
-      m[32 + L + 32 * k + 4 * i + 1] = (uint8_t)(xs[k].w[i] >> 8);
-      m[32 + L + 32 * k + 4 * i + 2] = (uint8_t)(xs[k].w[i] >> 16);
-      m[32 + L + 32 * k + 4 * i + 3] = (uint8_t)(xs[k].w[i] >> 24);
-    }
-  sha256_fixed(m, t.st);
+  const Transcript old = t;
+  sha256_gen<32 + L + 32 * K>(t.h, [&](int k) -> uint32_t {
+    if (k < 32) return state_byte(old, k);
+    if (k < 32 + L) return (uint8_t)label[k - 32];
+    const int e = (k - 32 - L) >> 5, b = (k - 32 - L) & 31;
+    return fr_byte(xs[e], b);
+  });
 }
 
 // squeeze(label): a canonical, uniformly distributed field element
@@ -198,19 +218,21 @@ template <int LN>
 VL_HD Fr tr_squeeze_fixed(Transcript& t, const char (&label)[LN]) {
   constexpr int L = LN - 1;
   for (uint32_t ctr = 0;; ++ctr) {
-    uint8_t m[32 + L + 4];
+    uint32_t h[8];
+    sha256_gen<32 + L + 4>(h, [&](int k) -> uint32_t {
+      if (k < 32) return state_byte(t, k);
+      if (k < 32 + L) return (uint8_t)label[k - 32];
+      return (ctr >> (8 * (k - 32 - L))) & 0xffu;
+    });
+    // the digest read as a little-endian integer: limb j is byte-swapped word j
+    Fr x;
 #pragma unroll
-    for (int i = 0; i < 32; ++i) m[i] = t.st[i];
-#pragma unroll
-    for (int i = 0; i < L; ++i) m[32 + i] = (uint8_t)label[i];
-    put_u32le(m + 32 + L, ctr);
-    uint8_t h[32];
-    sha256_fixed(m, h);
-    Fr x = fr_from_bytes(h);
+    for (int j = 0; j < 8; ++j)
+      x.w[j] = ((h[j] & 0xffu) << 24) | ((h[j] & 0xff00u) << 8) | ((h[j] >> 8) & 0xff00u) | (h[j] >> 24);
     x.w[7] &= 0x7fffffffu;
     if (fr_lt_p(x)) {
 #pragma unroll
-      for (int i = 0; i < 32; ++i) t.st[i] = h[i];
+      for (int i = 0; i < 8; ++i) t.h[i] = h[i];
       return x;
     }
   }

@@ -186,10 +186,12 @@ def test_async_prove_into_device_buffers(B):
         assert raw[offs[i]:offs[i + 1]].hex() == gold["proof_hex"]
 
 
-@pytest.mark.parametrize("cfg", ["cfg2", "cfg3"])
+@pytest.mark.parametrize("cfg", ["cfg2", "cfg3", "cfg4"])
 def test_full_size_config_matches_oracle(B, cfg):
     _say(f"{cfg}: generating")
-    w = workloads.make_config(cfg)
+    # the 7B block's witness products run as float64 GEMMs on the GPU (exact:
+    # all partial sums are integers below 2^53); the others on the host
+    w = workloads.make_config(cfg, **({"device": "cuda"} if cfg == "cfg4" else {}))
     gold = golden(cfg)
     _say(f"{cfg}: proving {len(w.groups)} groups")
     proofs, digests = _prove(B, w, 1)
