@@ -44,28 +44,32 @@ def algorithmic_macs(shapes_by_group):
     return total
 
 
-def int16_contraction_macs(groups):
+def int16_contraction_macs(groups, cols_rows=1):
     """Entries streamed by the int16 contraction kernels, by stage (kernel
     kind), following the library's planning rule: a row contraction with at
     least 256 outputs runs 4 columns per lane with 8-byte loads; the column
     kernels read 16-byte aligned rows with vector loads (all operands here are
-    aligned)."""
+    aligned), two rows per lane when tuned so and there are >= 128 rows."""
     from paper_2508_21393_amd import binding as B
-    k = {n: 0 for n in ("i16_rows", "i16_rows4_vec", "i16_cols_vec")}
+    k = {n: 0 for n in ("i16_rows", "i16_rows4_vec", "i16_cols_vec", "i16_cols2_vec")}
+
+    def cols(n_out):
+        return "i16_cols2_vec" if cols_rows == 2 and n_out >= 128 else "i16_cols_vec"
+
     for g in groups:
         for p in g.products:
             d0, d1, d2 = p.dims
             # A side: outputs are the D1 columns of op(A)
             if p.transA:
-                k["i16_cols_vec"] += d0 * d1
+                k[cols(d1)] += d0 * d1
             else:
                 k["i16_rows4_vec" if d1 >= 256 else "i16_rows"] += d0 * d1
             # B side: outputs are the D1 rows of op(B)
             if p.transB:
                 k["i16_rows4_vec" if d1 >= 256 else "i16_rows"] += d1 * d2
             else:
-                k["i16_cols_vec"] += d1 * d2
-    return {B.STAGE_NAMES.index(n): v for n, v in k.items()}
+                k[cols(d1)] += d1 * d2
+    return {B.STAGE_NAMES.index(n): v for n, v in k.items() if v}
 
 
 def cpu_baseline(workload, budget_s=15.0):
@@ -100,6 +104,29 @@ def peak_rates():
     return {n: L.vlpeak_lane_ops_per_s(i, 8192, 4096) for i, n in enumerate(names)}
 
 
+def autotune(B, gas, seed, mode, reps=3):
+    """Time each launch shape of a small grid (results are identical for
+    all of them) and return the fastest with the table of timings."""
+    import torch
+    grid = [(lm, sg, cr) for lm in (4096, 8192, 16384) for sg in (1, 2, 4) for cr in (1, 2)]
+    best, table = None, []
+    for lm, sg, cr in grid:
+        t = B.tuning(lane_macs=lm, segments=sg, cols_rows=cr)
+        ws = torch.empty(B.workspace_size(gas, mode, tuning_=t), dtype=torch.uint8, device="cuda")
+        B.sumcheck_matmul_prove(gas, seed, mode=mode, workspace=ws, tuning_=t)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            B.sumcheck_matmul_prove(gas, seed, mode=mode, workspace=ws, tuning_=t)
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        table.append({"lane_macs": lm, "segments": sg, "cols_rows": cr, "ms": round(ms, 3)})
+        print(json.dumps(table[-1]), file=sys.stderr, flush=True)
+        if best is None or ms < best[0]:
+            best = (ms, t)
+        del ws
+    return best[1], table
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +137,12 @@ def main():
     ap.add_argument("--per-instance-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-peak", action="store_true")
+    ap.add_argument("--lane-macs", type=int, default=0, help="vl_tuning.lane_macs (0: library default)")
+    ap.add_argument("--min-tasks", type=int, default=0, help="vl_tuning.min_tasks (0: library default)")
+    ap.add_argument("--segments", type=int, default=0, help="vl_tuning.segments (0: library default)")
+    ap.add_argument("--cols-rows", type=int, default=0, help="vl_tuning.cols_rows (0: library default)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time a grid of launch shapes first and bench the fastest")
     args = ap.parse_args()
     ws = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or ws != 1:
@@ -137,10 +170,14 @@ def main():
     shapes = [g.shapes for g in groups]
     macs = algorithmic_macs(shapes)
     n_products = sum(len(s) for s in shapes)
-    workspace = torch.empty(B.workspace_size(gas, mode), dtype=torch.uint8, device="cuda")
+    tun = B.tuning(args.lane_macs, args.min_tasks, args.segments, args.cols_rows)
+    tried = None
+    if args.autotune:
+        tun, tried = autotune(B, gas, w.seed, mode)
+    workspace = torch.empty(B.workspace_size(gas, mode, tuning_=tun), dtype=torch.uint8, device="cuda")
 
     def step(stage=None):
-        return B.sumcheck_matmul_prove(gas, w.seed, mode=mode, workspace=workspace, stage_ms=stage)
+        return B.sumcheck_matmul_prove(gas, w.seed, mode=mode, workspace=workspace, stage_ms=stage, tuning_=tun)
 
     for _ in range(args.warmup):
         ref, ref_dig = step()
@@ -177,7 +214,7 @@ def main():
         del ws_pi
 
     # dominant kernel: the int16 contraction kind with the most device time
-    k16 = int16_contraction_macs(groups)
+    k16 = int16_contraction_macs(groups, cols_rows=tun.cols_rows)
     dom = max(k16, key=lambda k: stage_avg[k])
     dom_ms = stage_avg[dom]
     achieved = k16[dom] / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0
@@ -206,7 +243,11 @@ def main():
         "roofline": roofline,
         "valu_lane_ops_per_s": rates,
         "witness_setup_s": t_gen,
+        "tuning": {"lane_macs": tun.lane_macs, "min_tasks": tun.min_tasks, "segments": tun.segments,
+                   "cols_rows": tun.cols_rows},
     }
+    if tried is not None:
+        out["autotune"] = tried
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -94,6 +94,20 @@ typedef struct {
 #define VL_MAX_PRODS 8
 #define VL_MAX_DIM (1u << 20)
 
+/* Launch-shape knobs, for autotuning.  A zero field takes the library's
+ * default.  No value changes any result: they only decide how the
+ * contractions are cut into wave tasks and how a batched call is pipelined. */
+typedef struct {
+  uint32_t lane_macs;      /* multiply-adds per lane and contraction task          */
+  uint32_t min_tasks;      /* halve a contraction's chunk until it has this many
+                              wave tasks (chunks stay >= 256 entries)               */
+  uint32_t segments;       /* batched mode: pipeline segments, 1..8; the rounds of
+                              one segment overlap the contractions of the next     */
+  uint32_t cols_rows;      /* rows per lane in the vector cols kernels (int16 and
+                              |x| < 2^47 int64): 1 or 2                            */
+  uint32_t reserved;       /* must be 0                                            */
+} vl_tuning;
+
 typedef struct {
   int32_t mode;            /* VL_MODE_*; every mode yields identical bytes            */
   int32_t async;           /* 0: proofs/digests are host buffers and the call returns
@@ -103,7 +117,7 @@ typedef struct {
   void* workspace;         /* device memory, >= vl_workspace_size() bytes             */
   uint64_t workspace_bytes;
   int32_t* status;         /* async only: device int32[n_groups], VL_OK / VL_ERR_*     */
-  const void* plan;        /* reserved, must be NULL                                  */
+  const vl_tuning* tuning; /* optional launch shape; NULL: defaults                    */
   float* stage_ms;         /* optional host float[VL_STAGE_COUNT] (blocking mode only):
                               device time of each stage, from HIP events recorded on
                               the call's stream around the stage's launches, summed over
@@ -113,15 +127,17 @@ typedef struct {
 /* stages of a prove call, in launch order */
 #define VL_STAGE_UPLOAD 0      /* job descriptors to device memory                 */
 #define VL_STAGE_EQ 1          /* eq tables and their byte-sliced "pack" form      */
-#define VL_STAGE_CONTRACT 2    /* + kind: integer contraction kernels, 14 kinds:
+#define VL_STAGE_CONTRACT 2    /* + kind: integer contraction kernels, 16 kinds:
                                   int16 rows (1 column per lane; 4 columns with
                                   element loads; 4 columns with 8-byte loads),
-                                  int16 cols (element loads; 16-byte row loads);
-                                  then rows, cols, cols-vec for int32, int64 with
-                                  |x| < 2^47, and int64                            */
-#define VL_STAGE_FINISH 16     /* split-contraction sums and zero padding          */
-#define VL_STAGE_ROUNDS 17     /* claim, prover guard, sumcheck rounds, proof bytes */
-#define VL_STAGE_COUNT 18
+                                  int16 cols (element loads; 16-byte row loads,
+                                  1 or 2 rows per lane); int32 rows, cols,
+                                  cols-vec; int64 with |x| < 2^47 rows, cols,
+                                  cols-vec (1 or 2 rows per lane); int64 rows,
+                                  cols, cols-vec                                   */
+#define VL_STAGE_FINISH 18     /* split-contraction sums and zero padding          */
+#define VL_STAGE_ROUNDS 19     /* claim, prover guard, sumcheck rounds, proof bytes */
+#define VL_STAGE_COUNT 20
 
 /* Lift n signed integers (dtype) at device pointer src into Fr (Montgomery,
  * structure-of-limbs) at dst (dst.n >= n).  Negative x becomes p - |x|. */
@@ -137,7 +153,8 @@ vl_status vl_fr_export(vl_fr_vec src, uint64_t n, uint32_t* dst, void* stream);
 vl_status vl_eq_table(const vl_fr* point, uint32_t nvars, vl_fr_vec out, void* stream);
 
 /* Workspace bytes needed by vl_mle_partial_eval for this shape. */
-uint64_t vl_partial_eval_workspace_size(uint32_t rows, uint32_t cols, int32_t contract, int32_t dtype);
+uint64_t vl_partial_eval_workspace_size(uint32_t rows, uint32_t cols, int32_t contract, int32_t dtype,
+                                        const vl_tuning* tuning);
 
 /* Partial evaluation of a matrix MLE (the A~(u, .) and B~(., v) of
  * eq. (zk-mle-matmul)).  M: device rows x cols integers (dtype), row-major,
@@ -145,10 +162,12 @@ uint64_t vl_partial_eval_workspace_size(uint32_t rows, uint32_t cols, int32_t co
  *   VL_CONTRACT_ROWS: out[c] = sum_r eq[r] M[r][c]   (needs eq.n >= rows)
  *   VL_CONTRACT_COLS: out[r] = sum_c M[r][c] eq[c]   (needs eq.n >= cols)
  * Entries of out beyond the result length (cols resp. rows) up to out.n are
- * set to zero, so out is the zero-padded table of a multilinear function. */
+ * set to zero, so out is the zero-padded table of a multilinear function.
+ * tuning: optional (NULL: defaults); the workspace size depends on it. */
 vl_status vl_mle_partial_eval(const void* M, int32_t dtype, uint32_t rows, uint32_t cols,
                               uint64_t ld, int32_t contract, vl_fr_vec eq, vl_fr_vec out,
-                              void* workspace, uint64_t workspace_bytes, void* stream);
+                              void* workspace, uint64_t workspace_bytes, const vl_tuning* tuning,
+                              void* stream);
 
 /* Bytes of one group's proof:
  * 32 * (1 + (n_prods - 1) + sum over products of (3 * n1 + 2)),

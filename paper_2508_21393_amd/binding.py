@@ -18,10 +18,10 @@ VL_I16, VL_I32, VL_I64 = 1, 2, 3
 VL_CONTRACT_ROWS, VL_CONTRACT_COLS = 0, 1
 VL_MODE_PER_INSTANCE, VL_MODE_BATCHED, VL_MODE_PERSISTENT = 0, 1, 2
 VL_MAX_PRODS = 8
-VL_STAGE_COUNT = 18
-STAGE_NAMES = ["upload", "eq", "i16_rows", "i16_rows4", "i16_rows4_vec", "i16_cols", "i16_cols_vec", "i32_rows",
-               "i32_cols", "i32_cols_vec", "i64s_rows", "i64s_cols", "i64s_cols_vec", "i64_rows",
-               "i64_cols", "i64_cols_vec", "finish", "rounds"]
+VL_STAGE_COUNT = 20
+STAGE_NAMES = ["upload", "eq", "i16_rows", "i16_rows4", "i16_rows4_vec", "i16_cols", "i16_cols_vec",
+               "i16_cols2_vec", "i32_rows", "i32_cols", "i32_cols_vec", "i64s_rows", "i64s_cols",
+               "i64s_cols_vec", "i64s_cols2_vec", "i64_rows", "i64_cols", "i64_cols_vec", "finish", "rounds"]
 
 STATUS_NAMES = {0: "VL_OK", 1: "VL_ERR_INVALID_ARG", 2: "VL_ERR_SHAPE", 3: "VL_ERR_DTYPE",
                 4: "VL_ERR_WORKSPACE", 5: "VL_ERR_HIP", 6: "VL_ERR_FALSE_STATEMENT",
@@ -53,9 +53,23 @@ class vl_group(ctypes.Structure):
                 ("C", c_vp), ("dtype_c", c_i32), ("ldc", c_u64)]
 
 
+class vl_tuning(ctypes.Structure):
+    _fields_ = [("lane_macs", c_u32), ("min_tasks", c_u32), ("segments", c_u32), ("cols_rows", c_u32),
+                ("reserved", c_u32)]
+
+
+def tuning(lane_macs: int = 0, min_tasks: int = 0, segments: int = 0, cols_rows: int = 0) -> vl_tuning:
+    """Launch-shape knobs (0 = library default); results never depend on them."""
+    return vl_tuning(lane_macs, min_tasks, segments, cols_rows, 0)
+
+
+def _tun(t):
+    return ctypes.pointer(t) if t is not None else None
+
+
 class vl_prove_opts(ctypes.Structure):
     _fields_ = [("mode", c_i32), ("async_", c_i32), ("workspace", c_vp), ("workspace_bytes", c_u64),
-                ("status", c_vp), ("plan", c_vp), ("stage_ms", c_vp)]
+                ("status", c_vp), ("tuning", ctypes.POINTER(vl_tuning)), ("stage_ms", c_vp)]
 
 
 class VLError(RuntimeError):
@@ -76,10 +90,10 @@ def lib():
         L.vl_fr_lift.argtypes = [c_vp, c_i32, c_u64, vl_fr_vec, c_vp]
         L.vl_fr_export.argtypes = [vl_fr_vec, c_u64, c_vp, c_vp]
         L.vl_eq_table.argtypes = [ctypes.POINTER(vl_fr), c_u32, vl_fr_vec, c_vp]
-        L.vl_partial_eval_workspace_size.argtypes = [c_u32, c_u32, c_i32, c_i32]
+        L.vl_partial_eval_workspace_size.argtypes = [c_u32, c_u32, c_i32, c_i32, ctypes.POINTER(vl_tuning)]
         L.vl_partial_eval_workspace_size.restype = c_u64
         L.vl_mle_partial_eval.argtypes = [c_vp, c_i32, c_u32, c_u32, c_u64, c_i32, vl_fr_vec, vl_fr_vec,
-                                          c_vp, c_u64, c_vp]
+                                          c_vp, c_u64, ctypes.POINTER(vl_tuning), c_vp]
         L.vl_proof_size.argtypes = [ctypes.POINTER(vl_group)]
         L.vl_proof_size.restype = c_u64
         L.vl_workspace_size.argtypes = [ctypes.POINTER(vl_group), c_u64, ctypes.POINTER(vl_prove_opts)]
@@ -200,41 +214,43 @@ def eq_table(point: Sequence[int], out: vl_fr_vec, stream=None):
     _check(lib().vl_eq_table(arr, len(point), out, _stream(stream)))
 
 
-def partial_eval_workspace_size(rows: int, cols: int, contract: int, dtype) -> int:
-    return lib().vl_partial_eval_workspace_size(rows, cols, contract, dtype_code(dtype))
+def partial_eval_workspace_size(rows: int, cols: int, contract: int, dtype, tuning_=None) -> int:
+    return lib().vl_partial_eval_workspace_size(rows, cols, contract, dtype_code(dtype), _tun(tuning_))
 
 
-def mle_partial_eval(M, contract: int, eq: vl_fr_vec, out: vl_fr_vec, workspace, stream=None):
+def mle_partial_eval(M, contract: int, eq: vl_fr_vec, out: vl_fr_vec, workspace, stream=None, tuning_=None):
     rows, cols = M.shape
     _check(lib().vl_mle_partial_eval(_ptr(M), dtype_code(M.dtype), rows, cols, _row_stride(M), contract,
                                      eq, out, _ptr(workspace), workspace.numel() * workspace.element_size(),
-                                     _stream(stream)))
+                                     _tun(tuning_), _stream(stream)))
 
 
 def proof_size(group: GroupArgs) -> int:
     return lib().vl_proof_size(ctypes.byref(group.struct))
 
 
-def workspace_size(groups: Sequence[GroupArgs], mode: int = VL_MODE_BATCHED, async_: bool = False) -> int:
+def workspace_size(groups: Sequence[GroupArgs], mode: int = VL_MODE_BATCHED, async_: bool = False,
+                   tuning_=None) -> int:
     arr = group_array(groups)
-    opts = vl_prove_opts(mode, int(async_), None, 0, None, None, None)
+    opts = vl_prove_opts(mode, int(async_), None, 0, None, _tun(tuning_), None)
     return lib().vl_workspace_size(arr, len(groups), ctypes.byref(opts))
 
 
 def sumcheck_matmul_prove(groups: Sequence[GroupArgs], seed: int, mode: int = VL_MODE_BATCHED,
-                          workspace=None, stream=None, with_digests: bool = True, stage_ms=None):
+                          workspace=None, stream=None, with_digests: bool = True, stage_ms=None,
+                          tuning_=None):
     """Blocking prove: returns (list of proof bytes, list of 32-byte digests).
 
     ``stage_ms``: optional list that receives VL_STAGE_COUNT per-stage device
-    times (HIP events) of this call."""
+    times (HIP events) of this call.  ``tuning_``: optional vl_tuning."""
     import torch
     arr = group_array(groups)
     n = len(groups)
-    ws_bytes = workspace_size(groups, mode)
+    ws_bytes = workspace_size(groups, mode, tuning_=tuning_)
     if workspace is None:
         workspace = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device="cuda")
     timing = (ctypes.c_float * VL_STAGE_COUNT)() if stage_ms is not None else None
-    opts = vl_prove_opts(mode, 0, workspace.data_ptr(), workspace.numel(), None, None,
+    opts = vl_prove_opts(mode, 0, workspace.data_ptr(), workspace.numel(), None, _tun(tuning_),
                          ctypes.addressof(timing) if timing is not None else None)
     total = sum(proof_size(g) for g in groups)
     buf = ctypes.create_string_buffer(max(total, 1))
@@ -252,12 +268,14 @@ def sumcheck_matmul_prove(groups: Sequence[GroupArgs], seed: int, mode: int = VL
 
 
 def sumcheck_matmul_prove_async(groups: Sequence[GroupArgs], seed: int, proofs_dev, status_dev,
-                                workspace, mode: int = VL_MODE_BATCHED, digests_dev=None, stream=None):
+                                workspace, mode: int = VL_MODE_BATCHED, digests_dev=None, stream=None,
+                                tuning_=None):
     """Enqueue a prove on the stream; proofs/status/digests land in device
     buffers.  Returns the host offsets of each group's proof."""
     arr = group_array(groups)
     n = len(groups)
-    opts = vl_prove_opts(mode, 1, workspace.data_ptr(), workspace.numel(), status_dev.data_ptr(), None, None)
+    opts = vl_prove_opts(mode, 1, workspace.data_ptr(), workspace.numel(), status_dev.data_ptr(),
+                         _tun(tuning_), None)
     offs = (c_u64 * (n + 1))()
     _check(lib().vl_sumcheck_matmul_prove(arr, n, seed, ctypes.byref(opts), proofs_dev.data_ptr(),
                                           proofs_dev.numel(), offs,

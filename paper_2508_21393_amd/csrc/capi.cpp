@@ -14,6 +14,8 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -79,6 +81,28 @@ vl_status check_group(const vl_group& g, bool need_ptrs) {
   return VL_OK;
 }
 
+// The rounds stream paired with a caller's stream (default priority), created
+// on first use and kept for the life of the process.
+hipError_t rounds_stream_for(hipStream_t s, hipStream_t* out) {
+  static std::mutex mu;
+  static std::map<std::pair<int, hipStream_t>, hipStream_t> streams;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = streams.find({dev, s});
+  if (it != streams.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  hipStream_t s2;
+  e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  streams[{dev, s}] = s2;
+  *out = s2;
+  return hipSuccess;
+}
+
 uint64_t proof_elems(const vl_group& g) {
   uint64_t n = g.n_prods;  // c and the part claims
   for (uint32_t k = 0; k < g.n_prods; ++k) n += 3ull * nvars_of(g.prods[k].D1) + 2;
@@ -134,10 +158,11 @@ int digits_for(int dtype) { return dtype == VL_I16 ? 1 : (dtype == VL_I32 ? 2 : 
 static int contract_kind(int dtype, int nd, bool rows, bool vec, int opl) {
   if (dtype == VL_I16) {
     if (rows) return opl == 4 ? (vec ? CK_I16_ROWS4_VEC : CK_I16_ROWS4) : CK_I16_ROWS;
-    return vec ? CK_I16_COLS_VEC : CK_I16_COLS;
+    return vec ? (opl == 2 ? CK_I16_COLS2_VEC : CK_I16_COLS_VEC) : CK_I16_COLS;
   }
-  const int base = dtype == VL_I32 ? CK_I32_ROWS : (nd == 2 ? CK_I64S_ROWS : CK_I64_ROWS);
-  return base + (rows ? 0 : (vec ? 2 : 1));
+  if (dtype == VL_I32) return rows ? CK_I32_ROWS : (vec ? CK_I32_COLS_VEC : CK_I32_COLS);
+  if (nd == 2) return rows ? CK_I64S_ROWS : (vec ? (opl == 2 ? CK_I64S_COLS2_VEC : CK_I64S_COLS_VEC) : CK_I64S_COLS);
+  return rows ? CK_I64_ROWS : (vec ? CK_I64_COLS_VEC : CK_I64_COLS);
 }
 
 void Builder::contract(const void* M, int dtype, int nd, uint64_t ld, bool rows, uint32_t n_out,
@@ -151,12 +176,18 @@ void Builder::contract(const void* M, int dtype, int nd, uint64_t ld, bool rows,
                         : ((reinterpret_cast<uintptr_t>(M) % 16 == 0) && ((ld * es) % 16 == 0));
   // four adjacent columns per lane for wide int16 row contractions: one
   // scalar load of the eq digits then feeds 32 multiply-adds
-  const int opl = (rows && dtype == VL_I16 && n_out >= 256) ? 4 : 1;
+  // two rows per lane in the vector cols kernels (tuning): each scalar load
+  // of eq digits then feeds twice the multiply-adds
+  int opl = (rows && dtype == VL_I16 && n_out >= 256) ? 4 : 1;
+  if (!rows && vec && T.cols_rows == 2 && (dtype == VL_I16 || nd == 2) && n_out >= 128) opl = 2;
   const int kind = contract_kind(dtype, nd, rows, vec, opl);
   const uint32_t out_waves = (n_out + 64 * opl - 1) / (64 * opl);
   // chunk: about T.lane_macs multiply-adds per lane and task
   uint64_t chunk = std::max<uint64_t>(64, T.lane_macs / (8ull * nd * opl));
   chunk = std::min<uint64_t>(chunk, kMaxChunk);
+  // narrow contractions (one output wave): split the contraction index finely
+  // so that the job spreads over the GPU instead of one long chain per wave
+  if (out_waves <= 2) chunk = std::min<uint64_t>(chunk, std::max<uint64_t>(64, len / 64));
   chunk = std::min<uint64_t>(chunk, align_up(len, kChunkAlign));
   chunk = align_up(chunk, kChunkAlign);
   while (T.min_tasks > 1 && chunk > 256 &&
@@ -170,7 +201,7 @@ void Builder::contract(const void* M, int dtype, int nd, uint64_t ld, bool rows,
   j.chunk = (uint32_t)chunk;
   j.n_chunks = n_chunks;
   j.out_waves = out_waves;
-  j.task_begin = P.cj_tasks[kind];
+  j.task_begin = S().cj_tasks[kind];
   j.pack = pack;
   j.err = err;
   FinishJob f{};
@@ -186,20 +217,20 @@ void Builder::contract(const void* M, int dtype, int nd, uint64_t ld, bool rows,
     f.part = nullptr;
   } else {
     const uint64_t pld = align_up(n_out, 64);
-    uint32_t* part = dev<uint32_t>(take((uint64_t)n_chunks * 8 * pld * 4));
+    uint32_t* part = dev<uint32_t>(take((uint64_t)n_chunks * kLimbs * pld * 4));
     j.dst = part;
     j.dst_ld = pld;
-    j.chunk_stride = 8 * pld;
+    j.chunk_stride = kLimbs * pld;
     f.part = part;
     f.part_ld = pld;
-    f.chunk_stride = 8 * pld;
+    f.chunk_stride = kLimbs * pld;
   }
-  P.cj_tasks[kind] += out_waves * n_chunks;
-  P.cj[kind].push_back(j);
+  S().cj_tasks[kind] += out_waves * n_chunks;
+  S().cj[kind].push_back(j);
   if (f.part || f.n_total > f.n_valid) {
-    f.thread_begin = P.fin_threads;
-    P.fin_threads += f.n_total;
-    P.fin.push_back(f);
+    f.block_begin = S().fin_blocks;
+    S().fin_blocks += (f.n_total + 63) / 64;
+    S().fin.push_back(f);
   }
 }
 
@@ -282,7 +313,7 @@ void Builder::group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev,
     rj.prods[k].ld = L1;
     rj.prods[k].n1 = n1;
   }
-  P.rounds.push_back(rj);
+  S().rounds.push_back(rj);
 }
 
 BlobLayout blob_layout(const Plan& P) {
@@ -292,16 +323,20 @@ BlobLayout blob_layout(const Plan& P) {
   o = align_up(o + 4ull * std::max<uint32_t>(P.n_err, 1), 64);
   L.eq = o;
   o = align_up(o + P.eq.size() * sizeof(EqJob), 64);
-  for (int k = 0; k < CK_COUNT; ++k) {
-    L.cj[k] = o;
-    o = align_up(o + P.cj[k].size() * sizeof(ContractJob), 64);
-  }
-  L.fin = o;
-  o = align_up(o + P.fin.size() * sizeof(FinishJob), 64);
-  L.rounds = o;
-  o = align_up(o + P.rounds.size() * sizeof(RoundsJob), 64);
   L.points = o;
   for (const auto& pt : P.points) o = align_up(o + pt.size() * 4, 64);
+  L.seg.resize(P.seg.size());
+  for (size_t k = 0; k < P.seg.size(); ++k) {
+    const Segment& G = P.seg[k];
+    for (int c = 0; c < CK_COUNT; ++c) {
+      L.seg[k].cj[c] = o;
+      o = align_up(o + G.cj[c].size() * sizeof(ContractJob), 64);
+    }
+    L.seg[k].fin = o;
+    o = align_up(o + G.fin.size() * sizeof(FinishJob), 64);
+    L.seg[k].rounds = o;
+    o = align_up(o + G.rounds.size() * sizeof(RoundsJob), 64);
+  }
   L.total = align_up(o, 256);
   return L;
 }
@@ -312,9 +347,10 @@ uint64_t blob_bound(const vl_group* groups, uint64_t n) {
     cj += 1 + 2ull * groups[i].n_prods;
     pts += 2ull * (nvars_of(groups[i].prods[0].D0) + nvars_of(groups[i].prods[0].D2)) * 32 + 128;
   }
+  // every segment may pad each of its CK_COUNT + 2 arrays to 64 bytes
   return align_up(4 * n + 64 + 2 * n * (sizeof(EqJob) + 64) +
                       cj * (sizeof(ContractJob) + sizeof(FinishJob) + 128) +
-                      n * (sizeof(RoundsJob) + 64) + pts + 64 * CK_COUNT + 1024,
+                      n * (sizeof(RoundsJob) + 64) + pts + 64 * (CK_COUNT + 2) * (n + 1) + 1024,
                   256);
 }
 
@@ -328,41 +364,42 @@ void fill_blob(Plan& P, const BlobLayout& L, uint8_t* dblob) {
     po = align_up(po + P.points[i].size() * 4, 64);
   }
   memcpy(P.blob.data() + L.eq, P.eq.data(), P.eq.size() * sizeof(EqJob));
-  for (int k = 0; k < CK_COUNT; ++k)
-    if (!P.cj[k].empty())
-      memcpy(P.blob.data() + L.cj[k], P.cj[k].data(), P.cj[k].size() * sizeof(ContractJob));
-  if (!P.fin.empty()) memcpy(P.blob.data() + L.fin, P.fin.data(), P.fin.size() * sizeof(FinishJob));
-  if (!P.rounds.empty())
-    memcpy(P.blob.data() + L.rounds, P.rounds.data(), P.rounds.size() * sizeof(RoundsJob));
+  for (size_t k = 0; k < P.seg.size(); ++k) {
+    const Segment& G = P.seg[k];
+    for (int c = 0; c < CK_COUNT; ++c)
+      if (!G.cj[c].empty())
+        memcpy(P.blob.data() + L.seg[k].cj[c], G.cj[c].data(), G.cj[c].size() * sizeof(ContractJob));
+    if (!G.fin.empty()) memcpy(P.blob.data() + L.seg[k].fin, G.fin.data(), G.fin.size() * sizeof(FinishJob));
+    if (!G.rounds.empty())
+      memcpy(P.blob.data() + L.seg[k].rounds, G.rounds.data(), G.rounds.size() * sizeof(RoundsJob));
+  }
 }
 
-hipError_t StageEvents::create() {
-  for (int i = 0; i < 2 * VL_STAGE_COUNT; ++i) {
-    const hipError_t e = hipEventCreate(&ev[i]);
-    if (e != hipSuccess) return e;
+hipError_t StageEvents::begin(int st, hipStream_t s) {
+  const size_t i = stage.size();
+  while (pool.size() < 2 * i + 2) {
+    hipEvent_t e;
+    const hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    pool.push_back(e);
   }
-  return hipSuccess;
+  stage.push_back(st);
+  return hipEventRecord(pool[2 * i], s);
+}
+
+hipError_t StageEvents::end(int, hipStream_t s) { return hipEventRecord(pool[2 * (stage.size() - 1) + 1], s); }
+
+void StageEvents::accumulate(float* ms) {
+  for (size_t i = 0; i < stage.size(); ++i) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, pool[2 * i], pool[2 * i + 1]) == hipSuccess) ms[stage[i]] += t;
+  }
+  stage.clear();
 }
 
 void StageEvents::destroy() {
-  for (int i = 0; i < 2 * VL_STAGE_COUNT; ++i)
-    if (ev[i]) (void)hipEventDestroy(ev[i]);
-}
-
-hipError_t StageEvents::begin(int stage, hipStream_t s) {
-  used[stage] = true;
-  return hipEventRecord(ev[2 * stage], s);
-}
-
-hipError_t StageEvents::end(int stage, hipStream_t s) { return hipEventRecord(ev[2 * stage + 1], s); }
-
-void StageEvents::accumulate(float* ms) {
-  for (int i = 0; i < VL_STAGE_COUNT; ++i) {
-    if (!used[i]) continue;
-    float t = 0.f;
-    if (hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) == hipSuccess) ms[i] += t;
-    used[i] = false;
-  }
+  for (auto e : pool) (void)hipEventDestroy(e);
+  pool.clear();
 }
 
 #define VL_STAGE(ev, st, s, launch)                   \
@@ -379,30 +416,105 @@ void StageEvents::accumulate(float* ms) {
     }                                                  \
   } while (0)
 
+// Per-call fork/join events between the caller's stream and the rounds
+// stream: cached per host thread, created on first use.
+struct ForkEvents {
+  std::vector<hipEvent_t> ev;
+  hipError_t need(size_t n) {
+    while (ev.size() < n) {
+      hipEvent_t e;
+      const hipError_t r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+      if (r != hipSuccess) return r;
+      ev.push_back(e);
+    }
+    return hipSuccess;
+  }
+  ~ForkEvents() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
 hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipStream_t s,
-                        StageEvents* ev) {
+                        hipStream_t s2, StageEvents* ev) {
+  thread_local ForkEvents fork;
+  const size_t nseg = P.seg.size();
+  const bool two = s2 != s;
+  if (two) {
+    const hipError_t e = fork.need(nseg + 2);
+    if (e != hipSuccess) return e;
+  }
   VL_STAGE(ev, VL_STAGE_UPLOAD, s, launch_upload(dblob, P.blob.data(), L.total, s));
   VL_STAGE(ev, VL_STAGE_EQ, s,
            launch_eq(reinterpret_cast<const EqJob*>(dblob + L.eq), (uint32_t)P.eq.size(), P.eq_threads, s));
-  for (int k = 0; k < CK_COUNT; ++k) {
-    if (P.cj[k].empty()) continue;
-    VL_STAGE(ev, VL_STAGE_CONTRACT + k, s,
-             launch_contract(k, reinterpret_cast<const ContractJob*>(dblob + L.cj[k]),
-                             (uint32_t)P.cj[k].size(), P.cj_tasks[k], s));
+  if (two) {
+    // the rounds stream starts after everything queued before this call
+    hipError_t e = hipEventRecord(fork.ev[nseg], s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s2, fork.ev[nseg], 0);
+    if (e != hipSuccess) return e;
   }
-  if (!P.fin.empty())
-    VL_STAGE(ev, VL_STAGE_FINISH, s,
-             launch_finish(reinterpret_cast<const FinishJob*>(dblob + L.fin), (uint32_t)P.fin.size(),
-                           P.fin_threads, s));
-  VL_STAGE(ev, VL_STAGE_ROUNDS, s,
-           launch_rounds(reinterpret_cast<const RoundsJob*>(dblob + L.rounds), (uint32_t)P.rounds.size(), s));
+  for (size_t k = 0; k < nseg; ++k) {
+    const Segment& G = P.seg[k];
+    for (int c = 0; c < CK_COUNT; ++c) {
+      if (G.cj[c].empty()) continue;
+      VL_STAGE(ev, VL_STAGE_CONTRACT + c, s,
+               launch_contract(c, reinterpret_cast<const ContractJob*>(dblob + L.seg[k].cj[c]),
+                               (uint32_t)G.cj[c].size(), G.cj_tasks[c], s));
+    }
+    if (!G.fin.empty())
+      VL_STAGE(ev, VL_STAGE_FINISH, s,
+               launch_finish(reinterpret_cast<const FinishJob*>(dblob + L.seg[k].fin), (uint32_t)G.fin.size(),
+                             G.fin_blocks, s));
+    if (G.rounds.empty()) continue;
+    if (two) {
+      hipError_t e = hipEventRecord(fork.ev[k], s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s2, fork.ev[k], 0);
+      if (e != hipSuccess) return e;
+    }
+    VL_STAGE(ev, VL_STAGE_ROUNDS, s2,
+             launch_rounds(reinterpret_cast<const RoundsJob*>(dblob + L.seg[k].rounds),
+                           (uint32_t)G.rounds.size(), s2));
+  }
+  if (two) {
+    // join: the caller's stream sees every rounds launch
+    hipError_t e = hipEventRecord(fork.ev[nseg + 1], s2);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, fork.ev[nseg + 1], 0);
+    if (e != hipSuccess) return e;
+  }
   return hipSuccess;
+}
+
+// defaults, then the caller's non-zero knobs
+static void apply_tuning(Tuning& t, const vl_tuning* k) {
+  if (!k) return;
+  if (k->lane_macs) t.lane_macs = k->lane_macs;
+  if (k->min_tasks) t.min_tasks = k->min_tasks;
+  if (k->segments && !t.per_instance) t.segments = k->segments;
+  if (k->cols_rows) t.cols_rows = k->cols_rows;
+}
+
+static vl_status check_tuning(const vl_tuning* k) {
+  if (!k) return VL_OK;
+  if (k->reserved) return fail(VL_ERR_INVALID_ARG, "vl_tuning.reserved must be 0");
+  if (k->segments > kMaxSegments)
+    return fail(VL_ERR_INVALID_ARG, "vl_tuning.segments must be <= %u", kMaxSegments);
+  if (k->lane_macs && k->lane_macs < 64) return fail(VL_ERR_INVALID_ARG, "vl_tuning.lane_macs must be >= 64");
+  if (k->cols_rows > 2) return fail(VL_ERR_INVALID_ARG, "vl_tuning.cols_rows must be 0, 1 or 2");
+  return VL_OK;
 }
 
 Tuning tuning_for(const vl_prove_opts* o) {
   Tuning t;
   t.per_instance = !o || o->mode == VL_MODE_PER_INSTANCE;
   t.min_tasks = t.per_instance ? 1024 : 1;
+  t.segments = t.per_instance ? 1 : kDefaultSegments;
+  if (o) apply_tuning(t, o->tuning);
+  return t;
+}
+
+static Tuning pe_tuning(const vl_tuning* k) {
+  Tuning t;
+  t.min_tasks = 1024;
+  apply_tuning(t, k);
   return t;
 }
 
@@ -435,6 +547,24 @@ void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, 
     P.out_proof_bytes = proof_total;
     P.out_off = B.take(align_up(proof_total, 256) + align_up(4 * n, 256) + 32 * n);
   }
+  // pipeline segments: groups with the longest sumchecks first, so that their
+  // rounds overlap the contractions of the groups after them
+  std::vector<uint64_t> order(n);
+  for (uint64_t i = 0; i < n; ++i) order[i] = i;
+  auto rounds_cost = [&](uint64_t i) {
+    uint64_t c = 0;
+    for (uint32_t k = 0; k < groups[g0 + i].n_prods; ++k) {
+      const uint32_t n1 = nvars_of(groups[g0 + i].prods[k].D1);
+      c += (5ull << n1) + 20000ull * n1;   // field products plus per-round hashing
+    }
+    return c;
+  };
+  std::stable_sort(order.begin(), order.end(),
+                   [&](uint64_t a, uint64_t b) { return rounds_cost(a) > rounds_cost(b); });
+  const uint32_t nseg = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(T.segments, n));
+  P.seg.assign(nseg, Segment());
+  std::vector<uint32_t> seg_of(n);
+  for (uint64_t r = 0; r < n; ++r) seg_of[order[r]] = (uint32_t)(r * nseg / n);
   uint64_t rel = 0;
   for (uint64_t i = g0; i < g1; ++i) {
     uint8_t* pd;
@@ -452,6 +582,7 @@ void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, 
     }
     rel += 32 * proof_elems(groups[i]);
     int32_t* err = reinterpret_cast<int32_t*>(ws + 4 * (i - g0));  // blob starts with the flags
+    B.cur = seg_of[i - g0];
     B.group(groups[i], ch[i - g0], pd, sd, dd, err);
   }
   P.data_end = B.off;
@@ -495,7 +626,7 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
                                    uint64_t* offsets, uint8_t* digests, void* stream) {
   if (!groups || n == 0 || !o || !proofs || !offsets)
     return fail(VL_ERR_INVALID_ARG, "null argument");
-  if (o->plan) return fail(VL_ERR_INVALID_ARG, "plan must be NULL");
+  if (check_tuning(o->tuning) != VL_OK) return VL_ERR_INVALID_ARG;
   if (o->mode < VL_MODE_PER_INSTANCE || o->mode > VL_MODE_PERSISTENT)
     return fail(VL_ERR_INVALID_ARG, "unknown mode %d", o->mode);
   if (o->async && !o->status) return fail(VL_ERR_INVALID_ARG, "async mode needs a status array");
@@ -522,11 +653,6 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
   StageEvents* ev = nullptr;
   if (o->stage_ms && !async) {
     for (int i = 0; i < VL_STAGE_COUNT; ++i) o->stage_ms[i] = 0.f;
-    const hipError_t e = events.create();
-    if (e != hipSuccess) {
-      events.destroy();
-      return fail(VL_ERR_HIP, "event create: %s", hipGetErrorString(e));
-    }
     ev = &events;
   }
   struct Cleanup {
@@ -567,7 +693,12 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
                   (unsigned long long)o->workspace_bytes, (unsigned long long)align_up(P.data_end, 256));
     const BlobLayout L = blob_layout(P);
     fill_blob(P, L, ws);
-    const hipError_t e = enqueue_plan(P, L, ws, s, ev);
+    hipStream_t s2 = s;
+    if (P.seg.size() > 1) {
+      const hipError_t e2 = rounds_stream_for(s, &s2);
+      if (e2 != hipSuccess) return fail(VL_ERR_HIP, "rounds stream: %s", hipGetErrorString(e2));
+    }
+    const hipError_t e = enqueue_plan(P, L, ws, s, s2, ev);
     if (e != hipSuccess) return fail(VL_ERR_HIP, "launch: %s", hipGetErrorString(e));
     return async ? VL_OK : fetch(g0, g1);
   };
@@ -623,15 +754,16 @@ vl_status vl_eq_table(const vl_fr* point, uint32_t nvars, vl_fr_vec out, void* s
 static uint64_t pe_pack_bytes(uint64_t len) { return align_up(len * 32, 256); }
 static constexpr uint64_t kPeBlob = 1024;
 
-uint64_t vl_partial_eval_workspace_size(uint32_t rows, uint32_t cols, int32_t contract, int32_t dtype) {
+uint64_t vl_partial_eval_workspace_size(uint32_t rows, uint32_t cols, int32_t contract, int32_t dtype,
+                                        const vl_tuning* tuning) {
   if (rows == 0 || cols == 0 || !esize(dtype) ||
       (contract != VL_CONTRACT_ROWS && contract != VL_CONTRACT_COLS))
     return 0;
   const bool rws = contract == VL_CONTRACT_ROWS;
   const uint64_t len = rws ? rows : cols, n_out = rws ? cols : rows;
+  if (check_tuning(tuning) != VL_OK) return 0;
   Plan P;
-  Tuning T;
-  T.min_tasks = 1024;
+  const Tuning T = pe_tuning(tuning);
   Builder B(P, T, 0, pe_pack_bytes(len) + kPeBlob);
   // alignment of M is unknown here; the plan's size does not depend on it
   B.contract(nullptr, dtype, digits_for(dtype), cols, rws, (uint32_t)n_out, (uint32_t)len, nullptr,
@@ -641,7 +773,7 @@ uint64_t vl_partial_eval_workspace_size(uint32_t rows, uint32_t cols, int32_t co
 
 vl_status vl_mle_partial_eval(const void* M, int32_t dtype, uint32_t rows, uint32_t cols, uint64_t ld,
                               int32_t contract, vl_fr_vec eq, vl_fr_vec out, void* workspace,
-                              uint64_t workspace_bytes, void* stream) {
+                              uint64_t workspace_bytes, const vl_tuning* tuning, void* stream) {
   if (!M || !eq.base || !out.base || !workspace) return fail(VL_ERR_INVALID_ARG, "null pointer");
   if (!esize(dtype)) return fail(VL_ERR_DTYPE, "dtype must be VL_I16/I32/I64");
   if (contract != VL_CONTRACT_ROWS && contract != VL_CONTRACT_COLS)
@@ -652,31 +784,32 @@ vl_status vl_mle_partial_eval(const void* M, int32_t dtype, uint32_t rows, uint3
   const uint32_t len = rws ? rows : cols, n_out = rws ? cols : rows;
   if (eq.n < len || eq.ld < eq.n) return fail(VL_ERR_SHAPE, "eq vector shorter than the contraction");
   if (out.n < n_out || out.ld < out.n) return fail(VL_ERR_SHAPE, "out vector too short");
-  if (workspace_bytes < vl_partial_eval_workspace_size(rows, cols, contract, dtype))
+  if (check_tuning(tuning) != VL_OK) return VL_ERR_INVALID_ARG;
+  if (workspace_bytes < vl_partial_eval_workspace_size(rows, cols, contract, dtype, tuning))
     return fail(VL_ERR_WORKSPACE, "workspace too small");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   uint8_t* ws = reinterpret_cast<uint8_t*>(workspace);
   uint32_t* pack = reinterpret_cast<uint32_t*>(ws);
   uint8_t* dblob = ws + pe_pack_bytes(len);
   Plan P;
-  Tuning T;
-  T.min_tasks = 1024;
+  const Tuning T = pe_tuning(tuning);
   Builder B(P, T, reinterpret_cast<uint64_t>(ws), pe_pack_bytes(len) + kPeBlob);
   B.contract(M, dtype, digits_for(dtype), ld, rws, n_out, len, pack, out.base, out.ld, out.n,
              reinterpret_cast<int32_t*>(dblob));
   int kind = -1;
+  const Segment& G = P.seg[0];
   for (int k = 0; k < CK_COUNT; ++k)
-    if (!P.cj[k].empty()) kind = k;
+    if (!G.cj[k].empty()) kind = k;
   std::vector<uint8_t> blob(kPeBlob, 0);   // [err flag][contract job][finish job]
   const uint64_t jo = 64, fo = 64 + align_up(sizeof(ContractJob), 64);
-  memcpy(blob.data() + jo, &P.cj[kind][0], sizeof(ContractJob));
-  if (!P.fin.empty()) memcpy(blob.data() + fo, &P.fin[0], sizeof(FinishJob));
+  memcpy(blob.data() + jo, &G.cj[kind][0], sizeof(ContractJob));
+  if (!G.fin.empty()) memcpy(blob.data() + fo, &G.fin[0], sizeof(FinishJob));
   hipError_t e = launch_upload(dblob, blob.data(), blob.size(), s);
   if (e == hipSuccess) e = launch_pack(eq.base, eq.ld, len, pack, s);
   if (e == hipSuccess)
-    e = launch_contract(kind, reinterpret_cast<const ContractJob*>(dblob + jo), 1, P.cj_tasks[kind], s);
-  if (e == hipSuccess && !P.fin.empty())
-    e = launch_finish(reinterpret_cast<const FinishJob*>(dblob + fo), 1, P.fin_threads, s);
+    e = launch_contract(kind, reinterpret_cast<const ContractJob*>(dblob + jo), 1, G.cj_tasks[kind], s);
+  if (e == hipSuccess && !G.fin.empty())
+    e = launch_finish(reinterpret_cast<const FinishJob*>(dblob + fo), 1, G.fin_blocks, s);
   if (e != hipSuccess) return fail(VL_ERR_HIP, "partial_eval: %s", hipGetErrorString(e));
   return VL_OK;
 }

@@ -130,6 +130,23 @@ VL_HD Fr fr_sub(const Fr& a, const Fr& b) {
 VL_HD Fr fr_neg(const Fr& a) { return fr_sub(fr_zero(), a); }
 VL_HD Fr fr_double(const Fr& a) { return fr_add(a, a); }
 
+// a / 2: a (even) or a + p (odd) shifted right by one; a + p < 2^256
+VL_HD Fr fr_half(const Fr& a) {
+  Fr t = a;
+  if (a.w[0] & 1u) {
+    uint64_t c = 0;
+    for (int j = 0; j < 8; ++j) {
+      c += (uint64_t)a.w[j] + p_limb(j);
+      t.w[j] = (uint32_t)c;
+      c >>= 32;
+    }
+  }
+  Fr r;
+  for (int j = 0; j < 7; ++j) r.w[j] = (t.w[j] >> 1) | (t.w[j + 1] << 31);
+  r.w[7] = t.w[7] >> 1;
+  return r;
+}
+
 #if defined(__HIP_DEVICE_COMPILE__)
 // Device Montgomery product by product scanning with the reduction folded in
 // (Koc, Acar, Kaliski's finely integrated product scanning).  Column k sums

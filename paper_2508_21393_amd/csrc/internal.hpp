@@ -58,21 +58,27 @@ struct ContractJob {
   uint32_t out_waves;         // ceil(n_out / 64)
   uint32_t task_begin;        // prefix sum of tasks (out_waves * n_chunks) within a launch
   const uint32_t* pack;       // eq pack table of the contraction index
-  uint32_t* dst;              // n_chunks == 1: final SoL vector; else partial SoL slot 0
-  uint64_t dst_ld;            // plane stride of dst (final vector or one partial)
-  uint64_t chunk_stride;      // words between consecutive chunk partials
+  uint32_t* dst;              // n_chunks == 1: final SoL vector (8 planes); else the raw
+                              // partial of chunk 0 (kLimbs planes)
+  uint64_t dst_ld;            // plane stride of dst
+  uint64_t chunk_stride;      // words between consecutive chunk partials (0: final)
   int32_t* err;               // set to 1 if an entry cannot be represented (int32/int64)
 };
 
-// Sum chunk partials into the final SoL vector and zero its padding.
+// A split contraction's chunks leave their exact sums unreduced: kLimbs
+// 32-bit two's-complement limbs per output and chunk.  The finish kernel
+// adds them up and reduces once per output.
+constexpr int kLimbs = 12;
+
+// Sum the raw chunk partials into the final SoL vector and zero its padding.
 struct FinishJob {
-  const uint32_t* part;       // SoL partial 0 (null if the contraction wrote dst directly)
+  const uint32_t* part;       // raw partial of chunk 0 (null if the contraction wrote out)
   uint64_t part_ld;
   uint64_t chunk_stride;
   uint32_t n_chunks;
   uint32_t n_valid;           // outputs written by the contraction
   uint32_t n_total;           // padded length (power of two)
-  uint32_t thread_begin;
+  uint32_t block_begin;       // prefix sum of blocks (64 outputs each) within a launch
   uint32_t* out;
   uint64_t out_ld;
 };
@@ -105,7 +111,7 @@ struct RoundsJob {
 hipError_t launch_eq(const EqJob* jobs_dev, uint32_t n_jobs, uint32_t n_threads, hipStream_t s);
 hipError_t launch_contract(int kind, const ContractJob* jobs_dev, uint32_t n_jobs, uint32_t n_tasks,
                            hipStream_t s);
-hipError_t launch_finish(const FinishJob* jobs_dev, uint32_t n_jobs, uint32_t n_threads, hipStream_t s);
+hipError_t launch_finish(const FinishJob* jobs_dev, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s);
 hipError_t launch_rounds(const RoundsJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
 hipError_t launch_lift(const void* src, int dtype, uint64_t n, uint32_t* dst, uint64_t ld, hipStream_t s);
 hipError_t launch_export(const uint32_t* src, uint64_t ld, uint64_t n, uint32_t* dst, hipStream_t s);
@@ -121,11 +127,14 @@ enum ContractKind {
   CK_I16_ROWS4 = 1,      // int16, 1 x 16, rows, 4 (element loads)
   CK_I16_ROWS4_VEC = 2,  // int16, 1 x 16, rows, 4 (8-byte loads)
   CK_I16_COLS = 3,       // int16, cols, element loads
-  CK_I16_COLS_VEC = 4,   // int16, cols, 16-byte row loads
-  CK_I32_ROWS = 5, CK_I32_COLS = 6, CK_I32_COLS_VEC = 7,        // int32, 2 x 24
-  CK_I64S_ROWS = 8, CK_I64S_COLS = 9, CK_I64S_COLS_VEC = 10,    // int64 with |x| < 2^47, 2 x 24
-  CK_I64_ROWS = 11, CK_I64_COLS = 12, CK_I64_COLS_VEC = 13,     // int64, 3 x 24
-  CK_COUNT = 14
+  CK_I16_COLS_VEC = 4,   // int16, cols, 16-byte row loads, 1 row per lane
+  CK_I16_COLS2_VEC = 5,  // int16, cols, 16-byte row loads, 2 rows per lane
+  CK_I32_ROWS = 6, CK_I32_COLS = 7, CK_I32_COLS_VEC = 8,        // int32, 2 x 24
+  CK_I64S_ROWS = 9, CK_I64S_COLS = 10, CK_I64S_COLS_VEC = 11,   // int64 with |x| < 2^47, 2 x 24
+  CK_I64S_COLS2_VEC = 12,                                       // the same, 2 rows per lane
+  CK_I64_ROWS = 13, CK_I64_COLS = 14, CK_I64_COLS_VEC = 15,     // int64, 3 x 24
+  CK_COUNT = 16
 };
+static_assert(VL_STAGE_CONTRACT + CK_COUNT == VL_STAGE_FINISH, "one stage per contraction kind");
 
 }  // namespace vl

@@ -11,17 +11,17 @@
 //                    canonical form
 //
 // The integer contraction (the hot loop) never multiplies two field elements.
-// Each eq entry e (stored as e * R^2 mod p < 2^255, so that one Montgomery
-// reduction at the end lands in Montgomery form) is cut into 32 bytes e_k,
-// each matrix entry x into signed 16-bit digits d_t.  The exact integer
-//     sum_m e[m] * x[m] = sum_{k,t} 2^(8k + 16t) * sum_m e_k[m] * d_t[m]
-// is accumulated with v_dot2_i32_i16, two consecutive m per instruction:
-// the byte pair (e_k[m], e_k[m+1]) comes from a scalar register (the eq
-// table is wave-uniform) and the digit pair from a vector register.  Each
-// dot2 adds at most 2 * 255 * 2^15 < 2^24 in magnitude, so 128 of them fit an
-// int32 accumulator; every 128 pairs the 32 accumulators are folded into
-// 64-bit limb sums.  At the end of a chunk the signed ~300-bit sum is reduced
-// with one Montgomery multiplication (see finalize).
+// Each eq entry e is stored as e * R^2 mod p (so that one Montgomery
+// reduction at the end lands in Montgomery form) cut into 8 signed 32-bit
+// digits e_j; each matrix entry x is one signed 16-bit digit (int16) or two or
+// three signed 24-bit digits d_t (wider types).  The exact integer
+//     sum_m e[m] * x[m] = sum_{j,t} 2^(32 j + DB t) * sum_m e_j[m] * d_t[m]
+// is accumulated with v_mad_i64_i32 into 64-bit accumulators, one
+// instruction per (j, t) and entry: the eq digits are wave-uniform and come
+// from scalar registers, the matrix digits from vector registers.  The
+// signed ~300-bit sum is reduced with one Montgomery multiplication
+// (limbs_to_fr) once per output: a contraction split into chunks stores each
+// chunk's sum as raw limbs, which finish_kernel adds up before reducing.
 #include <cstring>
 
 #include "internal.hpp"
@@ -29,9 +29,12 @@
 
 namespace vl {
 
-typedef short v2i16 __attribute__((ext_vector_type(2)));
 typedef const __attribute__((address_space(4))) uint32_t* cu32_ptr;
 typedef const __attribute__((address_space(4))) int32_t* ci32_ptr;
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T*;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 // e (canonical, < p < 2^255) as 8 signed 32-bit digits, e = sum_j d_j 2^(32 j),
 // d_j in [-2^31, 2^31); the top limb of p is below 2^31 - 1, so d_7 never
@@ -46,11 +49,6 @@ __device__ __forceinline__ void signed_digits(const Fr& e, uint32_t* out) {
     out[j] = v;                           // as int32: v - 2^32 when up
     c = up ? 1u : 0u;
   }
-}
-
-__device__ __forceinline__ int32_t sdot2(uint32_t e, uint32_t x, int32_t acc) {
-  return __builtin_amdgcn_sdot2(__builtin_bit_cast(v2i16, e), __builtin_bit_cast(v2i16, x), acc,
-                                false);
 }
 
 __device__ __forceinline__ Fr load_sol(const uint32_t* base, uint64_t ld, uint64_t i) {
@@ -187,6 +185,18 @@ __device__ __forceinline__ void mac8(ci32_ptr e, const int32_t (&d)[OPL][ND],
   }
 }
 
+// the same with the eq digits already in registers
+template <int OPL, int ND>
+__device__ __forceinline__ void mac8v(const int32_t (&e)[8], const int32_t (&d)[OPL][ND],
+                                      int64_t (&acc)[OPL][ND][8]) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+#pragma unroll
+    for (int o = 0; o < OPL; ++o)
+#pragma unroll
+      for (int t = 0; t < ND; ++t) acc[o][t][j] += (int64_t)e[j] * (int64_t)d[o][t];
+}
+
 // wide digits (DB = 24): move the high words out before an int64 can overflow
 template <int OPL, int ND>
 __device__ __forceinline__ void spill_high(int64_t (&acc)[OPL][ND][8], int64_t (&hi)[OPL][ND][8]) {
@@ -203,16 +213,14 @@ __device__ __forceinline__ void spill_high(int64_t (&acc)[OPL][ND][8], int64_t (
 }
 
 // V = sum_{t,j} (acc + 2^32 hi) 2^(DB t + 32 j), congruent to R^2 * value
-// (the eq digits hold e * R^2 mod p).  With V = lo + 2^256 hi (lo unsigned
-// 256-bit, |hi| < 2^80): V * R^-1 = lo * R^-1 + hi (mod p), i.e. one
-// Montgomery multiplication by 1 plus a small signed lift.  (A direct
-// 12-limb REDC written with 64-bit adds lost a carry when compiled for gfx950
-// at -O3, so the reduction goes through the field multiplier.)
+// (the eq digits hold e * R^2 mod p), as kLimbs 32-bit two's-complement
+// limbs (|V| < 2^340 for every entry type and length).
 template <int ND, int DB>
-__device__ __forceinline__ Fr finalize_digits(const int64_t (&acc)[ND][8], const int64_t (&hi)[ND][8]) {
-  int64_t S[12];
+__device__ __forceinline__ void digits_to_limbs(const int64_t (&acc)[ND][8], const int64_t (&hi)[ND][8],
+                                                uint32_t (&L)[kLimbs]) {
+  int64_t S[kLimbs];
 #pragma unroll
-  for (int q = 0; q < 12; ++q) S[q] = 0;
+  for (int q = 0; q < kLimbs; ++q) S[q] = 0;
 #pragma unroll
   for (int t = 0; t < ND; ++t) {
 #pragma unroll
@@ -228,14 +236,21 @@ __device__ __forceinline__ Fr finalize_digits(const int64_t (&acc)[ND][8], const
       S[b + 2] += sh == 0 ? (H >> 32) : (H >> (32 - sh));
     }
   }
-  uint32_t L[12];
   int64_t carry = 0;
 #pragma unroll
-  for (int q = 0; q < 12; ++q) {
+  for (int q = 0; q < kLimbs; ++q) {
     const int64_t v = S[q] + carry;
     L[q] = (uint32_t)v;
     carry = v >> 32;
   }
+}
+
+// V * R^-1 mod p in Montgomery form for V given as limbs.  With V = lo +
+// 2^256 hi (lo unsigned 256-bit, |hi| < 2^127): V * R^-1 = lo * R^-1 + hi
+// (mod p), i.e. one Montgomery multiplication by 1 plus a small signed lift.
+// (A direct 12-limb REDC written with 64-bit adds lost a carry when compiled
+// for gfx950 at -O3, so the reduction goes through the field multiplier.)
+__device__ __forceinline__ Fr limbs_to_fr(const uint32_t (&L)[kLimbs]) {
   Fr lo;
 #pragma unroll
   for (int j = 0; j < 8; ++j) lo.w[j] = L[j];
@@ -300,126 +315,215 @@ contract_kernel(const ContractJob* __restrict__ jobs, uint32_t n_jobs, uint32_t 
       for (int j = 0; j < 8; ++j) acc[o][t][j] = hi[o][t][j] = 0;
   uint32_t bad = 0;
 
-  uint32_t m = m0;
+  // All matrix reads go through global (not generic) pointers: generic loads
+  // also count against the scalar-load counter, so every wait for the eq
+  // digits would drain the vector loads in flight as well.
+  const gptr<T> Mg = (gptr<T>)M;
   if constexpr (VEC && !ROWS) {
-    // cols layout, 16-byte aligned rows: each lane streams its own row 16
-    // bytes at a time, the next 16 bytes in flight while these are used
-    static_assert(OPL == 1, "vector cols kernel has one row per lane");
+    // cols layout, 16-byte aligned rows (m0 is a multiple of the vector
+    // width): OPL rows per lane, streamed 16 bytes at a time through a ring
+    // of PF vectors per row.  Lanes past the last row re-read the last row
+    // (their results are not stored); the prefetch index is clamped to the
+    // chunk, and the aligned 16-byte block holding a row's last entry never
+    // crosses a page, so every load stays inside the matrix's pages.
     constexpr uint32_t BE = 16 / sizeof(T);
-    const bool valid = n0 < n_out;
-    const uint4* row = (const uint4*)(M + (uint64_t)(valid ? n0 : 0u) * ld);
-    const uint32_t mv = m0 + ((m1 - m0) / BE) * BE;
-    if (m < mv) {
-      uint4 cur = valid ? row[m / BE] : make_uint4(0, 0, 0, 0);
-      while (m < mv) {
-        const uint32_t bend = WIDE ? min(m + kSpill, mv) : mv;
-        for (; m < bend; m += BE) {
-          uint4 nxt = make_uint4(0, 0, 0, 0);
-          if (valid && m + BE < mv) nxt = row[m / BE + 1];
-          const T* x = (const T*)&cur;
+    constexpr uint32_t PF = 4;
+    constexpr uint32_t G = WIDE ? kSpill / (PF * BE) : 0;   // groups between spills
+    const uint32_t span = m1 - m0, full = span / BE, nvec = (span + BE - 1) / BE;
+    gptr<u32x4> rowp[OPL];
+#pragma unroll
+    for (int o = 0; o < OPL; ++o)
+      rowp[o] = (gptr<u32x4>)(Mg + (uint64_t)min(n0 + o, n_out - 1) * ld + m0);
+    u32x4 buf[PF][OPL];
+#pragma unroll
+    for (uint32_t s = 0; s < PF; ++s)
+#pragma unroll
+      for (int o = 0; o < OPL; ++o) buf[s][o] = rowp[o][min(s, nvec - 1)];
+    uint32_t grp = 0;
+    for (uint32_t v = 0; v < full; v += PF) {
+#pragma unroll
+      for (uint32_t s = 0; s < PF; ++s) {
+        if (v + s < full) {
+          // the vector's eq digits in one batch of scalar loads, one wait
+          ci32_ptr pe = pack + (uint64_t)(m0 + (v + s) * BE) * 8;
+          int32_t e[BE][8];
+#pragma unroll
+          for (uint32_t q = 0; q < BE; ++q)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) e[q][j] = pe[q * 8 + j];
 #pragma unroll
           for (uint32_t q = 0; q < BE; ++q) {
-            int32_t d[1][ND];
-            entry_digits<T, ND, DB>(x[q], d[0], bad);
-            mac8<1, ND>(pack + (uint64_t)(m + q) * 8, d, acc);
+            int32_t d[OPL][ND];
+#pragma unroll
+            for (int o = 0; o < OPL; ++o) entry_digits<T, ND, DB>(((const T*)&buf[s][o])[q], d[o], bad);
+            mac8v<OPL, ND>(e[q], d, acc);
           }
-          cur = nxt;
         }
-        if constexpr (WIDE) spill_high<OPL, ND>(acc, hi);
+#pragma unroll
+        for (int o = 0; o < OPL; ++o) buf[s][o] = rowp[o][min(v + s + PF, nvec - 1)];
+      }
+      if constexpr (WIDE) {
+        if (++grp == G) {
+          spill_high<OPL, ND>(acc, hi);
+          grp = 0;
+        }
       }
     }
-  }
-  if constexpr (VEC && ROWS) {
-    // rows layout, four int16 columns per lane read as one 8-byte load;
-    // batches of four rows, the next batch in flight while this one is used
-    static_assert(OPL == 4 && sizeof(T) == 2 && !WIDE, "vector rows kernel: int16, 4 columns");
-    constexpr uint32_t BR = 4;
-    const bool full = n0 + 3 < n_out;
-    auto load4 = [&](uint32_t mm) -> uint2 {
-      uint2 v = make_uint2(0, 0);
-      if (mm < m1) {
-        if (full) {
-          v = *(const uint2*)(M + (uint64_t)mm * ld + n0);
-        } else {
-          uint16_t e[4] = {0, 0, 0, 0};
+    if (full < nvec) {   // last, partial vector of the row
+      u32x4 t[OPL];
 #pragma unroll
-          for (int o = 0; o < 4; ++o)
-            if (n0 + o < n_out) e[o] = (uint16_t)M[(uint64_t)mm * ld + n0 + o];
-          v = make_uint2(e[0] | ((uint32_t)e[1] << 16), e[2] | ((uint32_t)e[3] << 16));
-        }
-      }
-      return v;
-    };
-    uint2 cur[BR];
+      for (int o = 0; o < OPL; ++o) t[o] = rowp[o][full];
+      const uint32_t rem = span - full * BE;
 #pragma unroll
-    for (uint32_t r = 0; r < BR; ++r) cur[r] = load4(m + r);
-    for (; m < m1; m += BR) {
-      uint2 nxt[BR];
-#pragma unroll
-      for (uint32_t r = 0; r < BR; ++r) nxt[r] = load4(m + BR + r);
-#pragma unroll
-      for (uint32_t r = 0; r < BR; ++r) {
-        if (m + r < m1) {
+      for (uint32_t q = 0; q < BE; ++q) {
+        if (q < rem) {
           int32_t d[OPL][ND];
-          d[0][0] = (int32_t)(int16_t)(cur[r].x & 0xffffu);
-          d[1][0] = (int32_t)(int16_t)(cur[r].x >> 16);
-          d[2][0] = (int32_t)(int16_t)(cur[r].y & 0xffffu);
-          d[3][0] = (int32_t)(int16_t)(cur[r].y >> 16);
-          mac8<OPL, ND>(pack + (uint64_t)(m + r) * 8, d, acc);
+#pragma unroll
+          for (int o = 0; o < OPL; ++o) entry_digits<T, ND, DB>(((const T*)&t[o])[q], d[o], bad);
+          mac8<OPL, ND>(pack + (uint64_t)(m0 + full * BE + q) * 8, d, acc);
         }
       }
-#pragma unroll
-      for (uint32_t r = 0; r < BR; ++r) cur[r] = nxt[r];
     }
-  }
-  while (m < m1) {
-    const uint32_t bend = WIDE ? min(m + kSpill, m1) : m1;
-#pragma unroll 4
-    for (; m < bend; ++m) {
-      int32_t d[OPL][ND];
+  } else if constexpr (VEC && ROWS) {
+    // rows layout, four int16 columns per lane read as one 8-byte load per
+    // row, a ring of PF rows in flight.  Lanes past the last column group
+    // re-read the last group (results not stored).
+    static_assert(OPL == 4 && sizeof(T) == 2 && !WIDE, "vector rows kernel: int16, 4 columns");
+    constexpr uint32_t PF = 8;
+    const uint32_t nc = min(n0, ((n_out - 1) / 4) * 4);
+    const gptr<T> base = Mg + (uint64_t)m0 * ld + nc;
+    const uint32_t rows = m1 - m0;
+    auto row = [&](uint32_t r) -> u32x2 { return *(gptr<u32x2>)(base + (uint64_t)min(r, rows - 1) * ld); };
+    u32x2 buf[PF];
 #pragma unroll
-      for (int o = 0; o < OPL; ++o) {
-        const uint32_t n = n0 + o;
-        T x = 0;
-        if (n < n_out) x = ROWS ? M[(uint64_t)m * ld + n] : M[(uint64_t)n * ld + m];
-        entry_digits<T, ND, DB>(x, d[o], bad);
+    for (uint32_t s = 0; s < PF; ++s) buf[s] = row(s);
+    const uint32_t fullr = rows & ~(PF - 1);
+    for (uint32_t r = 0; r < fullr; r += PF) {
+      // eq digits of the PF rows in one batch of scalar loads, one wait
+      ci32_ptr pe = pack + (uint64_t)(m0 + r) * 8;
+      int32_t e[PF][8];
+#pragma unroll
+      for (uint32_t s = 0; s < PF; ++s)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) e[s][j] = pe[s * 8 + j];
+#pragma unroll
+      for (uint32_t s = 0; s < PF; ++s) {
+        int32_t d[OPL][ND];
+        d[0][0] = (int32_t)(int16_t)(buf[s].x & 0xffffu);
+        d[1][0] = (int32_t)(int16_t)(buf[s].x >> 16);
+        d[2][0] = (int32_t)(int16_t)(buf[s].y & 0xffffu);
+        d[3][0] = (int32_t)(int16_t)(buf[s].y >> 16);
+        mac8v<OPL, ND>(e[s], d, acc);
+        buf[s] = row(r + s + PF);
       }
-      mac8<OPL, ND>(pack + (uint64_t)m * 8, d, acc);
     }
-    if constexpr (WIDE) spill_high<OPL, ND>(acc, hi);
+#pragma unroll
+    for (uint32_t s = 0; s < PF; ++s) {   // last rows (fewer than PF)
+      if (fullr + s < rows) {
+        int32_t d[OPL][ND];
+        d[0][0] = (int32_t)(int16_t)(buf[s].x & 0xffffu);
+        d[1][0] = (int32_t)(int16_t)(buf[s].x >> 16);
+        d[2][0] = (int32_t)(int16_t)(buf[s].y & 0xffffu);
+        d[3][0] = (int32_t)(int16_t)(buf[s].y >> 16);
+        mac8<OPL, ND>(pack + (uint64_t)(m0 + fullr + s) * 8, d, acc);
+      }
+    }
+  } else {
+    uint32_t m = m0;
+    while (m < m1) {
+      const uint32_t bend = WIDE ? min(m + kSpill, m1) : m1;
+#pragma unroll 4
+      for (; m < bend; ++m) {
+        int32_t d[OPL][ND];
+#pragma unroll
+        for (int o = 0; o < OPL; ++o) {
+          const uint32_t n = n0 + o;
+          T x = 0;
+          if (n < n_out) x = ROWS ? Mg[(uint64_t)m * ld + n] : Mg[(uint64_t)n * ld + m];
+          entry_digits<T, ND, DB>(x, d[o], bad);
+        }
+        mac8<OPL, ND>(pack + (uint64_t)m * 8, d, acc);
+      }
+      if constexpr (WIDE) spill_high<OPL, ND>(acc, hi);
+    }
   }
   if constexpr (ND > 1 || sizeof(T) > 2) {
     if (bad && J.err) atomicOr(J.err, 1);
   }
 #pragma unroll
   for (int o = 0; o < OPL; ++o) {
-    const Fr r = finalize_digits<ND, DB>(acc[o], hi[o]);
+    uint32_t L[kLimbs];
+    digits_to_limbs<ND, DB>(acc[o], hi[o], L);
     const uint32_t n = n0 + o;
-    if (n < n_out) store_sol(J.dst + (uint64_t)chunk * J.chunk_stride, J.dst_ld, n, r);
+    if (J.chunk_stride == 0) {          // the whole contraction: final value
+      const Fr r = limbs_to_fr(L);
+      if (n < n_out) store_sol(J.dst, J.dst_ld, n, r);
+    } else if (n < n_out) {             // one chunk: raw limbs, reduced by finish_kernel
+      uint32_t* d = J.dst + (uint64_t)chunk * J.chunk_stride;
+#pragma unroll
+      for (int q = 0; q < kLimbs; ++q) d[q * J.dst_ld + n] = L[q];
+    }
   }
 }
 
 // ---------------------------------------------------------------- finish ----
+// One block per 64 outputs of a job: the four waves add up every fourth
+// chunk's raw limbs (64-bit sums per limb, exact), wave 0 combines them,
+// propagates the carries and reduces once.  Outputs past n_valid up to
+// n_total are the zero padding of the table.
 __global__ void __launch_bounds__(256) finish_kernel(const FinishJob* __restrict__ jobs,
-                                                     uint32_t n_jobs, uint32_t n_threads) {
-  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= n_threads) return;
+                                                     uint32_t n_jobs, uint32_t n_blocks) {
+  const uint32_t blk = blockIdx.x;
+  if (blk >= n_blocks) return;
   uint32_t lo = 0, hi = n_jobs;
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (jobs[mid].thread_begin <= tid) lo = mid; else hi = mid;
+    if (jobs[mid].block_begin <= blk) lo = mid; else hi = mid;
   }
   const FinishJob& J = jobs[lo];
-  const uint32_t i = tid - J.thread_begin;
-  if (i < J.n_valid) {
-    if (!J.part) return;
-    Fr s = load_sol(J.part, J.part_ld, i);
-    for (uint32_t c = 1; c < J.n_chunks; ++c)
-      s = fr_add(s, load_sol(J.part + (uint64_t)c * J.chunk_stride, J.part_ld, i));
-    store_sol(J.out, J.out_ld, i, s);
-  } else if (i < J.n_total) {
-    store_sol(J.out, J.out_ld, i, fr_zero());
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  const uint32_t i = (blk - J.block_begin) * 64u + lane;
+  __shared__ int64_t red[3][kLimbs][64];
+  if (!J.part) {
+    if (wave == 0 && i >= J.n_valid && i < J.n_total) store_sol(J.out, J.out_ld, i, fr_zero());
+    return;
   }
+  int64_t T[kLimbs];
+#pragma unroll
+  for (int q = 0; q < kLimbs; ++q) T[q] = 0;
+  if (i < J.n_valid) {
+    const gptr<uint32_t> base = (gptr<uint32_t>)J.part + i;
+#pragma unroll 4
+    for (uint32_t c = wave; c < J.n_chunks; c += 4) {
+      const gptr<uint32_t> p = base + (uint64_t)c * J.chunk_stride;
+#pragma unroll
+      for (int q = 0; q < kLimbs - 1; ++q) T[q] += (int64_t)p[q * J.part_ld];
+      T[kLimbs - 1] += (int64_t)(int32_t)p[(kLimbs - 1) * J.part_ld];
+    }
+  }
+  if (wave > 0)
+#pragma unroll
+    for (int q = 0; q < kLimbs; ++q) red[wave - 1][q][lane] = T[q];
+  __syncthreads();
+  if (wave != 0 || i >= J.n_total) return;
+  if (i >= J.n_valid) {
+    store_sol(J.out, J.out_ld, i, fr_zero());
+    return;
+  }
+#pragma unroll
+  for (int w = 0; w < 3; ++w)
+#pragma unroll
+    for (int q = 0; q < kLimbs; ++q) T[q] += red[w][q][lane];
+  // each T[q] < n_chunks * 2^32 in magnitude: carries fit in 64 bits
+  uint32_t L[kLimbs];
+  int64_t carry = 0;
+#pragma unroll
+  for (int q = 0; q < kLimbs; ++q) {
+    const int64_t v = T[q] + carry;
+    L[q] = (uint32_t)v;
+    carry = v >> 32;
+  }
+  store_sol(J.out, J.out_ld, i, limbs_to_fr(L));
 }
 
 // ---------------------------------------------------------------- rounds ----
@@ -458,11 +562,19 @@ __device__ __forceinline__ void block_sum(Fr (&v)[K], uint32_t* lds) {
   __syncthreads();
 }
 
-__device__ __forceinline__ void put_fr(uint8_t* dst, const Fr& mont) {
-  const Fr c = fr_from_mont(mont);
-  uint8_t b[32];
-  fr_to_bytes(c, b);
-  for (int i = 0; i < 32; ++i) dst[i] = b[i];
+
+// canonical element c to 32 proof bytes (little-endian words); word stores
+// when the destination is 4-byte aligned
+__device__ __forceinline__ void put_canon(uint8_t* dst, const Fr& c) {
+  if ((reinterpret_cast<uintptr_t>(dst) & 3u) == 0) {
+    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) d[j] = c.w[j];
+  } else {
+    uint8_t b[32];
+    fr_to_bytes(c, b);
+    for (int i = 0; i < 32; ++i) dst[i] = b[i];
+  }
 }
 
 __device__ __forceinline__ void lds_put(uint32_t* dst, const Fr& v) {
@@ -486,6 +598,10 @@ __device__ __forceinline__ Fr at_two(const Fr& a, const Fr& b) { return fr_sub(f
 // the proof bytes unchanged.
 __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* __restrict__ jobs) {
   const RoundsJob& J = jobs[blockIdx.x];
+  // the rounds are one serial chain per group (transcript hashing on a
+  // single lane); when they overlap contraction kernels on the same CUs,
+  // their waves go first
+  __builtin_amdgcn_s_setprio(3);
   __shared__ uint32_t red[3 * 8 * (kRoundsBlock / kWave)];
   __shared__ uint32_t first[VL_MAX_PRODS][3][8];   // round-1 values per product
   __shared__ uint32_t bcast[2][8];                 // r and the next claim
@@ -534,26 +650,23 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
   }
   __syncthreads();
 
+  // the transcript lives in thread 0; every thread keeps the same proof cursor
   Transcript tr;
   uint8_t* out = J.proof;
   if (tid == 0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) tr.h[i] = J.st[i];
     const Fr cc[1] = {fr_from_mont(c)};
-    put_fr(out, c);
-    out += 32;
+    put_canon(out, cc[0]);
     tr_absorb_frs(tr, VL_LBL_CLAIM, cc);
     for (uint32_t p = 0; p + 1 < J.n_prods; ++p) {
-      const Fr sp = fr_add(lds_get(first[p][0]), lds_get(first[p][1]));
-      const Fr sc[1] = {fr_from_mont(sp)};
-      put_fr(out, sp);
-      out += 32;
+      const Fr sc[1] = {fr_from_mont(fr_add(lds_get(first[p][0]), lds_get(first[p][1])))};
+      put_canon(out + 32 * (1 + p), sc[0]);
       tr_absorb_frs(tr, VL_LBL_PART, sc);
     }
   }
-  const Fr one = fr_R(), two = fr_double(fr_R());
-  const Fr inv2 = fr_from_limbs(0xffffffffu, 0x00000000u, 0x0001a401u, 0xac425bfdu, 0xf65e27fau,
-                                0xccc627f7u, 0xd66282b7u, 0x0c1258acu);  // 2^-1 R mod p
+  out += 32 * J.n_prods;
+  const Fr one = fr_R();
   for (uint32_t p = 0; p < J.n_prods; ++p) {
     const RoundsProd& P = J.prods[p];
     uint32_t* a = P.a;
@@ -580,23 +693,29 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
         g[1] = fr_sub(claim, q[0]);
         g[2] = q[1];
       }
-      if (tid == 0) {
+      // wave 0: lane k < 3 converts g(k) to canonical form and writes it to
+      // the proof; lane 0 then runs the transcript on the gathered values
+      if (tid < kWave) {
+        const Fr mine = tid == 0 ? g[0] : (tid == 1 ? g[1] : g[2]);
+        const Fr cm = fr_from_mont(mine);
+        if (tid < 3) put_canon(out + 32 * tid, cm);
         Fr gc[3];
-        for (int k = 0; k < 3; ++k) {
-          gc[k] = fr_from_mont(g[k]);
-          put_fr(out, g[k]);
-          out += 32;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) gc[k].w[j] = __builtin_amdgcn_readlane(cm.w[j], k);
+        out += 96;
+        if (tid == 0) {
+          tr_absorb_frs(tr, VL_LBL_ROUND, gc);
+          const Fr r = fr_to_mont(tr_squeeze_fixed(tr, VL_LBL_R));
+          // g(r) in Newton form on {0, 1, 2}: g0 + r (d1 + (r - 1) h2) with
+          // d1 = g1 - g0 and h2 = (g2 - 2 g1 + g0) / 2
+          const Fr d1 = fr_sub(g[1], g[0]);
+          const Fr h2 = fr_half(fr_add(fr_sub(g[2], fr_double(g[1])), g[0]));
+          const Fr next = fr_add(g[0], fr_mul(r, fr_add(d1, fr_mul(fr_sub(r, one), h2))));
+          lds_put(bcast[0], r);
+          lds_put(bcast[1], next);
         }
-        tr_absorb_frs(tr, VL_LBL_ROUND, gc);
-        const Fr r = fr_to_mont(tr_squeeze_fixed(tr, VL_LBL_R));
-        // g(r) = g0 (r-1)(r-2)/2 - g1 r (r-2) + g2 r (r-1)/2
-        const Fr rm1 = fr_sub(r, one), rm2 = fr_sub(r, two);
-        const Fr l0 = fr_mul(fr_mul(rm1, rm2), inv2);
-        const Fr l1 = fr_neg(fr_mul(r, rm2));
-        const Fr l2 = fr_mul(fr_mul(r, rm1), inv2);
-        const Fr next = fr_add(fr_add(fr_mul(g[0], l0), fr_mul(g[1], l1)), fr_mul(g[2], l2));
-        lds_put(bcast[0], r);
-        lds_put(bcast[1], next);
       }
       __syncthreads();
       const Fr r = lds_get(bcast[0]);
@@ -612,16 +731,13 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
     }
     if (tid == 0) {
       Fr fin[2];
-      fin[0] = load_sol(a, ld, 0);
-      fin[1] = load_sol(b, ld, 0);
-      put_fr(out, fin[0]);
-      out += 32;
-      put_fr(out, fin[1]);
-      out += 32;
-      fin[0] = fr_from_mont(fin[0]);
-      fin[1] = fr_from_mont(fin[1]);
+      fin[0] = fr_from_mont(load_sol(a, ld, 0));
+      fin[1] = fr_from_mont(load_sol(b, ld, 0));
+      put_canon(out, fin[0]);
+      put_canon(out + 32, fin[1]);
       tr_absorb_frs(tr, VL_LBL_FINAL, fin);
     }
+    out += 64;
     __syncthreads();
   }
   if (tid == 0) {
@@ -715,12 +831,14 @@ hipError_t launch_contract(int kind, const ContractJob* jobs, uint32_t n_jobs, u
     VL_CK(CK_I16_ROWS4_VEC, int16_t, 1, 16, true, true, 4)
     VL_CK(CK_I16_COLS, int16_t, 1, 16, false, false, 1)
     VL_CK(CK_I16_COLS_VEC, int16_t, 1, 16, false, true, 1)
+    VL_CK(CK_I16_COLS2_VEC, int16_t, 1, 16, false, true, 2)
     VL_CK(CK_I32_ROWS, int32_t, 2, 24, true, false, 1)
     VL_CK(CK_I32_COLS, int32_t, 2, 24, false, false, 1)
     VL_CK(CK_I32_COLS_VEC, int32_t, 2, 24, false, true, 1)
     VL_CK(CK_I64S_ROWS, int64_t, 2, 24, true, false, 1)
     VL_CK(CK_I64S_COLS, int64_t, 2, 24, false, false, 1)
     VL_CK(CK_I64S_COLS_VEC, int64_t, 2, 24, false, true, 1)
+    VL_CK(CK_I64S_COLS2_VEC, int64_t, 2, 24, false, true, 2)
     VL_CK(CK_I64_ROWS, int64_t, 3, 24, true, false, 1)
     VL_CK(CK_I64_COLS, int64_t, 3, 24, false, false, 1)
     VL_CK(CK_I64_COLS_VEC, int64_t, 3, 24, false, true, 1)
@@ -729,10 +847,9 @@ hipError_t launch_contract(int kind, const ContractJob* jobs, uint32_t n_jobs, u
 #undef VL_CK
 }
 
-hipError_t launch_finish(const FinishJob* jobs, uint32_t n_jobs, uint32_t n_threads, hipStream_t s) {
-  if (n_threads == 0) return hipSuccess;
-  hipLaunchKernelGGL(finish_kernel, dim3(blocks_for(n_threads, 256)), dim3(256), 0, s, jobs, n_jobs,
-                     n_threads);
+hipError_t launch_finish(const FinishJob* jobs, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s) {
+  if (n_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(finish_kernel, dim3(n_blocks), dim3(256), 0, s, jobs, n_jobs, n_blocks);
   return hipGetLastError();
 }
 

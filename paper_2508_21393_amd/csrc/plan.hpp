@@ -27,30 +27,48 @@ struct Challenges {
   std::vector<Fr> u, v;
 };
 
+constexpr uint32_t kMaxSegments = 8;
+constexpr uint32_t kDefaultSegments = 1;
+
 struct Tuning {
   bool per_instance = false;
   uint32_t lane_macs = 16384;     // multiply-adds per lane and contraction task
+  uint32_t segments = 1;          // pipeline segments (batched mode)
   uint32_t min_tasks = 1;         // split a contraction until it has this many tasks
+  uint32_t cols_rows = 1;         // rows per lane, vector cols kernels (1 or 2)
 };
 
-struct Plan {
-  std::vector<uint8_t> blob;      // host image of [err flags][jobs...][points]
-  uint64_t data_end = 0;          // workspace bytes used
-  std::vector<EqJob> eq;
-  uint32_t eq_threads = 0;
+// Jobs of one pipeline segment: its groups' contractions, finish jobs and
+// rounds.  Segments run their contractions in order on the caller's stream;
+// a segment's rounds start on a second stream as soon as its contractions
+// are done, overlapping the later segments' contractions.
+struct Segment {
   std::vector<ContractJob> cj[CK_COUNT];
   uint32_t cj_tasks[CK_COUNT] = {};
   std::vector<FinishJob> fin;
-  uint32_t fin_threads = 0;
+  uint32_t fin_blocks = 0;
   std::vector<RoundsJob> rounds;
+};
+
+struct Plan {
+  std::vector<uint8_t> blob;      // host image of [err flags][eq jobs][points][segments]
+  uint64_t data_end = 0;          // workspace bytes used
+  std::vector<EqJob> eq;
+  uint32_t eq_threads = 0;
+  std::vector<Segment> seg;
   std::vector<std::vector<uint32_t>> points;  // per eq job: (x_j, 1 - x_j) Montgomery
   uint32_t n_err = 0;
   uint64_t out_off = 0;                       // blocking mode: gathered proofs|status|digests
   uint64_t out_proof_bytes = 0;
 };
 
+struct SegLayout {
+  uint64_t cj[CK_COUNT], fin, rounds;
+};
+
 struct BlobLayout {
-  uint64_t err, eq, cj[CK_COUNT], fin, rounds, points, total;
+  uint64_t err, eq, points, total;
+  std::vector<SegLayout> seg;
 };
 
 // Builds jobs; device addresses are base + workspace offset (base 0 = sizing).
@@ -59,7 +77,11 @@ struct Builder {
   const Tuning& T;
   uint64_t base;
   uint64_t off;
-  Builder(Plan& p, const Tuning& t, uint64_t b, uint64_t start) : P(p), T(t), base(b), off(start) {}
+  size_t cur = 0;                 // segment receiving new jobs
+  Builder(Plan& p, const Tuning& t, uint64_t b, uint64_t start) : P(p), T(t), base(b), off(start) {
+    if (P.seg.empty()) P.seg.resize(1);
+  }
+  Segment& S() { return P.seg[cur]; }
   uint64_t take(uint64_t bytes) {
     off = align_up(off, 256);
     const uint64_t r = off;
@@ -78,19 +100,21 @@ struct Builder {
 BlobLayout blob_layout(const Plan& P);
 uint64_t blob_bound(const vl_group* groups, uint64_t n);
 void fill_blob(Plan& P, const BlobLayout& L, uint8_t* dblob);
-// HIP events around each stage (blocking mode timing)
+// HIP events around every launch (blocking mode timing); one pair per
+// launch, summed per stage after the call's streams are synchronised.
 struct StageEvents {
-  hipEvent_t ev[2 * VL_STAGE_COUNT] = {};
-  bool used[VL_STAGE_COUNT] = {};
-  hipError_t create();
+  std::vector<hipEvent_t> pool;
+  std::vector<int> stage;     // stage of pair i (events 2i, 2i+1)
+  hipError_t begin(int st, hipStream_t s);
+  hipError_t end(int st, hipStream_t s);
+  void accumulate(float* ms);
   void destroy();
-  hipError_t begin(int stage, hipStream_t s);
-  hipError_t end(int stage, hipStream_t s);
-  void accumulate(float* ms);  // after the stream has been synchronised
 };
 
+// Enqueue a filled plan on stream s; rounds of segment k run on stream s2
+// after segment k's contractions (s2 may equal s: then everything is serial).
 hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipStream_t s,
-                        StageEvents* ev = nullptr);
+                        hipStream_t s2, StageEvents* ev = nullptr);
 Tuning tuning_for(const vl_prove_opts* o);
 void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, uint64_t g1,
                  uint64_t seed, uint8_t* ws, bool async, uint8_t* proofs_dev, const uint64_t* offsets,

@@ -18,6 +18,31 @@ namespace vl {
 
 VL_HD uint32_t rotr32(uint32_t x, int n) { return (x >> n) | (x << (32 - n)); }
 
+// Three-input helpers.  On the device each is one VALU instruction
+// (v_add3_u32, v_bfi_b32), which the compiler does not form by itself here;
+// the SHA-256 rounds of the transcript run on a single lane and are latency
+// bound, so instruction count is time.
+VL_HD uint32_t add3_u32(uint32_t a, uint32_t b, uint32_t c) {
+#if __HIP_DEVICE_COMPILE__
+  uint32_t r;
+  asm("v_add3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+#else
+  return a + b + c;
+#endif
+}
+
+// bitwise select: bits of x where m is 1, bits of y where m is 0
+VL_HD uint32_t bitsel(uint32_t m, uint32_t x, uint32_t y) {
+#if __HIP_DEVICE_COMPILE__
+  uint32_t r;
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(m), "v"(x), "v"(y));
+  return r;
+#else
+  return (m & x) | (~m & y);
+#endif
+}
+
 // FIPS 180-4 compression of one block given as 16 big-endian message words
 VL_HD void sha256_compress_w(uint32_t h[8], const uint32_t (&win)[16]) {
   const uint32_t K[64] = {
@@ -44,16 +69,15 @@ VL_HD void sha256_compress_w(uint32_t h[8], const uint32_t (&win)[16]) {
       const uint32_t w15 = w[(i - 15) & 15], w2 = w[(i - 2) & 15];
       const uint32_t s0 = rotr32(w15, 7) ^ rotr32(w15, 18) ^ (w15 >> 3);
       const uint32_t s1 = rotr32(w2, 17) ^ rotr32(w2, 19) ^ (w2 >> 10);
-      wi = w[i & 15] + s0 + w[(i - 7) & 15] + s1;
+      wi = add3_u32(w[i & 15], s0, w[(i - 7) & 15]) + s1;
       w[i & 15] = wi;
     }
     const uint32_t S1 = rotr32(e, 6) ^ rotr32(e, 11) ^ rotr32(e, 25);
-    const uint32_t ch = (e & f) ^ (~e & g);
-    const uint32_t t1 = hh + S1 + ch + K[i] + wi;
+    const uint32_t ch = bitsel(e, f, g);                 // Ch(e, f, g)
+    const uint32_t t1 = add3_u32(hh, S1, ch) + (wi + K[i]);
     const uint32_t S0 = rotr32(a, 2) ^ rotr32(a, 13) ^ rotr32(a, 22);
-    const uint32_t mj = (a & b) ^ (a & c) ^ (b & c);
-    const uint32_t t2 = S0 + mj;
-    hh = g; g = f; f = e; e = d + t1; d = c; c = b; b = a; a = t1 + t2;
+    const uint32_t mj = bitsel(a ^ b, c, a);             // Maj(a, b, c)
+    hh = g; g = f; f = e; e = d + t1; d = c; c = b; b = a; a = add3_u32(t1, S0, mj);
   }
   h[0] += a; h[1] += b; h[2] += c; h[3] += d; h[4] += e; h[5] += f; h[6] += g; h[7] += hh;
 }
