@@ -165,6 +165,7 @@ def main():
     dev = lambda x: torch.from_numpy(x).to("cuda")  # noqa: E731
     gas = [B.GroupArgs(g.group_id, [(dev(p.A), dev(p.B), p.transA, p.transB) for p in g.products],
                        dev(g.C)) for g in groups]
+    batch = B.GroupBatch(gas)   # the vl_group array, built once for every call
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
     shapes = [g.shapes for g in groups]
@@ -173,11 +174,11 @@ def main():
     tun = B.tuning(args.lane_macs, args.min_tasks, args.segments, args.cols_rows)
     tried = None
     if args.autotune:
-        tun, tried = autotune(B, gas, w.seed, mode)
-    workspace = torch.empty(B.workspace_size(gas, mode, tuning_=tun), dtype=torch.uint8, device="cuda")
+        tun, tried = autotune(B, batch, w.seed, mode)
+    workspace = torch.empty(B.workspace_size(batch, mode, tuning_=tun), dtype=torch.uint8, device="cuda")
 
     def step(stage=None):
-        return B.sumcheck_matmul_prove(gas, w.seed, mode=mode, workspace=workspace, stage_ms=stage, tuning_=tun)
+        return B.sumcheck_matmul_prove(batch, w.seed, mode=mode, workspace=workspace, stage_ms=stage, tuning_=tun)
 
     for _ in range(args.warmup):
         ref, ref_dig = step()
@@ -202,13 +203,13 @@ def main():
     # per-instance prover on the same inputs (the baseline the batched path must beat)
     per_inst_ms = None
     if mode != B.VL_MODE_PER_INSTANCE and args.per_instance_steps > 0:
-        ws_pi = torch.empty(B.workspace_size(gas, B.VL_MODE_PER_INSTANCE), dtype=torch.uint8, device="cuda")
-        pi, _ = B.sumcheck_matmul_prove(gas, w.seed, mode=B.VL_MODE_PER_INSTANCE, workspace=ws_pi)
+        ws_pi = torch.empty(B.workspace_size(batch, B.VL_MODE_PER_INSTANCE), dtype=torch.uint8, device="cuda")
+        pi, _ = B.sumcheck_matmul_prove(batch, w.seed, mode=B.VL_MODE_PER_INSTANCE, workspace=ws_pi)
         assert pi == ref, "per-instance proofs differ from the batched ones"
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(args.per_instance_steps):
-            B.sumcheck_matmul_prove(gas, w.seed, mode=B.VL_MODE_PER_INSTANCE, workspace=ws_pi)
+            B.sumcheck_matmul_prove(batch, w.seed, mode=B.VL_MODE_PER_INSTANCE, workspace=ws_pi)
         torch.cuda.synchronize()
         per_inst_ms = 1e3 * (time.perf_counter() - t1) / args.per_instance_steps
         del ws_pi

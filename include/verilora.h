@@ -136,8 +136,10 @@ typedef struct {
                                   cols-vec (1 or 2 rows per lane); int64 rows,
                                   cols, cols-vec                                   */
 #define VL_STAGE_FINISH 18     /* split-contraction sums and zero padding          */
-#define VL_STAGE_ROUNDS 19     /* claim, prover guard, sumcheck rounds, proof bytes */
-#define VL_STAGE_COUNT 20
+#define VL_STAGE_PASS1 19      /* claim c and round 1 of every product, as partial
+                                  sums across the GPU                              */
+#define VL_STAGE_ROUNDS 20     /* prover guard, sumcheck rounds, proof bytes       */
+#define VL_STAGE_COUNT 21
 
 /* Lift n signed integers (dtype) at device pointer src into Fr (Montgomery,
  * structure-of-limbs) at dst (dst.n >= n).  Negative x becomes p - |x|. */

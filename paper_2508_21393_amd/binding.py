@@ -18,10 +18,11 @@ VL_I16, VL_I32, VL_I64 = 1, 2, 3
 VL_CONTRACT_ROWS, VL_CONTRACT_COLS = 0, 1
 VL_MODE_PER_INSTANCE, VL_MODE_BATCHED, VL_MODE_PERSISTENT = 0, 1, 2
 VL_MAX_PRODS = 8
-VL_STAGE_COUNT = 20
+VL_STAGE_COUNT = 21
 STAGE_NAMES = ["upload", "eq", "i16_rows", "i16_rows4", "i16_rows4_vec", "i16_cols", "i16_cols_vec",
                "i16_cols2_vec", "i32_rows", "i32_cols", "i32_cols_vec", "i64s_rows", "i64s_cols",
-               "i64s_cols_vec", "i64s_cols2_vec", "i64_rows", "i64_cols", "i64_cols_vec", "finish", "rounds"]
+               "i64s_cols_vec", "i64s_cols2_vec", "i64_rows", "i64_cols", "i64_cols_vec", "finish", "pass1",
+               "rounds"]
 
 STATUS_NAMES = {0: "VL_OK", 1: "VL_ERR_INVALID_ARG", 2: "VL_ERR_SHAPE", 3: "VL_ERR_DTYPE",
                 4: "VL_ERR_WORKSPACE", 5: "VL_ERR_HIP", 6: "VL_ERR_FALSE_STATEMENT",
@@ -200,6 +201,33 @@ def group_array(groups: Sequence[GroupArgs]):
     return arr
 
 
+class GroupBatch:
+    """The vl_group array of a list of groups with their proof sizes, built
+    once and reusable for any number of prove calls over the same operand
+    buffers (their contents may change between calls)."""
+
+    def __init__(self, groups: Sequence[GroupArgs]):
+        self.groups = list(groups)
+        self.arr = group_array(self.groups)
+        self.sizes = [proof_size(g) for g in self.groups]
+        self.total = sum(self.sizes)
+        self._ws = {}
+
+    def __len__(self):
+        return len(self.groups)
+
+    def workspace_size(self, mode: int, async_: bool = False, tuning_=None) -> int:
+        key = (mode, bool(async_), None if tuning_ is None else bytes(tuning_))
+        if key not in self._ws:
+            opts = vl_prove_opts(mode, int(async_), None, 0, None, _tun(tuning_), None)
+            self._ws[key] = lib().vl_workspace_size(self.arr, len(self.groups), ctypes.byref(opts))
+        return self._ws[key]
+
+
+def _batch(groups) -> GroupBatch:
+    return groups if isinstance(groups, GroupBatch) else GroupBatch(groups)
+
+
 # ---------------------------------------------------------------- the ABI ----
 def fr_lift(src, n: int, dst: vl_fr_vec, stream=None):
     _check(lib().vl_fr_lift(_ptr(src), dtype_code(src.dtype), n, dst, _stream(stream)))
@@ -229,34 +257,33 @@ def proof_size(group: GroupArgs) -> int:
     return lib().vl_proof_size(ctypes.byref(group.struct))
 
 
-def workspace_size(groups: Sequence[GroupArgs], mode: int = VL_MODE_BATCHED, async_: bool = False,
-                   tuning_=None) -> int:
-    arr = group_array(groups)
-    opts = vl_prove_opts(mode, int(async_), None, 0, None, _tun(tuning_), None)
-    return lib().vl_workspace_size(arr, len(groups), ctypes.byref(opts))
+def workspace_size(groups, mode: int = VL_MODE_BATCHED, async_: bool = False, tuning_=None) -> int:
+    """Workspace bytes for a list of GroupArgs or a GroupBatch."""
+    return _batch(groups).workspace_size(mode, async_, tuning_)
 
 
-def sumcheck_matmul_prove(groups: Sequence[GroupArgs], seed: int, mode: int = VL_MODE_BATCHED,
+def sumcheck_matmul_prove(groups, seed: int, mode: int = VL_MODE_BATCHED,
                           workspace=None, stream=None, with_digests: bool = True, stage_ms=None,
                           tuning_=None):
-    """Blocking prove: returns (list of proof bytes, list of 32-byte digests).
+    """Blocking prove of a list of GroupArgs (or a GroupBatch): returns
+    (list of proof bytes, list of 32-byte digests).
 
     ``stage_ms``: optional list that receives VL_STAGE_COUNT per-stage device
     times (HIP events) of this call.  ``tuning_``: optional vl_tuning."""
     import torch
-    arr = group_array(groups)
-    n = len(groups)
-    ws_bytes = workspace_size(groups, mode, tuning_=tuning_)
+    batch = _batch(groups)
+    n = len(batch)
     if workspace is None:
+        ws_bytes = batch.workspace_size(mode, False, tuning_)
         workspace = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device="cuda")
     timing = (ctypes.c_float * VL_STAGE_COUNT)() if stage_ms is not None else None
     opts = vl_prove_opts(mode, 0, workspace.data_ptr(), workspace.numel(), None, _tun(tuning_),
                          ctypes.addressof(timing) if timing is not None else None)
-    total = sum(proof_size(g) for g in groups)
+    total = batch.total
     buf = ctypes.create_string_buffer(max(total, 1))
     offs = (c_u64 * (n + 1))()
     dig = ctypes.create_string_buffer(32 * n) if with_digests else None
-    _check(lib().vl_sumcheck_matmul_prove(arr, n, seed, ctypes.byref(opts), ctypes.addressof(buf), total,
+    _check(lib().vl_sumcheck_matmul_prove(batch.arr, n, seed, ctypes.byref(opts), ctypes.addressof(buf), total,
                                           offs, ctypes.addressof(dig) if dig is not None else None,
                                           _stream(stream)))
     if timing is not None:
@@ -272,12 +299,12 @@ def sumcheck_matmul_prove_async(groups: Sequence[GroupArgs], seed: int, proofs_d
                                 tuning_=None):
     """Enqueue a prove on the stream; proofs/status/digests land in device
     buffers.  Returns the host offsets of each group's proof."""
-    arr = group_array(groups)
-    n = len(groups)
+    batch = _batch(groups)
+    n = len(batch)
     opts = vl_prove_opts(mode, 1, workspace.data_ptr(), workspace.numel(), status_dev.data_ptr(),
                          _tun(tuning_), None)
     offs = (c_u64 * (n + 1))()
-    _check(lib().vl_sumcheck_matmul_prove(arr, n, seed, ctypes.byref(opts), proofs_dev.data_ptr(),
+    _check(lib().vl_sumcheck_matmul_prove(batch.arr, n, seed, ctypes.byref(opts), proofs_dev.data_ptr(),
                                           proofs_dev.numel(), offs,
                                           digests_dev.data_ptr() if digests_dev is not None else None,
                                           _stream(stream)))

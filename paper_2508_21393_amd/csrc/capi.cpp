@@ -83,6 +83,70 @@ vl_status check_group(const vl_group& g, bool need_ptrs) {
 
 // The rounds stream paired with a caller's stream (default priority), created
 // on first use and kept for the life of the process.
+// Descriptor upload.  Small images go as kernel arguments (no host buffer
+// to keep alive, nothing to wait for); larger ones through a ring of pinned
+// host buffers per device, one asynchronous copy each.  A slot is reused
+// only after the copy it last issued has completed (an event per slot), so
+// the host waits only if kStagingSlots uploads are still in flight.
+constexpr int kStagingSlots = 4;
+constexpr uint64_t kArgUploadMax = 4 * kUploadBytes;
+
+struct StagingRing {
+  struct Slot {
+    void* host = nullptr;
+    uint64_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool issued = false;
+  };
+  std::mutex mu;
+  Slot slot[kStagingSlots];
+  int next = 0;
+};
+
+static hipError_t upload_blob(void* dst, const void* src, uint64_t bytes, hipStream_t s) {
+  if (bytes <= kArgUploadMax) return launch_upload(dst, src, bytes, s);
+  static std::mutex mu;
+  static std::map<int, StagingRing*> rings;   // per device, live for the process
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  StagingRing* ring;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    StagingRing*& r = rings[dev];
+    if (!r) r = new StagingRing();
+    ring = r;
+  }
+  std::lock_guard<std::mutex> lock(ring->mu);
+  StagingRing::Slot& sl = ring->slot[ring->next];
+  ring->next = (ring->next + 1) % kStagingSlots;
+  if (sl.issued) {
+    e = hipEventSynchronize(sl.done);
+    if (e != hipSuccess) return e;
+    sl.issued = false;
+  }
+  if (!sl.done) {
+    e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  if (sl.cap < bytes) {
+    if (sl.host) (void)hipHostFree(sl.host);
+    sl.host = nullptr;
+    sl.cap = 0;
+    const uint64_t cap = align_up(bytes + bytes / 2, 1 << 16);
+    e = hipHostMalloc(&sl.host, cap, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    sl.cap = cap;
+  }
+  memcpy(sl.host, src, bytes);
+  e = hipMemcpyAsync(dst, sl.host, bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(sl.done, s);
+  if (e != hipSuccess) return e;
+  sl.issued = true;
+  return hipSuccess;
+}
+
 hipError_t rounds_stream_for(hipStream_t s, hipStream_t* out) {
   static std::mutex mu;
   static std::map<std::pair<int, hipStream_t>, hipStream_t> streams;
@@ -135,8 +199,10 @@ void all_challenges(const vl_group* groups, uint64_t g0, uint64_t g1, uint64_t s
   auto work = [&](uint64_t lo, uint64_t hi) {
     for (uint64_t i = lo; i < hi; ++i) group_challenges(groups[g0 + i], seed, out[i].tr, out[i].u, out[i].v);
   };
+  // a group costs a few microseconds of hashing (tens of blocks): threads
+  // only pay off for a dozen groups or more each
   const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
-  const uint64_t nt = std::min<uint64_t>(hw, n / 4);
+  const uint64_t nt = std::min<uint64_t>(hw, n / 12);
   if (nt <= 1) {
     work(0, n);
     return;
@@ -234,9 +300,10 @@ void Builder::contract(const void* M, int dtype, int nd, uint64_t ld, bool rows,
   }
 }
 
-void Builder::eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_len) {
+void Builder::eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_len, bool pack_r2) {
   EqJob e{};
   e.nvars = (uint32_t)x.size();
+  e.pack_r2 = pack_r2 ? 1u : 0u;
   e.pack_len = pack_len;
   e.thread_begin = P.eq_threads;
   e.eq = eq;
@@ -245,9 +312,7 @@ void Builder::eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uin
   std::vector<uint32_t> pts;
   for (const Fr& xi : x) {
     const Fr xm = fr_to_mont(xi);
-    const Fr om = fr_sub(fr_R(), xm);
     pts.insert(pts.end(), xm.w, xm.w + 8);
-    pts.insert(pts.end(), om.w, om.w + 8);
   }
   P.points.push_back(pts);
   const uint32_t threads = std::max<uint32_t>(1, (uint32_t)((1ull << x.size()) / 2));
@@ -267,8 +332,11 @@ void Builder::group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev,
   uint32_t* packU = dev<uint32_t>(take((uint64_t)D0 * 32));
   uint32_t* packV = dev<uint32_t>(take((uint64_t)D2 * 32));
   uint32_t* tvec = dev<uint32_t>(take(8 * L0 * 4));
-  eq_job(u, eqU, packU, D0);
-  eq_job(v, nullptr, packV, D2);
+  // A~(u, w) in Montgomery form (pack of e R^2); B~(w, v) and the claim's
+  // t in canonical form (pack of e R): every product a * b of the rounds is
+  // then canonical, and so are the round values that go into the proof
+  eq_job(u, eqU, packU, D0, true);
+  eq_job(v, nullptr, packV, D2, false);
 
   // claim contraction: t[i] = sum_j C[i][j] eq(v, j).  Two 24-bit digits
   // cover |C| < 2^47 - 2^23, enough for sums of int16 products with a total
@@ -287,6 +355,7 @@ void Builder::group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev,
   contract(g.C, g.dtype_c, ndc, g.ldc, false, D0, D2, packV, tvec, L0, L0, err);
 
   RoundsJob rj{};
+  rj.c_part = pass1(eqU, L0, tvec, L0, (uint32_t)L0, true, rj.c_nparts);
   memcpy(rj.st, tr.h, 32);
   rj.n_prods = g.n_prods;
   rj.n0 = n0;
@@ -312,8 +381,28 @@ void Builder::group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev,
     rj.prods[k].b = b;
     rj.prods[k].ld = L1;
     rj.prods[k].n1 = n1;
+    // round 1 (for D1 = 1 the single product a[0] b[0])
+    rj.prods[k].g_part = n1 ? pass1(a, L1, b, L1, (uint32_t)(L1 / 2), false, rj.prods[k].g_nparts)
+                            : pass1(a, L1, b, L1, 1, true, rj.prods[k].g_nparts);
   }
   S().rounds.push_back(rj);
+}
+
+const uint32_t* Builder::pass1(const uint32_t* a, uint64_t a_ld, const uint32_t* b, uint64_t b_ld, uint32_t h,
+                               bool dot, uint32_t& nparts) {
+  Pass1Job j{};
+  j.a = a;
+  j.b = b;
+  j.a_ld = a_ld;
+  j.b_ld = b_ld;
+  j.h = h;
+  j.dot = dot ? 1u : 0u;
+  nparts = std::max<uint32_t>(1, (h + kPass1Pairs - 1) / kPass1Pairs);
+  j.block_begin = S().pass1_blocks;
+  j.out = dev<uint32_t>(take((uint64_t)nparts * 96));
+  S().pass1_blocks += nparts;
+  S().pass1.push_back(j);
+  return j.out;
 }
 
 BlobLayout blob_layout(const Plan& P) {
@@ -334,6 +423,8 @@ BlobLayout blob_layout(const Plan& P) {
     }
     L.seg[k].fin = o;
     o = align_up(o + G.fin.size() * sizeof(FinishJob), 64);
+    L.seg[k].pass1 = o;
+    o = align_up(o + G.pass1.size() * sizeof(Pass1Job), 64);
     L.seg[k].rounds = o;
     o = align_up(o + G.rounds.size() * sizeof(RoundsJob), 64);
   }
@@ -347,10 +438,11 @@ uint64_t blob_bound(const vl_group* groups, uint64_t n) {
     cj += 1 + 2ull * groups[i].n_prods;
     pts += 2ull * (nvars_of(groups[i].prods[0].D0) + nvars_of(groups[i].prods[0].D2)) * 32 + 128;
   }
-  // every segment may pad each of its CK_COUNT + 2 arrays to 64 bytes
+  // pass-1 jobs: the claim and one per product; every segment may pad each
+  // of its CK_COUNT + 3 arrays to 64 bytes
   return align_up(4 * n + 64 + 2 * n * (sizeof(EqJob) + 64) +
-                      cj * (sizeof(ContractJob) + sizeof(FinishJob) + 128) +
-                      n * (sizeof(RoundsJob) + 64) + pts + 64 * (CK_COUNT + 2) * (n + 1) + 1024,
+                      cj * (sizeof(ContractJob) + sizeof(FinishJob) + sizeof(Pass1Job) + 128) +
+                      n * (sizeof(RoundsJob) + 64) + pts + 64 * (CK_COUNT + 3) * (n + 1) + 1024,
                   256);
 }
 
@@ -370,6 +462,8 @@ void fill_blob(Plan& P, const BlobLayout& L, uint8_t* dblob) {
       if (!G.cj[c].empty())
         memcpy(P.blob.data() + L.seg[k].cj[c], G.cj[c].data(), G.cj[c].size() * sizeof(ContractJob));
     if (!G.fin.empty()) memcpy(P.blob.data() + L.seg[k].fin, G.fin.data(), G.fin.size() * sizeof(FinishJob));
+    if (!G.pass1.empty())
+      memcpy(P.blob.data() + L.seg[k].pass1, G.pass1.data(), G.pass1.size() * sizeof(Pass1Job));
     if (!G.rounds.empty())
       memcpy(P.blob.data() + L.seg[k].rounds, G.rounds.data(), G.rounds.size() * sizeof(RoundsJob));
   }
@@ -436,14 +530,20 @@ struct ForkEvents {
 
 hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipStream_t s,
                         hipStream_t s2, StageEvents* ev) {
-  thread_local ForkEvents fork;
+  thread_local std::map<int, ForkEvents> forks;   // per host thread and device
   const size_t nseg = P.seg.size();
   const bool two = s2 != s;
+  int dev = 0;
+  if (two) {
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+  }
+  ForkEvents& fork = forks[dev];
   if (two) {
     const hipError_t e = fork.need(nseg + 2);
     if (e != hipSuccess) return e;
   }
-  VL_STAGE(ev, VL_STAGE_UPLOAD, s, launch_upload(dblob, P.blob.data(), L.total, s));
+  VL_STAGE(ev, VL_STAGE_UPLOAD, s, upload_blob(dblob, P.blob.data(), L.total, s));
   VL_STAGE(ev, VL_STAGE_EQ, s,
            launch_eq(reinterpret_cast<const EqJob*>(dblob + L.eq), (uint32_t)P.eq.size(), P.eq_threads, s));
   if (two) {
@@ -464,6 +564,10 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
       VL_STAGE(ev, VL_STAGE_FINISH, s,
                launch_finish(reinterpret_cast<const FinishJob*>(dblob + L.seg[k].fin), (uint32_t)G.fin.size(),
                              G.fin_blocks, s));
+    if (!G.pass1.empty())
+      VL_STAGE(ev, VL_STAGE_PASS1, s,
+               launch_pass1(reinterpret_cast<const Pass1Job*>(dblob + L.seg[k].pass1), (uint32_t)G.pass1.size(),
+                            G.pass1_blocks, s));
     if (G.rounds.empty()) continue;
     if (two) {
       hipError_t e = hipEventRecord(fork.ev[k], s);
@@ -649,18 +753,19 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
   const Tuning T = tuning_for(o);
   const bool async = o->async != 0;
   Plan P;
-  StageEvents events;
+  // stage timing events: a pool per host thread and device, kept for the
+  // process (events belong to the device they were created on)
+  thread_local std::map<int, StageEvents> event_pools;
   StageEvents* ev = nullptr;
   if (o->stage_ms && !async) {
+    int dev = 0;
+    const hipError_t de = hipGetDevice(&dev);
+    if (de != hipSuccess) return fail(VL_ERR_HIP, "device: %s", hipGetErrorString(de));
+    StageEvents& events = event_pools[dev];
     for (int i = 0; i < VL_STAGE_COUNT; ++i) o->stage_ms[i] = 0.f;
+    events.stage.clear();
     ev = &events;
   }
-  struct Cleanup {
-    StageEvents* e;
-    ~Cleanup() {
-      if (e) e->destroy();
-    }
-  } cleanup{ev};
 
   // blocking mode: one copy of the gathered proofs, statuses and digests
   auto fetch = [&](uint64_t g0, uint64_t g1) -> vl_status {

@@ -20,8 +20,9 @@ struct EqJob {
   uint32_t nvars;
   uint32_t pack_len;          // entries to emit into pack (8 signed digits each)
   uint32_t thread_begin;      // prefix sum of threads over jobs in a launch
-  uint32_t pad_;
-  const uint32_t* point;      // device: 2 * nvars Montgomery elements, AoS (x_j, 1 - x_j)
+  uint32_t pack_r2;           // 1: pack holds e * R^2 (contractions land in Montgomery
+                              // form); 0: e * R (they land in canonical form)
+  const uint32_t* point;      // device: nvars Montgomery elements x_j (8 words each)
   uint32_t* eq;               // SoL Montgomery output, may be null
   uint64_t eq_ld;
   uint32_t* pack;             // pack_len * 8 words, may be null
@@ -83,12 +84,27 @@ struct FinishJob {
   uint64_t out_ld;
 };
 
+// Round 1 of one product (or the claim's dot product c = sum_i eqU[i] t[i])
+// as per-block partial sums, computed across the GPU before the rounds.
+constexpr uint32_t kPass1Pairs = 512;   // pairs (entries for the dot) per 256-thread block
+struct Pass1Job {
+  const uint32_t* a;          // SoL table (eqU for the claim)
+  const uint32_t* b;          // SoL table (t for the claim)
+  uint64_t a_ld, b_ld;
+  uint32_t h;                 // pairs (t, t + h), or entries of the dot product
+  uint32_t dot;               // 1: sum_i a[i] b[i]; 0: the round-1 values g(0), g(1), g(2)
+  uint32_t block_begin;       // prefix sum of blocks within a launch
+  uint32_t pad_;
+  uint32_t* out;              // 3 elements (24 words) per block
+};
+
 struct RoundsProd {
   uint32_t* a;
   uint32_t* b;
   uint64_t ld;
   uint32_t n1;
-  uint32_t pad_;
+  uint32_t g_nparts;          // pass-1 partials of round 1 (3 elements each)
+  const uint32_t* g_part;
 };
 
 // The sumcheck rounds of one group, run by one workgroup.
@@ -104,6 +120,9 @@ struct RoundsJob {
   int32_t* status;            // device status word of this group
   uint8_t* digest;            // device 32 bytes or null
   const int32_t* err;         // range flag of this group's contractions
+  const uint32_t* c_part;     // pass-1 partials of c (element 0 of each)
+  uint32_t c_nparts;
+  uint32_t pad_;
   RoundsProd prods[VL_MAX_PRODS];
 };
 
@@ -112,6 +131,7 @@ hipError_t launch_eq(const EqJob* jobs_dev, uint32_t n_jobs, uint32_t n_threads,
 hipError_t launch_contract(int kind, const ContractJob* jobs_dev, uint32_t n_jobs, uint32_t n_tasks,
                            hipStream_t s);
 hipError_t launch_finish(const FinishJob* jobs_dev, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s);
+hipError_t launch_pass1(const Pass1Job* jobs_dev, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s);
 hipError_t launch_rounds(const RoundsJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
 hipError_t launch_lift(const void* src, int dtype, uint64_t n, uint32_t* dst, uint64_t ld, hipStream_t s);
 hipError_t launch_export(const uint32_t* src, uint64_t ld, uint64_t n, uint32_t* dst, hipStream_t s);

@@ -82,22 +82,19 @@ __global__ void __launch_bounds__(256) eq_kernel(const EqJob* __restrict__ jobs,
     e0 = fr_R();
     e1 = fr_zero();
   } else {
+    // factor j is x_j for bit 1 and 1 - x_j for bit 0 (point: x_j only)
     Fr base = fr_R();
     for (uint32_t j = 0; j + 1 < n; ++j) {
       const uint32_t bit = (t >> (n - 2 - j)) & 1u;
-      const uint32_t* xp = J.point + (2 * j + (bit ? 0 : 1)) * 8;
       Fr x;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) x.w[k] = xp[k];
-      base = fr_mul(base, x);
+      for (int k = 0; k < 8; ++k) x.w[k] = J.point[j * 8 + k];
+      base = fr_mul(base, bit ? x : fr_sub(fr_R(), x));
     }
-    Fr xl, oml;
+    Fr xl;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      xl.w[k] = J.point[(2 * (n - 1)) * 8 + k];
-      oml.w[k] = J.point[(2 * (n - 1) + 1) * 8 + k];
-    }
-    e0 = fr_mul(base, oml);
+    for (int k = 0; k < 8; ++k) xl.w[k] = J.point[(n - 1) * 8 + k];
+    e0 = fr_mul(base, fr_sub(fr_R(), xl));
     e1 = fr_mul(base, xl);
   }
   if (J.eq) {
@@ -105,9 +102,9 @@ __global__ void __launch_bounds__(256) eq_kernel(const EqJob* __restrict__ jobs,
     if (2ull * t + 1 < len) store_sol(J.eq, J.eq_ld, 2ull * t + 1, e1);
   }
   if (J.pack) {
-    // pack: e * R^2 mod p as signed digits, 8 words per entry
-    if (2 * t < J.pack_len) signed_digits(fr_to_mont(e0), J.pack + (uint64_t)(2 * t) * 8);
-    if (2 * t + 1 < J.pack_len) signed_digits(fr_to_mont(e1), J.pack + (uint64_t)(2 * t + 1) * 8);
+    // pack: e * R^2 (or e * R) mod p as signed digits, 8 words per entry
+    if (2 * t < J.pack_len) signed_digits(J.pack_r2 ? fr_to_mont(e0) : e0, J.pack + (uint64_t)(2 * t) * 8);
+    if (2 * t + 1 < J.pack_len) signed_digits(J.pack_r2 ? fr_to_mont(e1) : e1, J.pack + (uint64_t)(2 * t + 1) * 8);
   }
 }
 
@@ -158,6 +155,17 @@ template <typename T, int ND, int DB>
 __device__ __forceinline__ void entry_digits(T x, int32_t (&d)[ND], uint32_t& bad) {
   if constexpr (ND == 1 && sizeof(T) == 2) {
     d[0] = (int32_t)x;
+  } else if constexpr (ND == 2 && DB == 24) {
+    // x = d0 + 2^24 d1: d0 the sign-extended low 24 bits, d1 = floor(x / 2^24)
+    // plus bit 23 (the borrow of a negative d0).  For int64 the entry must
+    // satisfy -2^47 <= x < 2^47, so d1 fits 32 bits (|d1| <= 2^23 keeps the
+    // int64 accumulators safe between spills); otherwise it is flagged.
+    const uint32_t lo = (uint32_t)(uint64_t)(int64_t)x;
+    const uint32_t hw = sizeof(T) == 8 ? (uint32_t)((uint64_t)(int64_t)x >> 32) : (uint32_t)((int32_t)lo >> 31);
+    d[0] = __builtin_amdgcn_sbfe((int32_t)lo, 0, 24);
+    const uint32_t top = sizeof(T) == 8 ? __builtin_amdgcn_alignbit(hw, lo, 24) : (uint32_t)((int32_t)lo >> 24);
+    d[1] = (int32_t)(top + __builtin_amdgcn_ubfe(lo, 23, 1));
+    if constexpr (sizeof(T) == 8) bad |= (hw + 0x8000u) >> 16;
   } else {
     int64_t r = (int64_t)x;
 #pragma unroll
@@ -321,54 +329,67 @@ contract_kernel(const ContractJob* __restrict__ jobs, uint32_t n_jobs, uint32_t 
   const gptr<T> Mg = (gptr<T>)M;
   if constexpr (VEC && !ROWS) {
     // cols layout, 16-byte aligned rows (m0 is a multiple of the vector
-    // width): OPL rows per lane, streamed 16 bytes at a time through a ring
-    // of PF vectors per row.  Lanes past the last row re-read the last row
-    // (their results are not stored); the prefetch index is clamped to the
-    // chunk, and the aligned 16-byte block holding a row's last entry never
-    // crosses a page, so every load stays inside the matrix's pages.
+    // width): OPL rows per lane.  Each lane reads its row 128 bytes at a
+    // time (GV 16-byte loads issued together, so every cache line is fetched
+    // once instead of being re-read after eviction), the next group in
+    // flight while this one is used.  Lanes past the last row re-read the
+    // last row (their results are not stored); load indices are clamped to
+    // the chunk, and the aligned 16-byte block holding a row's last entry
+    // never crosses a page, so every load stays inside the matrix's pages.
     constexpr uint32_t BE = 16 / sizeof(T);
-    constexpr uint32_t PF = 4;
-    constexpr uint32_t G = WIDE ? kSpill / (PF * BE) : 0;   // groups between spills
+    constexpr uint32_t GV = 8;
     const uint32_t span = m1 - m0, full = span / BE, nvec = (span + BE - 1) / BE;
     gptr<u32x4> rowp[OPL];
 #pragma unroll
     for (int o = 0; o < OPL; ++o)
       rowp[o] = (gptr<u32x4>)(Mg + (uint64_t)min(n0 + o, n_out - 1) * ld + m0);
-    u32x4 buf[PF][OPL];
+    auto ldg = [&](uint32_t g, u32x4 (&b)[GV][OPL]) {
 #pragma unroll
-    for (uint32_t s = 0; s < PF; ++s)
+      for (uint32_t v = 0; v < GV; ++v)
 #pragma unroll
-      for (int o = 0; o < OPL; ++o) buf[s][o] = rowp[o][min(s, nvec - 1)];
-    uint32_t grp = 0;
-    for (uint32_t v = 0; v < full; v += PF) {
+        for (int o = 0; o < OPL; ++o) b[v][o] = rowp[o][min(g * GV + v, nvec - 1)];
+    };
+    // one 16-byte vector: its eq digits in one batch of scalar loads (one
+    // wait), then the multiply-adds
+    auto vec16 = [&](const u32x4 (&x)[OPL], uint32_t v) {
+      ci32_ptr pe = pack + (uint64_t)(m0 + v * BE) * 8;
+      int32_t e[BE][8];
 #pragma unroll
-      for (uint32_t s = 0; s < PF; ++s) {
-        if (v + s < full) {
-          // the vector's eq digits in one batch of scalar loads, one wait
-          ci32_ptr pe = pack + (uint64_t)(m0 + (v + s) * BE) * 8;
-          int32_t e[BE][8];
+      for (uint32_t q = 0; q < BE; ++q)
 #pragma unroll
-          for (uint32_t q = 0; q < BE; ++q)
+        for (int j = 0; j < 8; ++j) e[q][j] = pe[q * 8 + j];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) e[q][j] = pe[q * 8 + j];
+      for (uint32_t q = 0; q < BE; ++q) {
+        int32_t d[OPL][ND];
 #pragma unroll
-          for (uint32_t q = 0; q < BE; ++q) {
-            int32_t d[OPL][ND];
-#pragma unroll
-            for (int o = 0; o < OPL; ++o) entry_digits<T, ND, DB>(((const T*)&buf[s][o])[q], d[o], bad);
-            mac8v<OPL, ND>(e[q], d, acc);
-          }
-        }
-#pragma unroll
-        for (int o = 0; o < OPL; ++o) buf[s][o] = rowp[o][min(v + s + PF, nvec - 1)];
+        for (int o = 0; o < OPL; ++o) entry_digits<T, ND, DB>(((const T*)&x[o])[q], d[o], bad);
+        mac8v<OPL, ND>(e[q], d, acc);
       }
-      if constexpr (WIDE) {
-        if (++grp == G) {
-          spill_high<OPL, ND>(acc, hi);
-          grp = 0;
-        }
+    };
+    // complete groups; wide entries spill their high words every kSpill
+    // entries (GB groups)
+    constexpr uint32_t GB = WIDE ? kSpill / (BE * GV) : 1;
+    const uint32_t ng = full / GV;
+    u32x4 cur[GV][OPL];
+    ldg(0, cur);
+    for (uint32_t gb = 0; gb < ng; gb += (WIDE ? GB : ng)) {
+      const uint32_t ge = WIDE ? min(gb + GB, ng) : ng;
+      for (uint32_t g = gb; g < ge; ++g) {
+        u32x4 nxt[GV][OPL];
+        ldg(g + 1, nxt);
+#pragma unroll
+        for (uint32_t v = 0; v < GV; ++v) vec16(cur[v], g * GV + v);
+#pragma unroll
+        for (uint32_t v = 0; v < GV; ++v)
+#pragma unroll
+          for (int o = 0; o < OPL; ++o) cur[v][o] = nxt[v][o];
       }
+      if constexpr (WIDE) spill_high<OPL, ND>(acc, hi);
     }
+    // the full vectors of the last, incomplete group (already loaded)
+#pragma unroll
+    for (uint32_t v = 0; v < GV; ++v)
+      if (ng * GV + v < full) vec16(cur[v], ng * GV + v);
     if (full < nvec) {   // last, partial vector of the row
       u32x4 t[OPL];
 #pragma unroll
@@ -527,19 +548,28 @@ __global__ void __launch_bounds__(256) finish_kernel(const FinishJob* __restrict
 }
 
 // ---------------------------------------------------------------- rounds ----
+// sum of K field elements over the lanes of a wave (xor butterfly over
+// lane distances < width, a power of two <= 64: every lane of each aligned
+// group of `width` lanes ends with that group's sum)
 template <int K>
-__device__ __forceinline__ void block_sum(Fr (&v)[K], uint32_t* lds) {
-  constexpr int NW = kRoundsBlock / kWave;
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
+__device__ __forceinline__ void wave_sum(Fr (&v)[K], uint32_t width) {
+  for (uint32_t off = width >> 1; off >= 1; off >>= 1) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       Fr o;
 #pragma unroll
-      for (int j = 0; j < 8; ++j) o.w[j] = __shfl_xor(v[k].w[j], off, kWave);
+      for (int j = 0; j < 8; ++j) o.w[j] = __shfl_xor(v[k].w[j], (int)off, kWave);
       v[k] = fr_add(v[k], o);
     }
   }
+}
+
+// sum over the workgroup; the total lands in lanes 0..7 of wave 0 (the
+// transcript's lanes), the other lanes keep partial values
+template <int K>
+__device__ __forceinline__ void block_sum_w0(Fr (&v)[K], uint32_t* lds) {
+  constexpr int NW = kRoundsBlock / kWave;
+  wave_sum<K>(v, kWave);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 0) {
 #pragma unroll
@@ -548,20 +578,14 @@ __device__ __forceinline__ void block_sum(Fr (&v)[K], uint32_t* lds) {
       for (int j = 0; j < 8; ++j) lds[(k * 8 + j) * NW + wave] = v[k].w[j];
   }
   __syncthreads();
+  if (wave == 0) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    Fr s = fr_zero();
-    for (int w = 0; w < NW; ++w) {
-      Fr o;
+    for (int k = 0; k < K; ++k)
 #pragma unroll
-      for (int j = 0; j < 8; ++j) o.w[j] = lds[(k * 8 + j) * NW + w];
-      s = fr_add(s, o);
-    }
-    v[k] = s;
+      for (int j = 0; j < 8; ++j) v[k].w[j] = lane < NW ? lds[(k * 8 + j) * NW + lane] : 0u;
+    wave_sum<K>(v, NW);
   }
-  __syncthreads();
 }
-
 
 // canonical element c to 32 proof bytes (little-endian words); word stores
 // when the destination is 4-byte aligned
@@ -588,14 +612,107 @@ __device__ __forceinline__ Fr lds_get(const uint32_t* src) {
   return v;
 }
 
+__device__ __forceinline__ Fr lds_or_global_fr(const uint32_t* src) {
+  Fr v;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v.w[j] = src[j];
+  return v;
+}
+
+__device__ __forceinline__ Fr readlane_fr(const Fr& x, int l) {
+  Fr r;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) r.w[j] = __builtin_amdgcn_readlane(x.w[j], l);
+  return r;
+}
+
 // (2 b - a) for the evaluation at X = 2 of the line through (0, a), (1, b)
 __device__ __forceinline__ Fr at_two(const Fr& a, const Fr& b) { return fr_sub(fr_double(b), a); }
 
-// One workgroup per group.  Round 1 of every product is computed in a first
-// pass (its g(0) + g(1) is the product's sum, so the prover guard needs no
-// extra pass); later rounds compute g(0) and g(2) and take g(1) = claim - g(0),
-// the claim moving to g(r) by interpolation on {0, 1, 2}.  All of it leaves
-// the proof bytes unchanged.
+// One sumcheck round's messages and challenge, run by wave 0 (all its
+// lanes, g canonical and valid in lane 0): lane k < 3 writes g(k) to the
+// proof; lane 0 absorbs the three values and squeezes r.  Returns r in
+// Montgomery form in every lane of wave 0.
+__device__ __forceinline__ Fr round_challenge(Transcript& tr, const Fr (&g)[3], uint8_t* out, uint32_t lane) {
+  Fr gc[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gc[k] = readlane_fr(g[k], 0);
+  const Fr mine = lane == 0 ? gc[0] : (lane == 1 ? gc[1] : gc[2]);
+  if (lane < 3) put_canon(out + 32 * lane, mine);
+  Fr r = fr_zero();
+  if (lane == 0) {
+    tr_absorb_frs(tr, VL_LBL_ROUND, gc);
+    r = fr_to_mont(tr_squeeze_fixed(tr, VL_LBL_R));
+  }
+  return readlane_fr(r, 0);
+}
+
+// Pass 1: the claim's dot product and round 1 of every product as partial
+// sums, kPass1Pairs pairs per 256-thread block, spread over the whole GPU
+// (the rounds kernel of a group runs on one CU and only adds the partials).
+__global__ void __launch_bounds__(256) pass1_kernel(const Pass1Job* __restrict__ jobs, uint32_t n_jobs,
+                                                    uint32_t n_blocks) {
+  const uint32_t blk = blockIdx.x;
+  if (blk >= n_blocks) return;
+  uint32_t lo = 0, hi = n_jobs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (jobs[mid].block_begin <= blk) lo = mid; else hi = mid;
+  }
+  const Pass1Job& J = jobs[lo];
+  const uint32_t base = (blk - J.block_begin) * kPass1Pairs;
+  const uint32_t end = min(base + kPass1Pairs, J.h);
+  Fr g[3];
+  g[0] = g[1] = g[2] = fr_zero();
+  for (uint32_t t = base + threadIdx.x; t < end; t += 256) {
+    if (J.dot) {
+      g[0] = fr_add(g[0], fr_mul(load_sol(J.a, J.a_ld, t), load_sol(J.b, J.b_ld, t)));
+    } else {
+      const Fr a0 = load_sol(J.a, J.a_ld, t), a1 = load_sol(J.a, J.a_ld, t + J.h);
+      const Fr b0 = load_sol(J.b, J.b_ld, t), b1 = load_sol(J.b, J.b_ld, t + J.h);
+      g[0] = fr_add(g[0], fr_mul(a0, b0));
+      g[1] = fr_add(g[1], fr_mul(a1, b1));
+      g[2] = fr_add(g[2], fr_mul(at_two(a0, a1), at_two(b0, b1)));
+    }
+  }
+  __shared__ uint32_t red[3 * 8 * 4];
+  wave_sum<3>(g, kWave);
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) red[(k * 8 + j) * 4 + wave] = g[k].w[j];
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) g[k].w[j] = lane < 4 ? red[(k * 8 + j) * 4 + lane] : 0u;
+    wave_sum<3>(g, 4);
+    if (lane == 0) {
+      uint32_t* o = J.out + (uint64_t)(blk - J.block_begin) * 24;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[k * 8 + j] = g[k].w[j];
+    }
+  }
+}
+
+// One workgroup per group.  Round 1 of every product comes from the pass-1
+// partials (its g(0) + g(1) is the product's sum, so the prover guard needs
+// no extra pass).  Every later round computes g(0), g(1) and g(2) from the
+// folded tables (g(0) + g(1) equals the previous round's g(r) by the folding
+// identity, for any tables).  The a~ tables are in Montgomery form and the
+// b~ tables in canonical form, so every product a * b, and with it every
+// round value, is canonical; folding by r in Montgomery form keeps both
+// forms.  While the half-table is
+// larger than a wave the tables live in global memory and the whole group
+// works; the last rounds (half-table <= 64) run in wave 0 alone with the
+// pairs in registers: lane t holds entries t and t + h, and folding moves
+// entry t + h/2 down by h/2 lanes.  The transcript lane's chain (hashing,
+// two field conversions) is the serial part of every round.
 __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* __restrict__ jobs) {
   const RoundsJob& J = jobs[blockIdx.x];
   // the rounds are one serial chain per group (transcript hashing on a
@@ -604,51 +721,47 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
   __builtin_amdgcn_s_setprio(3);
   __shared__ uint32_t red[3 * 8 * (kRoundsBlock / kWave)];
   __shared__ uint32_t first[VL_MAX_PRODS][3][8];   // round-1 values per product
-  __shared__ uint32_t bcast[2][8];                 // r and the next claim
+  __shared__ uint32_t bcast[8];                    // the round's challenge
+  __shared__ int32_t verdict;
   const uint32_t tid = threadIdx.x, NT = blockDim.x;
+  const uint32_t wave = tid >> 6, lane = tid & 63u;
 
   if (J.err && *(volatile const int32_t*)J.err) {
     if (tid == 0) *J.status = VL_ERR_RANGE;
     return;
   }
-  // c = C~(u, v) = sum_i eq(u, i) t[i]
+  // c = C~(u, v) = sum_i eq(u, i) t[i], from the pass-1 partials (canonical:
+  // eqU is in Montgomery form, t in canonical form)
   Fr v1[1];
   v1[0] = fr_zero();
-  const uint32_t len0 = 1u << J.n0;
-  for (uint32_t i = tid; i < len0; i += NT)
-    v1[0] = fr_add(v1[0], fr_mul(load_sol(J.eqU, J.eqU_ld, i), load_sol(J.t, J.t_ld, i)));
-  block_sum<1>(v1, red);
-  const Fr c = v1[0];
+  for (uint32_t i = tid; i < J.c_nparts; i += NT) v1[0] = fr_add(v1[0], lds_or_global_fr(J.c_part + 24ull * i));
+  block_sum_w0<1>(v1, red);
+  const Fr c = v1[0];   // valid in lane 0 of wave 0
+  __syncthreads();      // red is reused by the next sum
 
-  // round 1 of every product; its g(0) + g(1) = sum_w a_p[w] b_p[w]
+  // round 1 of every product from its partials; its g(0) + g(1) is
+  // sum_w a_p[w] b_p[w]
   Fr total = fr_zero();
   for (uint32_t p = 0; p < J.n_prods; ++p) {
     const RoundsProd& P = J.prods[p];
     Fr g[3];
     g[0] = g[1] = g[2] = fr_zero();
-    if (P.n1 == 0) {
-      if (tid == 0) g[0] = fr_mul(load_sol(P.a, P.ld, 0), load_sol(P.b, P.ld, 0));
-    } else {
-      const uint32_t h = 1u << (P.n1 - 1);
-      for (uint32_t t = tid; t < h; t += NT) {
-        const Fr a0 = load_sol(P.a, P.ld, t), a1 = load_sol(P.a, P.ld, t + h);
-        const Fr b0 = load_sol(P.b, P.ld, t), b1 = load_sol(P.b, P.ld, t + h);
-        g[0] = fr_add(g[0], fr_mul(a0, b0));
-        g[1] = fr_add(g[1], fr_mul(a1, b1));
-        g[2] = fr_add(g[2], fr_mul(at_two(a0, a1), at_two(b0, b1)));
-      }
-    }
-    block_sum<3>(g, red);
+    for (uint32_t i = tid; i < P.g_nparts; i += NT)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) g[k] = fr_add(g[k], lds_or_global_fr(P.g_part + 24ull * i + 8 * k));
+    block_sum_w0<3>(g, red);
     if (tid == 0)
 #pragma unroll
       for (int k = 0; k < 3; ++k) lds_put(first[p][k], g[k]);
     total = fr_add(total, fr_add(g[0], g[1]));
+    __syncthreads();   // red is reused by the next sum
   }
-  if (!fr_eq(total, c)) {
+  if (tid == 0) verdict = fr_eq(total, c) ? 1 : 0;
+  __syncthreads();
+  if (!verdict) {
     if (tid == 0) *J.status = VL_ERR_FALSE_STATEMENT;
     return;
   }
-  __syncthreads();
 
   // the transcript lives in thread 0; every thread keeps the same proof cursor
   Transcript tr;
@@ -656,70 +769,48 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
   if (tid == 0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) tr.h[i] = J.st[i];
-    const Fr cc[1] = {fr_from_mont(c)};
+    const Fr cc[1] = {c};
     put_canon(out, cc[0]);
     tr_absorb_frs(tr, VL_LBL_CLAIM, cc);
     for (uint32_t p = 0; p + 1 < J.n_prods; ++p) {
-      const Fr sc[1] = {fr_from_mont(fr_add(lds_get(first[p][0]), lds_get(first[p][1])))};
+      const Fr sc[1] = {fr_add(lds_get(first[p][0]), lds_get(first[p][1]))};
       put_canon(out + 32 * (1 + p), sc[0]);
       tr_absorb_frs(tr, VL_LBL_PART, sc);
     }
   }
   out += 32 * J.n_prods;
-  const Fr one = fr_R();
   for (uint32_t p = 0; p < J.n_prods; ++p) {
     const RoundsProd& P = J.prods[p];
     uint32_t* a = P.a;
     uint32_t* b = P.b;
     const uint64_t ld = P.ld;
-    Fr claim = fr_add(lds_get(first[p][0]), lds_get(first[p][1]));
-    for (uint32_t rd = 0; rd < P.n1; ++rd) {
+    uint32_t rd = 0;
+    // rounds over tables in global memory, the whole workgroup
+    for (; rd < P.n1; ++rd) {
       const uint32_t h = 1u << (P.n1 - 1 - rd);
+      if (h <= kWave) break;
       Fr g[3];
       if (rd == 0) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) g[k] = lds_get(first[p][k]);
       } else {
-        Fr q[2];
-        q[0] = q[1] = fr_zero();
+        g[0] = g[1] = g[2] = fr_zero();
         for (uint32_t t = tid; t < h; t += NT) {
           const Fr a0 = load_sol(a, ld, t), a1 = load_sol(a, ld, t + h);
           const Fr b0 = load_sol(b, ld, t), b1 = load_sol(b, ld, t + h);
-          q[0] = fr_add(q[0], fr_mul(a0, b0));
-          q[1] = fr_add(q[1], fr_mul(at_two(a0, a1), at_two(b0, b1)));
+          g[0] = fr_add(g[0], fr_mul(a0, b0));
+          g[1] = fr_add(g[1], fr_mul(a1, b1));
+          g[2] = fr_add(g[2], fr_mul(at_two(a0, a1), at_two(b0, b1)));
         }
-        block_sum<2>(q, red);
-        g[0] = q[0];
-        g[1] = fr_sub(claim, q[0]);
-        g[2] = q[1];
+        block_sum_w0<3>(g, red);
       }
-      // wave 0: lane k < 3 converts g(k) to canonical form and writes it to
-      // the proof; lane 0 then runs the transcript on the gathered values
-      if (tid < kWave) {
-        const Fr mine = tid == 0 ? g[0] : (tid == 1 ? g[1] : g[2]);
-        const Fr cm = fr_from_mont(mine);
-        if (tid < 3) put_canon(out + 32 * tid, cm);
-        Fr gc[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-          for (int j = 0; j < 8; ++j) gc[k].w[j] = __builtin_amdgcn_readlane(cm.w[j], k);
-        out += 96;
-        if (tid == 0) {
-          tr_absorb_frs(tr, VL_LBL_ROUND, gc);
-          const Fr r = fr_to_mont(tr_squeeze_fixed(tr, VL_LBL_R));
-          // g(r) in Newton form on {0, 1, 2}: g0 + r (d1 + (r - 1) h2) with
-          // d1 = g1 - g0 and h2 = (g2 - 2 g1 + g0) / 2
-          const Fr d1 = fr_sub(g[1], g[0]);
-          const Fr h2 = fr_half(fr_add(fr_sub(g[2], fr_double(g[1])), g[0]));
-          const Fr next = fr_add(g[0], fr_mul(r, fr_add(d1, fr_mul(fr_sub(r, one), h2))));
-          lds_put(bcast[0], r);
-          lds_put(bcast[1], next);
-        }
+      if (wave == 0) {
+        const Fr r = round_challenge(tr, g, out, lane);
+        if (lane == 0) lds_put(bcast, r);
       }
+      out += 96;
       __syncthreads();
-      const Fr r = lds_get(bcast[0]);
-      claim = lds_get(bcast[1]);
+      const Fr r = lds_get(bcast);
       for (uint32_t t = tid; t < h; t += NT) {
         const Fr a0 = load_sol(a, ld, t), a1 = load_sol(a, ld, t + h);
         const Fr b0 = load_sol(b, ld, t), b1 = load_sol(b, ld, t + h);
@@ -729,13 +820,61 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
       __threadfence_block();
       __syncthreads();
     }
-    if (tid == 0) {
-      Fr fin[2];
-      fin[0] = fr_from_mont(load_sol(a, ld, 0));
-      fin[1] = fr_from_mont(load_sol(b, ld, 0));
-      put_canon(out, fin[0]);
-      put_canon(out + 32, fin[1]);
-      tr_absorb_frs(tr, VL_LBL_FINAL, fin);
+    // the last rounds (half-table h <= 64): wave 0, pairs in registers
+    if (wave == 0) {
+      Fr fa, fb;   // the product's final a~ and b~ (lane 0)
+      if (rd < P.n1) {
+        uint32_t h = 1u << (P.n1 - 1 - rd);
+        Fr A0 = fr_zero(), A1 = fr_zero(), B0 = fr_zero(), B1 = fr_zero();
+        if (lane < h) {
+          A0 = load_sol(a, ld, lane);
+          A1 = load_sol(a, ld, lane + h);
+          B0 = load_sol(b, ld, lane);
+          B1 = load_sol(b, ld, lane + h);
+        }
+        for (; rd < P.n1; ++rd, h >>= 1) {
+          Fr g[3];
+          g[0] = fr_mul(A0, B0);   // lanes >= h hold zeros
+          g[1] = fr_mul(A1, B1);
+          g[2] = fr_mul(at_two(A0, A1), at_two(B0, B1));
+          wave_sum<3>(g, h);
+          const Fr r = round_challenge(tr, g, out, lane);
+          out += 96;
+          // fold; then entry t + h/2 of the folded table comes from lane t + h/2
+          Fr na = fr_add(A0, fr_mul(r, fr_sub(A1, A0)));
+          Fr nb = fr_add(B0, fr_mul(r, fr_sub(B1, B0)));
+          if (lane >= h) na = nb = fr_zero();
+          const uint32_t hh = h >> 1;
+          Fr ua, ub;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            ua.w[j] = __shfl(na.w[j], (int)(lane + hh), kWave);
+            ub.w[j] = __shfl(nb.w[j], (int)(lane + hh), kWave);
+          }
+          A0 = na;
+          B0 = nb;
+          A1 = lane < hh ? ua : fr_zero();
+          B1 = lane < hh ? ub : fr_zero();
+          if (lane >= hh) A0 = B0 = fr_zero();
+          if (h == 1) {   // last round: the folded single entries
+            fa = na;
+            fb = nb;
+          }
+        }
+      } else {   // no rounds (D1 = 1) or the global rounds folded to one entry
+        fa = load_sol(a, ld, 0);
+        fb = load_sol(b, ld, 0);
+      }
+      if (lane == 0) {
+        Fr fin[2];
+        fin[0] = fr_from_mont(fa);   // a~ tables are in Montgomery form,
+        fin[1] = fb;                 // b~ tables in canonical form
+        put_canon(out, fin[0]);
+        put_canon(out + 32, fin[1]);
+        tr_absorb_frs(tr, VL_LBL_FINAL, fin);
+      }
+    } else {
+      out += 96 * (P.n1 - rd);
     }
     out += 64;
     __syncthreads();
@@ -850,6 +989,12 @@ hipError_t launch_contract(int kind, const ContractJob* jobs, uint32_t n_jobs, u
 hipError_t launch_finish(const FinishJob* jobs, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s) {
   if (n_blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(finish_kernel, dim3(n_blocks), dim3(256), 0, s, jobs, n_jobs, n_blocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass1(const Pass1Job* jobs, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s) {
+  if (n_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(pass1_kernel, dim3(n_blocks), dim3(256), 0, s, jobs, n_jobs, n_blocks);
   return hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ constexpr uint32_t kDefaultSegments = 1;
 
 struct Tuning {
   bool per_instance = false;
-  uint32_t lane_macs = 16384;     // multiply-adds per lane and contraction task
+  uint32_t lane_macs = 8192;      // multiply-adds per lane and contraction task
   uint32_t segments = 1;          // pipeline segments (batched mode)
   uint32_t min_tasks = 1;         // split a contraction until it has this many tasks
   uint32_t cols_rows = 1;         // rows per lane, vector cols kernels (1 or 2)
@@ -47,6 +47,8 @@ struct Segment {
   uint32_t cj_tasks[CK_COUNT] = {};
   std::vector<FinishJob> fin;
   uint32_t fin_blocks = 0;
+  std::vector<Pass1Job> pass1;
+  uint32_t pass1_blocks = 0;
   std::vector<RoundsJob> rounds;
 };
 
@@ -63,7 +65,7 @@ struct Plan {
 };
 
 struct SegLayout {
-  uint64_t cj[CK_COUNT], fin, rounds;
+  uint64_t cj[CK_COUNT], fin, pass1, rounds;
 };
 
 struct BlobLayout {
@@ -92,7 +94,10 @@ struct Builder {
   X* dev(uint64_t o) const { return reinterpret_cast<X*>(base + o); }
   void contract(const void* M, int dtype, int nd, uint64_t ld, bool rows, uint32_t n_out, uint32_t len,
                 const uint32_t* pack, uint32_t* dst, uint64_t dst_ld, uint64_t n_total, int32_t* err);
-  void eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_len);
+  void eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_len, bool pack_r2);
+  // pass-1 job over a, b; returns the partials buffer, sets its block count
+  const uint32_t* pass1(const uint32_t* a, uint64_t a_ld, const uint32_t* b, uint64_t b_ld, uint32_t h,
+                        bool dot, uint32_t& nparts);
   void group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev, int32_t* status_dev,
              uint8_t* digest_dev, int32_t* err);
 };

@@ -11,6 +11,10 @@
 // with little-endian integers and canonical 32-byte field elements.
 #pragma once
 #include <stdint.h>
+#if !defined(__HIP_DEVICE_COMPILE__) && defined(__x86_64__)
+#include <cpuid.h>
+#include <immintrin.h>
+#endif
 
 #include "fr.hpp"
 
@@ -43,41 +47,120 @@ VL_HD uint32_t bitsel(uint32_t m, uint32_t x, uint32_t y) {
 #endif
 }
 
-// FIPS 180-4 compression of one block given as 16 big-endian message words
+// FIPS 180-4 round constants
+#define VL_SHA256_K                                                                                \
+  0x428a2f98u, 0x71374491u, 0xb5c0fbcfu, 0xe9b5dba5u, 0x3956c25bu, 0x59f111f1u, 0x923f82a4u,     \
+      0xab1c5ed5u, 0xd807aa98u, 0x12835b01u, 0x243185beu, 0x550c7dc3u, 0x72be5d74u, 0x80deb1feu, \
+      0x9bdc06a7u, 0xc19bf174u, 0xe49b69c1u, 0xefbe4786u, 0x0fc19dc6u, 0x240ca1ccu, 0x2de92c6fu, \
+      0x4a7484aau, 0x5cb0a9dcu, 0x76f988dau, 0x983e5152u, 0xa831c66du, 0xb00327c8u, 0xbf597fc7u, \
+      0xc6e00bf3u, 0xd5a79147u, 0x06ca6351u, 0x14292967u, 0x27b70a85u, 0x2e1b2138u, 0x4d2c6dfcu, \
+      0x53380d13u, 0x650a7354u, 0x766a0abbu, 0x81c2c92eu, 0x92722c85u, 0xa2bfe8a1u, 0xa81a664bu, \
+      0xc24b8b70u, 0xc76c51a3u, 0xd192e819u, 0xd6990624u, 0xf40e3585u, 0x106aa070u, 0x19a4c116u, \
+      0x1e376c08u, 0x2748774cu, 0x34b0bcb5u, 0x391c0cb3u, 0x4ed8aa4au, 0x5b9cca4fu, 0x682e6ff3u, \
+      0x748f82eeu, 0x78a5636fu, 0x84c87814u, 0x8cc70208u, 0x90befffau, 0xa4506cebu, 0xbef9a3f7u, \
+      0xc67178f2u
+
+#if defined(__HIP__)
+// device copy: the compression loop below reads 16 of them per iteration
+// with scalar loads
+static __constant__ uint32_t kSha256KDev[64] = {VL_SHA256_K};
+#endif
+static const uint32_t kSha256KHost[64] = {VL_SHA256_K};
+
+VL_HD const uint32_t* sha256_k() {
+#if __HIP_DEVICE_COMPILE__
+  return kSha256KDev;
+#else
+  return kSha256KHost;
+#endif
+}
+
+#if !defined(__HIP_DEVICE_COMPILE__) && defined(__x86_64__)
+// Host: the x86 SHA extensions (SHA256RNDS2 does two rounds on the state
+// held as {A, B, E, F} and {C, D, G, H}; SHA256MSG1/MSG2 extend the message
+// schedule four words at a time), used when the CPU has them.
+__attribute__((target("sha,sse4.1"))) inline void sha256_compress_ni(uint32_t h[8], const uint32_t (&w)[16]) {
+  const uint32_t* K = kSha256KHost;
+  __m128i abef = _mm_set_epi32((int)h[0], (int)h[1], (int)h[4], (int)h[5]);
+  __m128i cdgh = _mm_set_epi32((int)h[2], (int)h[3], (int)h[6], (int)h[7]);
+  const __m128i abef0 = abef, cdgh0 = cdgh;
+  __m128i W[4];   // ring of the last 16 schedule words, 4 per register (lowest = first)
+  for (int j = 0; j < 16; ++j) {
+    __m128i m;
+    if (j < 4) {
+      m = _mm_set_epi32((int)w[4 * j + 3], (int)w[4 * j + 2], (int)w[4 * j + 1], (int)w[4 * j]);
+    } else {
+      // W[4j..4j+3] from W[4j-16..], W[4j-15..] (msg1), W[4j-7..] and W[4j-2..] (msg2)
+      __m128i t = _mm_sha256msg1_epu32(W[j & 3], W[(j + 1) & 3]);
+      t = _mm_add_epi32(t, _mm_alignr_epi8(W[(j + 3) & 3], W[(j + 2) & 3], 4));
+      m = _mm_sha256msg2_epu32(t, W[(j + 3) & 3]);
+    }
+    W[j & 3] = m;
+    __m128i wk = _mm_add_epi32(m, _mm_loadu_si128(reinterpret_cast<const __m128i*>(K + 4 * j)));
+    cdgh = _mm_sha256rnds2_epu32(cdgh, abef, wk);   // rounds 4j, 4j+1: cdgh now holds ABEF
+    wk = _mm_shuffle_epi32(wk, 0x0E);
+    abef = _mm_sha256rnds2_epu32(abef, cdgh, wk);   // rounds 4j+2, 4j+3
+  }
+  abef = _mm_add_epi32(abef, abef0);
+  cdgh = _mm_add_epi32(cdgh, cdgh0);
+  alignas(16) uint32_t x[4], y[4];
+  _mm_store_si128(reinterpret_cast<__m128i*>(x), abef);
+  _mm_store_si128(reinterpret_cast<__m128i*>(y), cdgh);
+  h[0] = x[3]; h[1] = x[2]; h[4] = x[1]; h[5] = x[0];
+  h[2] = y[3]; h[3] = y[2]; h[6] = y[1]; h[7] = y[0];
+}
+
+inline bool sha256_ni_available() {
+  static const bool ok = [] {
+    unsigned a, b, c, d;
+    if (!__get_cpuid_count(7, 0, &a, &b, &c, &d)) return false;
+    const bool sha = (b >> 29) & 1u;
+    if (!__get_cpuid(1, &a, &b, &c, &d)) return false;
+    const bool sse41 = (c >> 19) & 1u, ssse3 = (c >> 9) & 1u;
+    return sha && sse41 && ssse3;
+  }();
+  return ok;
+}
+#endif
+
+// FIPS 180-4 compression of one block given as 16 big-endian message words.
+// The 64 rounds run as 4 iterations of 16 (the message schedule's ring
+// length): the device code stays small enough for the instruction cache,
+// which matters more than the loop overhead on the single lane that hashes.
 VL_HD void sha256_compress_w(uint32_t h[8], const uint32_t (&win)[16]) {
-  const uint32_t K[64] = {
-      0x428a2f98u, 0x71374491u, 0xb5c0fbcfu, 0xe9b5dba5u, 0x3956c25bu, 0x59f111f1u, 0x923f82a4u,
-      0xab1c5ed5u, 0xd807aa98u, 0x12835b01u, 0x243185beu, 0x550c7dc3u, 0x72be5d74u, 0x80deb1feu,
-      0x9bdc06a7u, 0xc19bf174u, 0xe49b69c1u, 0xefbe4786u, 0x0fc19dc6u, 0x240ca1ccu, 0x2de92c6fu,
-      0x4a7484aau, 0x5cb0a9dcu, 0x76f988dau, 0x983e5152u, 0xa831c66du, 0xb00327c8u, 0xbf597fc7u,
-      0xc6e00bf3u, 0xd5a79147u, 0x06ca6351u, 0x14292967u, 0x27b70a85u, 0x2e1b2138u, 0x4d2c6dfcu,
-      0x53380d13u, 0x650a7354u, 0x766a0abbu, 0x81c2c92eu, 0x92722c85u, 0xa2bfe8a1u, 0xa81a664bu,
-      0xc24b8b70u, 0xc76c51a3u, 0xd192e819u, 0xd6990624u, 0xf40e3585u, 0x106aa070u, 0x19a4c116u,
-      0x1e376c08u, 0x2748774cu, 0x34b0bcb5u, 0x391c0cb3u, 0x4ed8aa4au, 0x5b9cca4fu, 0x682e6ff3u,
-      0x748f82eeu, 0x78a5636fu, 0x84c87814u, 0x8cc70208u, 0x90befffau, 0xa4506cebu, 0xbef9a3f7u,
-      0xc67178f2u};
+#if !defined(__HIP_DEVICE_COMPILE__) && defined(__x86_64__)
+  if (sha256_ni_available()) {
+    sha256_compress_ni(h, win);
+    return;
+  }
+#endif
+  const uint32_t* K = sha256_k();
   uint32_t w[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) w[i] = win[i];
   uint32_t a = h[0], b = h[1], c = h[2], d = h[3], e = h[4], f = h[5], g = h[6], hh = h[7];
+#pragma unroll 1
+  for (int it = 0; it < 4; ++it) {
+    if (it > 0) {
+      // w[i] <- W[16 it + i] for i = 0..15, in order (each uses the new w[i-2])
 #pragma unroll
-  for (int i = 0; i < 64; ++i) {
-    uint32_t wi;
-    if (i < 16) {
-      wi = w[i];
-    } else {
-      const uint32_t w15 = w[(i - 15) & 15], w2 = w[(i - 2) & 15];
-      const uint32_t s0 = rotr32(w15, 7) ^ rotr32(w15, 18) ^ (w15 >> 3);
-      const uint32_t s1 = rotr32(w2, 17) ^ rotr32(w2, 19) ^ (w2 >> 10);
-      wi = add3_u32(w[i & 15], s0, w[(i - 7) & 15]) + s1;
-      w[i & 15] = wi;
+      for (int i = 0; i < 16; ++i) {
+        const uint32_t w15 = w[(i + 1) & 15], w2 = w[(i + 14) & 15];
+        const uint32_t s0 = rotr32(w15, 7) ^ rotr32(w15, 18) ^ (w15 >> 3);
+        const uint32_t s1 = rotr32(w2, 17) ^ rotr32(w2, 19) ^ (w2 >> 10);
+        w[i] = add3_u32(w[i], s0, w[(i + 9) & 15]) + s1;
+      }
     }
-    const uint32_t S1 = rotr32(e, 6) ^ rotr32(e, 11) ^ rotr32(e, 25);
-    const uint32_t ch = bitsel(e, f, g);                 // Ch(e, f, g)
-    const uint32_t t1 = add3_u32(hh, S1, ch) + (wi + K[i]);
-    const uint32_t S0 = rotr32(a, 2) ^ rotr32(a, 13) ^ rotr32(a, 22);
-    const uint32_t mj = bitsel(a ^ b, c, a);             // Maj(a, b, c)
-    hh = g; g = f; f = e; e = d + t1; d = c; c = b; b = a; a = add3_u32(t1, S0, mj);
+    const uint32_t* Kt = K + 16 * it;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const uint32_t S1 = rotr32(e, 6) ^ rotr32(e, 11) ^ rotr32(e, 25);
+      const uint32_t ch = bitsel(e, f, g);                 // Ch(e, f, g)
+      const uint32_t t1 = add3_u32(hh, S1, ch) + (w[i] + Kt[i]);
+      const uint32_t S0 = rotr32(a, 2) ^ rotr32(a, 13) ^ rotr32(a, 22);
+      const uint32_t mj = bitsel(a ^ b, c, a);             // Maj(a, b, c)
+      hh = g; g = f; f = e; e = d + t1; d = c; c = b; b = a; a = add3_u32(t1, S0, mj);
+    }
   }
   h[0] += a; h[1] += b; h[2] += c; h[3] += d; h[4] += e; h[5] += f; h[6] += g; h[7] += hh;
 }
