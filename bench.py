@@ -6,12 +6,17 @@ T = 2048 tokens with rank-16 LoRA on q, k, v, o, gate, up and down: every
 forward, backward and LoRA-update product, 56 products in 49 groups, int16
 operands and exact int64 outputs (seeded synthetic data, ``workloads``).  A
 step proves all 49 groups in one call with inputs resident in HBM and the
-proof bytes copied back to the host.
+proof bytes copied back to the host.  Throughput (value, ms_per_step) is
+measured with --inflight proofs in flight on separate streams (the
+asynchronous entry point); latency and per-stage device times with one
+blocking call at a time.
 
 Reports (one JSON line): algorithmic Fr MACs/s (value), proofs/s, p50/p99
 step latency, the per-instance prover on the same inputs, the dominant
-kernel against its VALU ceiling (HIP-event stage timing over the timed
-steps), and the CPU oracle on a bounded sample of the same workload.
+kernel against the HBM roofline (algorithmic matrix bytes over its
+HIP-event launch time in the timed steps) with every contraction kind's
+GB/s and fraction of the 32-bit multiply peak, and the CPU oracle on a
+bounded sample of the same workload.
 """
 import argparse
 import json
@@ -25,7 +30,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Fr MACs/s + matmul-sumcheck proofs/s; batched vs per-instance; p50/p99 latency"
 CU, LANES_PER_CLK, CLOCK_HZ = 256, 64, 2.4e9   # MI355X: CUs, VALU lanes per CU per clock, peak clock
-MAD_PER_I16_MAC = 8                             # 8 signed 32-bit eq digits x one int16 entry
+HBM_GBPS = 8000.0                               # MI355X HBM3E peak
+# v_mad_i64_i32 per matrix entry: 8 eq digits x the entry's digits
+MAD_PER_ENTRY = {"i16_rows": 8, "i16_rows4_vec": 8, "i16_cols_vec": 8, "i16_cols2_vec": 8,
+                 "i64s_cols_vec": 16, "i64s_cols2_vec": 16}
 
 
 def nv(d):
@@ -44,32 +52,40 @@ def algorithmic_macs(shapes_by_group):
     return total
 
 
-def int16_contraction_macs(groups, cols_rows=1):
-    """Entries streamed by the int16 contraction kernels, by stage (kernel
-    kind), following the library's planning rule: a row contraction with at
-    least 256 outputs runs 4 columns per lane with 8-byte loads; the column
-    kernels read 16-byte aligned rows with vector loads (all operands here are
-    aligned), two rows per lane when tuned so and there are >= 128 rows."""
+def contraction_bytes(groups, cols_rows=1):
+    """Matrix bytes and entries streamed per prove call by each contraction
+    kernel kind (stage index -> (bytes, entries)), following the library's
+    planning rule for these operands (int16 A and B, int64 C with
+    |C| < 2^47, all 16-byte aligned): a row contraction with at least 256
+    outputs runs 4 columns per lane with 8-byte loads, else 1 column per
+    lane; column contractions read 16-byte vectors, two rows per lane when
+    tuned so and there are >= 128 rows; C is contracted over its columns."""
     from paper_2508_21393_amd import binding as B
-    k = {n: 0 for n in ("i16_rows", "i16_rows4_vec", "i16_cols_vec", "i16_cols2_vec")}
+    k = {}
 
-    def cols(n_out):
+    def add(name, entries, esize):
+        b, e = k.get(name, (0, 0))
+        k[name] = (b + entries * esize, e + entries)
+
+    def cols16(n_out):
         return "i16_cols2_vec" if cols_rows == 2 and n_out >= 128 else "i16_cols_vec"
 
     for g in groups:
+        d0, _, d2 = g.products[0].dims
+        add("i64s_cols2_vec" if cols_rows == 2 and d0 >= 128 else "i64s_cols_vec", d0 * d2, 8)
         for p in g.products:
             d0, d1, d2 = p.dims
             # A side: outputs are the D1 columns of op(A)
             if p.transA:
-                k[cols(d1)] += d0 * d1
+                add(cols16(d1), d0 * d1, 2)
             else:
-                k["i16_rows4_vec" if d1 >= 256 else "i16_rows"] += d0 * d1
+                add("i16_rows4_vec" if d1 >= 256 else "i16_rows", d0 * d1, 2)
             # B side: outputs are the D1 rows of op(B)
             if p.transB:
-                k["i16_rows4_vec" if d1 >= 256 else "i16_rows"] += d1 * d2
+                add("i16_rows4_vec" if d1 >= 256 else "i16_rows", d1 * d2, 2)
             else:
-                k[cols(d1)] += d1 * d2
-    return {B.STAGE_NAMES.index(n): v for n, v in k.items() if v}
+                add(cols16(d1), d1 * d2, 2)
+    return {B.STAGE_NAMES.index(n): v for n, v in k.items() if v[1]}
 
 
 def cpu_baseline(workload, budget_s=15.0):
@@ -141,6 +157,8 @@ def main():
     ap.add_argument("--min-tasks", type=int, default=0, help="vl_tuning.min_tasks (0: library default)")
     ap.add_argument("--segments", type=int, default=0, help="vl_tuning.segments (0: library default)")
     ap.add_argument("--cols-rows", type=int, default=0, help="vl_tuning.cols_rows (0: library default)")
+    ap.add_argument("--inflight", type=int, default=2,
+                    help="proofs in flight in the throughput phase (asynchronous entry point)")
     ap.add_argument("--autotune", action="store_true",
                     help="time a grid of launch shapes first and bench the fastest")
     args = ap.parse_args()
@@ -183,8 +201,67 @@ def main():
     for _ in range(args.warmup):
         ref, ref_dig = step()
     torch.cuda.synchronize()
-    lat, stage_sum = [], [0.0] * B.VL_STAGE_COUNT
+    ref_cat = b"".join(ref)
+
+    # Throughput: `inflight` proofs in flight, each on its own stream with
+    # its own workspace and device proof buffer (the asynchronous entry
+    # point); the host plans the next proof while the GPU runs earlier ones,
+    # and one proof's single-CU sumcheck rounds overlap the next one's
+    # contractions.  Every proof is copied back and compared with the
+    # reference bytes.
+    n_groups = len(groups)
+
+    class Slot:
+        def __init__(self):
+            self.stream = torch.cuda.Stream()
+            self.ws = torch.empty(max(256, B.workspace_size(batch, mode, async_=True, tuning_=tun)),
+                                  dtype=torch.uint8, device="cuda")
+            self.proofs = torch.empty(batch.total, dtype=torch.uint8, device="cuda")
+            self.status = torch.empty(n_groups, dtype=torch.int32, device="cuda")
+            self.host = torch.empty(batch.total, dtype=torch.uint8, pin_memory=True)
+            self.hstat = torch.empty(n_groups, dtype=torch.int32, pin_memory=True)
+            self.done = torch.cuda.Event()
+            self.pending = False
+
+        def submit(self):
+            B.sumcheck_matmul_prove_async(batch, w.seed, self.proofs, self.status, self.ws, mode=mode,
+                                          stream=self.stream, tuning_=tun)
+            with torch.cuda.stream(self.stream):
+                self.host.copy_(self.proofs, non_blocking=True)
+                self.hstat.copy_(self.status, non_blocking=True)
+            self.done.record(self.stream)
+            self.pending = True
+
+        def collect(self):
+            self.done.synchronize()
+            assert not self.hstat.any(), "a group failed"
+            assert self.host.numpy().tobytes() == ref_cat, "proofs differ from the blocking run"
+            self.pending = False
+
+    slots = [Slot() for _ in range(max(1, args.inflight))]
+
+    def pipelined(nsteps):
+        for i in range(nsteps):
+            sl = slots[i % len(slots)]
+            if sl.pending:
+                sl.collect()
+            sl.submit()
+        for sl in slots:
+            if sl.pending:
+                sl.collect()
+
+    pipelined(max(args.warmup, len(slots)))
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
+    pipelined(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    # Latency and stage times: one proof at a time (blocking entry point),
+    # HIP events around every launch
+    lat, stage_sum = [], [0.0] * B.VL_STAGE_COUNT
+    tb = time.perf_counter()
     for _ in range(args.steps):
         s0 = time.perf_counter()
         st = []
@@ -193,8 +270,7 @@ def main():
         stage_sum = [a + b for a, b in zip(stage_sum, st)]
         assert dig == ref_dig, "proofs changed between steps"
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = 1e3 * elapsed / args.steps
+    blocking_ms = 1e3 * (time.perf_counter() - tb) / args.steps
     lat_ms = sorted(1e3 * x for x in lat)
     p50 = lat_ms[len(lat_ms) // 2]
     p99 = lat_ms[min(len(lat_ms) - 1, int(math.ceil(0.99 * len(lat_ms))) - 1)]
@@ -214,18 +290,25 @@ def main():
         per_inst_ms = 1e3 * (time.perf_counter() - t1) / args.per_instance_steps
         del ws_pi
 
-    # dominant kernel: the int16 contraction kind with the most device time
-    k16 = int16_contraction_macs(groups, cols_rows=tun.cols_rows)
-    dom = max(k16, key=lambda k: stage_avg[k])
+    # dominant kernel: the contraction kind with the most device time.  Its
+    # algorithmic traffic is the matrix bytes it must stream (every entry
+    # once); the eq digits and partial sums are small and mostly cache hits.
+    kinds = contraction_bytes(groups, cols_rows=tun.cols_rows)
+    dom = max(kinds, key=lambda k: stage_avg[k])
     dom_ms = stage_avg[dom]
-    achieved = k16[dom] / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0
+    dom_bytes, dom_entries = kinds[dom]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
     rates = None if args.no_peak else peak_rates()
-    mad_rate = CU * LANES_PER_CLK * CLOCK_HZ
-    peak = mad_rate / MAD_PER_I16_MAC / 1e12
-    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T Fr-MAC/s",
-                "frac": achieved / peak if peak else None, "traffic": None,
-                "kernel": f"contract_kernel {B.STAGE_NAMES[dom]} (int16 x eq digits, v_mad_i64_i32)",
-                "work_per_launch": k16[dom], "avg_launch_ms": dom_ms}
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_GBPS, "traffic": None,
+                "kernel": f"contract_kernel {B.STAGE_NAMES[dom]} (eq digits x matrix digits, v_mad_i64_i32)",
+                "bytes_per_launch": dom_bytes, "entries_per_launch": dom_entries, "avg_launch_ms": dom_ms,
+                "per_kind": {B.STAGE_NAMES[k]: {"ms": stage_avg[k], "GBps": b / (stage_avg[k] * 1e-3) / 1e9
+                                                if stage_avg[k] > 0 else None,
+                                                "valu_frac": (e * MAD_PER_ENTRY[B.STAGE_NAMES[k]] /
+                                                              (stage_avg[k] * 1e-3) / (CU * LANES_PER_CLK * CLOCK_HZ))
+                                                if stage_avg[k] > 0 else None}
+                             for k, (b, e) in kinds.items()}}
 
     out = {
         "metric": METRIC, "value": macs * args.steps / elapsed, "unit": "Fr-MAC/s",
@@ -237,9 +320,11 @@ def main():
                                f"q,k,v,o,gate,up,down: fwd+bwd+update", "groups": len(groups),
                    "products": n_products, "mode": args.mode, "algorithmic_macs_per_step": macs},
         "proofs_per_s": n_products * args.steps / elapsed,
-        "latency_ms": {"p50": p50, "p99": p99},
+        "latency_ms": {"p50": p50, "p99": p99, "blocking_ms_per_step": blocking_ms},
+        "inflight": len(slots),
         "per_instance_ms_per_step": per_inst_ms,
         "speedup_vs_per_instance": (per_inst_ms / ms_per_step) if per_inst_ms else None,
+        "speedup_vs_per_instance_blocking": (per_inst_ms / blocking_ms) if per_inst_ms else None,
         "stage_ms": {B.STAGE_NAMES[i]: stage_avg[i] for i in range(B.VL_STAGE_COUNT) if stage_avg[i] > 0},
         "roofline": roofline,
         "valu_lane_ops_per_s": rates,

@@ -46,14 +46,23 @@ typedef enum {
   VL_ERR_FALSE_STATEMENT = 6,  /* the products do not sum to C: no proof       */
   VL_ERR_REJECT = 7,           /* verification failed                          */
   VL_ERR_BUFFER_TOO_SMALL = 8, /* an output buffer is too small                */
-  VL_ERR_RANGE = 9             /* a claimed C entry is outside the range the
+  VL_ERR_RANGE = 9,            /* a claimed C entry is outside the range the
                                   planned contraction digits represent (about
                                   |C| >= 2^47 for int64 C of int16 products)   */
+  VL_ERR_TIMEOUT = 10          /* persistent mode: a group's rounds gave up
+                                  waiting for its contractions (spin limit)    */
 } vl_status;
 
 typedef enum { VL_I16 = 1, VL_I32 = 2, VL_I64 = 3 } vl_dtype;
 
 enum { VL_CONTRACT_ROWS = 0, VL_CONTRACT_COLS = 1 };
+/* PER_INSTANCE: each group planned and launched on its own, one after the
+ * other.  BATCHED: all groups in one launch per stage.  PERSISTENT: like
+ * BATCHED, but the rounds workgroups (one per group) are launched first, on
+ * an internal stream, and stay resident: each waits (bounded, see
+ * vl_tuning.spin_limit) for its group's contractions, so the sumchecks of
+ * early groups overlap the contractions of later ones.  At most 256 groups
+ * per call in this mode. */
 enum { VL_MODE_PER_INSTANCE = 0, VL_MODE_BATCHED = 1, VL_MODE_PERSISTENT = 2 };
 
 typedef struct { uint32_t w[8]; } vl_fr;
@@ -105,6 +114,9 @@ typedef struct {
                               one segment overlap the contractions of the next     */
   uint32_t cols_rows;      /* rows per lane in the vector cols kernels (int16 and
                               |x| < 2^47 int64): 1 or 2                            */
+  uint32_t spin_limit;     /* persistent mode: polls (about 0.2 us each) of a
+                              group's readiness before its rounds give up with
+                              VL_ERR_TIMEOUT                                       */
   uint32_t reserved;       /* must be 0                                            */
 } vl_tuning;
 

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libverilora.so")
 
 VL_OK, VL_ERR_INVALID_ARG, VL_ERR_SHAPE, VL_ERR_DTYPE, VL_ERR_WORKSPACE, VL_ERR_HIP, \
-    VL_ERR_FALSE_STATEMENT, VL_ERR_REJECT, VL_ERR_BUFFER_TOO_SMALL, VL_ERR_RANGE = range(10)
+    VL_ERR_FALSE_STATEMENT, VL_ERR_REJECT, VL_ERR_BUFFER_TOO_SMALL, VL_ERR_RANGE, VL_ERR_TIMEOUT = range(11)
 VL_I16, VL_I32, VL_I64 = 1, 2, 3
 VL_CONTRACT_ROWS, VL_CONTRACT_COLS = 0, 1
 VL_MODE_PER_INSTANCE, VL_MODE_BATCHED, VL_MODE_PERSISTENT = 0, 1, 2
@@ -26,7 +26,7 @@ STAGE_NAMES = ["upload", "eq", "i16_rows", "i16_rows4", "i16_rows4_vec", "i16_co
 
 STATUS_NAMES = {0: "VL_OK", 1: "VL_ERR_INVALID_ARG", 2: "VL_ERR_SHAPE", 3: "VL_ERR_DTYPE",
                 4: "VL_ERR_WORKSPACE", 5: "VL_ERR_HIP", 6: "VL_ERR_FALSE_STATEMENT",
-                7: "VL_ERR_REJECT", 8: "VL_ERR_BUFFER_TOO_SMALL", 9: "VL_ERR_RANGE"}
+                7: "VL_ERR_REJECT", 8: "VL_ERR_BUFFER_TOO_SMALL", 9: "VL_ERR_RANGE", 10: "VL_ERR_TIMEOUT"}
 
 EXPORTED = ("vl_fr_lift", "vl_fr_export", "vl_eq_table", "vl_partial_eval_workspace_size",
             "vl_mle_partial_eval", "vl_proof_size", "vl_workspace_size",
@@ -56,12 +56,15 @@ class vl_group(ctypes.Structure):
 
 class vl_tuning(ctypes.Structure):
     _fields_ = [("lane_macs", c_u32), ("min_tasks", c_u32), ("segments", c_u32), ("cols_rows", c_u32),
-                ("reserved", c_u32)]
+                ("spin_limit", c_u32), ("reserved", c_u32)]
 
 
-def tuning(lane_macs: int = 0, min_tasks: int = 0, segments: int = 0, cols_rows: int = 0) -> vl_tuning:
-    """Launch-shape knobs (0 = library default); results never depend on them."""
-    return vl_tuning(lane_macs, min_tasks, segments, cols_rows, 0)
+def tuning(lane_macs: int = 0, min_tasks: int = 0, segments: int = 0, cols_rows: int = 0,
+           spin_limit: int = 0) -> vl_tuning:
+    """Launch-shape knobs (0 = library default); results never depend on them
+    (a spin limit too small for the work makes persistent-mode groups fail
+    with VL_ERR_TIMEOUT instead)."""
+    return vl_tuning(lane_macs, min_tasks, segments, cols_rows, spin_limit, 0)
 
 
 def _tun(t):

@@ -321,7 +321,7 @@ void Builder::eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uin
 }
 
 void Builder::group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev, int32_t* status_dev,
-                    uint8_t* digest_dev, int32_t* err) {
+                    uint8_t* digest_dev, int32_t* err, uint32_t* ready) {
   const Transcript& tr = ch.tr;
   const std::vector<Fr>& u = ch.u;
   const std::vector<Fr>& v = ch.v;
@@ -355,7 +355,10 @@ void Builder::group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev,
   contract(g.C, g.dtype_c, ndc, g.ldc, false, D0, D2, packV, tvec, L0, L0, err);
 
   RoundsJob rj{};
-  rj.c_part = pass1(eqU, L0, tvec, L0, (uint32_t)L0, true, rj.c_nparts);
+  rj.c_part = pass1(eqU, L0, tvec, L0, (uint32_t)L0, true, rj.c_nparts, ready);
+  rj.ready = ready;
+  rj.ready_target = rj.c_nparts;
+  rj.spin_limit = T.spin_limit;
   memcpy(rj.st, tr.h, 32);
   rj.n_prods = g.n_prods;
   rj.n0 = n0;
@@ -382,15 +385,18 @@ void Builder::group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev,
     rj.prods[k].ld = L1;
     rj.prods[k].n1 = n1;
     // round 1 (for D1 = 1 the single product a[0] b[0])
-    rj.prods[k].g_part = n1 ? pass1(a, L1, b, L1, (uint32_t)(L1 / 2), false, rj.prods[k].g_nparts)
-                            : pass1(a, L1, b, L1, 1, true, rj.prods[k].g_nparts);
+    rj.prods[k].g_part = n1 ? pass1(a, L1, b, L1, (uint32_t)(L1 / 2), false, rj.prods[k].g_nparts, ready)
+                            : pass1(a, L1, b, L1, 1, true, rj.prods[k].g_nparts, ready);
+    rj.ready_target += rj.prods[k].g_nparts;
   }
-  S().rounds.push_back(rj);
+  // persistent mode: one resident launch for every group (segment 0's list)
+  (T.persistent ? P.seg[0] : S()).rounds.push_back(rj);
 }
 
 const uint32_t* Builder::pass1(const uint32_t* a, uint64_t a_ld, const uint32_t* b, uint64_t b_ld, uint32_t h,
-                               bool dot, uint32_t& nparts) {
+                               bool dot, uint32_t& nparts, uint32_t* ready) {
   Pass1Job j{};
+  j.ready = ready;
   j.a = a;
   j.b = b;
   j.a_ld = a_ld;
@@ -408,8 +414,8 @@ const uint32_t* Builder::pass1(const uint32_t* a, uint64_t a_ld, const uint32_t*
 BlobLayout blob_layout(const Plan& P) {
   BlobLayout L{};
   uint64_t o = 0;
-  L.err = o;
-  o = align_up(o + 4ull * std::max<uint32_t>(P.n_err, 1), 64);
+  L.err = o;   // per group: a range flag, then (persistent mode) a readiness counter
+  o = align_up(o + 8ull * std::max<uint32_t>(P.n_err, 1), 64);
   L.eq = o;
   o = align_up(o + P.eq.size() * sizeof(EqJob), 64);
   L.points = o;
@@ -440,7 +446,7 @@ uint64_t blob_bound(const vl_group* groups, uint64_t n) {
   }
   // pass-1 jobs: the claim and one per product; every segment may pad each
   // of its CK_COUNT + 3 arrays to 64 bytes
-  return align_up(4 * n + 64 + 2 * n * (sizeof(EqJob) + 64) +
+  return align_up(8 * n + 64 + 2 * n * (sizeof(EqJob) + 64) +
                       cj * (sizeof(ContractJob) + sizeof(FinishJob) + sizeof(Pass1Job) + 128) +
                       n * (sizeof(RoundsJob) + 64) + pts + 64 * (CK_COUNT + 3) * (n + 1) + 1024,
                   256);
@@ -552,6 +558,14 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
     if (e == hipSuccess) e = hipStreamWaitEvent(s2, fork.ev[nseg], 0);
     if (e != hipSuccess) return e;
   }
+  if (P.persistent) {
+    // resident rounds first: each workgroup waits for its group's pass 1
+    for (size_t k = 0; k < nseg; ++k)
+      if (!P.seg[k].rounds.empty())
+        VL_STAGE(ev, VL_STAGE_ROUNDS, s2,
+                 launch_rounds(reinterpret_cast<const RoundsJob*>(dblob + L.seg[k].rounds),
+                               (uint32_t)P.seg[k].rounds.size(), s2));
+  }
   for (size_t k = 0; k < nseg; ++k) {
     const Segment& G = P.seg[k];
     for (int c = 0; c < CK_COUNT; ++c) {
@@ -568,7 +582,7 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
       VL_STAGE(ev, VL_STAGE_PASS1, s,
                launch_pass1(reinterpret_cast<const Pass1Job*>(dblob + L.seg[k].pass1), (uint32_t)G.pass1.size(),
                             G.pass1_blocks, s));
-    if (G.rounds.empty()) continue;
+    if (G.rounds.empty() || P.persistent) continue;
     if (two) {
       hipError_t e = hipEventRecord(fork.ev[k], s);
       if (e == hipSuccess) e = hipStreamWaitEvent(s2, fork.ev[k], 0);
@@ -594,6 +608,7 @@ static void apply_tuning(Tuning& t, const vl_tuning* k) {
   if (k->min_tasks) t.min_tasks = k->min_tasks;
   if (k->segments && !t.per_instance) t.segments = k->segments;
   if (k->cols_rows) t.cols_rows = k->cols_rows;
+  if (k->spin_limit) t.spin_limit = k->spin_limit;
 }
 
 static vl_status check_tuning(const vl_tuning* k) {
@@ -609,8 +624,9 @@ static vl_status check_tuning(const vl_tuning* k) {
 Tuning tuning_for(const vl_prove_opts* o) {
   Tuning t;
   t.per_instance = !o || o->mode == VL_MODE_PER_INSTANCE;
+  t.persistent = o && o->mode == VL_MODE_PERSISTENT;
   t.min_tasks = t.per_instance ? 1024 : 1;
-  t.segments = t.per_instance ? 1 : kDefaultSegments;
+  t.segments = t.per_instance ? 1 : (t.persistent ? kPersistentSegments : kDefaultSegments);
   if (o) apply_tuning(t, o->tuning);
   return t;
 }
@@ -630,6 +646,7 @@ void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, 
                  uint64_t seed, uint8_t* ws, bool async, uint8_t* proofs_dev, const uint64_t* offsets,
                  int32_t* status_dev, uint8_t* digests_dev) {
   P = Plan();
+  P.persistent = T.persistent;
   const uint64_t blob = blob_bound(groups + g0, g1 - g0);
   Builder B(P, T, reinterpret_cast<uint64_t>(ws), blob);
   P.n_err = (uint32_t)(g1 - g0);
@@ -686,8 +703,9 @@ void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, 
     }
     rel += 32 * proof_elems(groups[i]);
     int32_t* err = reinterpret_cast<int32_t*>(ws + 4 * (i - g0));  // blob starts with the flags
+    uint32_t* ready = T.persistent ? reinterpret_cast<uint32_t*>(ws + 4 * (n + (i - g0))) : nullptr;
     B.cur = seg_of[i - g0];
-    B.group(groups[i], ch[i - g0], pd, sd, dd, err);
+    B.group(groups[i], ch[i - g0], pd, sd, dd, err, ready);
   }
   P.data_end = B.off;
 }
@@ -734,6 +752,9 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
   if (o->mode < VL_MODE_PER_INSTANCE || o->mode > VL_MODE_PERSISTENT)
     return fail(VL_ERR_INVALID_ARG, "unknown mode %d", o->mode);
   if (o->async && !o->status) return fail(VL_ERR_INVALID_ARG, "async mode needs a status array");
+  if (o->mode == VL_MODE_PERSISTENT && n > kMaxPersistentGroups)
+    return fail(VL_ERR_INVALID_ARG, "persistent mode takes at most %llu groups per call",
+                (unsigned long long)kMaxPersistentGroups);
   for (uint64_t i = 0; i < n; ++i) {
     const vl_status st = check_group(groups[i], true);
     if (st != VL_OK) return st;
@@ -787,6 +808,9 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
       if (st == VL_ERR_RANGE)
         return fail(VL_ERR_RANGE, "group %u: an entry of C exceeds the contraction digit range",
                     groups[i].group_id);
+      if (st == VL_ERR_TIMEOUT)
+        return fail(VL_ERR_TIMEOUT, "group %u: the rounds gave up waiting for the contractions",
+                    groups[i].group_id);
       if (st != VL_OK) return fail(VL_ERR_HIP, "group %u: prover status %d", groups[i].group_id, st);
     }
     return VL_OK;
@@ -799,7 +823,7 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
     const BlobLayout L = blob_layout(P);
     fill_blob(P, L, ws);
     hipStream_t s2 = s;
-    if (P.seg.size() > 1) {
+    if (P.seg.size() > 1 || P.persistent) {
       const hipError_t e2 = rounds_stream_for(s, &s2);
       if (e2 != hipSuccess) return fail(VL_ERR_HIP, "rounds stream: %s", hipGetErrorString(e2));
     }

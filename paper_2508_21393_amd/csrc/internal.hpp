@@ -12,7 +12,7 @@ constexpr int kWave = 64;
 constexpr int kContractBlock = 256;            // 4 waves, one task per wave
 constexpr uint32_t kChunkAlign = 32;           // contraction chunks start at multiples of 32
 constexpr uint32_t kMaxChunk = 1u << 16;       // int64 accumulators of int16 digits hold 2^16 entries
-constexpr int kRoundsBlock = 512;
+constexpr int kRoundsBlock = 256;
 
 // An eq table to build: out[i] = prod_j (x_j or 1 - x_j), i < 2^nvars, plus
 // its "pack" form used by the integer contractions (see contract kernel).
@@ -96,6 +96,7 @@ struct Pass1Job {
   uint32_t block_begin;       // prefix sum of blocks within a launch
   uint32_t pad_;
   uint32_t* out;              // 3 elements (24 words) per block
+  uint32_t* ready;            // persistent mode: the group's readiness counter, else null
 };
 
 struct RoundsProd {
@@ -122,7 +123,10 @@ struct RoundsJob {
   const int32_t* err;         // range flag of this group's contractions
   const uint32_t* c_part;     // pass-1 partials of c (element 0 of each)
   uint32_t c_nparts;
-  uint32_t pad_;
+  uint32_t ready_target;      // persistent mode: pass-1 blocks of this group
+  const uint32_t* ready;      // persistent mode: readiness counter, else null
+  uint32_t spin_limit;        // polls of `ready` before giving up (VL_ERR_TIMEOUT)
+  uint32_t pad2_;
   RoundsProd prods[VL_MAX_PRODS];
 };
 

@@ -301,8 +301,11 @@ contract_kernel(const ContractJob* __restrict__ jobs, uint32_t n_jobs, uint32_t 
   }
   const ContractJob& J = jobs[lo];
   const uint32_t local = task - J.task_begin;
-  const uint32_t chunk = local % J.n_chunks;
-  const uint32_t owave = local / J.n_chunks;
+  // output groups vary fastest: the waves of a block (one CU) work on the
+  // same chunk, so they share its eq digits in the scalar cache (and the
+  // row kernels read adjacent segments of the same rows)
+  const uint32_t owave = local % J.out_waves;
+  const uint32_t chunk = local / J.out_waves;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t n0 = (owave * 64u + lane) * OPL;
   const uint32_t m0 = chunk * J.chunk;
@@ -696,6 +699,10 @@ __global__ void __launch_bounds__(256) pass1_kernel(const Pass1Job* __restrict__
       for (int k = 0; k < 3; ++k)
 #pragma unroll
         for (int j = 0; j < 8; ++j) o[k * 8 + j] = g[k].w[j];
+      // persistent mode: count this block for the group's resident rounds
+      // workgroup (release: the partials, and everything the earlier
+      // kernels of the stream wrote, are visible to whoever sees the count)
+      if (J.ready) __hip_atomic_fetch_add(J.ready, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
@@ -726,6 +733,27 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
   const uint32_t tid = threadIdx.x, NT = blockDim.x;
   const uint32_t wave = tid >> 6, lane = tid & 63u;
 
+  if (J.ready) {
+    // persistent mode: wait until every pass-1 block of this group has
+    // counted itself (acquire), at most spin_limit polls
+    if (tid == 0) {
+      uint32_t polls = 0;
+      int32_t ok = 1;
+      while (__hip_atomic_load(J.ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < J.ready_target) {
+        if (++polls > J.spin_limit) {
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(8);
+      }
+      verdict = ok;
+    }
+    __syncthreads();
+    if (!verdict) {
+      if (tid == 0) *J.status = VL_ERR_TIMEOUT;
+      return;
+    }
+  }
   if (J.err && *(volatile const int32_t*)J.err) {
     if (tid == 0) *J.status = VL_ERR_RANGE;
     return;

@@ -28,7 +28,9 @@ struct Challenges {
 };
 
 constexpr uint32_t kMaxSegments = 8;
+constexpr uint64_t kMaxPersistentGroups = 256;
 constexpr uint32_t kDefaultSegments = 1;
+constexpr uint32_t kPersistentSegments = 4;
 
 struct Tuning {
   bool per_instance = false;
@@ -36,6 +38,8 @@ struct Tuning {
   uint32_t segments = 1;          // pipeline segments (batched mode)
   uint32_t min_tasks = 1;         // split a contraction until it has this many tasks
   uint32_t cols_rows = 1;         // rows per lane, vector cols kernels (1 or 2)
+  bool persistent = false;        // rounds launched first, waiting on readiness counters
+  uint32_t spin_limit = 1u << 24; // persistent mode: polls before VL_ERR_TIMEOUT
 };
 
 // Jobs of one pipeline segment: its groups' contractions, finish jobs and
@@ -54,6 +58,7 @@ struct Segment {
 
 struct Plan {
   std::vector<uint8_t> blob;      // host image of [err flags][eq jobs][points][segments]
+  bool persistent = false;        // rounds launched before the contractions
   uint64_t data_end = 0;          // workspace bytes used
   std::vector<EqJob> eq;
   uint32_t eq_threads = 0;
@@ -97,9 +102,9 @@ struct Builder {
   void eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_len, bool pack_r2);
   // pass-1 job over a, b; returns the partials buffer, sets its block count
   const uint32_t* pass1(const uint32_t* a, uint64_t a_ld, const uint32_t* b, uint64_t b_ld, uint32_t h,
-                        bool dot, uint32_t& nparts);
+                        bool dot, uint32_t& nparts, uint32_t* ready);
   void group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev, int32_t* status_dev,
-             uint8_t* digest_dev, int32_t* err);
+             uint8_t* digest_dev, int32_t* err, uint32_t* ready);
 };
 
 BlobLayout blob_layout(const Plan& P);

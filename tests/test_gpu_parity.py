@@ -199,3 +199,44 @@ def test_full_size_config_matches_oracle(B, cfg):
         assert rec["name"] == g.name
         assert sha(pr) == rec["proof_sha256"], g.name
         assert dg.hex() == rec["state"], g.name
+
+
+# --------------------------------------------------------------- persistent --
+def test_persistent_mode_matches_oracle_bytes(B):
+    # resident rounds workgroups waiting on readiness counters: same bytes
+    w, spec = tiny_workload()
+    _say("tiny cases mode=persistent")
+    proofs, digests = _prove(B, w, B.VL_MODE_PERSISTENT)
+    for g, pr, dg, gold in zip(w.groups, proofs, digests, spec["groups"]):
+        assert pr.hex() == gold["proof_hex"], g.name
+        assert dg.hex() == gold["state"], g.name
+
+
+def test_persistent_mode_full_size_cfg3(B):
+    _say("cfg3 persistent: generating")
+    w = workloads.make_config("cfg3")
+    gold = golden("cfg3")
+    for segments in (1, 4):
+        _say(f"cfg3 persistent: proving, {segments} segments")
+        gs = [device_group(g, B) for g in w.groups]
+        proofs, digests = B.sumcheck_matmul_prove(gs, w.seed, mode=B.VL_MODE_PERSISTENT,
+                                                  tuning_=B.tuning(segments=segments))
+        for g, pr, dg, rec in zip(w.groups, proofs, digests, gold["groups"]):
+            assert sha(pr) == rec["proof_sha256"], g.name
+            assert dg.hex() == rec["state"], g.name
+
+
+def test_persistent_spin_limit_reports_timeout(B):
+    # a spin limit of one poll (forced from the host): the resident rounds
+    # give up long before the contractions are done, report VL_ERR_TIMEOUT,
+    # and every kernel still exits normally
+    g = workloads.tiny_random_group(11, [(512, 4096, 512)])
+    _say("persistent timeout")
+    with pytest.raises(B.VLError) as e:
+        B.sumcheck_matmul_prove([device_group(g, B)], 1, mode=B.VL_MODE_PERSISTENT,
+                                tuning_=B.tuning(spin_limit=1))
+    assert e.value.status == B.VL_ERR_TIMEOUT
+    # the same call with the default limit proves
+    proofs, _ = B.sumcheck_matmul_prove([device_group(g, B)], 1, mode=B.VL_MODE_PERSISTENT)
+    ref, _ = B.sumcheck_matmul_prove([device_group(g, B)], 1, mode=B.VL_MODE_BATCHED)
+    assert proofs == ref
