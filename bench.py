@@ -88,6 +88,26 @@ def contraction_bytes(groups, cols_rows=1):
     return {B.STAGE_NAMES.index(n): v for n, v in k.items() if v[1]}
 
 
+def measured_traffic(stage_name):
+    """HBM bytes per launch of a contraction kind from the rocprofv3 counter
+    summary in profiles/, or None when there is none for this kind or the
+    kernel source changed since the counters were taken."""
+    import glob
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_2508_21393_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()
+    for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md")):
+        m = re.search(r"```json\s*(\{.*?\})\s*```", open(path).read(), re.S)
+        if not m:
+            continue
+        rec = json.loads(m.group(1))
+        if rec.get("stage") == stage_name and rec.get("kernels_hip_sha256") == h:
+            return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    return None
+
+
 def cpu_baseline(workload, budget_s=15.0):
     """The oracle, unmodified, single-threaded, on the cheapest groups of the
     same workload until the time budget is used."""
@@ -300,7 +320,7 @@ def main():
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
     rates = None if args.no_peak else peak_rates()
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_GBPS, "unit": "GB/s",
-                "frac": achieved / HBM_GBPS, "traffic": None,
+                "frac": achieved / HBM_GBPS, "traffic": measured_traffic(B.STAGE_NAMES[dom]),
                 "kernel": f"contract_kernel {B.STAGE_NAMES[dom]} (eq digits x matrix digits, v_mad_i64_i32)",
                 "bytes_per_launch": dom_bytes, "entries_per_launch": dom_entries, "avg_launch_ms": dom_ms,
                 "per_kind": {B.STAGE_NAMES[k]: {"ms": stage_avg[k], "GBps": b / (stage_avg[k] * 1e-3) / 1e9
