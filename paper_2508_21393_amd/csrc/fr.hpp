@@ -67,14 +67,38 @@ VL_HD bool fr_is_zero(const Fr& a) {
   return d == 0;
 }
 
+// 32-bit add/subtract with carry in and out (one v_add_co/v_addc_co or
+// v_sub_co/v_subb_co on the device with clang's builtins)
+VL_HD uint32_t adc32(uint32_t a, uint32_t b, uint32_t cin, uint32_t& cout) {
+#if defined(__clang__)
+  unsigned c;
+  const uint32_t r = __builtin_addc(a, b, cin, &c);
+  cout = c;
+  return r;
+#else
+  const uint64_t t = (uint64_t)a + b + cin;
+  cout = (uint32_t)(t >> 32);
+  return (uint32_t)t;
+#endif
+}
+VL_HD uint32_t sbb32(uint32_t a, uint32_t b, uint32_t bin, uint32_t& bout) {
+#if defined(__clang__)
+  unsigned c;
+  const uint32_t r = __builtin_subc(a, b, bin, &c);
+  bout = c;
+  return r;
+#else
+  const uint64_t t = (uint64_t)a - b - bin;
+  bout = (uint32_t)(t >> 63);
+  return (uint32_t)t;
+#endif
+}
+
 // a < p ?
 VL_HD bool fr_lt_p(const Fr& a) {
   uint32_t borrow = 0;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    uint64_t d = (uint64_t)a.w[i] - p_limb(i) - borrow;
-    borrow = (uint32_t)(d >> 63);
-  }
+  for (int i = 0; i < 8; ++i) (void)sbb32(a.w[i], p_limb(i), borrow, borrow);
   return borrow != 0;
 }
 
@@ -83,11 +107,7 @@ VL_HD Fr fr_reduce_once(const Fr& a) {
   Fr t;
   uint32_t borrow = 0;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    uint64_t d = (uint64_t)a.w[i] - p_limb(i) - borrow;
-    t.w[i] = (uint32_t)d;
-    borrow = (uint32_t)(d >> 63);
-  }
+  for (int i = 0; i < 8; ++i) t.w[i] = sbb32(a.w[i], p_limb(i), borrow, borrow);
   Fr r;
 #pragma unroll
   for (int i = 0; i < 8; ++i) r.w[i] = borrow ? a.w[i] : t.w[i];
@@ -98,11 +118,7 @@ VL_HD Fr fr_add(const Fr& a, const Fr& b) {
   Fr s;
   uint32_t c = 0;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    uint64_t t = (uint64_t)a.w[i] + b.w[i] + c;
-    s.w[i] = (uint32_t)t;
-    c = (uint32_t)(t >> 32);
-  }
+  for (int i = 0; i < 8; ++i) s.w[i] = adc32(a.w[i], b.w[i], c, c);
   return fr_reduce_once(s);   // a + b < 2p < 2^256: no carry out
 }
 
@@ -110,20 +126,12 @@ VL_HD Fr fr_sub(const Fr& a, const Fr& b) {
   Fr d;
   uint32_t borrow = 0;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    uint64_t t = (uint64_t)a.w[i] - b.w[i] - borrow;
-    d.w[i] = (uint32_t)t;
-    borrow = (uint32_t)(t >> 63);
-  }
+  for (int i = 0; i < 8; ++i) d.w[i] = sbb32(a.w[i], b.w[i], borrow, borrow);
   // if it went negative add p back
-  uint32_t mask = 0u - borrow;
+  const uint32_t mask = 0u - borrow;
   uint32_t c = 0;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    uint64_t t = (uint64_t)d.w[i] + (p_limb(i) & mask) + c;
-    d.w[i] = (uint32_t)t;
-    c = (uint32_t)(t >> 32);
-  }
+  for (int i = 0; i < 8; ++i) d.w[i] = adc32(d.w[i], p_limb(i) & mask, c, c);
   return d;
 }
 
@@ -132,16 +140,13 @@ VL_HD Fr fr_double(const Fr& a) { return fr_add(a, a); }
 
 // a / 2: a (even) or a + p (odd) shifted right by one; a + p < 2^256
 VL_HD Fr fr_half(const Fr& a) {
-  Fr t = a;
-  if (a.w[0] & 1u) {
-    uint64_t c = 0;
-    for (int j = 0; j < 8; ++j) {
-      c += (uint64_t)a.w[j] + p_limb(j);
-      t.w[j] = (uint32_t)c;
-      c >>= 32;
-    }
-  }
+  const uint32_t mask = 0u - (a.w[0] & 1u);
+  Fr t;
+  uint32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) t.w[j] = adc32(a.w[j], p_limb(j) & mask, c, c);
   Fr r;
+#pragma unroll
   for (int j = 0; j < 7; ++j) r.w[j] = (t.w[j] >> 1) | (t.w[j + 1] << 31);
   r.w[7] = t.w[7] >> 1;
   return r;
