@@ -33,7 +33,7 @@ CU, LANES_PER_CLK, CLOCK_HZ = 256, 64, 2.4e9   # MI355X: CUs, VALU lanes per CU 
 HBM_GBPS = 8000.0                               # MI355X HBM3E peak
 # v_mad_i64_i32 per matrix entry: 8 eq digits x the entry's digits
 MAD_PER_ENTRY = {"i16_rows": 8, "i16_rows4_vec": 8, "i16_cols_vec": 8, "i16_cols2_vec": 8,
-                 "i64s_cols_vec": 16, "i64s_cols2_vec": 16}
+                 "i64s_cols_vec": 16, "i64s_cols2_vec": 16, "i64s_rows2_vec": 16, "i64s_rows": 16}
 
 
 def nv(d):
@@ -52,14 +52,16 @@ def algorithmic_macs(shapes_by_group):
     return total
 
 
-def contraction_bytes(groups, cols_rows=1):
+def contraction_bytes(groups, cols_rows=1, claim_order=0):
     """Matrix bytes and entries streamed per prove call by each contraction
     kernel kind (stage index -> (bytes, entries)), following the library's
     planning rule for these operands (int16 A and B, int64 C with
     |C| < 2^47, all 16-byte aligned): a row contraction with at least 256
     outputs runs 4 columns per lane with 8-byte loads, else 1 column per
     lane; column contractions read 16-byte vectors, two rows per lane when
-    tuned so and there are >= 128 rows; C is contracted over its columns."""
+    tuned so and there are >= 128 rows; C is contracted over its rows (two
+    columns per lane, 16-byte loads) when it has >= 256 columns or when
+    tuned so, else over its columns."""
     from paper_2508_21393_amd import binding as B
     k = {}
 
@@ -72,7 +74,10 @@ def contraction_bytes(groups, cols_rows=1):
 
     for g in groups:
         d0, _, d2 = g.products[0].dims
-        add("i64s_cols2_vec" if cols_rows == 2 and d0 >= 128 else "i64s_cols_vec", d0 * d2, 8)
+        if claim_order == 2 or (claim_order == 0 and d2 >= 256):
+            add("i64s_rows2_vec" if d2 >= 128 else "i64s_rows", d0 * d2, 8)
+        else:
+            add("i64s_cols2_vec" if cols_rows == 2 and d0 >= 128 else "i64s_cols_vec", d0 * d2, 8)
         for p in g.products:
             d0, d1, d2 = p.dims
             # A side: outputs are the D1 columns of op(A)
@@ -177,6 +182,8 @@ def main():
     ap.add_argument("--min-tasks", type=int, default=0, help="vl_tuning.min_tasks (0: library default)")
     ap.add_argument("--segments", type=int, default=0, help="vl_tuning.segments (0: library default)")
     ap.add_argument("--cols-rows", type=int, default=0, help="vl_tuning.cols_rows (0: library default)")
+    ap.add_argument("--claim-order", type=int, default=0,
+                    help="vl_tuning.claim_order (0: library default, 1: C by columns, 2: C by rows)")
     ap.add_argument("--inflight", type=int, default=2,
                     help="proofs in flight in the throughput phase (asynchronous entry point)")
     ap.add_argument("--autotune", action="store_true",
@@ -209,7 +216,7 @@ def main():
     shapes = [g.shapes for g in groups]
     macs = algorithmic_macs(shapes)
     n_products = sum(len(s) for s in shapes)
-    tun = B.tuning(args.lane_macs, args.min_tasks, args.segments, args.cols_rows)
+    tun = B.tuning(args.lane_macs, args.min_tasks, args.segments, args.cols_rows, 0, args.claim_order)
     tried = None
     if args.autotune:
         tun, tried = autotune(B, batch, w.seed, mode)
@@ -313,7 +320,7 @@ def main():
     # dominant kernel: the contraction kind with the most device time.  Its
     # algorithmic traffic is the matrix bytes it must stream (every entry
     # once); the eq digits and partial sums are small and mostly cache hits.
-    kinds = contraction_bytes(groups, cols_rows=tun.cols_rows)
+    kinds = contraction_bytes(groups, cols_rows=tun.cols_rows, claim_order=tun.claim_order)
     dom = max(kinds, key=lambda k: stage_avg[k])
     dom_ms = stage_avg[dom]
     dom_bytes, dom_entries = kinds[dom]
@@ -350,7 +357,7 @@ def main():
         "valu_lane_ops_per_s": rates,
         "witness_setup_s": t_gen,
         "tuning": {"lane_macs": tun.lane_macs, "min_tasks": tun.min_tasks, "segments": tun.segments,
-                   "cols_rows": tun.cols_rows},
+                   "cols_rows": tun.cols_rows, "claim_order": tun.claim_order},
     }
     if tried is not None:
         out["autotune"] = tried

@@ -117,7 +117,10 @@ typedef struct {
   uint32_t spin_limit;     /* persistent mode: polls (about 0.2 us each) of a
                               group's readiness before its rounds give up with
                               VL_ERR_TIMEOUT                                       */
-  uint32_t reserved;       /* must be 0                                            */
+  uint32_t claim_order;    /* the claim's contraction over C: 0 = by rows when C
+                              has >= 256 columns, else by columns; 1 = always by
+                              columns, t[i] = sum_j C[i][j] eq(v, j); 2 = always
+                              by rows, s[j] = sum_i eq(u, i) C[i][j]              */
 } vl_tuning;
 
 typedef struct {
@@ -139,19 +142,21 @@ typedef struct {
 /* stages of a prove call, in launch order */
 #define VL_STAGE_UPLOAD 0      /* job descriptors to device memory                 */
 #define VL_STAGE_EQ 1          /* eq tables and their byte-sliced "pack" form      */
-#define VL_STAGE_CONTRACT 2    /* + kind: integer contraction kernels, 16 kinds:
+#define VL_STAGE_CONTRACT 2    /* + kind: integer contraction kernels, 19 kinds:
                                   int16 rows (1 column per lane; 4 columns with
                                   element loads; 4 columns with 8-byte loads),
                                   int16 cols (element loads; 16-byte row loads,
-                                  1 or 2 rows per lane); int32 rows, cols,
-                                  cols-vec; int64 with |x| < 2^47 rows, cols,
-                                  cols-vec (1 or 2 rows per lane); int64 rows,
-                                  cols, cols-vec                                   */
-#define VL_STAGE_FINISH 18     /* split-contraction sums and zero padding          */
-#define VL_STAGE_PASS1 19      /* claim c and round 1 of every product, as partial
+                                  1 or 2 rows per lane); int32 rows (1 column;
+                                  4 columns with 16-byte loads), cols, cols-vec;
+                                  int64 with |x| < 2^47 rows (1 column; 2 columns
+                                  with 16-byte loads), cols, cols-vec (1 or 2
+                                  rows per lane); int64 rows (1 column; 2
+                                  columns with 16-byte loads), cols, cols-vec     */
+#define VL_STAGE_FINISH 21     /* split-contraction sums and zero padding          */
+#define VL_STAGE_PASS1 22      /* claim c and round 1 of every product, as partial
                                   sums across the GPU                              */
-#define VL_STAGE_ROUNDS 20     /* prover guard, sumcheck rounds, proof bytes       */
-#define VL_STAGE_COUNT 21
+#define VL_STAGE_ROUNDS 23     /* prover guard, sumcheck rounds, proof bytes       */
+#define VL_STAGE_COUNT 24
 
 /* Lift n signed integers (dtype) at device pointer src into Fr (Montgomery,
  * structure-of-limbs) at dst (dst.n >= n).  Negative x becomes p - |x|. */

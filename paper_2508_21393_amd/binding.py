@@ -18,11 +18,11 @@ VL_I16, VL_I32, VL_I64 = 1, 2, 3
 VL_CONTRACT_ROWS, VL_CONTRACT_COLS = 0, 1
 VL_MODE_PER_INSTANCE, VL_MODE_BATCHED, VL_MODE_PERSISTENT = 0, 1, 2
 VL_MAX_PRODS = 8
-VL_STAGE_COUNT = 21
+VL_STAGE_COUNT = 24
 STAGE_NAMES = ["upload", "eq", "i16_rows", "i16_rows4", "i16_rows4_vec", "i16_cols", "i16_cols_vec",
-               "i16_cols2_vec", "i32_rows", "i32_cols", "i32_cols_vec", "i64s_rows", "i64s_cols",
-               "i64s_cols_vec", "i64s_cols2_vec", "i64_rows", "i64_cols", "i64_cols_vec", "finish", "pass1",
-               "rounds"]
+               "i16_cols2_vec", "i32_rows", "i32_rows4_vec", "i32_cols", "i32_cols_vec", "i64s_rows",
+               "i64s_rows2_vec", "i64s_cols", "i64s_cols_vec", "i64s_cols2_vec", "i64_rows", "i64_rows2_vec",
+               "i64_cols", "i64_cols_vec", "finish", "pass1", "rounds"]
 
 STATUS_NAMES = {0: "VL_OK", 1: "VL_ERR_INVALID_ARG", 2: "VL_ERR_SHAPE", 3: "VL_ERR_DTYPE",
                 4: "VL_ERR_WORKSPACE", 5: "VL_ERR_HIP", 6: "VL_ERR_FALSE_STATEMENT",
@@ -56,15 +56,15 @@ class vl_group(ctypes.Structure):
 
 class vl_tuning(ctypes.Structure):
     _fields_ = [("lane_macs", c_u32), ("min_tasks", c_u32), ("segments", c_u32), ("cols_rows", c_u32),
-                ("spin_limit", c_u32), ("reserved", c_u32)]
+                ("spin_limit", c_u32), ("claim_order", c_u32)]
 
 
 def tuning(lane_macs: int = 0, min_tasks: int = 0, segments: int = 0, cols_rows: int = 0,
-           spin_limit: int = 0) -> vl_tuning:
+           spin_limit: int = 0, claim_order: int = 0) -> vl_tuning:
     """Launch-shape knobs (0 = library default); results never depend on them
     (a spin limit too small for the work makes persistent-mode groups fail
     with VL_ERR_TIMEOUT instead)."""
-    return vl_tuning(lane_macs, min_tasks, segments, cols_rows, spin_limit, 0)
+    return vl_tuning(lane_macs, min_tasks, segments, cols_rows, spin_limit, claim_order)
 
 
 def _tun(t):

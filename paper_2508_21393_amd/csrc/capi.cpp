@@ -226,9 +226,16 @@ static int contract_kind(int dtype, int nd, bool rows, bool vec, int opl) {
     if (rows) return opl == 4 ? (vec ? CK_I16_ROWS4_VEC : CK_I16_ROWS4) : CK_I16_ROWS;
     return vec ? (opl == 2 ? CK_I16_COLS2_VEC : CK_I16_COLS_VEC) : CK_I16_COLS;
   }
-  if (dtype == VL_I32) return rows ? CK_I32_ROWS : (vec ? CK_I32_COLS_VEC : CK_I32_COLS);
-  if (nd == 2) return rows ? CK_I64S_ROWS : (vec ? (opl == 2 ? CK_I64S_COLS2_VEC : CK_I64S_COLS_VEC) : CK_I64S_COLS);
-  return rows ? CK_I64_ROWS : (vec ? CK_I64_COLS_VEC : CK_I64_COLS);
+  if (dtype == VL_I32) {
+    if (rows) return (vec && opl == 4) ? CK_I32_ROWS4_VEC : CK_I32_ROWS;
+    return vec ? CK_I32_COLS_VEC : CK_I32_COLS;
+  }
+  if (nd == 2) {
+    if (rows) return (vec && opl == 2) ? CK_I64S_ROWS2_VEC : CK_I64S_ROWS;
+    return vec ? (opl == 2 ? CK_I64S_COLS2_VEC : CK_I64S_COLS_VEC) : CK_I64S_COLS;
+  }
+  if (rows) return (vec && opl == 2) ? CK_I64_ROWS2_VEC : CK_I64_ROWS;
+  return vec ? CK_I64_COLS_VEC : CK_I64_COLS;
 }
 
 void Builder::contract(const void* M, int dtype, int nd, uint64_t ld, bool rows, uint32_t n_out,
@@ -236,21 +243,29 @@ void Builder::contract(const void* M, int dtype, int nd, uint64_t ld, bool rows,
                        uint64_t n_total, int32_t* err) {
   ContractJob j{};
   const uint64_t es = esize(dtype);
-  // vector loads: 16-byte aligned rows (cols kernels), 8-byte aligned groups
-  // of four columns (int16 rows kernel)
-  const bool vec = rows ? ((reinterpret_cast<uintptr_t>(M) % 8 == 0) && ((ld * es) % 8 == 0))
-                        : ((reinterpret_cast<uintptr_t>(M) % 16 == 0) && ((ld * es) % 16 == 0));
-  // four adjacent columns per lane for wide int16 row contractions: one
-  // scalar load of the eq digits then feeds 32 multiply-adds
-  // two rows per lane in the vector cols kernels (tuning): each scalar load
-  // of eq digits then feeds twice the multiply-adds
-  int opl = (rows && dtype == VL_I16 && n_out >= 256) ? 4 : 1;
+  const bool wide = dtype != VL_I16;
+  // outputs per lane.  Rows kernels: adjacent columns read as one vector per
+  // row (4 int16 = 8 bytes; 4 int32 or 2 int64 = 16 bytes), so that one
+  // scalar load of eq digits feeds 32 or more multiply-adds.  Vector cols
+  // kernels: two rows per lane on request (tuning).
+  int opl = 1;
+  if (rows && n_out >= 256) opl = (int)((dtype == VL_I16 ? 8 : 16) / es);
+  if (rows && wide && es == 8 && n_out >= 128) opl = 2;
+  // vector loads: aligned groups of opl columns (rows kernels), 16-byte
+  // aligned rows (cols kernels)
+  const uint64_t vb = rows ? opl * es : 16;
+  const bool vec = (!rows || opl > 1) && (reinterpret_cast<uintptr_t>(M) % vb == 0) && ((ld * es) % vb == 0);
+  if (rows && wide && !vec) opl = 1;   // wide rows kernels with element loads: one column per lane
   if (!rows && vec && T.cols_rows == 2 && (dtype == VL_I16 || nd == 2) && n_out >= 128) opl = 2;
   const int kind = contract_kind(dtype, nd, rows, vec, opl);
   const uint32_t out_waves = (n_out + 64 * opl - 1) / (64 * opl);
   // chunk: about T.lane_macs multiply-adds per lane and task
   uint64_t chunk = std::max<uint64_t>(64, T.lane_macs / (8ull * nd * opl));
   chunk = std::min<uint64_t>(chunk, kMaxChunk);
+  // the vector rows kernels of wide entries keep no high-word accumulators:
+  // a chunk holds at most kWideSpill rows
+  const bool no_spill = rows && wide && vec;
+  if (no_spill) chunk = std::min<uint64_t>(chunk, kWideSpill);
   // narrow contractions (one output wave): split the contraction index finely
   // so that the job spreads over the GPU instead of one long chain per wave
   if (out_waves <= 2) chunk = std::min<uint64_t>(chunk, std::max<uint64_t>(64, len / 64));
@@ -300,10 +315,12 @@ void Builder::contract(const void* M, int dtype, int nd, uint64_t ld, bool rows,
   }
 }
 
-void Builder::eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_len, bool pack_r2) {
+void Builder::eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_len, bool pack_r2,
+                     bool eq_canon) {
   EqJob e{};
   e.nvars = (uint32_t)x.size();
   e.pack_r2 = pack_r2 ? 1u : 0u;
+  e.eq_canon = eq_canon ? 1u : 0u;
   e.pack_len = pack_len;
   e.thread_begin = P.eq_threads;
   e.eq = eq;
@@ -328,20 +345,23 @@ void Builder::group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev,
   const vl_product& p0 = g.prods[0];
   const uint32_t D0 = p0.D0, D2 = p0.D2, n0 = (uint32_t)u.size();
   const uint64_t L0 = 1ull << n0;
-  uint32_t* eqU = dev<uint32_t>(take(8 * L0 * 4));
+  const uint32_t n2 = (uint32_t)v.size();
+  const uint64_t L2 = 1ull << n2;
   uint32_t* packU = dev<uint32_t>(take((uint64_t)D0 * 32));
   uint32_t* packV = dev<uint32_t>(take((uint64_t)D2 * 32));
-  uint32_t* tvec = dev<uint32_t>(take(8 * L0 * 4));
-  // A~(u, w) in Montgomery form (pack of e R^2); B~(w, v) and the claim's
-  // t in canonical form (pack of e R): every product a * b of the rounds is
-  // then canonical, and so are the round values that go into the proof
-  eq_job(u, eqU, packU, D0, true);
-  eq_job(v, nullptr, packV, D2, false);
 
-  // claim contraction: t[i] = sum_j C[i][j] eq(v, j).  Two 24-bit digits
-  // cover |C| < 2^47 - 2^23, enough for sums of int16 products with a total
-  // inner dimension <= 2^16; wider C uses three (an out-of-range entry makes
-  // the prover refuse with VL_ERR_RANGE rather than prove a wrong claim).
+  // The claim c = C~(u, v) = sum_{i,j} eq(u, i) C[i][j] eq(v, j) (eq.
+  // (zk-mle-matmul)), contracted in either order:
+  //   by columns: t[i] = sum_j C[i][j] eq(v, j) (canonical, pack of e R), then
+  //               c = sum_i eq(u, i) t[i] with eq(u, .) in Montgomery form;
+  //   by rows:    s[j] = sum_i eq(u, i) C[i][j] (Montgomery, pack of e R^2),
+  //               then c = sum_j eq(v, j) s[j] with eq(v, .) stored canonical.
+  // Both give c in canonical form.  By rows a wave reads adjacent columns of
+  // each row of C (coalesced), by columns each lane streams its own row.
+  // Two 24-bit digits cover |C| < 2^47 - 2^23, enough for sums of int16
+  // products with a total inner dimension <= 2^16; wider C uses three (an
+  // out-of-range entry makes the prover refuse with VL_ERR_RANGE rather than
+  // prove a wrong claim).
   int ndc = digits_for(g.dtype_c);
   if (g.dtype_c == VL_I64) {
     uint64_t sum_d1 = 0;
@@ -352,20 +372,29 @@ void Builder::group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev,
     }
     if (small && sum_d1 <= (1u << 16)) ndc = 2;
   }
-  contract(g.C, g.dtype_c, ndc, g.ldc, false, D0, D2, packV, tvec, L0, L0, err);
-
+  const bool by_rows = T.claim_order == 2 || (T.claim_order == 0 && D2 >= 256);
   RoundsJob rj{};
-  rj.c_part = pass1(eqU, L0, tvec, L0, (uint32_t)L0, true, rj.c_nparts, ready);
+  if (by_rows) {
+    uint32_t* eqV = dev<uint32_t>(take(8 * L2 * 4));
+    uint32_t* svec = dev<uint32_t>(take(8 * L2 * 4));
+    eq_job(u, nullptr, packU, D0, true, false);
+    eq_job(v, eqV, packV, D2, false, true);
+    contract(g.C, g.dtype_c, ndc, g.ldc, true, D2, D0, packU, svec, L2, L2, err);
+    rj.c_part = pass1(eqV, L2, svec, L2, (uint32_t)L2, true, rj.c_nparts, ready);
+  } else {
+    uint32_t* eqU = dev<uint32_t>(take(8 * L0 * 4));
+    uint32_t* tvec = dev<uint32_t>(take(8 * L0 * 4));
+    eq_job(u, eqU, packU, D0, true, false);
+    eq_job(v, nullptr, packV, D2, false, false);
+    contract(g.C, g.dtype_c, ndc, g.ldc, false, D0, D2, packV, tvec, L0, L0, err);
+    rj.c_part = pass1(eqU, L0, tvec, L0, (uint32_t)L0, true, rj.c_nparts, ready);
+  }
   rj.ready = ready;
   rj.ready_target = rj.c_nparts;
   rj.spin_limit = T.spin_limit;
   memcpy(rj.st, tr.h, 32);
   rj.n_prods = g.n_prods;
   rj.n0 = n0;
-  rj.eqU = eqU;
-  rj.eqU_ld = L0;
-  rj.t = tvec;
-  rj.t_ld = L0;
   rj.proof = proof_dev;
   rj.status = status_dev;
   rj.digest = digest_dev;
@@ -609,11 +638,12 @@ static void apply_tuning(Tuning& t, const vl_tuning* k) {
   if (k->segments && !t.per_instance) t.segments = k->segments;
   if (k->cols_rows) t.cols_rows = k->cols_rows;
   if (k->spin_limit) t.spin_limit = k->spin_limit;
+  if (k->claim_order) t.claim_order = k->claim_order;
 }
 
 static vl_status check_tuning(const vl_tuning* k) {
   if (!k) return VL_OK;
-  if (k->reserved) return fail(VL_ERR_INVALID_ARG, "vl_tuning.reserved must be 0");
+  if (k->claim_order > 2) return fail(VL_ERR_INVALID_ARG, "vl_tuning.claim_order must be 0, 1 or 2");
   if (k->segments > kMaxSegments)
     return fail(VL_ERR_INVALID_ARG, "vl_tuning.segments must be <= %u", kMaxSegments);
   if (k->lane_macs && k->lane_macs < 64) return fail(VL_ERR_INVALID_ARG, "vl_tuning.lane_macs must be >= 64");
@@ -891,13 +921,18 @@ uint64_t vl_partial_eval_workspace_size(uint32_t rows, uint32_t cols, int32_t co
   const bool rws = contract == VL_CONTRACT_ROWS;
   const uint64_t len = rws ? rows : cols, n_out = rws ? cols : rows;
   if (check_tuning(tuning) != VL_OK) return 0;
-  Plan P;
   const Tuning T = pe_tuning(tuning);
-  Builder B(P, T, 0, pe_pack_bytes(len) + kPeBlob);
-  // alignment of M is unknown here; the plan's size does not depend on it
-  B.contract(nullptr, dtype, digits_for(dtype), cols, rws, (uint32_t)n_out, (uint32_t)len, nullptr,
-             nullptr, 1, n_out, nullptr);
-  return align_up(B.off, 256);
+  // the alignment of M (which picks vector or element loads, and with them
+  // the chunking) is unknown here: the larger of the two plans
+  uint64_t need = 0;
+  for (uintptr_t m : {uintptr_t(0), uintptr_t(2)}) {
+    Plan P;
+    Builder B(P, T, 0, pe_pack_bytes(len) + kPeBlob);
+    B.contract(reinterpret_cast<const void*>(m), dtype, digits_for(dtype), cols, rws, (uint32_t)n_out,
+               (uint32_t)len, nullptr, nullptr, 1, n_out, nullptr);
+    need = std::max(need, B.off);
+  }
+  return align_up(need, 256);
 }
 
 vl_status vl_mle_partial_eval(const void* M, int32_t dtype, uint32_t rows, uint32_t cols, uint64_t ld,
@@ -925,6 +960,8 @@ vl_status vl_mle_partial_eval(const void* M, int32_t dtype, uint32_t rows, uint3
   Builder B(P, T, reinterpret_cast<uint64_t>(ws), pe_pack_bytes(len) + kPeBlob);
   B.contract(M, dtype, digits_for(dtype), ld, rws, n_out, len, pack, out.base, out.ld, out.n,
              reinterpret_cast<int32_t*>(dblob));
+  if (B.off > workspace_bytes)
+    return fail(VL_ERR_WORKSPACE, "workspace too small for this matrix's layout");
   int kind = -1;
   const Segment& G = P.seg[0];
   for (int k = 0; k < CK_COUNT; ++k)

@@ -12,6 +12,7 @@ constexpr int kWave = 64;
 constexpr int kContractBlock = 256;            // 4 waves, one task per wave
 constexpr uint32_t kChunkAlign = 32;           // contraction chunks start at multiples of 32
 constexpr uint32_t kMaxChunk = 1u << 16;       // int64 accumulators of int16 digits hold 2^16 entries
+constexpr uint32_t kWideSpill = 256;           // ... and of 24-bit digits 256 entries (products < 2^54)
 constexpr int kRoundsBlock = 256;
 
 // An eq table to build: out[i] = prod_j (x_j or 1 - x_j), i < 2^nvars, plus
@@ -22,8 +23,10 @@ struct EqJob {
   uint32_t thread_begin;      // prefix sum of threads over jobs in a launch
   uint32_t pack_r2;           // 1: pack holds e * R^2 (contractions land in Montgomery
                               // form); 0: e * R (they land in canonical form)
+  uint32_t eq_canon;          // 1: eq holds canonical values, 0: Montgomery form
+  uint32_t pad_;
   const uint32_t* point;      // device: nvars Montgomery elements x_j (8 words each)
-  uint32_t* eq;               // SoL Montgomery output, may be null
+  uint32_t* eq;               // SoL output, may be null
   uint64_t eq_ld;
   uint32_t* pack;             // pack_len * 8 words, may be null
 };
@@ -84,12 +87,13 @@ struct FinishJob {
   uint64_t out_ld;
 };
 
-// Round 1 of one product (or the claim's dot product c = sum_i eqU[i] t[i])
+// Round 1 of one product (or the claim's dot product: c = sum_i eqU[i] t[i]
+// after a contraction of C by columns, c = sum_j eqV[j] s[j] after one by rows)
 // as per-block partial sums, computed across the GPU before the rounds.
 constexpr uint32_t kPass1Pairs = 512;   // pairs (entries for the dot) per 256-thread block
 struct Pass1Job {
-  const uint32_t* a;          // SoL table (eqU for the claim)
-  const uint32_t* b;          // SoL table (t for the claim)
+  const uint32_t* a;          // SoL table (eqU or eqV for the claim)
+  const uint32_t* b;          // SoL table (t or s for the claim)
   uint64_t a_ld, b_ld;
   uint32_t h;                 // pairs (t, t + h), or entries of the dot product
   uint32_t dot;               // 1: sum_i a[i] b[i]; 0: the round-1 values g(0), g(1), g(2)
@@ -113,10 +117,6 @@ struct RoundsJob {
   uint32_t st[8];             // transcript state (digest words) after squeezing u and v
   uint32_t n_prods;
   uint32_t n0;
-  const uint32_t* eqU;        // SoL eq(u, .), length 2^n0
-  uint64_t eqU_ld;
-  const uint32_t* t;          // SoL t[i] = sum_j C[i][j] eq(v, j), length 2^n0
-  uint64_t t_ld;
   uint8_t* proof;             // device proof bytes of this group
   int32_t* status;            // device status word of this group
   uint8_t* digest;            // device 32 bytes or null
@@ -153,11 +153,13 @@ enum ContractKind {
   CK_I16_COLS = 3,       // int16, cols, element loads
   CK_I16_COLS_VEC = 4,   // int16, cols, 16-byte row loads, 1 row per lane
   CK_I16_COLS2_VEC = 5,  // int16, cols, 16-byte row loads, 2 rows per lane
-  CK_I32_ROWS = 6, CK_I32_COLS = 7, CK_I32_COLS_VEC = 8,        // int32, 2 x 24
-  CK_I64S_ROWS = 9, CK_I64S_COLS = 10, CK_I64S_COLS_VEC = 11,   // int64 with |x| < 2^47, 2 x 24
-  CK_I64S_COLS2_VEC = 12,                                       // the same, 2 rows per lane
-  CK_I64_ROWS = 13, CK_I64_COLS = 14, CK_I64_COLS_VEC = 15,     // int64, 3 x 24
-  CK_COUNT = 16
+  // wide entries (2 or 3 digits x 24 bits); the vector rows kinds read 16
+  // bytes (4 int32 or 2 int64 columns) per lane and row
+  CK_I32_ROWS = 6, CK_I32_ROWS4_VEC = 7, CK_I32_COLS = 8, CK_I32_COLS_VEC = 9,           // int32
+  CK_I64S_ROWS = 10, CK_I64S_ROWS2_VEC = 11, CK_I64S_COLS = 12, CK_I64S_COLS_VEC = 13,   // int64, |x| < 2^47
+  CK_I64S_COLS2_VEC = 14,                                                                // the same, 2 rows per lane
+  CK_I64_ROWS = 15, CK_I64_ROWS2_VEC = 16, CK_I64_COLS = 17, CK_I64_COLS_VEC = 18,       // int64, 3 digits
+  CK_COUNT = 19
 };
 static_assert(VL_STAGE_CONTRACT + CK_COUNT == VL_STAGE_FINISH, "one stage per contraction kind");
 

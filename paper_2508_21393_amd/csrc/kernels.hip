@@ -23,6 +23,7 @@
 // (limbs_to_fr) once per output: a contraction split into chunks stores each
 // chunk's sum as raw limbs, which finish_kernel adds up before reducing.
 #include <cstring>
+#include <type_traits>
 
 #include "internal.hpp"
 #include "sha256.hpp"
@@ -98,8 +99,8 @@ __global__ void __launch_bounds__(256) eq_kernel(const EqJob* __restrict__ jobs,
     e1 = fr_mul(base, xl);
   }
   if (J.eq) {
-    if (2ull * t < len) store_sol(J.eq, J.eq_ld, 2ull * t, e0);
-    if (2ull * t + 1 < len) store_sol(J.eq, J.eq_ld, 2ull * t + 1, e1);
+    if (2ull * t < len) store_sol(J.eq, J.eq_ld, 2ull * t, J.eq_canon ? fr_from_mont(e0) : e0);
+    if (2ull * t + 1 < len) store_sol(J.eq, J.eq_ld, 2ull * t + 1, J.eq_canon ? fr_from_mont(e1) : e1);
   }
   if (J.pack) {
     // pack: e * R^2 (or e * R) mod p as signed digits, 8 words per entry
@@ -291,7 +292,7 @@ template <typename T, int ND, int DB, bool ROWS, bool VEC, int OPL>
 __global__ void __launch_bounds__(kContractBlock)
 contract_kernel(const ContractJob* __restrict__ jobs, uint32_t n_jobs, uint32_t n_tasks) {
   constexpr bool WIDE = DB > 16;
-  constexpr uint32_t kSpill = 256;
+  constexpr uint32_t kSpill = kWideSpill;
   const uint32_t task = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (task >= n_tasks) return;
   uint32_t lo = 0, hi_i = n_jobs;
@@ -409,16 +410,31 @@ contract_kernel(const ContractJob* __restrict__ jobs, uint32_t n_jobs, uint32_t 
       }
     }
   } else if constexpr (VEC && ROWS) {
-    // rows layout, four int16 columns per lane read as one 8-byte load per
-    // row, a ring of PF rows in flight.  Lanes past the last column group
-    // re-read the last group (results not stored).
-    static_assert(OPL == 4 && sizeof(T) == 2 && !WIDE, "vector rows kernel: int16, 4 columns");
+    // rows layout: OPL adjacent columns per lane read as one vector per row
+    // (4 int16 = 8 bytes; 4 int32 or 2 int64 = 16 bytes), so a wave reads 512
+    // or 1024 contiguous bytes of each row; a ring of PF rows in flight.
+    // Lanes past the last column group re-read the last group, whose columns
+    // past n_out (inside the aligned vector that holds column n_out - 1, so
+    // inside the matrix's pages) are read but neither stored nor range
+    // checked.  Wide entries: the chunk holds at most kWideSpill rows (the
+    // planner caps it), so the accumulators need no high-word spill.
+    constexpr uint32_t VB = OPL * sizeof(T);
+    static_assert(VB == 8 || VB == 16, "vector rows kernel: 8- or 16-byte column groups");
+    static_assert(WIDE == (sizeof(T) > 2), "int16 entries are single 16-bit digits");
+    typedef typename std::conditional<VB == 8, u32x2, u32x4>::type LT;
     constexpr uint32_t PF = 8;
-    const uint32_t nc = min(n0, ((n_out - 1) / 4) * 4);
+    const uint32_t nc = min(n0, ((n_out - 1) / OPL) * OPL);
     const gptr<T> base = Mg + (uint64_t)m0 * ld + nc;
     const uint32_t rows = m1 - m0;
-    auto row = [&](uint32_t r) -> u32x2 { return *(gptr<u32x2>)(base + (uint64_t)min(r, rows - 1) * ld); };
-    u32x2 buf[PF];
+    auto row = [&](uint32_t r) -> LT { return *(gptr<LT>)(base + (uint64_t)min(r, rows - 1) * ld); };
+    uint32_t bad_o[OPL];
+#pragma unroll
+    for (int o = 0; o < OPL; ++o) bad_o[o] = 0;
+    auto digits = [&](const LT& x, int32_t (&d)[OPL][ND]) {
+#pragma unroll
+      for (int o = 0; o < OPL; ++o) entry_digits<T, ND, DB>(((const T*)&x)[o], d[o], bad_o[o]);
+    };
+    LT buf[PF];
 #pragma unroll
     for (uint32_t s = 0; s < PF; ++s) buf[s] = row(s);
     const uint32_t fullr = rows & ~(PF - 1);
@@ -433,10 +449,7 @@ contract_kernel(const ContractJob* __restrict__ jobs, uint32_t n_jobs, uint32_t 
 #pragma unroll
       for (uint32_t s = 0; s < PF; ++s) {
         int32_t d[OPL][ND];
-        d[0][0] = (int32_t)(int16_t)(buf[s].x & 0xffffu);
-        d[1][0] = (int32_t)(int16_t)(buf[s].x >> 16);
-        d[2][0] = (int32_t)(int16_t)(buf[s].y & 0xffffu);
-        d[3][0] = (int32_t)(int16_t)(buf[s].y >> 16);
+        digits(buf[s], d);
         mac8v<OPL, ND>(e[s], d, acc);
         buf[s] = row(r + s + PF);
       }
@@ -445,13 +458,13 @@ contract_kernel(const ContractJob* __restrict__ jobs, uint32_t n_jobs, uint32_t 
     for (uint32_t s = 0; s < PF; ++s) {   // last rows (fewer than PF)
       if (fullr + s < rows) {
         int32_t d[OPL][ND];
-        d[0][0] = (int32_t)(int16_t)(buf[s].x & 0xffffu);
-        d[1][0] = (int32_t)(int16_t)(buf[s].x >> 16);
-        d[2][0] = (int32_t)(int16_t)(buf[s].y & 0xffffu);
-        d[3][0] = (int32_t)(int16_t)(buf[s].y >> 16);
+        digits(buf[s], d);
         mac8<OPL, ND>(pack + (uint64_t)(m0 + fullr + s) * 8, d, acc);
       }
     }
+#pragma unroll
+    for (int o = 0; o < OPL; ++o)
+      if (n0 + o < n_out) bad |= bad_o[o];
   } else {
     uint32_t m = m0;
     while (m < m1) {
@@ -758,8 +771,8 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
     if (tid == 0) *J.status = VL_ERR_RANGE;
     return;
   }
-  // c = C~(u, v) = sum_i eq(u, i) t[i], from the pass-1 partials (canonical:
-  // eqU is in Montgomery form, t in canonical form)
+  // c = C~(u, v) from the pass-1 partials of its dot product (canonical:
+  // one factor in Montgomery form, the other canonical)
   Fr v1[1];
   v1[0] = fr_zero();
   for (uint32_t i = tid; i < J.c_nparts; i += NT) v1[0] = fr_add(v1[0], lds_or_global_fr(J.c_part + 24ull * i));
@@ -1000,13 +1013,16 @@ hipError_t launch_contract(int kind, const ContractJob* jobs, uint32_t n_jobs, u
     VL_CK(CK_I16_COLS_VEC, int16_t, 1, 16, false, true, 1)
     VL_CK(CK_I16_COLS2_VEC, int16_t, 1, 16, false, true, 2)
     VL_CK(CK_I32_ROWS, int32_t, 2, 24, true, false, 1)
+    VL_CK(CK_I32_ROWS4_VEC, int32_t, 2, 24, true, true, 4)
     VL_CK(CK_I32_COLS, int32_t, 2, 24, false, false, 1)
     VL_CK(CK_I32_COLS_VEC, int32_t, 2, 24, false, true, 1)
     VL_CK(CK_I64S_ROWS, int64_t, 2, 24, true, false, 1)
+    VL_CK(CK_I64S_ROWS2_VEC, int64_t, 2, 24, true, true, 2)
     VL_CK(CK_I64S_COLS, int64_t, 2, 24, false, false, 1)
     VL_CK(CK_I64S_COLS_VEC, int64_t, 2, 24, false, true, 1)
     VL_CK(CK_I64S_COLS2_VEC, int64_t, 2, 24, false, true, 2)
     VL_CK(CK_I64_ROWS, int64_t, 3, 24, true, false, 1)
+    VL_CK(CK_I64_ROWS2_VEC, int64_t, 3, 24, true, true, 2)
     VL_CK(CK_I64_COLS, int64_t, 3, 24, false, false, 1)
     VL_CK(CK_I64_COLS_VEC, int64_t, 3, 24, false, true, 1)
     default: return hipErrorInvalidValue;

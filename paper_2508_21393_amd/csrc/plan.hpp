@@ -38,6 +38,7 @@ struct Tuning {
   uint32_t segments = 1;          // pipeline segments (batched mode)
   uint32_t min_tasks = 1;         // split a contraction until it has this many tasks
   uint32_t cols_rows = 1;         // rows per lane, vector cols kernels (1 or 2)
+  uint32_t claim_order = 0;       // claim contraction: 0 auto, 1 by columns, 2 by rows
   bool persistent = false;        // rounds launched first, waiting on readiness counters
   uint32_t spin_limit = 1u << 24; // persistent mode: polls before VL_ERR_TIMEOUT
 };
@@ -99,7 +100,8 @@ struct Builder {
   X* dev(uint64_t o) const { return reinterpret_cast<X*>(base + o); }
   void contract(const void* M, int dtype, int nd, uint64_t ld, bool rows, uint32_t n_out, uint32_t len,
                 const uint32_t* pack, uint32_t* dst, uint64_t dst_ld, uint64_t n_total, int32_t* err);
-  void eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_len, bool pack_r2);
+  void eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_len, bool pack_r2,
+              bool eq_canon);
   // pass-1 job over a, b; returns the partials buffer, sets its block count
   const uint32_t* pass1(const uint32_t* a, uint64_t a_ld, const uint32_t* b, uint64_t b_ld, uint32_t h,
                         bool dot, uint32_t& nparts, uint32_t* ready);

@@ -71,6 +71,9 @@ PE_CASES = [
     (5, 1000, 1, np.int16, 15), (130, 777, 1, np.int16, 15), (64, 2048, 1, np.int16, 15),
     (3000, 65, 0, np.int16, 15), (33, 515, 1, np.int32, 31), (40, 77, 0, np.int64, 62),
     (17, 260, 1, np.int64, 40), (9, 4096, 1, np.int64, 44),
+    # vector rows kernels of wide entries: 4 int32 or 2 int64 columns per lane
+    # (16-byte loads), ragged column groups and row tails
+    (270, 516, 0, np.int32, 31), (300, 302, 0, np.int64, 62), (37, 1024, 0, np.int64, 62),
 ]
 
 
@@ -168,6 +171,43 @@ def test_range_error_on_oversized_claim_entry(B):
     with pytest.raises(B.VLError) as e:
         B.sumcheck_matmul_prove([device_group(g, B)], 1, mode=1)
     assert e.value.status == B.VL_ERR_RANGE
+
+
+def test_range_error_in_row_order_claim(B):
+    # C with 256 columns is contracted over its rows (two columns per lane,
+    # 16-byte loads): an entry outside |x| < 2^47 there is refused as well
+    g = workloads.tiny_random_group(5, [(8, 8, 256)])
+    g.C = g.C.copy()
+    g.C[3, 201] = 1 << 60
+    with pytest.raises(B.VLError) as e:
+        B.sumcheck_matmul_prove([device_group(g, B)], 1, mode=1)
+    assert e.value.status == B.VL_ERR_RANGE
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_claim_order_matches_oracle_bytes(B, order):
+    # the claim contracted over the columns of C (order 1) or over its rows
+    # (order 2) for every tiny case: same proof bytes
+    w, spec = tiny_workload()
+    _say(f"tiny cases claim_order={order}")
+    gs = [device_group(g, B) for g in w.groups]
+    proofs, digests = B.sumcheck_matmul_prove(gs, w.seed, mode=1, tuning_=B.tuning(claim_order=order))
+    for g, pr, dg, gold in zip(w.groups, proofs, digests, spec["groups"]):
+        assert pr.hex() == gold["proof_hex"], g.name
+        assert dg.hex() == gold["state"], g.name
+
+
+def test_claim_order_full_size_cfg3(B):
+    _say("cfg3 claim orders: generating")
+    w = workloads.make_config("cfg3")
+    gold = golden("cfg3")
+    gs = [device_group(g, B) for g in w.groups]
+    for order in (1, 2):
+        _say(f"cfg3: proving, claim_order={order}")
+        proofs, digests = B.sumcheck_matmul_prove(gs, w.seed, mode=1, tuning_=B.tuning(claim_order=order))
+        for g, pr, dg, rec in zip(w.groups, proofs, digests, gold["groups"]):
+            assert sha(pr) == rec["proof_sha256"], g.name
+            assert dg.hex() == rec["state"], g.name
 
 
 def test_async_prove_into_device_buffers(B):
