@@ -294,23 +294,20 @@ void Builder::contract(const void* M, int dtype, int nd, uint64_t ld, bool rows,
   if (n_chunks == 1) {
     j.dst = dst;
     j.dst_ld = dst_ld;
-    j.chunk_stride = 0;
     f.part = nullptr;
   } else {
-    const uint64_t pld = align_up(n_out, 64);
-    uint32_t* part = dev<uint32_t>(take((uint64_t)n_chunks * kLimbs * pld * 4));
+    // 64-output tiles of n_chunks * kLimbs words per output
+    uint32_t* part = dev<uint32_t>(take(partial_word(align_up(n_out, 64), 0, 0, n_chunks) * 4));
     j.dst = part;
-    j.dst_ld = pld;
-    j.chunk_stride = kLimbs * pld;
+    j.dst_ld = 0;
     f.part = part;
-    f.part_ld = pld;
-    f.chunk_stride = kLimbs * pld;
   }
   S().cj_tasks[kind] += out_waves * n_chunks;
   S().cj[kind].push_back(j);
   if (f.part || f.n_total > f.n_valid) {
+    f.split = (f.part && n_chunks >= kFinishSplitChunks) ? 1u : 0u;
     f.block_begin = S().fin_blocks;
-    S().fin_blocks += (f.n_total + 63) / 64;
+    S().fin_blocks += f.split ? (f.n_total + 63) / 64 : (f.n_total + 255) / 256;
     S().fin.push_back(f);
   }
 }

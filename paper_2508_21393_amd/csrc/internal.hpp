@@ -62,30 +62,36 @@ struct ContractJob {
   uint32_t out_waves;         // ceil(n_out / 64)
   uint32_t task_begin;        // prefix sum of tasks (out_waves * n_chunks) within a launch
   const uint32_t* pack;       // eq pack table of the contraction index
-  uint32_t* dst;              // n_chunks == 1: final SoL vector (8 planes); else the raw
-                              // partial of chunk 0 (kLimbs planes)
-  uint64_t dst_ld;            // plane stride of dst
-  uint64_t chunk_stride;      // words between consecutive chunk partials (0: final)
+  uint32_t* dst;              // n_chunks == 1: final SoL vector (8 planes, stride dst_ld);
+                              // else raw chunk partials in 64-output tiles (partial_word)
+  uint64_t dst_ld;
   int32_t* err;               // set to 1 if an entry cannot be represented (int32/int64)
 };
 
 // A split contraction's chunks leave their exact sums unreduced: kLimbs
 // 32-bit two's-complement limbs per output and chunk.  The finish kernel
-// adds them up and reduces once per output.
+// adds them up and reduces once per output.  Layout: 64-output tiles, each
+// holding every chunk's limbs of its outputs contiguously, so that the
+// finish pass reads one contiguous region per 64 outputs.
 constexpr int kLimbs = 12;
+__host__ __device__ constexpr uint64_t partial_word(uint32_t n, uint32_t chunk, int q, uint32_t n_chunks) {
+  return (uint64_t)(n >> 6) * n_chunks * (kLimbs * 64) + ((uint64_t)chunk * kLimbs + q) * 64 + (n & 63u);
+}
 
 // Sum the raw chunk partials into the final SoL vector and zero its padding.
 struct FinishJob {
-  const uint32_t* part;       // raw partial of chunk 0 (null if the contraction wrote out)
-  uint64_t part_ld;
-  uint64_t chunk_stride;
+  const uint32_t* part;       // raw chunk partials (null if the contraction wrote out)
   uint32_t n_chunks;
   uint32_t n_valid;           // outputs written by the contraction
   uint32_t n_total;           // padded length (power of two)
-  uint32_t block_begin;       // prefix sum of blocks (64 outputs each) within a launch
+  uint32_t block_begin;       // prefix sum of blocks within a launch
+  uint32_t split;             // 0: 256 outputs per block, one thread each; 1: 64
+                              // outputs per block, the 4 waves split the chunks
+  uint32_t pad_;
   uint32_t* out;
   uint64_t out_ld;
 };
+constexpr uint32_t kFinishSplitChunks = 16;   // split jobs with at least this many chunks
 
 // Round 1 of one product (or the claim's dot product: c = sum_i eqU[i] t[i]
 // after a contraction of C by columns, c = sum_j eqV[j] s[j] after one by rows)

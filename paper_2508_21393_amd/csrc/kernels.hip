@@ -466,19 +466,51 @@ contract_kernel(const ContractJob* __restrict__ jobs, uint32_t n_jobs, uint32_t 
     for (int o = 0; o < OPL; ++o)
       if (n0 + o < n_out) bad |= bad_o[o];
   } else {
+    // element loads (unaligned or narrow matrices): UB entries per output
+    // and their eq digits loaded together, then used (left to itself the
+    // scheduler waits for each load in turn).  Outputs past n_out read the
+    // last output's entries (in bounds) and use zero.
+    constexpr uint32_t UB = 8;
+    uint64_t eoff[OPL];
+    bool valid[OPL];
+#pragma unroll
+    for (int o = 0; o < OPL; ++o) {
+      const uint32_t n = min(n0 + o, n_out - 1);
+      valid[o] = n0 + o < n_out;
+      eoff[o] = ROWS ? n : (uint64_t)n * ld;
+    }
+    const uint64_t mstep = ROWS ? ld : 1;
+    auto elem = [&](uint32_t m, int o) -> T {
+      const T x = Mg[eoff[o] + (uint64_t)m * mstep];
+      return valid[o] ? x : T(0);
+    };
     uint32_t m = m0;
     while (m < m1) {
       const uint32_t bend = WIDE ? min(m + kSpill, m1) : m1;
-#pragma unroll 4
+      for (; m + UB <= bend; m += UB) {
+        ci32_ptr pe = pack + (uint64_t)m * 8;
+        int32_t e[UB][8];
+#pragma unroll
+        for (uint32_t u = 0; u < UB; ++u)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) e[u][j] = pe[u * 8 + j];
+        T x[UB][OPL];
+#pragma unroll
+        for (uint32_t u = 0; u < UB; ++u)
+#pragma unroll
+          for (int o = 0; o < OPL; ++o) x[u][o] = elem(m + u, o);
+#pragma unroll
+        for (uint32_t u = 0; u < UB; ++u) {
+          int32_t d[OPL][ND];
+#pragma unroll
+          for (int o = 0; o < OPL; ++o) entry_digits<T, ND, DB>(x[u][o], d[o], bad);
+          mac8v<OPL, ND>(e[u], d, acc);
+        }
+      }
       for (; m < bend; ++m) {
         int32_t d[OPL][ND];
 #pragma unroll
-        for (int o = 0; o < OPL; ++o) {
-          const uint32_t n = n0 + o;
-          T x = 0;
-          if (n < n_out) x = ROWS ? Mg[(uint64_t)m * ld + n] : Mg[(uint64_t)n * ld + m];
-          entry_digits<T, ND, DB>(x, d[o], bad);
-        }
+        for (int o = 0; o < OPL; ++o) entry_digits<T, ND, DB>(elem(m, o), d[o], bad);
         mac8<OPL, ND>(pack + (uint64_t)m * 8, d, acc);
       }
       if constexpr (WIDE) spill_high<OPL, ND>(acc, hi);
@@ -492,22 +524,67 @@ contract_kernel(const ContractJob* __restrict__ jobs, uint32_t n_jobs, uint32_t 
     uint32_t L[kLimbs];
     digits_to_limbs<ND, DB>(acc[o], hi[o], L);
     const uint32_t n = n0 + o;
-    if (J.chunk_stride == 0) {          // the whole contraction: final value
+    if (J.n_chunks == 1) {              // the whole contraction: final value
       const Fr r = limbs_to_fr(L);
       if (n < n_out) store_sol(J.dst, J.dst_ld, n, r);
     } else if (n < n_out) {             // one chunk: raw limbs, reduced by finish_kernel
-      uint32_t* d = J.dst + (uint64_t)chunk * J.chunk_stride;
+      uint32_t* d = J.dst + partial_word(n, chunk, 0, J.n_chunks);
 #pragma unroll
-      for (int q = 0; q < kLimbs; ++q) d[q * J.dst_ld + n] = L[q];
+      for (int q = 0; q < kLimbs; ++q) d[q * 64] = L[q];
     }
   }
 }
 
 // ---------------------------------------------------------------- finish ----
-// One block per 64 outputs of a job: the four waves add up every fourth
-// chunk's raw limbs (64-bit sums per limb, exact), wave 0 combines them,
-// propagates the carries and reduces once.  Outputs past n_valid up to
-// n_total are the zero padding of the table.
+// Sums each output's raw chunk limbs (64-bit sums per limb, exact),
+// propagates the carries and reduces once.  Jobs with few chunks take one
+// thread per output (256 per block); jobs with many chunks take 64 outputs
+// per block, the four waves adding up every fourth chunk and wave 0
+// combining them.  Outputs past n_valid up to n_total are the zero padding
+// of the table.
+__device__ __forceinline__ void finish_store(const FinishJob& J, uint32_t i, const int64_t (&T)[kLimbs]) {
+  // each T[q] < n_chunks * 2^32 in magnitude: carries fit in 64 bits
+  uint32_t L[kLimbs];
+  int64_t carry = 0;
+#pragma unroll
+  for (int q = 0; q < kLimbs; ++q) {
+    const int64_t v = T[q] + carry;
+    L[q] = (uint32_t)v;
+    carry = v >> 32;
+  }
+  store_sol(J.out, J.out_ld, i, limbs_to_fr(L));
+}
+
+// chunks [c0, c1) step dc of an output's limbs (p: chunk 0, limb 0 in the
+// tiled layout), FC chunks' loads issued together before they are added
+// (left to itself the scheduler waits for each load in turn)
+template <int FC>
+__device__ __forceinline__ void finish_add(int64_t (&T)[kLimbs], gptr<uint32_t> p, uint32_t c0, uint32_t c1,
+                                           uint32_t dc) {
+  uint32_t c = c0;
+  for (; c + (FC - 1) * dc < c1; c += FC * dc) {
+    uint32_t v[FC][kLimbs];
+#pragma unroll
+    for (int k = 0; k < FC; ++k)
+#pragma unroll
+      for (int q = 0; q < kLimbs; ++q) v[k][q] = __builtin_nontemporal_load(&p[(uint64_t)(c + k * dc) * (kLimbs * 64) + q * 64]);
+#pragma unroll
+    for (int k = 0; k < FC; ++k) {
+#pragma unroll
+      for (int q = 0; q < kLimbs - 1; ++q) T[q] += (int64_t)v[k][q];
+      T[kLimbs - 1] += (int64_t)(int32_t)v[k][kLimbs - 1];
+    }
+  }
+  for (; c < c1; c += dc) {
+    uint32_t v[kLimbs];
+#pragma unroll
+    for (int q = 0; q < kLimbs; ++q) v[q] = __builtin_nontemporal_load(&p[(uint64_t)c * (kLimbs * 64) + q * 64]);
+#pragma unroll
+    for (int q = 0; q < kLimbs - 1; ++q) T[q] += (int64_t)v[q];
+    T[kLimbs - 1] += (int64_t)(int32_t)v[kLimbs - 1];
+  }
+}
+
 __global__ void __launch_bounds__(256) finish_kernel(const FinishJob* __restrict__ jobs,
                                                      uint32_t n_jobs, uint32_t n_blocks) {
   const uint32_t blk = blockIdx.x;
@@ -518,25 +595,26 @@ __global__ void __launch_bounds__(256) finish_kernel(const FinishJob* __restrict
     if (jobs[mid].block_begin <= blk) lo = mid; else hi = mid;
   }
   const FinishJob& J = jobs[lo];
-  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-  const uint32_t i = (blk - J.block_begin) * 64u + lane;
-  __shared__ int64_t red[3][kLimbs][64];
-  if (!J.part) {
-    if (wave == 0 && i >= J.n_valid && i < J.n_total) store_sol(J.out, J.out_ld, i, fr_zero());
-    return;
-  }
   int64_t T[kLimbs];
 #pragma unroll
   for (int q = 0; q < kLimbs; ++q) T[q] = 0;
-  if (i < J.n_valid) {
-    const gptr<uint32_t> base = (gptr<uint32_t>)J.part + i;
-#pragma unroll 4
-    for (uint32_t c = wave; c < J.n_chunks; c += 4) {
-      const gptr<uint32_t> p = base + (uint64_t)c * J.chunk_stride;
-#pragma unroll
-      for (int q = 0; q < kLimbs - 1; ++q) T[q] += (int64_t)p[q * J.part_ld];
-      T[kLimbs - 1] += (int64_t)(int32_t)p[(kLimbs - 1) * J.part_ld];
+  if (!J.split) {   // uniform over the block
+    const uint32_t i = (blk - J.block_begin) * 256u + threadIdx.x;
+    if (i >= J.n_total) return;
+    if (i >= J.n_valid) {
+      store_sol(J.out, J.out_ld, i, fr_zero());
+      return;
     }
+    if (!J.part) return;
+    finish_add<4>(T, (gptr<uint32_t>)J.part + partial_word(i, 0, 0, J.n_chunks), 0, J.n_chunks, 1);
+    finish_store(J, i, T);
+    return;
+  }
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  const uint32_t i = (blk - J.block_begin) * 64u + lane;
+  __shared__ int64_t red[3][kLimbs][64];
+  if (i < J.n_valid) {
+    finish_add<4>(T, (gptr<uint32_t>)J.part + partial_word(i, 0, 0, J.n_chunks), wave, J.n_chunks, 4);
   }
   if (wave > 0)
 #pragma unroll
@@ -551,16 +629,7 @@ __global__ void __launch_bounds__(256) finish_kernel(const FinishJob* __restrict
   for (int w = 0; w < 3; ++w)
 #pragma unroll
     for (int q = 0; q < kLimbs; ++q) T[q] += red[w][q][lane];
-  // each T[q] < n_chunks * 2^32 in magnitude: carries fit in 64 bits
-  uint32_t L[kLimbs];
-  int64_t carry = 0;
-#pragma unroll
-  for (int q = 0; q < kLimbs; ++q) {
-    const int64_t v = T[q] + carry;
-    L[q] = (uint32_t)v;
-    carry = v >> 32;
-  }
-  store_sol(J.out, J.out_ld, i, limbs_to_fr(L));
+  finish_store(J, i, T);
 }
 
 // ---------------------------------------------------------------- rounds ----
