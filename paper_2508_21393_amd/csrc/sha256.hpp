@@ -47,6 +47,29 @@ VL_HD uint32_t bitsel(uint32_t m, uint32_t x, uint32_t y) {
 #endif
 }
 
+// three-input xor; on the device one v_bitop3_b32 (truth table 0x96)
+VL_HD uint32_t xor3_u32(uint32_t a, uint32_t b, uint32_t c) {
+#if __HIP_DEVICE_COMPILE__
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+#else
+  return a ^ b ^ c;
+#endif
+}
+
+// bitwise majority Maj(a, b, c); on the device one v_bitop3_b32 (truth
+// table 0xe8)
+VL_HD uint32_t maj_u32(uint32_t a, uint32_t b, uint32_t c) {
+#if __HIP_DEVICE_COMPILE__
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0xe8" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+#else
+  return (a & b) | (a & c) | (b & c);
+#endif
+}
+
 // FIPS 180-4 round constants
 #define VL_SHA256_K                                                                                \
   0x428a2f98u, 0x71374491u, 0xb5c0fbcfu, 0xe9b5dba5u, 0x3956c25bu, 0x59f111f1u, 0x923f82a4u,     \
@@ -146,19 +169,19 @@ VL_HD void sha256_compress_w(uint32_t h[8], const uint32_t (&win)[16]) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         const uint32_t w15 = w[(i + 1) & 15], w2 = w[(i + 14) & 15];
-        const uint32_t s0 = rotr32(w15, 7) ^ rotr32(w15, 18) ^ (w15 >> 3);
-        const uint32_t s1 = rotr32(w2, 17) ^ rotr32(w2, 19) ^ (w2 >> 10);
+        const uint32_t s0 = xor3_u32(rotr32(w15, 7), rotr32(w15, 18), w15 >> 3);
+        const uint32_t s1 = xor3_u32(rotr32(w2, 17), rotr32(w2, 19), w2 >> 10);
         w[i] = add3_u32(w[i], s0, w[(i + 9) & 15]) + s1;
       }
     }
     const uint32_t* Kt = K + 16 * it;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const uint32_t S1 = rotr32(e, 6) ^ rotr32(e, 11) ^ rotr32(e, 25);
+      const uint32_t S1 = xor3_u32(rotr32(e, 6), rotr32(e, 11), rotr32(e, 25));
       const uint32_t ch = bitsel(e, f, g);                 // Ch(e, f, g)
       const uint32_t t1 = add3_u32(hh, S1, ch) + (w[i] + Kt[i]);
-      const uint32_t S0 = rotr32(a, 2) ^ rotr32(a, 13) ^ rotr32(a, 22);
-      const uint32_t mj = bitsel(a ^ b, c, a);             // Maj(a, b, c)
+      const uint32_t S0 = xor3_u32(rotr32(a, 2), rotr32(a, 13), rotr32(a, 22));
+      const uint32_t mj = maj_u32(a, b, c);
       hh = g; g = f; f = e; e = d + t1; d = c; c = b; b = a; a = add3_u32(t1, S0, mj);
     }
   }
