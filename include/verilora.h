@@ -126,12 +126,16 @@ typedef struct {
 typedef struct {
   int32_t mode;            /* VL_MODE_*; every mode yields identical bytes            */
   int32_t async;           /* 0: proofs/digests are host buffers and the call returns
-                              after they are written; 1: they are device buffers, the
-                              call only enqueues work, and per-group status codes land
-                              in status[]                                             */
-  void* workspace;         /* device memory, >= vl_workspace_size() bytes             */
+                              after they are written (the kernels write them into
+                              pinned host memory of the library, no copy-engine
+                              transfer); 1: they are device-writable buffers, the
+                              call only enqueues work, and per-group status codes
+                              land in status[]                                       */
+  void* workspace;         /* device memory, >= vl_workspace_size() bytes, 256-byte
+                              aligned                                                 */
   uint64_t workspace_bytes;
-  int32_t* status;         /* async only: device int32[n_groups], VL_OK / VL_ERR_*     */
+  int32_t* status;         /* async only: device-writable int32[n_groups], VL_OK /
+                              VL_ERR_*                                                */
   const vl_tuning* tuning; /* optional launch shape; NULL: defaults                    */
   float* stage_ms;         /* optional host float[VL_STAGE_COUNT] (blocking mode only):
                               device time of each stage, from HIP events recorded on
@@ -182,7 +186,8 @@ uint64_t vl_partial_eval_workspace_size(uint32_t rows, uint32_t cols, int32_t co
  *   VL_CONTRACT_COLS: out[r] = sum_c M[r][c] eq[c]   (needs eq.n >= cols)
  * Entries of out beyond the result length (cols resp. rows) up to out.n are
  * set to zero, so out is the zero-padded table of a multilinear function.
- * tuning: optional (NULL: defaults); the workspace size depends on it. */
+ * tuning: optional (NULL: defaults); the workspace size depends on it.
+ * workspace: device memory, 256-byte aligned. */
 vl_status vl_mle_partial_eval(const void* M, int32_t dtype, uint32_t rows, uint32_t cols,
                               uint64_t ld, int32_t contract, vl_fr_vec eq, vl_fr_vec out,
                               void* workspace, uint64_t workspace_bytes, const vl_tuning* tuning,
@@ -200,11 +205,15 @@ uint64_t vl_workspace_size(const vl_group* groups, uint64_t n_groups, const vl_p
 
 /* Prove every group (the matmul sumcheck of eq. (zk-mle-matmul), Sec. II-C,
  * run by zkMat for each product of a LoRA step, Sec. IV-B).
- *   proofs   : host (async = 0) or device (async = 1) buffer of proofs_len
- *              bytes; group g's proof starts at offsets[g]
+ *   proofs   : host (async = 0) or device-writable (async = 1) buffer of
+ *              proofs_len bytes; group g's proof starts at offsets[g].
+ *              Device-writable means device memory or pinned host memory
+ *              (hipHostMalloc) given by its device-side address: the
+ *              kernels then write the proof bytes straight into host memory,
+ *              with no copy afterwards
  *   offsets  : host uint64[n_groups + 1], filled by the call
  *   digests  : optional (NULL) 32 bytes per group, the final transcript
- *              state; host or device like proofs
+ *              state; host or device-writable like proofs
  * The proof of a group depends only on (its matrices, seed, group_id); the
  * mode, the batching and other groups never change a byte.  Returns
  * VL_ERR_FALSE_STATEMENT (async = 0) if some group's products do not sum to

@@ -301,7 +301,8 @@ def sumcheck_matmul_prove_async(groups: Sequence[GroupArgs], seed: int, proofs_d
                                 workspace, mode: int = VL_MODE_BATCHED, digests_dev=None, stream=None,
                                 tuning_=None):
     """Enqueue a prove on the stream; proofs/status/digests land in device
-    buffers.  Returns the host offsets of each group's proof."""
+    tensors or pinned host tensors (written by the kernels, no copy).
+    Returns the host offsets of each group's proof."""
     batch = _batch(groups)
     n = len(batch)
     opts = vl_prove_opts(mode, 1, workspace.data_ptr(), workspace.numel(), status_dev.data_ptr(),

@@ -81,13 +81,13 @@ vl_status check_group(const vl_group& g, bool need_ptrs) {
   return VL_OK;
 }
 
-// The rounds stream paired with a caller's stream (default priority), created
-// on first use and kept for the life of the process.
 // Descriptor upload.  Small images go as kernel arguments (no host buffer
 // to keep alive, nothing to wait for); larger ones through a ring of pinned
-// host buffers per device, one asynchronous copy each.  A slot is reused
-// only after the copy it last issued has completed (an event per slot), so
-// the host waits only if kStagingSlots uploads are still in flight.
+// host buffers per device, which a kernel on the caller's stream copies to
+// the device (no copy-engine command: those are ordered across streams, so
+// one behind a busy stream would hold up the uploads of every other).  A
+// slot is reused only after the copy it last issued has completed (an event
+// per slot), so the host waits only if kStagingSlots uploads are in flight.
 constexpr int kStagingSlots = 4;
 constexpr uint64_t kArgUploadMax = 4 * kUploadBytes;
 
@@ -139,7 +139,10 @@ static hipError_t upload_blob(void* dst, const void* src, uint64_t bytes, hipStr
     sl.cap = cap;
   }
   memcpy(sl.host, src, bytes);
-  e = hipMemcpyAsync(dst, sl.host, bytes, hipMemcpyHostToDevice, s);
+  void* src_dev = nullptr;
+  e = hipHostGetDevicePointer(&src_dev, sl.host, 0);
+  if (e != hipSuccess) return e;
+  e = launch_copy_in(dst, src_dev, align_up(bytes, 16), s);
   if (e != hipSuccess) return e;
   e = hipEventRecord(sl.done, s);
   if (e != hipSuccess) return e;
@@ -147,6 +150,56 @@ static hipError_t upload_blob(void* dst, const void* src, uint64_t bytes, hipStr
   return hipSuccess;
 }
 
+// Pinned host memory that the kernels of a blocking call write the gathered
+// proofs, status words and digests into (one per host thread and device,
+// grown on demand): no copy back after the call's kernels.
+// (kept for the life of the process, like the staging ring)
+struct PinnedOut {
+  void* host = nullptr;
+  void* dev = nullptr;
+  uint64_t cap = 0;
+};
+
+static hipError_t pinned_out(uint64_t bytes, PinnedOut** out) {
+  thread_local std::map<int, PinnedOut> bufs;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  PinnedOut& b = bufs[dev];
+  if (b.cap < bytes) {
+    if (b.host) (void)hipHostFree(b.host);
+    b.host = b.dev = nullptr;
+    b.cap = 0;
+    const uint64_t cap = align_up(bytes + bytes / 2, 1 << 16);
+    void* h = nullptr;
+    e = hipHostMalloc(&h, cap, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    b.host = h;
+    e = hipHostGetDevicePointer(&b.dev, h, 0);
+    if (e != hipSuccess) return e;
+    b.cap = cap;
+  }
+  *out = &b;
+  return hipSuccess;
+}
+
+// An asynchronous call's output buffer: device memory as is; pinned host
+// memory (identity-mapped, as hipHostMalloc memory is with unified
+// addressing) at its own address.  Anything else (pageable host memory)
+// could not be written by the kernels and is refused.
+static vl_status device_writable(void* p, const char* what) {
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(VL_ERR_INVALID_ARG, "%s: neither device memory nor pinned host memory", what);
+  }
+  if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) return VL_OK;
+  if (a.type == hipMemoryTypeHost && a.hostPointer && a.devicePointer == a.hostPointer) return VL_OK;
+  return fail(VL_ERR_INVALID_ARG, "%s: neither device memory nor identity-mapped pinned host memory", what);
+}
+
+// The rounds stream paired with a caller's stream (default priority), created
+// on first use and kept for the life of the process.
 hipError_t rounds_stream_for(hipStream_t s, hipStream_t* out) {
   static std::mutex mu;
   static std::map<std::pair<int, hipStream_t>, hipStream_t> streams;
@@ -667,11 +720,12 @@ static Tuning pe_tuning(const vl_tuning* k) {
 
 // Plans groups [g0, g1) with the blob at workspace offset 0 and data after it.
 // Blocking mode gathers every proof, status word and digest of the call in
-// one region (proofs at their final offsets, then statuses, then digests) so
-// that one copy brings them back.  ws == nullptr plans for sizing only.
+// one region of pinned host memory (out: its device-side address; proofs at
+// their final offsets, then statuses, then digests) that the kernels write
+// directly.  ws == nullptr plans for sizing only.
 void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, uint64_t g1,
                  uint64_t seed, uint8_t* ws, bool async, uint8_t* proofs_dev, const uint64_t* offsets,
-                 int32_t* status_dev, uint8_t* digests_dev) {
+                 int32_t* status_dev, uint8_t* digests_dev, uint8_t* out) {
   P = Plan();
   P.persistent = T.persistent;
   const uint64_t blob = blob_bound(groups + g0, g1 - g0);
@@ -691,10 +745,7 @@ void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, 
   }
   uint64_t proof_total = 0;
   for (uint64_t i = g0; i < g1; ++i) proof_total += 32 * proof_elems(groups[i]);
-  if (!async) {
-    P.out_proof_bytes = proof_total;
-    P.out_off = B.take(align_up(proof_total, 256) + align_up(4 * n, 256) + 32 * n);
-  }
+  if (!async) P.out_proof_bytes = proof_total;
   // pipeline segments: groups with the longest sumchecks first, so that their
   // rounds overlap the contractions of the groups after them
   std::vector<uint64_t> order(n);
@@ -723,7 +774,7 @@ void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, 
       sd = status_dev ? status_dev + i : nullptr;
       dd = digests_dev ? digests_dev + 32 * i : nullptr;
     } else {
-      uint8_t* base = ws + P.out_off;
+      uint8_t* base = out;
       pd = base + rel;
       sd = reinterpret_cast<int32_t*>(base + align_up(proof_total, 256)) + (i - g0);
       dd = base + align_up(proof_total, 256) + align_up(4 * n, 256) + 32 * (i - g0);
@@ -761,12 +812,12 @@ uint64_t vl_workspace_size(const vl_group* groups, uint64_t n, const vl_prove_op
   if (T.per_instance) {
     uint64_t mx = 0;
     for (uint64_t i = 0; i < n; ++i) {
-      plan_groups(P, T, groups, i, i + 1, 0, nullptr, async, nullptr, offs.data(), nullptr, nullptr);
+      plan_groups(P, T, groups, i, i + 1, 0, nullptr, async, nullptr, offs.data(), nullptr, nullptr, nullptr);
       mx = std::max(mx, P.data_end);
     }
     return align_up(mx, 256);
   }
-  plan_groups(P, T, groups, 0, n, 0, nullptr, async, nullptr, offs.data(), nullptr, nullptr);
+  plan_groups(P, T, groups, 0, n, 0, nullptr, async, nullptr, offs.data(), nullptr, nullptr, nullptr);
   return align_up(P.data_end, 256);
 }
 
@@ -779,6 +830,12 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
   if (o->mode < VL_MODE_PER_INSTANCE || o->mode > VL_MODE_PERSISTENT)
     return fail(VL_ERR_INVALID_ARG, "unknown mode %d", o->mode);
   if (o->async && !o->status) return fail(VL_ERR_INVALID_ARG, "async mode needs a status array");
+  if (o->async) {
+    vl_status st = device_writable(proofs, "proofs");
+    if (st == VL_OK) st = device_writable(o->status, "status");
+    if (st == VL_OK && digests) st = device_writable(digests, "digests");
+    if (st != VL_OK) return st;
+  }
   if (o->mode == VL_MODE_PERSISTENT && n > kMaxPersistentGroups)
     return fail(VL_ERR_INVALID_ARG, "persistent mode takes at most %llu groups per call",
                 (unsigned long long)kMaxPersistentGroups);
@@ -796,6 +853,8 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
     return fail(VL_ERR_BUFFER_TOO_SMALL, "proof buffer holds %llu bytes, %llu needed",
                 (unsigned long long)proofs_len, (unsigned long long)tot);
   if (!o->workspace) return fail(VL_ERR_WORKSPACE, "no workspace");
+  if (reinterpret_cast<uintptr_t>(o->workspace) % 256)
+    return fail(VL_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   uint8_t* ws = reinterpret_cast<uint8_t*>(o->workspace);
   const Tuning T = tuning_for(o);
@@ -815,21 +874,21 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
     ev = &events;
   }
 
-  // blocking mode: one copy of the gathered proofs, statuses and digests
+  // blocking mode: the kernels write the gathered proofs, statuses and
+  // digests into pinned host memory; wait, then hand them out
+  PinnedOut* po = nullptr;
   auto fetch = [&](uint64_t g0, uint64_t g1) -> vl_status {
     const uint64_t n = g1 - g0;
     const uint64_t pa = align_up(P.out_proof_bytes, 256), sa = align_up(4 * n, 256);
-    std::vector<uint8_t> host(pa + sa + 32 * n);
-    hipError_t e = hipMemcpyAsync(host.data(), ws + P.out_off, host.size(), hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return fail(VL_ERR_HIP, "copy back: %s", hipGetErrorString(e));
-    e = hipStreamSynchronize(s);
+    const hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(VL_ERR_HIP, "prove: %s", hipGetErrorString(e));
     if (ev) ev->accumulate(o->stage_ms);
-    memcpy(proofs + offsets[g0], host.data(), P.out_proof_bytes);
-    if (digests) memcpy(digests + 32 * g0, host.data() + pa + sa, 32 * n);
+    const uint8_t* host = reinterpret_cast<const uint8_t*>(po->host);
+    memcpy(proofs + offsets[g0], host, P.out_proof_bytes);
+    if (digests) memcpy(digests + 32 * g0, host + pa + sa, 32 * n);
     for (uint64_t i = g0; i < g1; ++i) {
       int32_t st;
-      memcpy(&st, host.data() + pa + 4 * (i - g0), 4);
+      memcpy(&st, host + pa + 4 * (i - g0), 4);
       if (st == VL_ERR_FALSE_STATEMENT)
         return fail(VL_ERR_FALSE_STATEMENT, "group %u: the products do not sum to C", groups[i].group_id);
       if (st == VL_ERR_RANGE)
@@ -843,7 +902,15 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
     return VL_OK;
   };
   auto run = [&](uint64_t g0, uint64_t g1) -> vl_status {
-    plan_groups(P, T, groups, g0, g1, seed, ws, async, proofs, offsets, o->status, digests);
+    uint8_t* out = nullptr;
+    if (!async) {
+      const uint64_t n = g1 - g0;
+      const uint64_t bytes = align_up(offsets[g1] - offsets[g0], 256) + align_up(4 * n, 256) + 32 * n;
+      const hipError_t e = pinned_out(bytes, &po);
+      if (e != hipSuccess) return fail(VL_ERR_HIP, "pinned output buffer: %s", hipGetErrorString(e));
+      out = reinterpret_cast<uint8_t*>(po->dev);
+    }
+    plan_groups(P, T, groups, g0, g1, seed, ws, async, proofs, offsets, o->status, digests, out);
     if (P.data_end > o->workspace_bytes)
       return fail(VL_ERR_WORKSPACE, "workspace of %llu bytes, %llu needed",
                   (unsigned long long)o->workspace_bytes, (unsigned long long)align_up(P.data_end, 256));
@@ -936,6 +1003,8 @@ vl_status vl_mle_partial_eval(const void* M, int32_t dtype, uint32_t rows, uint3
                               int32_t contract, vl_fr_vec eq, vl_fr_vec out, void* workspace,
                               uint64_t workspace_bytes, const vl_tuning* tuning, void* stream) {
   if (!M || !eq.base || !out.base || !workspace) return fail(VL_ERR_INVALID_ARG, "null pointer");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(VL_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   if (!esize(dtype)) return fail(VL_ERR_DTYPE, "dtype must be VL_I16/I32/I64");
   if (contract != VL_CONTRACT_ROWS && contract != VL_CONTRACT_COLS)
     return fail(VL_ERR_INVALID_ARG, "contract must be VL_CONTRACT_ROWS or VL_CONTRACT_COLS");

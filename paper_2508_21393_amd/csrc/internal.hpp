@@ -149,6 +149,9 @@ hipError_t launch_eq_point(const EqPointArgs& a, hipStream_t s);
 hipError_t launch_pack(const uint32_t* eq, uint64_t ld, uint64_t len, uint32_t* pack, hipStream_t s);
 hipError_t launch_upload(void* dst, const void* src, uint64_t bytes, hipStream_t s);
 hipError_t launch_zero_words(uint32_t* p, uint64_t n_words, hipStream_t s);
+// bytes (a multiple of 16, both pointers 16-byte aligned) from pinned host
+// memory, given by its device-side address
+hipError_t launch_copy_in(void* dst, const void* src_dev, uint64_t bytes, hipStream_t s);
 
 // contraction kernel variants (index = kind)
 // (entry type, digits x digit bits, orientation, outputs per lane)

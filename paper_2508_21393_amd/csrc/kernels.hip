@@ -1033,6 +1033,15 @@ __global__ void __launch_bounds__(256) upload_kernel(UploadArgs a) {
   for (uint32_t k = i; k < nw; k += blockDim.x) d[k] = a.words[k];
 }
 
+// device copy of a pinned host buffer (src is its device-side address): the
+// GPU reads host memory directly, so the copy runs on the caller's stream
+// with no copy-engine command, which other streams' copies could queue behind
+__global__ void __launch_bounds__(256) copy_in_kernel(u32x4* __restrict__ dst, const u32x4* __restrict__ src,
+                                                      uint64_t n16) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 __global__ void __launch_bounds__(256) zero_kernel(uint32_t* __restrict__ p, uint64_t n) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -1149,6 +1158,14 @@ hipError_t launch_upload(void* dst, const void* src, uint64_t bytes, hipStream_t
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_copy_in(void* dst, const void* src, uint64_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  const uint64_t n16 = bytes / 16;
+  hipLaunchKernelGGL(copy_in_kernel, dim3((uint32_t)std::min<uint64_t>(blocks_for(n16, 256), 64)), dim3(256), 0, s,
+                     reinterpret_cast<u32x4*>(dst), reinterpret_cast<const u32x4*>(src), n16);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero_words(uint32_t* p, uint64_t n, hipStream_t s) {

@@ -66,7 +66,6 @@ struct Plan {
   std::vector<Segment> seg;
   std::vector<std::vector<uint32_t>> points;  // per eq job: (x_j, 1 - x_j) Montgomery
   uint32_t n_err = 0;
-  uint64_t out_off = 0;                       // blocking mode: gathered proofs|status|digests
   uint64_t out_proof_bytes = 0;
 };
 
@@ -130,6 +129,6 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
 Tuning tuning_for(const vl_prove_opts* o);
 void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, uint64_t g1,
                  uint64_t seed, uint8_t* ws, bool async, uint8_t* proofs_dev, const uint64_t* offsets,
-                 int32_t* status_dev, uint8_t* digests_dev);
+                 int32_t* status_dev, uint8_t* digests_dev, uint8_t* out);
 
 }  // namespace vl

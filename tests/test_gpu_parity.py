@@ -226,6 +226,42 @@ def test_async_prove_into_device_buffers(B):
         assert raw[offs[i]:offs[i + 1]].hex() == gold["proof_hex"]
 
 
+def test_async_prove_into_pinned_host_buffers(B):
+    # the kernels write proofs, status words and digests straight into pinned
+    # host memory; a slice at an offset checks interior pointers too
+    import torch
+    w, spec = tiny_workload()
+    gs = [device_group(g, B) for g in w.groups]
+    total = sum(B.proof_size(g) for g in gs)
+    buf = torch.zeros(total + 256, dtype=torch.uint8, pin_memory=True)
+    proofs = buf[256:]
+    status = torch.full((len(gs),), -1, dtype=torch.int32, pin_memory=True)
+    digests = torch.zeros(32 * len(gs), dtype=torch.uint8, pin_memory=True)
+    ws = torch.empty(B.workspace_size(gs, 1, async_=True), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    offs = B.sumcheck_matmul_prove_async(gs, w.seed, proofs, status, ws, mode=1, digests_dev=digests, stream=s)
+    s.synchronize()
+    assert status.tolist() == [0] * len(gs)
+    raw = proofs.numpy().tobytes()
+    dg = digests.numpy().tobytes()
+    assert not buf[:256].any()
+    for i, gold in enumerate(spec["groups"]):
+        assert raw[offs[i]:offs[i + 1]].hex() == gold["proof_hex"]
+        assert dg[32 * i:32 * i + 32].hex() == gold["state"]
+
+
+def test_async_refuses_pageable_host_buffers(B):
+    import torch
+    w, _ = tiny_workload()
+    gs = [device_group(g, B) for g in w.groups[:1]]
+    proofs = torch.zeros(B.proof_size(gs[0]), dtype=torch.uint8)        # pageable
+    status = torch.zeros(1, dtype=torch.int32, pin_memory=True)
+    ws = torch.empty(B.workspace_size(gs, 1, async_=True), dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.VLError) as e:
+        B.sumcheck_matmul_prove_async(gs, w.seed, proofs, status, ws, mode=1)
+    assert e.value.status == B.VL_ERR_INVALID_ARG
+
+
 @pytest.mark.parametrize("cfg", ["cfg2", "cfg3", "cfg4"])
 def test_full_size_config_matches_oracle(B, cfg):
     _say(f"{cfg}: generating")
