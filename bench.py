@@ -184,7 +184,7 @@ def main():
     ap.add_argument("--cols-rows", type=int, default=0, help="vl_tuning.cols_rows (0: library default)")
     ap.add_argument("--claim-order", type=int, default=0,
                     help="vl_tuning.claim_order (0: library default, 1: C by columns, 2: C by rows)")
-    ap.add_argument("--inflight", type=int, default=2,
+    ap.add_argument("--inflight", type=int, default=3,
                     help="proofs in flight in the throughput phase (asynchronous entry point)")
     ap.add_argument("--autotune", action="store_true",
                     help="time a grid of launch shapes first and bench the fastest")
