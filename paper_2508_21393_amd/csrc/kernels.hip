@@ -895,7 +895,14 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
     uint32_t* b = P.b;
     const uint64_t ld = P.ld;
     uint32_t rd = 0;
-    // rounds over tables in global memory, the whole workgroup
+    // rounds over tables in global memory, the whole workgroup.  Round 0's
+    // values come from pass 1; every later one folds the tables by the
+    // previous challenge and sums the new pairs in the same sweep: for
+    // t < h, entries t, t + h, t + 2h, t + 3h of the tables as they stand
+    // (half-size 2h) fold into entries t and t + h (half-size h), which are
+    // the round's pair.  Each thread reads and writes only its own entries.
+    bool pending = false;   // tables still to be folded by r
+    Fr r = fr_zero();
     for (; rd < P.n1; ++rd) {
       const uint32_t h = 1u << (P.n1 - 1 - rd);
       if (h <= kWave) break;
@@ -906,31 +913,38 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
       } else {
         g[0] = g[1] = g[2] = fr_zero();
         for (uint32_t t = tid; t < h; t += NT) {
-          const Fr a0 = load_sol(a, ld, t), a1 = load_sol(a, ld, t + h);
-          const Fr b0 = load_sol(b, ld, t), b1 = load_sol(b, ld, t + h);
+          const Fr a00 = load_sol(a, ld, t), a01 = load_sol(a, ld, t + 2 * h);
+          const Fr a10 = load_sol(a, ld, t + h), a11 = load_sol(a, ld, t + 3 * h);
+          const Fr b00 = load_sol(b, ld, t), b01 = load_sol(b, ld, t + 2 * h);
+          const Fr b10 = load_sol(b, ld, t + h), b11 = load_sol(b, ld, t + 3 * h);
+          const Fr a0 = fr_add(a00, fr_mul(r, fr_sub(a01, a00)));
+          const Fr a1 = fr_add(a10, fr_mul(r, fr_sub(a11, a10)));
+          const Fr b0 = fr_add(b00, fr_mul(r, fr_sub(b01, b00)));
+          const Fr b1 = fr_add(b10, fr_mul(r, fr_sub(b11, b10)));
+          store_sol(a, ld, t, a0);
+          store_sol(a, ld, t + h, a1);
+          store_sol(b, ld, t, b0);
+          store_sol(b, ld, t + h, b1);
           g[0] = fr_add(g[0], fr_mul(a0, b0));
           g[1] = fr_add(g[1], fr_mul(a1, b1));
           g[2] = fr_add(g[2], fr_mul(at_two(a0, a1), at_two(b0, b1)));
         }
+        __threadfence_block();   // the folded entries, for the next sweep
         block_sum_w0<3>(g, red);
       }
       if (wave == 0) {
-        const Fr r = round_challenge(tr, g, out, lane);
-        if (lane == 0) lds_put(bcast, r);
+        const Fr rr = round_challenge(tr, g, out, lane);
+        if (lane == 0) lds_put(bcast, rr);
       }
       out += 96;
       __syncthreads();
-      const Fr r = lds_get(bcast);
-      for (uint32_t t = tid; t < h; t += NT) {
-        const Fr a0 = load_sol(a, ld, t), a1 = load_sol(a, ld, t + h);
-        const Fr b0 = load_sol(b, ld, t), b1 = load_sol(b, ld, t + h);
-        store_sol(a, ld, t, fr_add(a0, fr_mul(r, fr_sub(a1, a0))));
-        store_sol(b, ld, t, fr_add(b0, fr_mul(r, fr_sub(b1, b0))));
-      }
-      __threadfence_block();
-      __syncthreads();
+      // every thread reads r before its next sweep's block sum, whose
+      // barrier wave 0 passes before it writes bcast again
+      r = lds_get(bcast);
+      pending = true;
     }
-    // the last rounds (half-table h <= 64): wave 0, pairs in registers
+    // the last rounds (half-table h <= 64): wave 0, pairs in registers (the
+    // last global challenge, if any, folded in as they are loaded)
     if (wave == 0) {
       Fr fa, fb;   // the product's final a~ and b~ (lane 0)
       if (rd < P.n1) {
@@ -941,6 +955,12 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
           A1 = load_sol(a, ld, lane + h);
           B0 = load_sol(b, ld, lane);
           B1 = load_sol(b, ld, lane + h);
+          if (pending) {
+            A0 = fr_add(A0, fr_mul(r, fr_sub(load_sol(a, ld, lane + 2 * h), A0)));
+            A1 = fr_add(A1, fr_mul(r, fr_sub(load_sol(a, ld, lane + 3 * h), A1)));
+            B0 = fr_add(B0, fr_mul(r, fr_sub(load_sol(b, ld, lane + 2 * h), B0)));
+            B1 = fr_add(B1, fr_mul(r, fr_sub(load_sol(b, ld, lane + 3 * h), B1)));
+          }
         }
         for (; rd < P.n1; ++rd, h >>= 1) {
           Fr g[3];
@@ -948,11 +968,11 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
           g[1] = fr_mul(A1, B1);
           g[2] = fr_mul(at_two(A0, A1), at_two(B0, B1));
           wave_sum<3>(g, h);
-          const Fr r = round_challenge(tr, g, out, lane);
+          const Fr rr = round_challenge(tr, g, out, lane);
           out += 96;
           // fold; then entry t + h/2 of the folded table comes from lane t + h/2
-          Fr na = fr_add(A0, fr_mul(r, fr_sub(A1, A0)));
-          Fr nb = fr_add(B0, fr_mul(r, fr_sub(B1, B0)));
+          Fr na = fr_add(A0, fr_mul(rr, fr_sub(A1, A0)));
+          Fr nb = fr_add(B0, fr_mul(rr, fr_sub(B1, B0)));
           if (lane >= h) na = nb = fr_zero();
           const uint32_t hh = h >> 1;
           Fr ua, ub;
@@ -971,7 +991,7 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
             fb = nb;
           }
         }
-      } else {   // no rounds (D1 = 1) or the global rounds folded to one entry
+      } else {   // no rounds (D1 = 1)
         fa = load_sol(a, ld, 0);
         fb = load_sol(b, ld, 0);
       }
