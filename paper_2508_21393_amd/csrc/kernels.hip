@@ -423,6 +423,7 @@ contract_kernel(const ContractJob* __restrict__ jobs, uint32_t n_jobs, uint32_t 
     static_assert(WIDE == (sizeof(T) > 2), "int16 entries are single 16-bit digits");
     typedef typename std::conditional<VB == 8, u32x2, u32x4>::type LT;
     constexpr uint32_t PF = 8;
+    static_assert((PF & (PF - 1)) == 0, "the ring length is a power of two");
     const uint32_t nc = min(n0, ((n_out - 1) / OPL) * OPL);
     const gptr<T> base = Mg + (uint64_t)m0 * ld + nc;
     const uint32_t rows = m1 - m0;
