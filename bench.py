@@ -93,22 +93,33 @@ def contraction_bytes(groups, cols_rows=1, claim_order=0):
     return {B.STAGE_NAMES.index(n): v for n, v in k.items() if v[1]}
 
 
+CONTRACT_SOURCES = ("contract.hip", "device.hpp", "internal.hpp", "fr.hpp")
+
+
+def contract_source_sha256():
+    """Fingerprint of the contraction kernels' source: the files they are
+    compiled from, in a fixed order."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in CONTRACT_SOURCES:
+        with open(os.path.join(ROOT, "paper_2508_21393_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(stage_name):
     """HBM bytes per launch of a contraction kind from the rocprofv3 counter
     summary in profiles/, or None when there is none for this kind or the
-    kernel source changed since the counters were taken."""
+    contraction source changed since the counters were taken."""
     import glob
-    import hashlib
     import re
-    src = os.path.join(ROOT, "paper_2508_21393_amd", "csrc", "kernels.hip")
-    with open(src, "rb") as f:
-        h = hashlib.sha256(f.read()).hexdigest()
+    h = contract_source_sha256()
     for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md")):
         m = re.search(r"```json\s*(\{.*?\})\s*```", open(path).read(), re.S)
         if not m:
             continue
         rec = json.loads(m.group(1))
-        if rec.get("stage") == stage_name and rec.get("kernels_hip_sha256") == h:
+        if rec.get("stage") == stage_name and rec.get("contract_source_sha256") == h:
             return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     return None
 
