@@ -197,6 +197,8 @@ def main():
                     help="vl_tuning.claim_order (0: library default, 1: C by columns, 2: C by rows)")
     ap.add_argument("--inflight", type=int, default=3,
                     help="proofs in flight in the throughput phase (asynchronous entry point)")
+    ap.add_argument("--graph", type=int, default=1,
+                    help="1: the throughput phase replays one captured HIP graph per slot (vl_prove_graph)")
     ap.add_argument("--autotune", action="store_true",
                     help="time a grid of launch shapes first and bench the fastest")
     args = ap.parse_args()
@@ -242,7 +244,8 @@ def main():
     ref_cat = b"".join(ref)
 
     # Throughput: `inflight` proofs in flight, each on its own stream with
-    # its own workspace (the asynchronous entry point); the host plans the
+    # its own workspace (a captured prove graph per slot, replayed per proof,
+    # or the asynchronous entry point with --graph 0); the host plans the
     # next proof while the GPU runs earlier ones, and one proof's single-CU
     # sumcheck rounds overlap the next one's contractions.  The kernels write
     # each proof straight into pinned host memory (a copy-engine transfer
@@ -259,10 +262,14 @@ def main():
             self.status = torch.empty(n_groups, dtype=torch.int32, pin_memory=True)
             self.done = torch.cuda.Event()
             self.pending = False
+            self.graph = B.ProveGraph(batch, self.ws, self.proofs, self.status, tuning_=tun) if args.graph else None
 
         def submit(self):
-            B.sumcheck_matmul_prove_async(batch, w.seed, self.proofs, self.status, self.ws, mode=mode,
-                                          stream=self.stream, tuning_=tun)
+            if self.graph is not None:
+                self.graph.launch(w.seed, stream=self.stream)
+            else:
+                B.sumcheck_matmul_prove_async(batch, w.seed, self.proofs, self.status, self.ws, mode=mode,
+                                              stream=self.stream, tuning_=tun)
             self.done.record(self.stream)
             self.pending = True
 
@@ -361,6 +368,7 @@ def main():
         "proofs_per_s": n_products * args.steps / elapsed,
         "latency_ms": {"p50": p50, "p99": p99, "blocking_ms_per_step": blocking_ms},
         "inflight": len(slots),
+        "graph": bool(args.graph),
         "per_instance_ms_per_step": per_inst_ms,
         "speedup_vs_per_instance": (per_inst_ms / ms_per_step) if per_inst_ms else None,
         "speedup_vs_per_instance_blocking": (per_inst_ms / blocking_ms) if per_inst_ms else None,

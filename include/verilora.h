@@ -222,6 +222,32 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n_groups, ui
                                    const vl_prove_opts* opts, uint8_t* proofs, uint64_t proofs_len,
                                    uint64_t* offsets, uint8_t* digests, void* stream);
 
+/* The same batched prove captured once into a HIP graph (one graph launch per
+ * call instead of the call's dozen kernel launches; Sec. IV-B's per-step
+ * proofs of one block repeat with new data and seeds but the same shapes).
+ * create: plans the groups with opts (async = 1, batched mode, no
+ *   stage_ms), fills offsets, and captures every launch with
+ *   the workspace, proofs, opts->status and digests addresses fixed; the
+ *   caller keeps those buffers, and the matrices the groups point to, alive
+ *   and unused by other work until destroy.  The group descriptors are
+ *   copied: a launch reads the matrices at the same addresses.
+ * launch: proves the groups' current matrix contents for seed on stream,
+ *   asynchronously, with bytes identical to vl_sumcheck_matmul_prove.  The
+ *   host rebuilds the descriptor blob (challenges depend on the seed and
+ *   group ids) and writes it into a pinned buffer of the handle, which the
+ *   graph's first kernel copies; a launch first waits for the previous
+ *   launch of the same handle to finish.  Launches of one handle run one at
+ *   a time; use one handle per workspace for overlap.
+ * destroy: waits for the last launch and frees the handle (NULL is a no-op).
+ * Errors: VL_ERR_INVALID_ARG (bad options, wrong device), VL_ERR_WORKSPACE,
+ * VL_ERR_BUFFER_TOO_SMALL, VL_ERR_HIP; a failed create returns no handle. */
+typedef struct vl_prove_graph vl_prove_graph;
+vl_status vl_prove_graph_create(const vl_group* groups, uint64_t n_groups, const vl_prove_opts* opts,
+                                uint8_t* proofs, uint64_t proofs_len, uint64_t* offsets, uint8_t* digests,
+                                vl_prove_graph** graph);
+vl_status vl_prove_graph_launch(vl_prove_graph* graph, uint64_t seed, void* stream);
+void vl_prove_graph_destroy(vl_prove_graph* graph);
+
 /* Host-side verifier (CPU only).  Replays the transcript for (shape, seed,
  * group_id), checks g(0) + g(1) against the running claim in every round,
  * moves the claim to g(r) by interpolation on {0, 1, 2}, and checks the last

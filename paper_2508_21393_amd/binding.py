@@ -30,7 +30,8 @@ STATUS_NAMES = {0: "VL_OK", 1: "VL_ERR_INVALID_ARG", 2: "VL_ERR_SHAPE", 3: "VL_E
 
 EXPORTED = ("vl_fr_lift", "vl_fr_export", "vl_eq_table", "vl_partial_eval_workspace_size",
             "vl_mle_partial_eval", "vl_proof_size", "vl_workspace_size",
-            "vl_sumcheck_matmul_prove", "vl_verify_transcript", "vl_last_error")
+            "vl_sumcheck_matmul_prove", "vl_verify_transcript", "vl_last_error",
+            "vl_prove_graph_create", "vl_prove_graph_launch", "vl_prove_graph_destroy")
 
 c_u32, c_u64, c_i32, c_vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p
 
@@ -109,8 +110,14 @@ def lib():
                                            ctypes.POINTER(vl_fr), c_u64, ctypes.POINTER(c_u64),
                                            ctypes.POINTER(c_i32)]
         L.vl_last_error.restype = ctypes.c_char_p
+        L.vl_prove_graph_create.argtypes = [ctypes.POINTER(vl_group), c_u64, ctypes.POINTER(vl_prove_opts), c_vp,
+                                            c_u64, ctypes.POINTER(c_u64), c_vp, ctypes.POINTER(c_vp)]
+        L.vl_prove_graph_launch.argtypes = [c_vp, c_u64, c_vp]
+        L.vl_prove_graph_destroy.argtypes = [c_vp]
+        L.vl_prove_graph_destroy.restype = None
         for f in ("vl_fr_lift", "vl_fr_export", "vl_eq_table", "vl_mle_partial_eval",
-                  "vl_sumcheck_matmul_prove", "vl_verify_transcript"):
+                  "vl_sumcheck_matmul_prove", "vl_verify_transcript", "vl_prove_graph_create",
+                  "vl_prove_graph_launch"):
             getattr(L, f).restype = c_i32
         _lib = L
     return _lib
@@ -313,6 +320,51 @@ def sumcheck_matmul_prove_async(groups: Sequence[GroupArgs], seed: int, proofs_d
                                           digests_dev.data_ptr() if digests_dev is not None else None,
                                           _stream(stream)))
     return [int(offs[i]) for i in range(n + 1)]
+
+
+class ProveGraph:
+    """vl_prove_graph: the batched prove of these groups captured once into a
+    HIP graph, with the workspace and output buffers fixed (device or pinned
+    host tensors).  launch(seed, stream) proves the groups' current
+    contents; close() (or the context manager) releases the graph."""
+
+    def __init__(self, groups: Sequence[GroupArgs], workspace, proofs_dev, status_dev, mode: int = VL_MODE_BATCHED,
+                 digests_dev=None, tuning_=None):
+        self.batch = _batch(groups)
+        n = len(self.batch)
+        # the tensors must outlive the graph: keep references
+        self._keep = (workspace, proofs_dev, status_dev, digests_dev, tuning_)
+        self._tun = _tun(tuning_)
+        self.opts = vl_prove_opts(mode, 1, workspace.data_ptr(), workspace.numel(), status_dev.data_ptr(),
+                                  self._tun, None)
+        offs = (c_u64 * (n + 1))()
+        h = c_vp()
+        _check(lib().vl_prove_graph_create(self.batch.arr, n, ctypes.byref(self.opts), proofs_dev.data_ptr(),
+                                           proofs_dev.numel(), offs,
+                                           digests_dev.data_ptr() if digests_dev is not None else None,
+                                           ctypes.byref(h)))
+        self.handle = h
+        self.offsets = [int(offs[i]) for i in range(n + 1)]
+
+    def launch(self, seed: int, stream=None):
+        _check(lib().vl_prove_graph_launch(self.handle, seed, _stream(stream)))
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            lib().vl_prove_graph_destroy(self.handle)
+        self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def verify_transcript(proof: bytes, group: GroupArgs, seed: int):

@@ -614,7 +614,7 @@ struct ForkEvents {
 };
 
 hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipStream_t s,
-                        hipStream_t s2, StageEvents* ev) {
+                        hipStream_t s2, StageEvents* ev, const void* blob_src_dev) {
   thread_local std::map<int, ForkEvents> forks;   // per host thread and device
   const size_t nseg = P.seg.size();
   const bool two = s2 != s;
@@ -628,7 +628,9 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
     const hipError_t e = fork.need(nseg + 2);
     if (e != hipSuccess) return e;
   }
-  VL_STAGE(ev, VL_STAGE_UPLOAD, s, upload_blob(dblob, P.blob.data(), L.total, s));
+  VL_STAGE(ev, VL_STAGE_UPLOAD, s,
+           blob_src_dev ? launch_copy_in(dblob, blob_src_dev, L.total, s)
+                        : upload_blob(dblob, P.blob.data(), L.total, s));
   VL_STAGE(ev, VL_STAGE_EQ, s,
            launch_eq(reinterpret_cast<const EqJob*>(dblob + L.eq), (uint32_t)P.eq.size(), P.eq_threads, s));
   if (two) {
@@ -821,9 +823,9 @@ uint64_t vl_workspace_size(const vl_group* groups, uint64_t n, const vl_prove_op
   return align_up(P.data_end, 256);
 }
 
-vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t seed,
-                                   const vl_prove_opts* o, uint8_t* proofs, uint64_t proofs_len,
-                                   uint64_t* offsets, uint8_t* digests, void* stream) {
+// Checks shared by the prove entry points; fills offsets.
+static vl_status validate_prove(const vl_group* groups, uint64_t n, const vl_prove_opts* o, uint8_t* proofs,
+                                uint64_t proofs_len, uint64_t* offsets, uint8_t* digests) {
   if (!groups || n == 0 || !o || !proofs || !offsets)
     return fail(VL_ERR_INVALID_ARG, "null argument");
   if (check_tuning(o->tuning) != VL_OK) return VL_ERR_INVALID_ARG;
@@ -855,6 +857,16 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
   if (!o->workspace) return fail(VL_ERR_WORKSPACE, "no workspace");
   if (reinterpret_cast<uintptr_t>(o->workspace) % 256)
     return fail(VL_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  return VL_OK;
+}
+
+vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t seed,
+                                   const vl_prove_opts* o, uint8_t* proofs, uint64_t proofs_len,
+                                   uint64_t* offsets, uint8_t* digests, void* stream) {
+  {
+    const vl_status st = validate_prove(groups, n, o, proofs, proofs_len, offsets, digests);
+    if (st != VL_OK) return st;
+  }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   uint8_t* ws = reinterpret_cast<uint8_t*>(o->workspace);
   const Tuning T = tuning_for(o);
@@ -971,6 +983,148 @@ vl_status vl_eq_table(const vl_fr* point, uint32_t nvars, vl_fr_vec out, void* s
   const hipError_t e = launch_eq_point(a, reinterpret_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(VL_ERR_HIP, "eq_table: %s", hipGetErrorString(e));
   return VL_OK;
+}
+
+// ------------------------------------------------------------ graph mode --
+// A prove call captured once into a HIP graph.  The graph holds every
+// launch of the call with fixed workspace and output addresses; its first
+// node copies the descriptor blob from a pinned host buffer of the handle.
+// A launch rebuilds the blob for its seed (the challenges and transcript
+// states change, the layout does not), writes it into that buffer and
+// replays the graph.
+}  // extern "C"
+
+struct vl_prove_graph {
+  int device = 0;
+  std::vector<vl_group> groups;
+  vl_prove_opts opts{};
+  vl_tuning tuning{};
+  bool has_tuning = false;
+  uint8_t* proofs = nullptr;
+  uint8_t* digests = nullptr;
+  std::vector<uint64_t> offsets;
+  uint64_t blob_total = 0;
+  void* pinned = nullptr;
+  void* pinned_dev = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+  bool launched = false;
+};
+
+namespace vl {
+// plans the handle's call for a seed and fills P's blob
+static vl_status graph_plan(vl_prove_graph* g, uint64_t seed, Plan& P, BlobLayout& L) {
+  const Tuning T = tuning_for(&g->opts);
+  plan_groups(P, T, g->groups.data(), 0, g->groups.size(), seed, reinterpret_cast<uint8_t*>(g->opts.workspace),
+              true, g->proofs, g->offsets.data(), g->opts.status, g->digests, nullptr);
+  if (P.data_end > g->opts.workspace_bytes)
+    return fail(VL_ERR_WORKSPACE, "workspace of %llu bytes, %llu needed",
+                (unsigned long long)g->opts.workspace_bytes, (unsigned long long)align_up(P.data_end, 256));
+  L = blob_layout(P);
+  fill_blob(P, L, reinterpret_cast<uint8_t*>(g->opts.workspace));
+  return VL_OK;
+}
+
+static void graph_free(vl_prove_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->done) (void)hipEventDestroy(g->done);
+  if (g->pinned) (void)hipHostFree(g->pinned);
+  delete g;
+}
+}  // namespace vl
+
+extern "C" {
+
+vl_status vl_prove_graph_create(const vl_group* groups, uint64_t n, const vl_prove_opts* o, uint8_t* proofs,
+                                uint64_t proofs_len, uint64_t* offsets, uint8_t* digests, vl_prove_graph** out) {
+  if (!out) return fail(VL_ERR_INVALID_ARG, "null handle pointer");
+  *out = nullptr;
+  {
+    const vl_status st = validate_prove(groups, n, o, proofs, proofs_len, offsets, digests);
+    if (st != VL_OK) return st;
+  }
+  if (!o->async) return fail(VL_ERR_INVALID_ARG, "a prove graph writes device-writable outputs: async must be 1");
+  // batched mode only: persistent mode's rounds workgroups wait for kernels
+  // that a graph executor may run after them
+  if (o->mode != VL_MODE_BATCHED) return fail(VL_ERR_INVALID_ARG, "a prove graph runs the batched mode");
+  if (o->stage_ms) return fail(VL_ERR_INVALID_ARG, "stage timing is not available in a prove graph");
+  vl_prove_graph* g = new vl_prove_graph();
+  hipError_t e = hipGetDevice(&g->device);
+  g->groups.assign(groups, groups + n);
+  g->opts = *o;
+  if (o->tuning) {
+    g->tuning = *o->tuning;
+    g->has_tuning = true;
+    g->opts.tuning = &g->tuning;
+  }
+  g->proofs = proofs;
+  g->digests = digests;
+  g->offsets.assign(offsets, offsets + n + 1);
+  Plan P;
+  BlobLayout L;
+  vl_status st = graph_plan(g, 0, P, L);
+  if (st != VL_OK) {
+    graph_free(g);
+    return st;
+  }
+  g->blob_total = L.total;
+  if (e == hipSuccess) e = hipHostMalloc(&g->pinned, L.total, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostGetDevicePointer(&g->pinned_dev, g->pinned, 0);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&g->done, hipEventDisableTiming);
+  // capture on a stream of our own (and, for segmented or persistent plans,
+  // the rounds stream paired with it, created before the capture starts)
+  hipStream_t cs = nullptr, s2 = nullptr;
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  s2 = cs;
+  if (e == hipSuccess && (P.seg.size() > 1 || P.persistent)) e = rounds_stream_for(cs, &s2);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    const hipError_t e1 = enqueue_plan(P, L, reinterpret_cast<uint8_t*>(g->opts.workspace), cs, s2, nullptr,
+                                       g->pinned_dev);
+    const hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
+    e = e1 != hipSuccess ? e1 : e2;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    graph_free(g);
+    return fail(VL_ERR_HIP, "prove graph: %s", hipGetErrorString(e));
+  }
+  *out = g;
+  return VL_OK;
+}
+
+vl_status vl_prove_graph_launch(vl_prove_graph* g, uint64_t seed, void* stream) {
+  if (!g) return fail(VL_ERR_INVALID_ARG, "null prove graph");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(VL_ERR_HIP, "device: %s", hipGetErrorString(e));
+  if (dev != g->device) return fail(VL_ERR_INVALID_ARG, "the prove graph belongs to device %d", g->device);
+  Plan P;
+  BlobLayout L;
+  const vl_status st = graph_plan(g, seed, P, L);
+  if (st != VL_OK) return st;
+  if (L.total != g->blob_total) return fail(VL_ERR_INVALID_ARG, "the plan changed since the graph was made");
+  // the previous replay must have copied the blob before it is overwritten
+  if (g->launched) {
+    e = hipEventSynchronize(g->done);
+    if (e != hipSuccess) return fail(VL_ERR_HIP, "prove graph: %s", hipGetErrorString(e));
+  }
+  memcpy(g->pinned, P.blob.data(), L.total);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  e = hipGraphLaunch(g->exec, s);
+  if (e == hipSuccess) e = hipEventRecord(g->done, s);
+  if (e != hipSuccess) return fail(VL_ERR_HIP, "prove graph launch: %s", hipGetErrorString(e));
+  g->launched = true;
+  return VL_OK;
+}
+
+void vl_prove_graph_destroy(vl_prove_graph* g) {
+  if (g && g->launched) (void)hipEventSynchronize(g->done);
+  graph_free(g);
 }
 
 // layout of the partial-eval workspace: [pack][job blob][split partials]

@@ -124,8 +124,10 @@ struct StageEvents {
 
 // Enqueue a filled plan on stream s; rounds of segment k run on stream s2
 // after segment k's contractions (s2 may equal s: then everything is serial).
+// blob_src_dev: device-side address of a pinned host buffer the blob is
+// copied from (graph capture), else the blob goes through the staging ring.
 hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipStream_t s,
-                        hipStream_t s2, StageEvents* ev = nullptr);
+                        hipStream_t s2, StageEvents* ev = nullptr, const void* blob_src_dev = nullptr);
 Tuning tuning_for(const vl_prove_opts* o);
 void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, uint64_t g1,
                  uint64_t seed, uint8_t* ws, bool async, uint8_t* proofs_dev, const uint64_t* offsets,

@@ -277,6 +277,77 @@ def test_full_size_config_matches_oracle(B, cfg):
         assert dg.hex() == rec["state"], g.name
 
 
+# ------------------------------------------------------------ graph mode ---
+@pytest.mark.parametrize("segments", [1, 3])
+def test_prove_graph_replays_match_eager(B, segments):
+    # one capture, replayed for several seeds with eager proves (their own
+    # launches and synchronisations) in between; every replay must equal the
+    # eager proof of its seed, and the workload's seed its oracle bytes
+    import torch
+    w, spec = tiny_workload()
+    gs = [device_group(g, B) for g in w.groups]
+    total = sum(B.proof_size(g) for g in gs)
+    proofs = torch.zeros(total, dtype=torch.uint8, device="cuda")
+    status = torch.full((len(gs),), -1, dtype=torch.int32, device="cuda")
+    digests = torch.zeros(32 * len(gs), dtype=torch.uint8, device="cuda")
+    tn = B.tuning(segments=segments)
+    ws = torch.empty(B.workspace_size(gs, 1, async_=True, tuning_=tn), dtype=torch.uint8, device="cuda")
+    _say(f"prove graph segments={segments}")
+    with B.ProveGraph(gs, ws, proofs, status, digests_dev=digests, tuning_=tn) as G:
+        for seed in (w.seed, 7, 7, w.seed + 1, w.seed):
+            proofs.zero_()
+            status.fill_(-1)
+            G.launch(seed)
+            torch.cuda.synchronize()
+            assert status.cpu().tolist() == [0] * len(gs)
+            raw = proofs.cpu().numpy().tobytes()
+            dg = digests.cpu().numpy().tobytes()
+            ref, ref_dig = B.sumcheck_matmul_prove(gs, seed, mode=1)
+            for i in range(len(gs)):
+                assert raw[G.offsets[i]:G.offsets[i + 1]] == ref[i], (seed, i)
+                assert dg[32 * i:32 * i + 32] == ref_dig[i], (seed, i)
+            if seed == w.seed:
+                for i, gold in enumerate(spec["groups"]):
+                    assert raw[G.offsets[i]:G.offsets[i + 1]].hex() == gold["proof_hex"]
+
+
+def test_prove_graph_full_size_cfg3(B):
+    import torch
+    _say("cfg3 graph: generating")
+    w = workloads.make_config("cfg3")
+    gold = golden("cfg3")
+    gs = [device_group(g, B) for g in w.groups]
+    total = sum(B.proof_size(g) for g in gs)
+    proofs = torch.empty(total, dtype=torch.uint8, pin_memory=True)
+    status = torch.empty(len(gs), dtype=torch.int32, pin_memory=True)
+    ws = torch.empty(B.workspace_size(gs, 1, async_=True), dtype=torch.uint8, device="cuda")
+    with B.ProveGraph(gs, ws, proofs, status) as G:
+        for rep in range(3):
+            _say(f"cfg3 graph: replay {rep}")
+            proofs.numpy()[:] = 0
+            G.launch(w.seed)
+            torch.cuda.synchronize()
+            assert not status.numpy().any()
+            raw = proofs.numpy().tobytes()
+            for i, (g, rec) in enumerate(zip(w.groups, gold["groups"])):
+                assert sha(raw[G.offsets[i]:G.offsets[i + 1]]) == rec["proof_sha256"], g.name
+            x = torch.randn(1 << 20, device="cuda")   # eager work between the replays
+            (x * 2).sum().item()
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+def test_prove_graph_refuses_other_modes(B, mode):
+    import torch
+    w, _ = tiny_workload()
+    gs = [device_group(g, B) for g in w.groups[:1]]
+    proofs = torch.zeros(B.proof_size(gs[0]), dtype=torch.uint8, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = torch.empty(B.workspace_size(gs, mode, async_=True), dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.VLError) as e:
+        B.ProveGraph(gs, ws, proofs, status, mode=mode)
+    assert e.value.status == B.VL_ERR_INVALID_ARG
+
+
 # --------------------------------------------------------------- persistent --
 def test_persistent_mode_matches_oracle_bytes(B):
     # resident rounds workgroups waiting on readiness counters: same bytes
