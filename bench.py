@@ -179,6 +179,55 @@ def autotune(B, gas, seed, mode, reps=3):
     return best[1], table
 
 
+def serving_leg(B, n_requests, pool_size=6, n_slots=4, seed=5):
+    """Continuous batching at 13B-class shapes: a resident pool of proof
+    requests (LoRA layers of hidden 5120 / FFN 13824, mixed T, rank and
+    fwd/bwd/upd type), Poisson arrivals at the serial service rate, served by
+    paper_2508_21393_amd.serve.  Each arrival proves a pooled witness with its
+    own seed; three results are checked against a solo prove."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2508_21393_amd import serve
+    dev = lambda x: x if torch.is_tensor(x) else torch.from_numpy(x).to("cuda")  # noqa: E731
+    kinds = workloads.serving_stream(pool_size, 1.0, seed=seed)
+    weights, pool, shapes = {}, [], []
+    for k, (_, target, T, r, kind) in enumerate(kinds):
+        if target not in weights:
+            weights[target] = workloads.frozen_weight(target, seed=seed)
+        wl = workloads.serving_request(k, target, T, r, kind, weights[target], seed=seed, device="cuda")
+        gas = [B.GroupArgs(g.group_id, [(dev(p.A), dev(p.B), p.transA, p.transB) for p in g.products], dev(g.C))
+               for g in wl.groups]
+        pool.append(gas)
+        shapes.append(f"{kind} {target} T={T} r={r}")
+    torch.cuda.synchronize()
+    solo = []
+    for gas in pool:
+        B.sumcheck_matmul_prove(gas, 1, mode=B.VL_MODE_BATCHED)
+        t0 = time.perf_counter()
+        B.sumcheck_matmul_prove(gas, 2, mode=B.VL_MODE_BATCHED)
+        solo.append(time.perf_counter() - t0)
+    mean_solo = sum(solo) / len(solo)
+    rate = 1.0 / mean_solo                     # offered load: the one-at-a-time service rate
+    gaps = np.random.default_rng([seed, 11]).exponential(1.0 / rate, size=n_requests)
+    arrivals = [(float(t), i % pool_size) for i, t in enumerate(np.cumsum(gaps))]
+    srv = serve.ProofServer(n_slots=n_slots, hbm_budget_bytes=64 << 30)
+    results, wall = serve.run_open_loop(srv, arrivals,
+                                        lambda i, k: serve.Request(i, pool[k], 7000 + i))
+    for r in results[:3]:
+        ref, _ = B.sumcheck_matmul_prove(pool[arrivals[r.rid][1]], 7000 + r.rid, mode=B.VL_MODE_BATCHED)
+        assert r.proofs == ref and not any(r.status), "a served proof differs from the solo prove"
+    summ = serve.latency_summary(results)
+    n_products = sum(sum(len(g.prods) for g in pool[k]) for _, k in arrivals)
+    return {"workload": "13B-class LoRA layer requests (hidden 5120, FFN 13824; T in {128, 512, 2048}, "
+                        "rank in {8, 16, 64}; fwd/bwd/upd)",
+            "pool": shapes, "requests": n_requests, "slots": n_slots, "arrival": "poisson",
+            "arrival_rate_per_s": rate, "solo_mean_ms": 1e3 * mean_solo,
+            "p50_ms": summ["p50_ms"], "p99_ms": summ["p99_ms"], "mean_ms": summ["mean_ms"],
+            "requests_per_s": n_requests / wall, "products_per_s": n_products / wall,
+            "peak_in_flight": srv.peak_in_flight}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,6 +248,8 @@ def main():
                     help="proofs in flight in the throughput phase (asynchronous entry point)")
     ap.add_argument("--graph", type=int, default=1,
                     help="1: the throughput phase replays one captured HIP graph per slot (vl_prove_graph)")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests in the serving leg at 13B-class shapes (0: skip it)")
     ap.add_argument("--autotune", action="store_true",
                     help="time a grid of launch shapes first and bench the fastest")
     args = ap.parse_args()
@@ -381,6 +432,12 @@ def main():
     }
     if tried is not None:
         out["autotune"] = tried
+    if args.serve_requests > 0:
+        for sl in slots:
+            sl.graph = None
+        del slots, workspace, batch, gas
+        torch.cuda.empty_cache()
+        out["serving"] = serving_leg(B, args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

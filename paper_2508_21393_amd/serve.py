@@ -2,14 +2,16 @@
 
 Proof requests (a list of groups with device-resident witnesses, and a seed)
 arrive over time.  The server keeps a fixed number of slots; each slot owns a
-HIP stream and, while busy, a workspace and device buffers for proofs and
-status.  A request is admitted when a slot is free and its device memory
-(workspace + proof + status bytes, plus its witness bytes if the caller says
-they are not yet counted) fits the HBM budget; otherwise it waits in FIFO
-order.  Admitted requests are enqueued with the asynchronous prove entry
-point, so requests on different slots overlap on the device; completion is
-found by polling HIP events, after which the proof bytes are copied back,
-latency is recorded and the slot and its memory are released.
+HIP stream and, while busy, a device workspace and pinned host buffers for
+proofs and status.  A request is admitted when a slot is free and its device
+memory (the workspace, plus its witness bytes if the caller says they are not
+yet counted) fits the HBM budget; otherwise it waits in FIFO order.  Admitted
+requests are enqueued with the asynchronous prove entry point, so requests on
+different slots overlap on the device; the kernels write proof bytes and
+status words straight into the pinned buffers (no copy-engine transfer, which
+would order the slots' streams behind each other).  Completion is found by
+polling HIP events, after which latency is recorded and the slot and its
+memory are released.
 
 The arithmetic is untouched: a request's proof bytes depend only on its
 matrices, its seed and its group ids, so a result is identical alone and in
@@ -73,9 +75,8 @@ class ProofServer:
     # -- sizing ---------------------------------------------------------------
     @staticmethod
     def request_bytes(req: Request) -> int:
-        ws = B.workspace_size(req.groups, req.mode, async_=True)
-        proof = sum(B.proof_size(g) for g in req.groups)
-        return ws + proof + 4 * len(req.groups) + 32 * len(req.groups) + req.witness_bytes
+        """HBM bytes a request holds while in flight (its outputs are in host memory)."""
+        return B.workspace_size(req.groups, req.mode, async_=True) + req.witness_bytes
 
     # -- queue ----------------------------------------------------------------
     def submit(self, req: Request):
@@ -100,16 +101,16 @@ class ProofServer:
             ws = torch.empty(max(256, B.workspace_size(req.groups, req.mode, async_=True)),
                              dtype=torch.uint8, device="cuda")
             total = sum(B.proof_size(g) for g in req.groups)
-            proofs = torch.empty(max(1, total), dtype=torch.uint8, device="cuda")
-            status = torch.full((ng,), -1, dtype=torch.int32, device="cuda")
+            proofs = torch.empty(max(1, total), dtype=torch.uint8, pin_memory=True)
+            status = torch.empty(ng, dtype=torch.int32, pin_memory=True)
+            status.numpy()[:] = -1
             # the slot's stream must see the allocations made on the current stream
             slot.stream.wait_stream(torch.cuda.current_stream())
             slot.offs = B.sumcheck_matmul_prove_async(req.groups, req.seed, proofs, status, ws,
                                                       mode=req.mode, stream=slot.stream)
             ev = torch.cuda.Event()
             ev.record(slot.stream)
-            for t in (ws, proofs, status):
-                t.record_stream(slot.stream)
+            ws.record_stream(slot.stream)
             slot.req, slot.event, slot.bufs, slot.bytes = req, ev, (ws, proofs, status), need
             slot.t_admit = time.perf_counter()
             self.in_use += need
@@ -121,8 +122,10 @@ class ProofServer:
             if s.req is None or not s.event.query():
                 continue
             ws, proofs, status = s.bufs
-            raw = proofs.cpu().numpy().tobytes()
-            st = status.cpu().tolist()
+            # numpy views of the pinned buffers: no torch CPU op (its thread
+            # pool would compete with the next admission's host work)
+            raw = proofs.numpy().tobytes()
+            st = status.numpy().tolist()
             req = s.req
             self.done[req.rid] = Result(req.rid, [raw[s.offs[i]:s.offs[i + 1]] for i in range(len(req.groups))],
                                         st, req.t_arrive, s.t_admit, time.perf_counter())
