@@ -134,7 +134,11 @@ def _check(status: int):
 
 # ---------------------------------------------------------------- helpers ----
 def dtype_code(dt) -> int:
+    """VL_I16/I32/I64 for a torch dtype, a numpy dtype or a numpy scalar type."""
     s = str(dt).replace("torch.", "")
+    if s not in ("int16", "int32", "int64"):
+        import numpy as np
+        s = np.dtype(dt).name
     return {"int16": VL_I16, "int32": VL_I32, "int64": VL_I64}[s]
 
 

@@ -201,7 +201,78 @@ contract_kernel(const ContractJob* __restrict__ jobs, uint32_t n_jobs, uint32_t 
   // also count against the scalar-load counter, so every wait for the eq
   // digits would drain the vector loads in flight as well.
   const gptr<T> Mg = (gptr<T>)M;
-  if constexpr (VEC && !ROWS) {
+  if constexpr (VEC && !ROWS && sizeof(T) == 2 && OPL == 1) {
+    // cols layout, int16, 16-byte aligned rows: the wave's 64 rows (one per
+    // lane) are read in stages of 64 entries (128 bytes) per row.  Each of a
+    // stage's 8 load instructions fetches 8 rows whole (lanes 8k .. 8k + 7
+    // one row, its eight 16-byte pieces rotated by the row index), so a load
+    // touches 8 cache lines instead of 64, and the pieces go through LDS to
+    // the lane of their row.  Lane r finds piece p of its row at slot
+    // ((r & 7) << 3) | ((p + r) & 7) of load r >> 3: each group of 8 lanes
+    // reads 8 different 16-byte bank groups, and at step p every lane holds
+    // entries 8p .. 8p + 7 of the stage, so the eq digits stay wave-uniform.
+    // One LDS buffer per wave (a wave's LDS accesses execute in order, so the
+    // next stage is written only after this one was read) and one stage in
+    // flight in registers keep the footprint at 8 KB of LDS and about 90
+    // VGPRs, five waves per SIMD.  Lanes past the last row re-read the last
+    // row; vector indexes are clamped to the row's last (partly) valid one,
+    // and eq digits are read only for entries inside the chunk.
+    constexpr uint32_t BE = 8, NP = 8, SE = BE * NP;
+    __shared__ u32x4 stage_lds[kContractBlock / kWave][NP * kWave];
+    u32x4* buf = stage_lds[threadIdx.x >> 6];
+    const uint32_t span = m1 - m0, nvec = (span + BE - 1) / BE, nst = (span + SE - 1) / SE;
+    const uint32_t lrow = lane >> 3, lpiece = ((lane & 7) - lrow) & 7;
+    const gptr<u32x4> lbase = (gptr<u32x4>)(Mg + (uint64_t)min(owave * 64u + lrow, n_out - 1) * ld + m0);
+    const uint64_t ldv = ld / BE;   // row stride in 16-byte vectors (ld * 2 is a multiple of 16)
+    auto lrowp = [&](uint32_t i) -> gptr<u32x4> {
+      // row owave*64 + 8i + lrow, clamped to the last row
+      const uint32_t row = owave * 64u + 8 * i + lrow;
+      return row < n_out ? lbase + (uint64_t)(8 * i) * ldv : (gptr<u32x4>)(Mg + (uint64_t)(n_out - 1) * ld + m0);
+    };
+    auto ldst = [&](uint32_t st, u32x4 (&b)[NP]) {
+#pragma unroll
+      for (uint32_t i = 0; i < NP; ++i) b[i] = lrowp(i)[min(st * NP + lpiece, nvec - 1)];
+    };
+    u32x4 r[NP];
+    ldst(0, r);
+    for (uint32_t st = 0; st < nst; ++st) {
+#pragma unroll
+      for (uint32_t i = 0; i < NP; ++i) buf[i * kWave + lane] = r[i];
+      ldst(st + 1, r);
+      const uint32_t mst = m0 + st * SE;
+#pragma unroll 1
+      for (uint32_t pc = 0; pc < NP; ++pc) {
+        const u32x4 x = buf[(lane >> 3) * kWave + (((lane & 7) << 3) | ((pc + lane) & 7))];
+        const uint32_t mp = mst + pc * BE;
+        if (mp >= m1) break;   // uniform: the rest of the stage is past the chunk
+        if (mp + BE <= m1) {   // the piece's eq digits in one batch of scalar loads
+          ci32_ptr pe = pack + (uint64_t)mp * 8;
+          int32_t e[BE][8];
+#pragma unroll
+          for (uint32_t q = 0; q < BE; ++q)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) e[q][j] = pe[q * 8 + j];
+#pragma unroll
+          for (uint32_t q = 0; q < BE; ++q) {
+            int32_t d[1][ND];
+            const uint32_t w = x[q >> 1];
+            d[0][0] = (q & 1) ? ((int32_t)w >> 16) : ((int32_t)(w << 16) >> 16);
+            mac8v<1, ND>(e[q], d, acc);
+          }
+        } else {               // the chunk's last, partial piece
+#pragma unroll
+          for (uint32_t q = 0; q < BE; ++q) {
+            if (mp + q < m1) {
+              int32_t d[1][ND];
+              const uint32_t w = x[q >> 1];
+              d[0][0] = (q & 1) ? ((int32_t)w >> 16) : ((int32_t)(w << 16) >> 16);
+              mac8<1, ND>(pack + (uint64_t)(mp + q) * 8, d, acc);
+            }
+          }
+        }
+      }
+    }
+  } else if constexpr (VEC && !ROWS) {
     // cols layout, 16-byte aligned rows (m0 is a multiple of the vector
     // width): OPL rows per lane.  Each lane reads its row 128 bytes at a
     // time (GV 16-byte loads issued together, so every cache line is fetched

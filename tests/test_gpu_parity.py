@@ -103,6 +103,29 @@ def test_mle_partial_eval(B, rows, cols, contract, dtype, bits):
     assert got == expect
 
 
+@pytest.mark.parametrize("rows,cols,ld,lane_macs", [(67, 1003, 1024, 2048), (130, 517, 520, 0), (9, 77, 80, 512)])
+def test_mle_partial_eval_strided_cols(B, rows, cols, ld, lane_macs):
+    # a strided view (ld > cols, rows 16-byte aligned) contracted over its
+    # columns: ragged stages and a last piece of fewer than 8 entries, in
+    # chunks of a few hundred entries
+    import torch
+    _say(f"partial_eval strided rows={rows} cols={cols} ld={ld} lane_macs={lane_macs}")
+    rng = np.random.default_rng(rows * 31 + cols)
+    big = rng.integers(-(1 << 15), 1 << 15, size=(rows, ld), dtype=np.int64).astype(np.int16)
+    Md = to_dev(big)[:, :cols]
+    nv = oracle.num_vars(cols)
+    prng = random.Random(cols)
+    pt = [prng.randrange(oracle.P) for _ in range(nv)]
+    eq = torch.empty((8, 1 << nv), dtype=torch.int32, device="cuda")
+    B.eq_table(pt, B.fr_vec(eq))
+    L = 1 << oracle.num_vars(rows)
+    out = torch.full((8, L), 7, dtype=torch.int32, device="cuda")
+    tn = B.tuning(lane_macs=lane_macs) if lane_macs else None
+    ws = torch.empty(B.partial_eval_workspace_size(rows, cols, 1, np.int16, tn), dtype=torch.uint8, device="cuda")
+    B.mle_partial_eval(Md, 1, B.fr_vec(eq), B.fr_vec(out), ws, tuning_=tn)
+    assert _export(B, out, L) == oracle.partial_eval_cols(big[:, :cols], pt)
+
+
 def _prove(B, w, mode):
     gs = [device_group(g, B) for g in w.groups]
     return B.sumcheck_matmul_prove(gs, w.seed, mode=mode)
