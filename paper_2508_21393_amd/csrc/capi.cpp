@@ -1042,15 +1042,16 @@ vl_status vl_prove_graph_create(const vl_group* groups, uint64_t n, const vl_pro
                                 uint64_t proofs_len, uint64_t* offsets, uint8_t* digests, vl_prove_graph** out) {
   if (!out) return fail(VL_ERR_INVALID_ARG, "null handle pointer");
   *out = nullptr;
-  {
-    const vl_status st = validate_prove(groups, n, o, proofs, proofs_len, offsets, digests);
-    if (st != VL_OK) return st;
-  }
+  if (!o) return fail(VL_ERR_INVALID_ARG, "null options");
   if (!o->async) return fail(VL_ERR_INVALID_ARG, "a prove graph writes device-writable outputs: async must be 1");
   // batched mode only: persistent mode's rounds workgroups wait for kernels
   // that a graph executor may run after them
   if (o->mode != VL_MODE_BATCHED) return fail(VL_ERR_INVALID_ARG, "a prove graph runs the batched mode");
   if (o->stage_ms) return fail(VL_ERR_INVALID_ARG, "stage timing is not available in a prove graph");
+  {
+    const vl_status st = validate_prove(groups, n, o, proofs, proofs_len, offsets, digests);
+    if (st != VL_OK) return st;
+  }
   vl_prove_graph* g = new vl_prove_graph();
   hipError_t e = hipGetDevice(&g->device);
   g->groups.assign(groups, groups + n);

@@ -108,3 +108,69 @@ def test_round_failure_reports_round_index():
     bad = proof[:32 * i] + ((x + 5) % oracle.P).to_bytes(32, "little") + proof[32 * i + 32:]
     ok, fr, _ = B.verify_transcript(bad, ga, 1)
     assert not ok and fr == 3
+
+
+# ------------------------------------------------------------ ABI details ---
+def test_stage_names_match_the_header():
+    header = open(os.path.join(ROOT, "include", "verilora.h")).read()
+    defs = dict((k, int(v)) for k, v in re.findall(r"#define (VL_STAGE_[A-Z0-9]+) (\d+)", header))
+    assert defs["VL_STAGE_COUNT"] == B.VL_STAGE_COUNT == len(B.STAGE_NAMES)
+    assert B.STAGE_NAMES[defs["VL_STAGE_UPLOAD"]] == "upload"
+    assert B.STAGE_NAMES[defs["VL_STAGE_EQ"]] == "eq"
+    assert B.STAGE_NAMES[defs["VL_STAGE_FINISH"]] == "finish"
+    assert B.STAGE_NAMES[defs["VL_STAGE_PASS1"]] == "pass1"
+    assert B.STAGE_NAMES[defs["VL_STAGE_ROUNDS"]] == "rounds"
+    kinds = defs["VL_STAGE_FINISH"] - defs["VL_STAGE_CONTRACT"]
+    assert len(B.STAGE_NAMES[defs["VL_STAGE_CONTRACT"]:defs["VL_STAGE_FINISH"]]) == kinds
+    assert f"{kinds} kinds" in header
+
+
+def test_tuning_struct_matches_the_header():
+    header = open(os.path.join(ROOT, "include", "verilora.h")).read()
+    end = header.index("} vl_tuning;")
+    body = header[header.rindex("typedef struct {", 0, end):end]
+    fields = re.findall(r"uint32_t (\w+);", body)
+    assert fields == [f for f, _ in B.vl_tuning._fields_]
+
+
+def _host_args(g: workloads.Group):
+    prods = [(p.A, p.B, p.transA, p.transB) for p in g.products]
+    return B.GroupArgs(g.group_id, prods, g.C)
+
+
+def test_prove_refuses_a_misaligned_workspace():
+    # refused by the host-side checks, before any device work
+    import ctypes
+    L = _lib_or_skip()
+    ga = _host_args(workloads.tiny_random_group(1, [(4, 4, 4)]))
+    opts = B.vl_prove_opts(B.VL_MODE_BATCHED, 0, 0x1000 + 8, 1 << 20, None, None, None)
+    proofs = ctypes.create_string_buffer(4096)
+    offs = (ctypes.c_uint64 * 2)()
+    st = L.vl_sumcheck_matmul_prove(ctypes.byref(ga.struct), 1, 1, ctypes.byref(opts),
+                                    ctypes.addressof(proofs), 4096, offs, None, None)
+    assert st == B.VL_ERR_WORKSPACE
+    assert "256-byte aligned" in B.last_error()
+
+
+@pytest.mark.parametrize("mode,async_,msg", [(B.VL_MODE_BATCHED, 0, "async must be 1"),
+                                             (B.VL_MODE_PER_INSTANCE, 1, "batched mode"),
+                                             (B.VL_MODE_PERSISTENT, 1, "batched mode")])
+def test_graph_create_refuses_unsupported_options(mode, async_, msg):
+    import ctypes
+    L = _lib_or_skip()
+    ga = _host_args(workloads.tiny_random_group(1, [(4, 4, 4)]))
+    opts = B.vl_prove_opts(mode, async_, 0x1000, 1 << 20, 0x2000, None, None)
+    offs = (ctypes.c_uint64 * 2)()
+    h = ctypes.c_void_p(123)
+    st = L.vl_prove_graph_create(ctypes.byref(ga.struct), 1, ctypes.byref(opts), 0x3000, 4096, offs, None,
+                                 ctypes.byref(h))
+    assert st == B.VL_ERR_INVALID_ARG and msg in B.last_error()
+    assert not h.value    # no handle on failure
+    L.vl_prove_graph_destroy(None)   # a null handle is a no-op
+
+
+def test_partial_eval_workspace_refuses_bad_tuning():
+    _lib_or_skip()
+    assert B.partial_eval_workspace_size(64, 64, 0, np.int16, B.tuning(claim_order=3)) == 0
+    assert B.partial_eval_workspace_size(64, 64, 0, np.int16, B.tuning(cols_rows=3)) == 0
+    assert B.partial_eval_workspace_size(64, 64, 0, np.int16, B.tuning(claim_order=2)) > 0
