@@ -934,7 +934,13 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
       if (e2 != hipSuccess) return fail(VL_ERR_HIP, "rounds stream: %s", hipGetErrorString(e2));
     }
     const hipError_t e = enqueue_plan(P, L, ws, s, s2, ev);
-    if (e != hipSuccess) return fail(VL_ERR_HIP, "launch: %s", hipGetErrorString(e));
+    if (e != hipSuccess) {
+      // what was enqueued before the failure may still write the outputs
+      // (the pinned buffer the next blocking call reuses): let it finish
+      (void)hipStreamSynchronize(s);
+      if (s2 != s) (void)hipStreamSynchronize(s2);
+      return fail(VL_ERR_HIP, "launch: %s", hipGetErrorString(e));
+    }
     return async ? VL_OK : fetch(g0, g1);
   };
   if (T.per_instance) {
