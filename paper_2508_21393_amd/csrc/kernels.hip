@@ -226,9 +226,11 @@ __global__ void __launch_bounds__(256) pass1_kernel(const Pass1Job* __restrict__
     } else {
       const Fr a0 = load_sol(J.a, J.a_ld, t), a1 = load_sol(J.a, J.a_ld, t + J.h);
       const Fr b0 = load_sol(J.b, J.b_ld, t), b1 = load_sol(J.b, J.b_ld, t + J.h);
-      g[0] = fr_add(g[0], fr_mul(a0, b0));
-      g[1] = fr_add(g[1], fr_mul(a1, b1));
-      g[2] = fr_add(g[2], fr_mul(at_two(a0, a1), at_two(b0, b1)));
+      const Fr x[3] = {a0, a1, at_two(a0, a1)}, y[3] = {b0, b1, at_two(b0, b1)};
+      Fr pr[3];
+      fr_mul_n<3>(x, y, pr);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) g[k] = fr_add(g[k], pr[k]);
     }
   }
   __shared__ uint32_t red[3 * 8 * 4];
@@ -282,6 +284,9 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
   __shared__ uint32_t red[3 * 8 * (kRoundsBlock / kWave)];
   __shared__ uint32_t first[VL_MAX_PRODS][3][8];   // round-1 values per product
   __shared__ uint32_t bcast[8];                    // the round's challenge
+  __shared__ uint32_t coef[2][3][3][8];            // register rounds: value k as c0 + c1 r + c2 r^2
+  __shared__ uint32_t rbuf[2][8];                  // register rounds: r_j by parity
+  __shared__ uint32_t finv[2][8];                  // the product's final a~, b~
   __shared__ int32_t verdict;
   const uint32_t tid = threadIdx.x, NT = blockDim.x;
   const uint32_t wave = tid >> 6, lane = tid & 63u;
@@ -393,17 +398,22 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
           const Fr a10 = load_sol(a, ld, t + h), a11 = load_sol(a, ld, t + 3 * h);
           const Fr b00 = load_sol(b, ld, t), b01 = load_sol(b, ld, t + 2 * h);
           const Fr b10 = load_sol(b, ld, t + h), b11 = load_sol(b, ld, t + 3 * h);
-          const Fr a0 = fr_add(a00, fr_mul(r, fr_sub(a01, a00)));
-          const Fr a1 = fr_add(a10, fr_mul(r, fr_sub(a11, a10)));
-          const Fr b0 = fr_add(b00, fr_mul(r, fr_sub(b01, b00)));
-          const Fr b1 = fr_add(b10, fr_mul(r, fr_sub(b11, b10)));
+          const Fr rr2[2] = {r, r}, da[2] = {fr_sub(a01, a00), fr_sub(a11, a10)};
+          const Fr db[2] = {fr_sub(b01, b00), fr_sub(b11, b10)};
+          Fr fa[2], fb[2];
+          fr_mul_n<2>(rr2, da, fa);
+          fr_mul_n<2>(rr2, db, fb);
+          const Fr a0 = fr_add(a00, fa[0]), a1 = fr_add(a10, fa[1]);
+          const Fr b0 = fr_add(b00, fb[0]), b1 = fr_add(b10, fb[1]);
           store_sol(a, ld, t, a0);
           store_sol(a, ld, t + h, a1);
           store_sol(b, ld, t, b0);
           store_sol(b, ld, t + h, b1);
-          g[0] = fr_add(g[0], fr_mul(a0, b0));
-          g[1] = fr_add(g[1], fr_mul(a1, b1));
-          g[2] = fr_add(g[2], fr_mul(at_two(a0, a1), at_two(b0, b1)));
+          const Fr x[3] = {a0, a1, at_two(a0, a1)}, y[3] = {b0, b1, at_two(b0, b1)};
+          Fr pr[3];
+          fr_mul_n<3>(x, y, pr);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) g[k] = fr_add(g[k], pr[k]);
         }
         __threadfence_block();   // the folded entries, for the next sweep
         block_sum_w0<3>(g, red);
@@ -419,54 +429,163 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
       r = lds_get(bcast);
       pending = true;
     }
-    // the last rounds (half-table h <= 64): wave 0, pairs in registers (the
-    // last global challenge, if any, folded in as they are loaded)
-    if (wave == 0) {
-      Fr fa, fb;   // the product's final a~ and b~ (lane 0)
-      if (rd < P.n1) {
-        uint32_t h = 1u << (P.n1 - 1 - rd);
-        Fr A0 = fr_zero(), A1 = fr_zero(), B0 = fr_zero(), B1 = fr_zero();
+    // The last rounds (half-table h <= 64), split over two waves so that the
+    // table work of a round overlaps the hashing of the one before:
+    //  - wave 1 holds the pairs in registers (lane t: entries t and t + h of
+    //    a and b; the last global challenge, if any, folded in as they are
+    //    loaded).  While wave 0 hashes round j it folds the tables by r_{j-1}
+    //    and writes the next round's three values as quadratics in the
+    //    challenge r_j it does not know yet: with the folded entries
+    //    x + r y, each value sum (x + r y)(x' + r y') has the coefficients
+    //    sum x x', sum (x y' + y x'), sum y y' (three products per pair);
+    //  - wave 0 evaluates round j's values from those coefficients at r_{j-1}
+    //    (exact: the same field elements as a direct sum), writes them to the
+    //    proof, absorbs them and squeezes r_j.
+    // One barrier per round hands r_j to wave 1 and the coefficients to wave
+    // 0 (both double-buffered by round parity); waves 2 and 3 only take part
+    // in the barriers.
+    if (rd < P.n1) {
+      const uint32_t rd0 = rd;
+      uint32_t h = 1u << (P.n1 - 1 - rd0);
+      Fr A0 = fr_zero(), A1 = fr_zero(), B0 = fr_zero(), B1 = fr_zero();
+      if (wave == 1) {
         if (lane < h) {
           A0 = load_sol(a, ld, lane);
           A1 = load_sol(a, ld, lane + h);
           B0 = load_sol(b, ld, lane);
           B1 = load_sol(b, ld, lane + h);
           if (pending) {
-            A0 = fr_add(A0, fr_mul(r, fr_sub(load_sol(a, ld, lane + 2 * h), A0)));
-            A1 = fr_add(A1, fr_mul(r, fr_sub(load_sol(a, ld, lane + 3 * h), A1)));
-            B0 = fr_add(B0, fr_mul(r, fr_sub(load_sol(b, ld, lane + 2 * h), B0)));
-            B1 = fr_add(B1, fr_mul(r, fr_sub(load_sol(b, ld, lane + 3 * h), B1)));
+            const Fr rr2[2] = {r, r};
+            const Fr da[2] = {fr_sub(load_sol(a, ld, lane + 2 * h), A0), fr_sub(load_sol(a, ld, lane + 3 * h), A1)};
+            const Fr db[2] = {fr_sub(load_sol(b, ld, lane + 2 * h), B0), fr_sub(load_sol(b, ld, lane + 3 * h), B1)};
+            Fr fa[2], fb[2];
+            fr_mul_n<2>(rr2, da, fa);
+            fr_mul_n<2>(rr2, db, fb);
+            A0 = fr_add(A0, fa[0]);
+            A1 = fr_add(A1, fa[1]);
+            B0 = fr_add(B0, fb[0]);
+            B1 = fr_add(B1, fb[1]);
           }
         }
-        for (; rd < P.n1; ++rd, h >>= 1) {
-          Fr g[3];
-          g[0] = fr_mul(A0, B0);   // lanes >= h hold zeros
-          g[1] = fr_mul(A1, B1);
-          g[2] = fr_mul(at_two(A0, A1), at_two(B0, B1));
-          wave_sum<3>(g, h);
-          const Fr rr = round_challenge(tr, g, out, lane);
-          out += 96;
-          // fold; then entry t + h/2 of the folded table comes from lane t + h/2
-          Fr na = fr_add(A0, fr_mul(rr, fr_sub(A1, A0)));
-          Fr nb = fr_add(B0, fr_mul(rr, fr_sub(B1, B0)));
-          if (lane >= h) na = nb = fr_zero();
-          const uint32_t hh = h >> 1;
-          Fr ua, ub;
+        // round rd0's values directly, as constant quadratics
+        Fr g[3];   // lanes >= h hold zeros
+        {
+          const Fr x[3] = {A0, A1, at_two(A0, A1)}, y[3] = {B0, B1, at_two(B0, B1)};
+          fr_mul_n<3>(x, y, g);
+        }
+        wave_sum<3>(g, h);
+        if (lane == 0)
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            ua.w[j] = __shfl(na.w[j], (int)(lane + hh), kWave);
-            ub.w[j] = __shfl(nb.w[j], (int)(lane + hh), kWave);
+          for (int k = 0; k < 3; ++k) {
+            lds_put(coef[rd0 & 1][k][0], g[k]);
+            lds_put(coef[rd0 & 1][k][1], fr_zero());
+            lds_put(coef[rd0 & 1][k][2], fr_zero());
           }
-          A0 = na;
-          B0 = nb;
-          A1 = lane < hh ? ua : fr_zero();
-          B1 = lane < hh ? ub : fr_zero();
-          if (lane >= hh) A0 = B0 = fr_zero();
-          if (h == 1) {   // last round: the folded single entries
-            fa = na;
-            fb = nb;
+      }
+      __syncthreads();
+      for (uint32_t j = rd0; j < P.n1; ++j, h >>= 1) {
+        if (wave == 0) {
+          const Fr rp = j > rd0 ? lds_get(rbuf[(j - 1) & 1]) : fr_zero();
+          // g_k = c0 + r (c1 + r c2), the three in step
+          Fr g[3], c2[3], t[3];
+          const Fr rp3[3] = {rp, rp, rp};
+#pragma unroll
+          for (int k = 0; k < 3; ++k) c2[k] = lds_get(coef[j & 1][k][2]);
+          fr_mul_n<3>(rp3, c2, t);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) t[k] = fr_add(lds_get(coef[j & 1][k][1]), t[k]);
+          fr_mul_n<3>(rp3, t, g);
+#pragma unroll
+          for (int k = 0; k < 3; ++k) g[k] = fr_add(lds_get(coef[j & 1][k][0]), g[k]);
+          const Fr rj = round_challenge(tr, g, out, lane);
+          if (lane == 0) lds_put(rbuf[j & 1], rj);
+        } else if (wave == 1) {
+          if (j > rd0) {
+            // fold by r_{j-1}; entry t + h of the folded table comes from lane t + h
+            const Fr rp = lds_get(rbuf[(j - 1) & 1]);
+            const uint32_t hp = 2 * h;   // the previous round's half-size
+            const Fr rp2[2] = {rp, rp}, d[2] = {fr_sub(A1, A0), fr_sub(B1, B0)};
+            Fr f[2];
+            fr_mul_n<2>(rp2, d, f);
+            Fr na = fr_add(A0, f[0]);
+            Fr nb = fr_add(B0, f[1]);
+            if (lane >= hp) na = nb = fr_zero();
+            Fr ua, ub;
+#pragma unroll
+            for (int w = 0; w < 8; ++w) {
+              ua.w[w] = __shfl(na.w[w], (int)(lane + h), kWave);
+              ub.w[w] = __shfl(nb.w[w], (int)(lane + h), kWave);
+            }
+            const bool in = lane < h;
+            A0 = in ? na : fr_zero();
+            B0 = in ? nb : fr_zero();
+            A1 = in ? ua : fr_zero();
+            B1 = in ? ub : fr_zero();
+          }
+          if (j + 1 < P.n1) {
+            // round j + 1 as quadratics in r_j: lane t < h/2 pairs its
+            // folded entry x + r y (from entries t, t + h) with lane
+            // t + h/2's (entries t + h/2, t + h/2 + h)
+            const uint32_t hh = h >> 1;
+            Fr qa0, qa1, qb0, qb1;   // lane t + hh's pair
+#pragma unroll
+            for (int w = 0; w < 8; ++w) {
+              qa0.w[w] = __shfl(A0.w[w], (int)(lane + hh), kWave);
+              qa1.w[w] = __shfl(A1.w[w], (int)(lane + hh), kWave);
+              qb0.w[w] = __shfl(B0.w[w], (int)(lane + hh), kWave);
+              qb1.w[w] = __shfl(B1.w[w], (int)(lane + hh), kWave);
+            }
+            Fr xa[3], ya[3], xb[3], yb[3];
+            xa[0] = A0;  ya[0] = fr_sub(A1, A0);
+            xb[0] = B0;  yb[0] = fr_sub(B1, B0);
+            xa[1] = qa0; ya[1] = fr_sub(qa1, qa0);
+            xb[1] = qb0; yb[1] = fr_sub(qb1, qb0);
+            xa[2] = at_two(xa[0], xa[1]); ya[2] = at_two(ya[0], ya[1]);
+            xb[2] = at_two(xb[0], xb[1]); yb[2] = at_two(yb[0], yb[1]);
+            Fr c[9];
+            Fr p0[3], p2[3], pm[3], sa[3], sb[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              sa[k] = fr_add(xa[k], ya[k]);
+              sb[k] = fr_add(xb[k], yb[k]);
+            }
+            fr_mul_n<3>(xa, xb, p0);
+            fr_mul_n<3>(ya, yb, p2);
+            fr_mul_n<3>(sa, sb, pm);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              c[3 * k] = p0[k];
+              c[3 * k + 1] = fr_sub(fr_sub(pm[k], p0[k]), p2[k]);
+              c[3 * k + 2] = p2[k];
+            }
+            if (lane >= hh)
+#pragma unroll
+              for (int k = 0; k < 9; ++k) c[k] = fr_zero();
+            wave_sum<9>(c, hh);
+            if (lane == 0)
+#pragma unroll
+              for (int k = 0; k < 9; ++k) lds_put(coef[(j + 1) & 1][k / 3][k % 3], c[k]);
           }
         }
+        out += 96;
+        __syncthreads();
+      }
+      // the last challenge folds the single remaining pair into the finals
+      if (wave == 1 && lane == 0) {
+        const Fr rl = lds_get(rbuf[(P.n1 - 1) & 1]);
+        const Fr rl2[2] = {rl, rl}, d[2] = {fr_sub(A1, A0), fr_sub(B1, B0)};
+        Fr f[2];
+        fr_mul_n<2>(rl2, d, f);
+        lds_put(finv[0], fr_add(A0, f[0]));
+        lds_put(finv[1], fr_add(B0, f[1]));
+      }
+      __syncthreads();
+    }
+    if (wave == 0) {
+      Fr fa, fb;   // the product's final a~ and b~ (lane 0)
+      if (P.n1 > 0) {
+        fa = lds_get(finv[0]);
+        fb = lds_get(finv[1]);
       } else {   // no rounds (D1 = 1)
         fa = load_sol(a, ld, 0);
         fb = load_sol(b, ld, 0);
@@ -479,8 +598,6 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
         put_canon(out + 32, fin[1]);
         tr_absorb_frs(tr, VL_LBL_FINAL, fin);
       }
-    } else {
-      out += 96 * (P.n1 - rd);
     }
     out += 64;
     __syncthreads();
