@@ -193,7 +193,9 @@ __device__ __forceinline__ Fr round_challenge(Transcript& tr, const Fr (&g)[3], 
   Fr gc[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) gc[k] = readlane_fr(g[k], 0);
-  const Fr mine = lane == 0 ? gc[0] : (lane == 1 ? gc[1] : gc[2]);
+  Fr mine;   // word by word: a select of whole values goes through scratch memory
+#pragma unroll
+  for (int j = 0; j < 8; ++j) mine.w[j] = lane == 0 ? gc[0].w[j] : (lane == 1 ? gc[1].w[j] : gc[2].w[j]);
   if (lane < 3) put_canon(out + 32 * lane, mine);
   Fr r = fr_zero();
   if (lane == 0) {
