@@ -61,7 +61,7 @@ enum { VL_CONTRACT_ROWS = 0, VL_CONTRACT_COLS = 1 };
  * BATCHED, but the rounds workgroups (one per group) are launched first, on
  * an internal stream, and stay resident: each waits (bounded, see
  * vl_tuning.spin_limit) for its group's contractions, so the sumchecks of
- * early groups overlap the contractions of later ones.  At most 256 groups
+ * early groups overlap the contractions of later ones.  At most 128 groups
  * per call in this mode. */
 enum { VL_MODE_PER_INSTANCE = 0, VL_MODE_BATCHED = 1, VL_MODE_PERSISTENT = 2 };
 

@@ -13,7 +13,6 @@ constexpr int kContractBlock = 256;            // 4 waves, one task per wave
 constexpr uint32_t kChunkAlign = 32;           // contraction chunks start at multiples of 32
 constexpr uint32_t kMaxChunk = 1u << 16;       // int64 accumulators of int16 digits hold 2^16 entries
 constexpr uint32_t kWideSpill = 256;           // ... and of 24-bit digits 256 entries (products < 2^54)
-constexpr int kRoundsBlock = 256;
 
 // An eq table to build: out[i] = prod_j (x_j or 1 - x_j), i < 2^nvars, plus
 // its "pack" form used by the integer contractions (see contract kernel).

@@ -120,6 +120,12 @@ __device__ __forceinline__ void wave_sum(Fr (&v)[K], uint32_t width) {
   }
 }
 
+// rounds workgroup: 8 waves, two per SIMD, so that the global sweeps have a
+// second wave to issue from while one waits on its loads or its multiply
+// chains.  At up to 256 VGPRs per wave one such workgroup fills its CU's
+// register file.
+constexpr int kRoundsBlock = 512;
+
 // sum over the workgroup; the total lands in lanes 0..7 of wave 0 (the
 // transcript's lanes), the other lanes keep partial values
 template <int K>

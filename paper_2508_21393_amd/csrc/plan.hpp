@@ -28,7 +28,10 @@ struct Challenges {
 };
 
 constexpr uint32_t kMaxSegments = 8;
-constexpr uint64_t kMaxPersistentGroups = 256;
+// persistent mode: the resident rounds workgroups (each fills a CU's register
+// file) may hold at most half of the 256 CUs, the contractions they wait for
+// run on the rest
+constexpr uint64_t kMaxPersistentGroups = 128;
 constexpr uint32_t kDefaultSegments = 1;
 constexpr uint32_t kPersistentSegments = 4;
 
