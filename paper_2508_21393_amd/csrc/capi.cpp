@@ -382,8 +382,10 @@ void Builder::eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uin
     pts.insert(pts.end(), xm.w, xm.w + 8);
   }
   P.points.push_back(pts);
-  const uint32_t threads = std::max<uint32_t>(1, (uint32_t)((1ull << x.size()) / 2));
-  P.eq_threads += std::max(threads, (pack_len + 1) / 2);
+  // one thread per 4 entries (one for the whole table below 2 variables);
+  // pack_len <= 2^nvars
+  const uint32_t threads = std::max<uint32_t>(1, (uint32_t)((1ull << x.size()) / 4));
+  P.eq_threads += std::max(threads, (pack_len + 3) / 4);
   P.eq.push_back(e);
 }
 

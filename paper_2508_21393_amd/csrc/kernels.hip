@@ -29,37 +29,50 @@ __global__ void __launch_bounds__(256) eq_kernel(const EqJob* __restrict__ jobs,
     if (jobs[mid].thread_begin <= tid) lo = mid; else hi = mid;
   }
   const EqJob& J = jobs[lo];
-  const uint32_t t = tid - J.thread_begin;   // pair index: entries 2t and 2t+1
+  // thread t covers entries 4t .. 4t + 3 (the whole table when nvars < 2)
+  const uint32_t t = tid - J.thread_begin;
   const uint32_t n = J.nvars;
   const uint64_t len = 1ull << n;
-  Fr e0, e1;
-  if (n == 0) {
-    e0 = fr_R();
-    e1 = fr_zero();
+  auto point = [&](uint32_t j) {
+    Fr x;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x.w[k] = J.point[j * 8 + k];
+    return x;
+  };
+  Fr e[4];
+  if (n < 2) {
+    e[0] = n == 0 ? fr_R() : fr_sub(fr_R(), point(0));
+    e[1] = n == 0 ? fr_zero() : point(0);
+    e[2] = e[3] = fr_zero();
   } else {
-    // factor j is x_j for bit 1 and 1 - x_j for bit 0 (point: x_j only)
+    // factor j is x_j for bit 1 and 1 - x_j for bit 0 (b_1 the most
+    // significant bit): the first n - 2 come from t, shared by the four
+    // entries; the last two split the product into a tree of 2 + 4 products
     Fr base = fr_R();
-    for (uint32_t j = 0; j + 1 < n; ++j) {
-      const uint32_t bit = (t >> (n - 2 - j)) & 1u;
-      Fr x;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) x.w[k] = J.point[j * 8 + k];
-      base = fr_mul(base, bit ? x : fr_sub(fr_R(), x));
+    for (uint32_t j = 0; j + 2 < n; ++j) {
+      const Fr x = point(j);
+      const Fr f = ((t >> (n - 3 - j)) & 1u) ? x : fr_sub(fr_R(), x);
+      base = j == 0 ? f : fr_mul(base, f);
     }
-    Fr xl;
+    const Fr xa = point(n - 2), xb = point(n - 1);
+    const Fr bb[2] = {base, base}, fa[2] = {fr_sub(fr_R(), xa), xa}, fb[2] = {fr_sub(fr_R(), xb), xb};
+    Fr h[2], q0[2], q1[2];
+    fr_mul_n<2>(bb, fa, h);
+    const Fr h0[2] = {h[0], h[0]}, h1[2] = {h[1], h[1]};
+    fr_mul_n<2>(h0, fb, q0);
+    fr_mul_n<2>(h1, fb, q1);
+    e[0] = q0[0];
+    e[1] = q0[1];
+    e[2] = q1[0];
+    e[3] = q1[1];
+  }
+  const uint64_t i0 = 4ull * t;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) xl.w[k] = J.point[(n - 1) * 8 + k];
-    e0 = fr_mul(base, fr_sub(fr_R(), xl));
-    e1 = fr_mul(base, xl);
-  }
-  if (J.eq) {
-    if (2ull * t < len) store_sol(J.eq, J.eq_ld, 2ull * t, J.eq_canon ? fr_from_mont(e0) : e0);
-    if (2ull * t + 1 < len) store_sol(J.eq, J.eq_ld, 2ull * t + 1, J.eq_canon ? fr_from_mont(e1) : e1);
-  }
-  if (J.pack) {
+  for (uint32_t q = 0; q < 4; ++q) {
+    const uint64_t i = i0 + q;
+    if (J.eq && i < len) store_sol(J.eq, J.eq_ld, i, J.eq_canon ? fr_from_mont(e[q]) : e[q]);
     // pack: e * R^2 (or e * R) mod p as signed digits, 8 words per entry
-    if (2 * t < J.pack_len) signed_digits(J.pack_r2 ? fr_to_mont(e0) : e0, J.pack + (uint64_t)(2 * t) * 8);
-    if (2 * t + 1 < J.pack_len) signed_digits(J.pack_r2 ? fr_to_mont(e1) : e1, J.pack + (uint64_t)(2 * t + 1) * 8);
+    if (J.pack && i < J.pack_len) signed_digits(J.pack_r2 ? fr_to_mont(e[q]) : e[q], J.pack + i * 8);
   }
 }
 
