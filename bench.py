@@ -212,6 +212,12 @@ def serving_leg(B, n_requests, pool_size=6, n_slots=4, seed=5):
     gaps = np.random.default_rng([seed, 11]).exponential(1.0 / rate, size=n_requests)
     arrivals = [(float(t), i % pool_size) for i, t in enumerate(np.cumsum(gaps))]
     srv = serve.ProofServer(n_slots=n_slots, hbm_budget_bytes=64 << 30)
+    # warm the server (each slot's pinned buffers, the allocator's blocks):
+    # every pooled request once per slot, back to back, not timed
+    for i in range(n_slots * pool_size):
+        srv.submit(serve.Request(-1 - i, pool[i % pool_size], 1))
+    srv.drain()
+    srv.done.clear()
     results, wall = serve.run_open_loop(srv, arrivals,
                                         lambda i, k: serve.Request(i, pool[k], 7000 + i))
     for r in results[:3]:

@@ -2,16 +2,18 @@
 
 Proof requests (a list of groups with device-resident witnesses, and a seed)
 arrive over time.  The server keeps a fixed number of slots; each slot owns a
-HIP stream and, while busy, a device workspace and pinned host buffers for
-proofs and status.  A request is admitted when a slot is free and its device
+HIP stream and pinned host buffers for proofs and status (kept across
+requests and grown when a request needs more), and, while busy, a device
+workspace.  A request is admitted when a slot is free and its device
 memory (the workspace, plus its witness bytes if the caller says they are not
 yet counted) fits the HBM budget; otherwise it waits in FIFO order.  Admitted
 requests are enqueued with the asynchronous prove entry point, so requests on
 different slots overlap on the device; the kernels write proof bytes and
 status words straight into the pinned buffers (no copy-engine transfer, which
 would order the slots' streams behind each other).  Completion is found by
-polling HIP events, after which latency is recorded and the slot and its
-memory are released.
+polling HIP events, after which latency is recorded, the proof bytes are
+copied out of the slot's pinned buffer and the slot and its device memory are
+released.
 
 The arithmetic is untouched: a request's proof bytes depend only on its
 matrices, its seed and its group ids, so a result is identical alone and in
@@ -59,6 +61,17 @@ class _Slot:
         self.offs = None
         self.bytes = 0
         self.t_admit = 0.0
+        self.host_proofs = None                # pinned, reused by the slot's requests
+        self.host_status = None
+
+    def host_buffers(self, torch, n_bytes: int, n_status: int):
+        """Views of the slot's pinned buffers of at least the given sizes
+        (reallocated only when a request needs more than any before it)."""
+        if self.host_proofs is None or self.host_proofs.numel() < n_bytes:
+            self.host_proofs = torch.empty(n_bytes, dtype=torch.uint8, pin_memory=True)
+        if self.host_status is None or self.host_status.numel() < n_status:
+            self.host_status = torch.empty(n_status, dtype=torch.int32, pin_memory=True)
+        return self.host_proofs[:n_bytes], self.host_status[:n_status]
 
 
 class ProofServer:
@@ -101,8 +114,8 @@ class ProofServer:
             ws = torch.empty(max(256, B.workspace_size(req.groups, req.mode, async_=True)),
                              dtype=torch.uint8, device="cuda")
             total = sum(B.proof_size(g) for g in req.groups)
-            proofs = torch.empty(max(1, total), dtype=torch.uint8, pin_memory=True)
-            status = torch.empty(ng, dtype=torch.int32, pin_memory=True)
+            # the slot is free, so nothing still writes its pinned buffers
+            proofs, status = slot.host_buffers(torch, max(1, total), ng)
             status.numpy()[:] = -1
             # the slot's stream must see the allocations made on the current stream
             slot.stream.wait_stream(torch.cuda.current_stream())
@@ -150,7 +163,7 @@ class ProofServer:
                 time.sleep(sleep_s)
 
 
-def run_open_loop(server: ProofServer, arrivals, make_request, sleep_s: float = 0.0002):
+def run_open_loop(server: ProofServer, arrivals, make_request, sleep_s: float = 0.00005):
     """Feed requests at their arrival times (seconds from start) and run the
     server until all are done.  ``arrivals`` is a list of (t, payload);
     ``make_request(i, payload)`` returns a Request.  Returns the results in
