@@ -111,19 +111,22 @@ class ProofServer:
                 return                       # FIFO: wait for memory to free up
             self.queue.popleft()
             ng = len(req.groups)
-            ws = torch.empty(max(256, B.workspace_size(req.groups, req.mode, async_=True)),
-                             dtype=torch.uint8, device="cuda")
+            # the workspace comes from the slot's stream: freed when the slot
+            # is released, its block is at once reusable by the slot's next
+            # request (no cross-stream event, no new device allocation)
+            with torch.cuda.stream(slot.stream):
+                ws = torch.empty(max(256, B.workspace_size(req.groups, req.mode, async_=True)),
+                                 dtype=torch.uint8, device="cuda")
             total = sum(B.proof_size(g) for g in req.groups)
             # the slot is free, so nothing still writes its pinned buffers
             proofs, status = slot.host_buffers(torch, max(1, total), ng)
             status.numpy()[:] = -1
-            # the slot's stream must see the allocations made on the current stream
+            # the slot's stream must see the witnesses made on the current stream
             slot.stream.wait_stream(torch.cuda.current_stream())
             slot.offs = B.sumcheck_matmul_prove_async(req.groups, req.seed, proofs, status, ws,
                                                       mode=req.mode, stream=slot.stream)
             ev = torch.cuda.Event()
             ev.record(slot.stream)
-            ws.record_stream(slot.stream)
             slot.req, slot.event, slot.bufs, slot.bytes = req, ev, (ws, proofs, status), need
             slot.t_admit = time.perf_counter()
             self.in_use += need
