@@ -88,3 +88,26 @@ def test_open_loop_poisson_arrivals(env):
     assert summ["n"] == len(reqs) and summ["p99_ms"] >= summ["p50_ms"] > 0
     for r in results:
         assert r.proofs == B.sumcheck_matmul_prove(*reqs[r.rid], mode=B.VL_MODE_BATCHED)[0]
+
+
+def test_one_slot_reuses_and_grows_its_buffers(env):
+    B, serve = env
+    # one slot, requests of different sizes in turn: the slot's pinned buffers
+    # grow for the larger ones and are reused (and overwritten) by the others;
+    # each result must still be that request's own solo proof
+    reqs = _requests(B, 6)
+    order = [4, 3, 0, 5, 4, 1, 3]          # small, large, mid, large, small, ...
+    srv = serve.ProofServer(n_slots=1, hbm_budget_bytes=1 << 30)
+    for i, k in enumerate(order):
+        srv.submit(serve.Request(i, *reqs[k]))
+    srv.drain()
+    assert srv.peak_in_flight == 1
+    sizes = set()
+    for i, k in enumerate(order):
+        gs, seed = reqs[k]
+        expect = B.sumcheck_matmul_prove(gs, seed, mode=B.VL_MODE_BATCHED)[0]
+        assert srv.done[i].status == [0, 0]
+        assert srv.done[i].proofs == expect
+        sizes.add(sum(len(p) for p in expect))
+    assert len(sizes) >= 3
+    assert srv.slots[0].host_proofs.numel() == max(sizes)
