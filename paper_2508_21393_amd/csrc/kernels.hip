@@ -204,9 +204,78 @@ __device__ __forceinline__ Fr readlane_fr(const Fr& x, int l) {
 // (2 b - a) for the evaluation at X = 2 of the line through (0, a), (1, b)
 __device__ __forceinline__ Fr at_two(const Fr& a, const Fr& b) { return fr_sub(fr_double(b), a); }
 
+// absorb("round", g(0), g(1), g(2)) by the lanes of wave 0: the message
+// (the state, the label and the three canonical values, 133 bytes in three
+// SHA-256 blocks) has its three blocks' message schedules computed side by
+// side, lane b < 3 holding block b's, and every lane then runs the 3 x 64
+// compression rounds on those words (uniform values read with v_readlane).
+// The same digest as tr_absorb_frs; the state is taken from lane 0.
+__device__ __forceinline__ void absorb_round_lanes(Transcript& tr, const Fr (&gc)[3], uint32_t lane) {
+  constexpr int L = sizeof(VL_LBL_ROUND) - 1;
+  constexpr int N = 32 + L + 96;
+  constexpr int NB = (N + 9 + 63) / 64;
+  static_assert(NB == 3, "the round absorb is three blocks");
+  uint32_t st[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) st[i] = __builtin_amdgcn_readlane(tr.h[i], 0);
+  auto byte_at = [&](int k) -> uint32_t {
+    if (k < 32) return (st[k >> 2] >> (24 - 8 * (k & 3))) & 0xffu;
+    if (k < 32 + L) return (uint8_t)VL_LBL_ROUND[k - 32];
+    if (k < N) return fr_byte(gc[(k - 32 - L) >> 5], (k - 32 - L) & 31);
+    if (k == N) return 0x80u;
+    if (k >= NB * 64 - 8) return (uint32_t)(((uint64_t)N * 8) >> (8 * (NB * 64 - 1 - k))) & 0xffu;
+    return 0u;
+  };
+  const uint32_t blk = min(lane, 2u);
+  uint32_t w[64];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    uint32_t v[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      uint32_t x = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x |= byte_at(64 * b + 4 * i + q) << (24 - 8 * q);
+      v[b] = x;
+    }
+    w[i] = blk == 0 ? v[0] : (blk == 1 ? v[1] : v[2]);
+  }
+#pragma unroll
+  for (int i = 16; i < 64; ++i) {
+    const uint32_t w15 = w[i - 15], w2 = w[i - 2];
+    const uint32_t s0 = xor3_u32(rotr32(w15, 7), rotr32(w15, 18), w15 >> 3);
+    const uint32_t s1 = xor3_u32(rotr32(w2, 17), rotr32(w2, 19), w2 >> 10);
+    w[i] = add3_u32(w[i - 16], s0, w[i - 7]) + s1;
+  }
+  const uint32_t* K = sha256_k();
+#pragma unroll
+  for (int i = 0; i < 64; ++i) w[i] += K[i];
+  // a fresh SHA-256 hash: the chaining value starts at the initial hash value
+  uint32_t h[8] = {0x6a09e667u, 0xbb67ae85u, 0x3c6ef372u, 0xa54ff53au,
+                   0x510e527fu, 0x9b05688cu, 0x1f83d9abu, 0x5be0cd19u};
+#pragma unroll 1
+  for (uint32_t b = 0; b < (uint32_t)NB; ++b) {
+    uint32_t a = h[0], bb = h[1], c = h[2], dd = h[3], e = h[4], f = h[5], g = h[6], hh = h[7];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+      const uint32_t wk = __builtin_amdgcn_readlane(w[i], b);
+      const uint32_t S1 = xor3_u32(rotr32(e, 6), rotr32(e, 11), rotr32(e, 25));
+      const uint32_t ch = bitsel(e, f, g);
+      const uint32_t t1 = add3_u32(hh, S1, ch) + wk;
+      const uint32_t S0 = xor3_u32(rotr32(a, 2), rotr32(a, 13), rotr32(a, 22));
+      const uint32_t mj = maj_u32(a, bb, c);
+      hh = g; g = f; f = e; e = dd + t1; dd = c; c = bb; bb = a; a = add3_u32(t1, S0, mj);
+    }
+    h[0] += a; h[1] += bb; h[2] += c; h[3] += dd; h[4] += e; h[5] += f; h[6] += g; h[7] += hh;
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) tr.h[i] = h[i];
+}
+
 // One sumcheck round's messages and challenge, run by wave 0 (all its
 // lanes, g canonical and valid in lane 0): lane k < 3 writes g(k) to the
-// proof; lane 0 absorbs the three values and squeezes r.  Returns r in
+// proof; the wave absorbs the three values (all 64 lanes must be active:
+// lanes 1 and 2 hold message schedules) and lane 0 squeezes r.  Returns r in
 // Montgomery form in every lane of wave 0.
 __device__ __forceinline__ Fr round_challenge(Transcript& tr, const Fr (&g)[3], uint8_t* out, uint32_t lane) {
   Fr gc[3];
@@ -217,10 +286,8 @@ __device__ __forceinline__ Fr round_challenge(Transcript& tr, const Fr (&g)[3], 
   for (int j = 0; j < 8; ++j) mine.w[j] = lane == 0 ? gc[0].w[j] : (lane == 1 ? gc[1].w[j] : gc[2].w[j]);
   if (lane < 3) put_canon(out + 32 * lane, mine);
   Fr r = fr_zero();
-  if (lane == 0) {
-    tr_absorb_frs(tr, VL_LBL_ROUND, gc);
-    r = fr_to_mont(tr_squeeze_fixed(tr, VL_LBL_R));
-  }
+  absorb_round_lanes(tr, gc, lane);
+  if (lane == 0) r = fr_to_mont(tr_squeeze_fixed(tr, VL_LBL_R));
   return readlane_fr(r, 0);
 }
 
