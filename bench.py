@@ -157,6 +157,20 @@ def peak_rates():
     return {n: L.vlpeak_lane_ops_per_s(i, 8192, 4096) for i, n in enumerate(names)}
 
 
+def streaming_read_GBps(nbytes=4 << 30):
+    """A plain 16-byte streaming read of a 4 GiB device buffer (libvlpeak.so):
+    the practical HBM read ceiling the contraction kernels are set against."""
+    import ctypes
+    from paper_2508_21393_amd.build import PEAK_LIB
+    if not os.path.exists(PEAK_LIB):
+        return None
+    L = ctypes.CDLL(PEAK_LIB)
+    L.vlpeak_hbm_read_GBps.restype = ctypes.c_double
+    L.vlpeak_hbm_read_GBps.argtypes = [ctypes.c_uint64]
+    v = L.vlpeak_hbm_read_GBps(nbytes)
+    return v if v > 0 else None
+
+
 def autotune(B, gas, seed, mode, reps=3):
     """Time each launch shape of a small grid (results are identical for
     all of them) and return the fastest with the table of timings."""
@@ -431,6 +445,10 @@ def main():
                                                               (stage_avg[k] * 1e-3) / (CU * LANES_PER_CLK * CLOCK_HZ))
                                                 if stage_avg[k] > 0 else None}
                              for k, (b, e) in kinds.items()}}
+    if not args.no_peak:
+        rd = streaming_read_GBps()
+        roofline["streaming_read_GBps"] = rd
+        roofline["frac_of_streaming_read"] = achieved / rd if rd else None
 
     out = {
         "metric": METRIC, "value": macs * args.steps / elapsed, "unit": "Fr-MAC/s",
