@@ -174,3 +174,21 @@ def test_partial_eval_workspace_refuses_bad_tuning():
     assert B.partial_eval_workspace_size(64, 64, 0, np.int16, B.tuning(claim_order=3)) == 0
     assert B.partial_eval_workspace_size(64, 64, 0, np.int16, B.tuning(cols_rows=3)) == 0
     assert B.partial_eval_workspace_size(64, 64, 0, np.int16, B.tuning(claim_order=2)) > 0
+
+
+def test_persistent_mode_refuses_more_than_128_groups():
+    # each resident rounds workgroup fills its CU's register file, so the
+    # persistent mode leaves half the CUs to the contractions: the group limit
+    # is checked on the host, before any device work
+    import ctypes
+    L = _lib_or_skip()
+    ga = _host_args(workloads.tiny_random_group(1, [(4, 4, 4)]))
+    n = 129
+    arr = (type(ga.struct) * n)(*([ga.struct] * n))
+    opts = B.vl_prove_opts(B.VL_MODE_PERSISTENT, 0, 0x1000, 1 << 20, None, None, None)
+    offs = (ctypes.c_uint64 * (n + 1))()
+    proofs = ctypes.create_string_buffer(4096)
+    st = L.vl_sumcheck_matmul_prove(arr, n, 1, ctypes.byref(opts), ctypes.addressof(proofs), 4096, offs,
+                                    None, None)
+    assert st == B.VL_ERR_INVALID_ARG
+    assert "at most 128 groups" in B.last_error()
