@@ -530,7 +530,7 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
     //    (exact: the same field elements as a direct sum), writes them to the
     //    proof, absorbs them and squeezes r_j.
     // One barrier per round hands r_j to wave 1 and the coefficients to wave
-    // 0 (both double-buffered by round parity); waves 2 and 3 only take part
+    // 0 (both double-buffered by round parity); the other waves only take part
     // in the barriers.
     if (rd < P.n1) {
       const uint32_t rd0 = rd;
