@@ -15,8 +15,8 @@ Reports (one JSON line): algorithmic Fr MACs/s (value), proofs/s, p50/p99
 step latency, the per-instance prover on the same inputs, the dominant
 kernel against the HBM roofline (algorithmic matrix bytes over its
 HIP-event launch time in the timed steps) with every contraction kind's
-GB/s and fraction of the 32-bit multiply peak, and the CPU oracle on a
-bounded sample of the same workload.
+GB/s and fraction of the 32-bit multiply peak, and the CPU oracle on the
+same block (every group, one worker process per host core).
 """
 import argparse
 import gc
@@ -125,24 +125,61 @@ def measured_traffic(stage_name):
     return None
 
 
-def cpu_baseline(workload, budget_s=15.0):
-    """The oracle, unmodified, single-threaded, on the cheapest groups of the
-    same workload until the time budget is used."""
-    import oracle  # noqa: F401
+_CPU_W = None
+
+
+def _cpu_prove(i):
     from oracle.zkmat import prove_workload_group
-    order = sorted(workload.groups, key=lambda g: algorithmic_macs([g.shapes]))
+    g = _CPU_W.groups[i]
+    t = time.perf_counter()
+    prove_workload_group(g, _CPU_W.seed)
+    return i, time.perf_counter() - t
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores(cap=16):
+    """CPU threads this process may use: its affinity set, at most `cap`
+    (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(cap, n))
+
+
+def cpu_baseline(workload, procs=None):
+    """The oracle, unmodified, on every group of the same block: one process
+    per host core (forked workers that share the witness arrays), largest
+    groups first, wall time from the first group to the last.  Witness
+    generation is not timed.  The workers only run Python integer arithmetic
+    and hashlib (nothing touches the GPU)."""
+    import multiprocessing as mp
+    import oracle  # noqa: F401
+    global _CPU_W
+    _CPU_W = workload
+    procs = procs or host_cores()
+    order = sorted(range(len(workload.groups)), key=lambda i: -algorithmic_macs([workload.groups[i].shapes]))
+    macs = algorithmic_macs([g.shapes for g in workload.groups])
     t0 = time.perf_counter()
-    macs, names = 0, []
-    for g in order:
-        if time.perf_counter() - t0 > budget_s:
-            break
-        prove_workload_group(g, workload.seed)
-        macs += algorithmic_macs([g.shapes])
-        names.append(g.name)
+    with mp.get_context("fork").Pool(procs) as pool:
+        res = pool.map(_cpu_prove, order, chunksize=1)
     dt = time.perf_counter() - t0
-    return {"value": macs / dt, "unit": "Fr-MAC/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(names)} of {len(workload.groups)} groups of the same block "
-                      f"(cheapest first: {', '.join(names)}), {macs / 1e6:.1f} M MACs in {dt:.1f} s"}
+    busy = sum(t for _, t in res)
+    return {"value": macs / dt, "unit": "Fr-MAC/s", "cores": procs, "kind": "oracle",
+            "sample": f"{len(res)} of {len(workload.groups)} groups of the same block (the whole block, "
+                      f"{macs / 1e6:.1f} M MACs) in {dt:.1f} s wall on {procs} worker processes "
+                      f"({busy:.1f} core-s of proving, {macs / busy / 1e6:.1f} M Fr-MAC/s per core); "
+                      f"host CPU: {cpu_model()}, {os.cpu_count()} logical CPUs visible, "
+                      f"{host_cores(1 << 30)} in this process's affinity set"}
 
 
 def peak_rates():

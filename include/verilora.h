@@ -57,12 +57,18 @@ typedef enum { VL_I16 = 1, VL_I32 = 2, VL_I64 = 3 } vl_dtype;
 
 enum { VL_CONTRACT_ROWS = 0, VL_CONTRACT_COLS = 1 };
 /* PER_INSTANCE: each group planned and launched on its own, one after the
- * other.  BATCHED: all groups in one launch per stage.  PERSISTENT: like
- * BATCHED, but the rounds workgroups (one per group) are launched first, on
- * an internal stream, and stay resident: each waits (bounded, see
+ * other.  BATCHED: all groups in one launch per stage.  PERSISTENT
+ * (experimental, slower than BATCHED on the 7B-class block): like BATCHED,
+ * but the rounds workgroups (one per group) are launched first, on an
+ * internal stream, and stay resident: each waits (bounded, see
  * vl_tuning.spin_limit) for its group's contractions, so the sumchecks of
- * early groups overlap the contractions of later ones.  At most 128 groups
- * per call in this mode. */
+ * early groups overlap the contractions of later ones.  This needs the
+ * internal stream and the caller's stream on different hardware queues and
+ * free CUs for the contractions; if they share a queue the rounds give up
+ * after spin_limit polls with VL_ERR_TIMEOUT.  At most 128 groups per call,
+ * and at most one persistent call per device at a time: a call made while
+ * another persistent call is still running on the device runs in BATCHED
+ * mode instead (same bytes). */
 enum { VL_MODE_PER_INSTANCE = 0, VL_MODE_BATCHED = 1, VL_MODE_PERSISTENT = 2 };
 
 typedef struct { uint32_t w[8]; } vl_fr;
@@ -163,7 +169,17 @@ typedef struct {
 #define VL_STAGE_COUNT 24
 
 /* Lift n signed integers (dtype) at device pointer src into Fr (Montgomery,
- * structure-of-limbs) at dst (dst.n >= n).  Negative x becomes p - |x|. */
+ * structure-of-limbs) at dst (dst.n >= n).  Negative x becomes p - |x|.
+ * The quantised tensors of a LoRA step hold signed fixed-point values from a
+ * bounded domain F_B = {-B/2, ..., B/2 - 1} of the field (Sec. IV-A,
+ * zkSwiGLU, which quantises with a scale factor zeta); the field element of
+ * such an x is x mod p, so that sums and products of lifted values are the
+ * lifted integer sums and products (eq. (matmul) then holds in F exactly when
+ * it holds over the integers without wrap-around).  The prove call performs
+ * the same lift inside its contraction kernels; this entry point
+ * materialises it for small tensors and tests.
+ * Errors: VL_ERR_INVALID_ARG (null src or dst.base), VL_ERR_DTYPE,
+ * VL_ERR_SHAPE (dst.n < n or dst.ld < dst.n), VL_ERR_HIP (launch). */
 vl_status vl_fr_lift(const void* src, int32_t dtype, uint64_t n, vl_fr_vec dst, void* stream);
 
 /* Convert n elements of a device vl_fr_vec to canonical form, written
@@ -229,8 +245,10 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n_groups, ui
  *   stage_ms), fills offsets, and captures every launch with
  *   the workspace, proofs, opts->status and digests addresses fixed; the
  *   caller keeps those buffers, and the matrices the groups point to, alive
- *   and unused by other work until destroy.  The group descriptors are
- *   copied: a launch reads the matrices at the same addresses.
+ *   and unused by other work until destroy.  The group and product
+ *   descriptors are copied (deep): the caller may free or reuse its vl_group
+ *   and vl_product arrays after create; a launch reads the matrices at the
+ *   same addresses.
  * launch: proves the groups' current matrix contents for seed on stream,
  *   asynchronously, with bytes identical to vl_sumcheck_matmul_prove.  The
  *   host rebuilds the descriptor blob (challenges depend on the seed and
@@ -248,13 +266,26 @@ vl_status vl_prove_graph_create(const vl_group* groups, uint64_t n_groups, const
 vl_status vl_prove_graph_launch(vl_prove_graph* graph, uint64_t seed, void* stream);
 void vl_prove_graph_destroy(vl_prove_graph* graph);
 
-/* Host-side verifier (CPU only).  Replays the transcript for (shape, seed,
- * group_id), checks g(0) + g(1) against the running claim in every round,
- * moves the claim to g(r) by interpolation on {0, 1, 2}, and checks the last
- * claim against a_final * b_final.  If the group's A, B (every product) and C
- * pointers are all non-NULL they are read as HOST matrices and c = C~(u, v),
- * a_final = A~(u, r), b_final = B~(r, v) are also checked by direct
- * evaluation (commitment openings are out of scope).
+/* Host-side verifier (CPU only) of the sumcheck of eq. (zk-mle-matmul)
+ * (Sec. II-C).  Replays the Fiat-Shamir transcript for (shape, seed,
+ * group_id) -- every challenge is a hash of all earlier public messages (the
+ * Fiat-Shamir footnote of Sec. IV-A, random-oracle model of Sec. V) -- and
+ * runs the verifier's side of the sumcheck rounds (Sec. II-B.1): g(0) + g(1)
+ * must equal the running claim in every round, the claim then moves to g(r)
+ * by interpolation on {0, 1, 2}, and the last claim must equal
+ * a_final * b_final, the product of the two evaluations at the random point
+ * that ends eq. (zk-mle-matmul)'s protocol.  If the group's A, B (every
+ * product) and C pointers are all non-NULL they are read as HOST matrices and
+ * c = C~(u, v), a_final = A~(u, r), b_final = B~(r, v) are also checked by
+ * direct evaluation of eq. (MLE), standing in for the commitment openings of
+ * Sec. II-A, which are out of scope.
+ * Soundness without commitments: u and v are squeezed from (seed, group_id,
+ * shapes) alone, before any message that depends on C, A or B.  In the paper
+ * the verifier draws them after the prover has committed to the matrices
+ * (Sec. II-A, II-C).  Here nothing binds C before u and v are known, so the
+ * witness check does not rule out a false C' = AB + D with D~(u, v) = 0 that
+ * a prover chose after seeing u and v; it binds the proof to the matrices only
+ * once a commitment (or a digest of the witness) is absorbed before u and v.
  *   reduced : optional host output of the reduced claims, canonical:
  *             c, u[n0], v[n2], then per product r[n1], a_final, b_final
  *   reduced_len : elements written (or needed, on VL_ERR_BUFFER_TOO_SMALL)

@@ -198,26 +198,73 @@ static vl_status device_writable(void* p, const char* what) {
   return fail(VL_ERR_INVALID_ARG, "%s: neither device memory nor identity-mapped pinned host memory", what);
 }
 
-// The rounds stream paired with a caller's stream (default priority), created
-// on first use and kept for the life of the process.
+// The rounds stream paired with a caller's stream: one of a fixed pool of
+// kRoundsStreams internal streams per device (default priority), created on
+// first use and kept for the life of the process.  Caller streams are given
+// pool streams round-robin in the order they are first seen, so a handful of
+// concurrent callers get distinct rounds streams while the number of streams
+// the library holds stays bounded however many caller streams come and go.
+// Two callers that share a rounds stream stay correct (every call forks and
+// joins through events); their rounds stages then run one after the other.
+constexpr int kRoundsStreams = 8;
+
 hipError_t rounds_stream_for(hipStream_t s, hipStream_t* out) {
+  struct Pool {
+    hipStream_t st[kRoundsStreams] = {};
+    std::map<hipStream_t, int> of;   // caller stream -> pool index
+    int next = 0;
+  };
   static std::mutex mu;
-  static std::map<std::pair<int, hipStream_t>, hipStream_t> streams;
+  static std::map<int, Pool> pools;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   std::lock_guard<std::mutex> lock(mu);
-  auto it = streams.find({dev, s});
-  if (it != streams.end()) {
-    *out = it->second;
-    return hipSuccess;
+  Pool& P = pools[dev];
+  auto it = P.of.find(s);
+  int k;
+  if (it != P.of.end()) {
+    k = it->second;
+  } else {
+    if (P.of.size() >= 256) P.of.clear();   // forget old caller streams (indices only)
+    k = P.next;
+    P.next = (P.next + 1) % kRoundsStreams;
+    P.of[s] = k;
   }
-  hipStream_t s2;
-  e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
-  if (e != hipSuccess) return e;
-  streams[{dev, s}] = s2;
-  *out = s2;
+  if (!P.st[k]) {
+    e = hipStreamCreateWithFlags(&P.st[k], hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      P.st[k] = nullptr;
+      return e;
+    }
+  }
+  *out = P.st[k];
   return hipSuccess;
+}
+
+// Persistent mode's resident rounds workgroups spin until the contractions of
+// their groups have run.  That needs the contractions to be dispatched while
+// the rounds workgroups wait: on a free hardware queue (the rounds stream and
+// the caller's stream must not share one) and on CUs the resident workgroups
+// leave free.  A second persistent call in flight on the same device would
+// put up to 2 x 128 spinning workgroups on the 256 CUs, so at most one
+// persistent call runs per device at a time: a call that finds another one
+// still running on its device (its completion event not yet reached, or its
+// host thread still enqueueing) runs in batched mode instead, which yields
+// the same bytes.
+struct PersistentGate {
+  std::mutex mu;
+  hipEvent_t done = nullptr;
+  bool issued = false;
+};
+
+static PersistentGate& persistent_gate(int dev) {
+  static std::mutex mu;
+  static std::map<int, PersistentGate*> gates;   // per device, live for the process
+  std::lock_guard<std::mutex> lock(mu);
+  PersistentGate*& g = gates[dev];
+  if (!g) g = new PersistentGate();
+  return *g;
 }
 
 uint64_t proof_elems(const vl_group& g) {
@@ -871,8 +918,39 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   uint8_t* ws = reinterpret_cast<uint8_t*>(o->workspace);
-  const Tuning T = tuning_for(o);
+  Tuning T = tuning_for(o);
   const bool async = o->async != 0;
+  // persistent mode: one call per device at a time (see PersistentGate); the
+  // gate's lock is held until this call's work is enqueued and its
+  // completion event recorded
+  std::unique_lock<std::mutex> gate_lock;
+  PersistentGate* gate = nullptr;
+  if (T.persistent) {
+    int dev = 0;
+    const hipError_t de = hipGetDevice(&dev);
+    if (de != hipSuccess) return fail(VL_ERR_HIP, "device: %s", hipGetErrorString(de));
+    PersistentGate& pg = persistent_gate(dev);
+    gate_lock = std::unique_lock<std::mutex>(pg.mu, std::try_to_lock);
+    bool free = gate_lock.owns_lock();
+    if (free && pg.issued) {
+      const hipError_t q = hipEventQuery(pg.done);
+      if (q == hipErrorNotReady) {
+        free = false;
+      } else if (q != hipSuccess) {
+        return fail(VL_ERR_HIP, "persistent gate: %s", hipGetErrorString(q));
+      }
+    }
+    if (free) {
+      gate = &pg;
+      if (!pg.done) {
+        const hipError_t ce = hipEventCreateWithFlags(&pg.done, hipEventDisableTiming);
+        if (ce != hipSuccess) return fail(VL_ERR_HIP, "persistent gate: %s", hipGetErrorString(ce));
+      }
+    } else {
+      if (gate_lock.owns_lock()) gate_lock.unlock();
+      T.persistent = false;   // batched, same bytes
+    }
+  }
   Plan P;
   // stage timing events: a pool per host thread and device, kept for the
   // process (events belong to the device they were created on)
@@ -935,7 +1013,13 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
       const hipError_t e2 = rounds_stream_for(s, &s2);
       if (e2 != hipSuccess) return fail(VL_ERR_HIP, "rounds stream: %s", hipGetErrorString(e2));
     }
-    const hipError_t e = enqueue_plan(P, L, ws, s, s2, ev);
+    hipError_t e = enqueue_plan(P, L, ws, s, s2, ev);
+    if (e == hipSuccess && gate) {
+      // the caller's stream has joined the rounds stream: its position now
+      // marks the end of this persistent call
+      e = hipEventRecord(gate->done, s);
+      if (e == hipSuccess) gate->issued = true;
+    }
     if (e != hipSuccess) {
       // what was enqueued before the failure may still write the outputs
       // (the pinned buffer the next blocking call reuses): let it finish
@@ -1005,6 +1089,7 @@ vl_status vl_eq_table(const vl_fr* point, uint32_t nvars, vl_fr_vec out, void* s
 struct vl_prove_graph {
   int device = 0;
   std::vector<vl_group> groups;
+  std::vector<vl_product> prods;   // the groups' products, owned by the handle
   vl_prove_opts opts{};
   vl_tuning tuning{};
   bool has_tuning = false;
@@ -1062,7 +1147,19 @@ vl_status vl_prove_graph_create(const vl_group* groups, uint64_t n, const vl_pro
   }
   vl_prove_graph* g = new vl_prove_graph();
   hipError_t e = hipGetDevice(&g->device);
+  // deep copy: every launch re-plans from these descriptors, so the caller
+  // may free or reuse its own group and product arrays after create
   g->groups.assign(groups, groups + n);
+  {
+    uint64_t np = 0;
+    for (uint64_t i = 0; i < n; ++i) np += groups[i].n_prods;
+    g->prods.reserve(np);
+    for (uint64_t i = 0; i < n; ++i) {
+      const size_t at = g->prods.size();
+      g->prods.insert(g->prods.end(), groups[i].prods, groups[i].prods + groups[i].n_prods);
+      g->groups[i].prods = g->prods.data() + at;   // no reallocation: reserved above
+    }
+  }
   g->opts = *o;
   if (o->tuning) {
     g->tuning = *o->tuning;
@@ -1083,12 +1180,17 @@ vl_status vl_prove_graph_create(const vl_group* groups, uint64_t n, const vl_pro
   if (e == hipSuccess) e = hipHostMalloc(&g->pinned, L.total, hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostGetDevicePointer(&g->pinned_dev, g->pinned, 0);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&g->done, hipEventDisableTiming);
-  // capture on a stream of our own (and, for segmented or persistent plans,
-  // the rounds stream paired with it, created before the capture starts)
-  hipStream_t cs = nullptr, s2 = nullptr;
+  // capture on a stream of our own (and, for segmented plans, a second
+  // private stream for the rounds, created before the capture starts: not one
+  // of the shared rounds streams, which other threads may be using for eager
+  // calls while this one captures)
+  hipStream_t cs = nullptr, s2 = nullptr, own2 = nullptr;
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   s2 = cs;
-  if (e == hipSuccess && (P.seg.size() > 1 || P.persistent)) e = rounds_stream_for(cs, &s2);
+  if (e == hipSuccess && (P.seg.size() > 1 || P.persistent)) {
+    e = hipStreamCreateWithFlags(&own2, hipStreamNonBlocking);
+    if (e == hipSuccess) s2 = own2;
+  }
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
   if (e == hipSuccess) {
     const hipError_t e1 = enqueue_plan(P, L, reinterpret_cast<uint8_t*>(g->opts.workspace), cs, s2, nullptr,
@@ -1098,6 +1200,7 @@ vl_status vl_prove_graph_create(const vl_group* groups, uint64_t n, const vl_pro
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
   if (cs) (void)hipStreamDestroy(cs);
+  if (own2) (void)hipStreamDestroy(own2);
   if (e != hipSuccess) {
     graph_free(g);
     return fail(VL_ERR_HIP, "prove graph: %s", hipGetErrorString(e));

@@ -93,6 +93,10 @@ class ProofServer:
 
     # -- queue ----------------------------------------------------------------
     def submit(self, req: Request):
+        if req.mode == B.VL_MODE_PERSISTENT:
+            # resident spinning rounds workgroups of several slots would hold
+            # CUs and hardware queues that the other slots' contractions need
+            raise ValueError("the server runs requests in batched mode; persistent mode is refused")
         if not req.t_arrive:
             req.t_arrive = time.perf_counter()
         if self.request_bytes(req) > self.budget:

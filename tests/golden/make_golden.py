@@ -3,11 +3,12 @@
 Only ``oracle`` and ``workloads`` are used: every stored value is what the
 oracle computes for the seeded synthetic inputs.  Usage:
 
-    python tests/golden/make_golden.py [cfg1 tiny cfg2 cfg3 cfg4] [--procs N]
+    python tests/golden/make_golden.py [cfg1 cfg1_sweep tiny cfg2 cfg3 cfg4 cfg5] [--procs N]
 
 Each config file lists, per group: name, group id, shapes, the SHA-256 of the
 proof bytes and the final transcript state; small configs also keep the full
-proof in hex.
+proof in hex.  cfg5 lists the requests of the 13B-class serving sample
+(workloads.serving_sample), each with its seed and its groups.
 """
 import argparse
 import hashlib
@@ -85,6 +86,50 @@ def tiny_groups():
     return workloads.Workload("tiny parity cases", 1234, out)
 
 
+N_CFG5 = 14   # requests of the 13B-class serving sample (workloads.serving_sample)
+
+_JOBS = None
+
+
+def _prove_job(i):
+    w, gi = _JOBS[i]
+    g = w.groups[gi]
+    t = time.time()
+    proof, state, _ = prove_workload_group(g, w.seed)
+    return i, proof, state, time.time() - t
+
+
+def record_cfg5(procs: int):
+    """The serving sample at 13B-class shapes: every group of every request,
+    proved by the oracle with the request's own seed."""
+    global _JOBS
+    specs = workloads.serving_sample(N_CFG5)
+    weights = {}
+    reqs = [workloads.serving_sample_workload(k, sp, weights) for k, sp in enumerate(specs)]
+    _JOBS = [(w, gi) for w in reqs for gi in range(len(w.groups))]
+    idx = sorted(range(len(_JOBS)), key=lambda i: -sum(d0 * d1 + d1 * d2 + d0 * d2 for d0, d1, d2 in
+                                                        _JOBS[i][0].groups[_JOBS[i][1]].shapes))
+    if procs > 1:
+        with mp.get_context("fork").Pool(procs) as pool:
+            res = pool.map(_prove_job, idx, chunksize=1)
+    else:
+        res = [_prove_job(i) for i in idx]
+    by_job = {i: (proof, state, dt) for i, proof, state, dt in res}
+    out, j = [], 0
+    for k, (sp, w) in enumerate(zip(specs, reqs)):
+        groups = []
+        for g in w.groups:
+            proof, state, dt = by_job[j]
+            j += 1
+            groups.append(dict(name=g.name, group_id=g.group_id, shapes=[list(x) for x in g.shapes],
+                               proof_sha256=hashlib.sha256(proof).hexdigest(), state=state.hex(),
+                               proof_len=len(proof)))
+            print(f"  req{k:<2d} {g.name:34s} {g.shapes} {dt:7.1f}s", flush=True)
+        out.append(dict(request=k, target=sp[0], T=sp[1], rank=sp[2], kind=sp[3], seed=w.seed,
+                        workload=w.name, groups=groups))
+    return dict(workload="13B-class serving sample (hidden 5120, FFN 13824)", n=N_CFG5, requests=out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("configs", nargs="*", default=["cfg1", "tiny", "cfg2", "cfg3"])
@@ -93,6 +138,12 @@ def main():
     for name in args.configs:
         t = time.time()
         print(f"{name}: generating", flush=True)
+        if name == "cfg5":
+            data = record_cfg5(args.procs)
+            with open(os.path.join(HERE, "cfg5.json"), "w") as f:
+                json.dump(data, f, indent=1)
+            print(f"{name}: done in {time.time() - t:.1f}s", flush=True)
+            continue
         if name == "tiny":
             w = tiny_groups()
         elif name == "cfg1_sweep":

@@ -126,6 +126,28 @@ def test_mle_partial_eval_strided_cols(B, rows, cols, ld, lane_macs):
     assert _export(B, out, L) == oracle.partial_eval_cols(big[:, :cols], pt)
 
 
+@pytest.mark.parametrize("rows,cols,ld", [(130, 777, 784), (256, 4096, 4096), (300, 1030, 1032), (129, 64, 64)])
+def test_mle_partial_eval_cols_two_rows_per_lane(B, rows, cols, ld):
+    # vl_tuning.cols_rows = 2: the int16 column kernel with two rows per lane
+    # (reached only through tuning), ragged last row pair and strided rows
+    import torch
+    _say(f"partial_eval cols_rows=2 rows={rows} cols={cols} ld={ld}")
+    rng = np.random.default_rng(rows * 13 + cols)
+    big = rng.integers(-(1 << 15), 1 << 15, size=(rows, ld), dtype=np.int64).astype(np.int16)
+    Md = to_dev(big)[:, :cols]
+    nv = oracle.num_vars(cols)
+    prng = random.Random(cols + 1)
+    pt = [prng.randrange(oracle.P) for _ in range(nv)]
+    eq = torch.empty((8, 1 << nv), dtype=torch.int32, device="cuda")
+    B.eq_table(pt, B.fr_vec(eq))
+    L = 1 << oracle.num_vars(rows)
+    out = torch.full((8, L), 7, dtype=torch.int32, device="cuda")
+    tn = B.tuning(cols_rows=2)
+    ws = torch.empty(B.partial_eval_workspace_size(rows, cols, 1, np.int16, tn), dtype=torch.uint8, device="cuda")
+    B.mle_partial_eval(Md, 1, B.fr_vec(eq), B.fr_vec(out), ws, tuning_=tn)
+    assert _export(B, out, L) == oracle.partial_eval_cols(big[:, :cols], pt)
+
+
 def _prove(B, w, mode):
     gs = [device_group(g, B) for g in w.groups]
     return B.sumcheck_matmul_prove(gs, w.seed, mode=mode)
@@ -218,6 +240,35 @@ def test_claim_order_matches_oracle_bytes(B, order):
     for g, pr, dg, gold in zip(w.groups, proofs, digests, spec["groups"]):
         assert pr.hex() == gold["proof_hex"], g.name
         assert dg.hex() == gold["state"], g.name
+
+
+def test_two_rows_per_lane_tiny_cases(B):
+    # cols_rows = 2 with the claim over the columns of C: the int16 and the
+    # two-digit int64 column kernels with two rows per lane where a
+    # contraction has >= 128 outputs
+    w, spec = tiny_workload()
+    _say("tiny cases cols_rows=2 claim_order=1")
+    gs = [device_group(g, B) for g in w.groups]
+    proofs, digests = B.sumcheck_matmul_prove(gs, w.seed, mode=1, tuning_=B.tuning(cols_rows=2, claim_order=1))
+    for g, pr, dg, gold in zip(w.groups, proofs, digests, spec["groups"]):
+        assert pr.hex() == gold["proof_hex"], g.name
+        assert dg.hex() == gold["state"], g.name
+
+
+@pytest.mark.parametrize("knobs", [dict(cols_rows=2, claim_order=1), dict(lane_macs=4096),
+                                   dict(lane_macs=16384)])
+def test_tuned_launch_shapes_full_size_cfg3(B, knobs):
+    # launch shapes the autotuner may pick, at full size: the proof bytes
+    # must still be the oracle's
+    _say(f"cfg3 tuned {knobs}: generating")
+    w = workloads.make_config("cfg3")
+    gold = golden("cfg3")
+    gs = [device_group(g, B) for g in w.groups]
+    _say(f"cfg3 tuned {knobs}: proving")
+    proofs, digests = B.sumcheck_matmul_prove(gs, w.seed, mode=1, tuning_=B.tuning(**knobs))
+    for g, pr, dg, rec in zip(w.groups, proofs, digests, gold["groups"]):
+        assert sha(pr) == rec["proof_sha256"], g.name
+        assert dg.hex() == rec["state"], g.name
 
 
 def test_claim_order_full_size_cfg3(B):
@@ -358,6 +409,35 @@ def test_prove_graph_full_size_cfg3(B):
             (x * 2).sum().item()
 
 
+def test_prove_graph_owns_its_descriptors(B):
+    # the caller's product descriptors are overwritten (every field zero)
+    # after create: the graph keeps its own copies, so its launches still
+    # prove the same matrices
+    import torch
+    w, spec = tiny_workload()
+    gs = [device_group(g, B) for g in w.groups]
+    batch = B.GroupBatch(gs)
+    total = batch.total
+    proofs = torch.zeros(total, dtype=torch.uint8, device="cuda")
+    status = torch.full((len(gs),), -1, dtype=torch.int32, device="cuda")
+    ws = torch.empty(B.workspace_size(batch, 1, async_=True), dtype=torch.uint8, device="cuda")
+    _say("prove graph: descriptors overwritten after create")
+    with B.ProveGraph(batch, ws, proofs, status) as G:
+        for ga in gs:
+            for k in range(len(ga.prods)):
+                ga.prods[k] = B.vl_product()
+        for i in range(len(batch.arr)):
+            batch.arr[i] = B.vl_group()
+        for rep in range(2):
+            proofs.zero_()
+            G.launch(w.seed)
+            torch.cuda.synchronize()
+            assert status.cpu().tolist() == [0] * len(gs)
+            raw = proofs.cpu().numpy().tobytes()
+            for i, gold in enumerate(spec["groups"]):
+                assert raw[G.offsets[i]:G.offsets[i + 1]].hex() == gold["proof_hex"], (rep, i)
+
+
 @pytest.mark.parametrize("mode", [0, 2])
 def test_prove_graph_refuses_other_modes(B, mode):
     import torch
@@ -394,6 +474,33 @@ def test_persistent_mode_full_size_cfg3(B):
         for g, pr, dg, rec in zip(w.groups, proofs, digests, gold["groups"]):
             assert sha(pr) == rec["proof_sha256"], g.name
             assert dg.hex() == rec["state"], g.name
+
+
+def test_persistent_calls_in_flight_fall_back_to_batched(B):
+    # two asynchronous persistent calls on two streams: the second finds the
+    # first still running on the device (or not; either way) and both prove
+    # the oracle's bytes
+    import torch
+    w, spec = tiny_workload()
+    gs = [device_group(g, B) for g in w.groups]
+    batch = B.GroupBatch(gs)
+    outs = []
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    _say("persistent: two calls in flight")
+    for s in streams:
+        proofs = torch.zeros(batch.total, dtype=torch.uint8, device="cuda")
+        status = torch.full((len(gs),), -1, dtype=torch.int32, device="cuda")
+        ws = torch.empty(B.workspace_size(batch, B.VL_MODE_PERSISTENT, async_=True), dtype=torch.uint8,
+                         device="cuda")
+        offs = B.sumcheck_matmul_prove_async(batch, w.seed, proofs, status, ws, mode=B.VL_MODE_PERSISTENT,
+                                             stream=s)
+        outs.append((proofs, status, offs, ws))
+    torch.cuda.synchronize()
+    for proofs, status, offs, _ in outs:
+        assert status.cpu().tolist() == [0] * len(gs)
+        raw = proofs.cpu().numpy().tobytes()
+        for i, gold in enumerate(spec["groups"]):
+            assert raw[offs[i]:offs[i + 1]].hex() == gold["proof_hex"]
 
 
 def test_persistent_spin_limit_reports_timeout(B):

@@ -1,8 +1,16 @@
-"""Continuous-batching server: each result is the same alone and in the mix."""
-import numpy as np
+"""Continuous-batching server: each result is the oracle's proof, alone and in the mix.
+
+Every served proof is compared with the CPU oracle's bytes for the same
+request (tiny shapes here, proved by the oracle in milliseconds), never with
+another GPU result.  The 13B-class sample (tests/test_gpu_cfg5.py) does the
+same at full size against stored oracle digests.
+"""
+import functools
+
 import pytest
 
 import workloads
+from oracle.zkmat import prove_workload_group
 from gpu_util import device_group
 
 pytestmark = pytest.mark.gpu
@@ -18,7 +26,8 @@ def env():
     return binding, serve
 
 
-def _requests(B, n=8):
+def _host_requests(n=8):
+    """(list of workloads.Group, seed) per request; every request has two groups."""
     reqs = []
     for i in range(n):
         dims = [[(64, 128, 32)], [(70, 33, 130)], [(17, 64, 9), (17, 3, 9)], [(300, 520, 129)],
@@ -26,14 +35,26 @@ def _requests(B, n=8):
         g = workloads.tiny_random_group(100 + i, dims, trans=(i % 2 == 1, i % 3 == 0), name=f"r{i}")
         g2 = workloads.tiny_random_group(200 + i, [(33, 40, 20)], name=f"s{i}")
         g.group_id, g2.group_id = 0, 1
-        reqs.append(([device_group(g, B), device_group(g2, B)], 1000 + i))
+        reqs.append(([g, g2], 1000 + i))
     return reqs
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_bytes(i):
+    """The oracle's proofs of request i (request i does not depend on n)."""
+    groups, seed = _host_requests(i + 1)[i]
+    return [prove_workload_group(g, seed)[0] for g in groups]
+
+
+def _requests(B, n=8):
+    return [([device_group(g, B) for g in gs], seed) for gs, seed in _host_requests(n)]
 
 
 def test_results_identical_alone_and_in_the_mix(env):
     B, serve = env
     reqs = _requests(B)
-    alone = [B.sumcheck_matmul_prove(gs, seed, mode=B.VL_MODE_BATCHED)[0] for gs, seed in reqs]
+    for i, (gs, seed) in enumerate(reqs):
+        assert B.sumcheck_matmul_prove(gs, seed, mode=B.VL_MODE_BATCHED)[0] == _oracle_bytes(i)
     srv = serve.ProofServer(n_slots=3, hbm_budget_bytes=1 << 30)
     for i, (gs, seed) in enumerate(reqs):
         srv.submit(serve.Request(i, gs, seed))
@@ -42,17 +63,18 @@ def test_results_identical_alone_and_in_the_mix(env):
     for i in range(len(reqs)):
         r = srv.done[i]
         assert r.status == [0, 0]
-        assert r.proofs == alone[i]
+        assert r.proofs == _oracle_bytes(i)
 
 
 def test_budget_limits_admission(env):
     B, serve = env
     # four requests of one shape (other seeds): a budget of one request's bytes
     # admits exactly one at a time
-    reqs = []
+    host = []
     for i in range(4):
         g = workloads.tiny_random_group(300 + i, [(64, 128, 32)], name=f"b{i}")
-        reqs.append(([device_group(g, B)], 2000 + i))
+        host.append(([g], 2000 + i))
+    reqs = [([device_group(g, B) for g in gs], seed) for gs, seed in host]
     need = serve.ProofServer.request_bytes(serve.Request(0, *reqs[0]))
     assert all(serve.ProofServer.request_bytes(serve.Request(0, *r)) == need for r in reqs)
     srv = serve.ProofServer(n_slots=4, hbm_budget_bytes=need)
@@ -60,8 +82,8 @@ def test_budget_limits_admission(env):
         srv.submit(serve.Request(i, gs, seed))
     srv.drain()
     assert srv.peak_in_flight == 1
-    for i, (gs, seed) in enumerate(reqs):
-        assert srv.done[i].proofs == B.sumcheck_matmul_prove(gs, seed, mode=B.VL_MODE_BATCHED)[0]
+    for i, (gs, seed) in enumerate(host):
+        assert srv.done[i].proofs == [prove_workload_group(g, seed)[0] for g in gs]
 
 
 def test_false_statement_reported_per_request(env):
@@ -75,26 +97,29 @@ def test_false_statement_reported_per_request(env):
     srv.submit(serve.Request(0, [device_group(g, B), device_group(good, B)], 5))
     srv.drain()
     assert srv.done[0].status == [B.VL_ERR_FALSE_STATEMENT, 0]
+    assert srv.done[0].proofs[1] == prove_workload_group(good, 5)[0]
 
 
 def test_open_loop_poisson_arrivals(env):
     B, serve = env
+    import numpy as np
     reqs = _requests(B, 6)
-    arrivals = [(0.002 * i, i) for i in range(len(reqs))]
+    gaps = np.random.default_rng(17).exponential(0.002, size=len(reqs))
+    arrivals = [(float(t), i) for i, t in enumerate(np.cumsum(gaps))]
     srv = serve.ProofServer(n_slots=2)
     results, wall = serve.run_open_loop(srv, arrivals, lambda i, k: serve.Request(i, *reqs[k]))
     assert len(results) == len(reqs)
     summ = serve.latency_summary(results)
     assert summ["n"] == len(reqs) and summ["p99_ms"] >= summ["p50_ms"] > 0
     for r in results:
-        assert r.proofs == B.sumcheck_matmul_prove(*reqs[r.rid], mode=B.VL_MODE_BATCHED)[0]
+        assert r.proofs == _oracle_bytes(r.rid)
 
 
 def test_one_slot_reuses_and_grows_its_buffers(env):
     B, serve = env
     # one slot, requests of different sizes in turn: the slot's pinned buffers
     # grow for the larger ones and are reused (and overwritten) by the others;
-    # each result must still be that request's own solo proof
+    # each result must still be that request's oracle proof
     reqs = _requests(B, 6)
     order = [4, 3, 0, 5, 4, 1, 3]          # small, large, mid, large, small, ...
     srv = serve.ProofServer(n_slots=1, hbm_budget_bytes=1 << 30)
@@ -104,10 +129,17 @@ def test_one_slot_reuses_and_grows_its_buffers(env):
     assert srv.peak_in_flight == 1
     sizes = set()
     for i, k in enumerate(order):
-        gs, seed = reqs[k]
-        expect = B.sumcheck_matmul_prove(gs, seed, mode=B.VL_MODE_BATCHED)[0]
+        expect = _oracle_bytes(k)
         assert srv.done[i].status == [0, 0]
         assert srv.done[i].proofs == expect
         sizes.add(sum(len(p) for p in expect))
     assert len(sizes) >= 3
     assert srv.slots[0].host_proofs.numel() == max(sizes)
+
+
+def test_server_refuses_persistent_mode(env):
+    B, serve = env
+    reqs = _requests(B, 1)
+    srv = serve.ProofServer(n_slots=1)
+    with pytest.raises(ValueError):
+        srv.submit(serve.Request(0, *reqs[0], mode=B.VL_MODE_PERSISTENT))

@@ -192,3 +192,39 @@ def test_persistent_mode_refuses_more_than_128_groups():
                                     None, None)
     assert st == B.VL_ERR_INVALID_ARG
     assert "at most 128 groups" in B.last_error()
+
+
+BOUNDARY_CALLS = ("vl_fr_lift", "vl_eq_table", "vl_mle_partial_eval", "vl_sumcheck_matmul_prove",
+                  "vl_verify_transcript")
+
+
+def _comment_before(header: str, name: str) -> str:
+    """The /* ... */ block that ends right before the declaration of name."""
+    decl = re.search(r"\n[a-z_0-9 ]*\b" + name + r"\s*\(", header)
+    assert decl, name
+    end = header.rindex("*/", 0, decl.start())
+    start = header.rindex("/*", 0, end)
+    between = header[end + 2:decl.start()]
+    assert "/*" not in between and ";" not in between, name
+    return header[start:end]
+
+
+@pytest.mark.parametrize("name", BOUNDARY_CALLS)
+def test_boundary_call_cites_the_paper(name):
+    # each of the five calls of the boundary says which passage of the paper
+    # defines the operation it performs
+    header = open(os.path.join(ROOT, "include", "verilora.h")).read()
+    comment = _comment_before(header, name)
+    assert re.search(r"\bSec\. [IVX]+(-[A-Z](\.\d)?)?|\beq\. \(", comment), name
+
+
+def test_header_compiles_as_c_and_cpp():
+    # the boundary header stands alone for C and C++ callers
+    import shutil
+    import subprocess
+    for cc, lang in (("gcc", "c"), ("g++", "c++")):
+        if not shutil.which(cc):
+            pytest.skip(f"{cc} not found")
+        r = subprocess.run([cc, "-x", lang, "-fsyntax-only", "-Wall", "-Werror",
+                            os.path.join(ROOT, "include", "verilora.h")], capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr

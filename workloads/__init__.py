@@ -10,5 +10,5 @@ from .gen import (  # noqa: F401
     Product, Group, Workload,
     quantize_gaussian, requant, exact_matmul,
     config1, lora_forward, lora_backward_update, config2, config3, config4,
-    serving_request, serving_stream, frozen_weight, tiny_random_group, CONFIG_NAMES, make_config,
+    serving_request, serving_stream, frozen_weight, serving_sample, serving_sample_workload, tiny_random_group, CONFIG_NAMES, make_config,
 )

@@ -301,6 +301,34 @@ def serving_stream(n: int, rate_per_s: float, seed: int = 5):
     return out
 
 
+def serving_sample(n: int = 12):
+    """A fixed request mix for parity checks at 13B-class shapes: list of
+    (target, T, rank, kind) covering every target, every T, every rank and
+    every request type at least once (n >= 7).  Request k takes target k mod 7,
+    T index k mod 3, rank index floor(k / 3) mod 3 and type index
+    (k + floor(k / 3)) mod 3, so the pairs (T, rank) and (T, type) vary too."""
+    if n < 7:
+        raise ValueError("the sample needs at least 7 requests to cover every target")
+    out = []
+    for k in range(n):
+        out.append((SERVE_TARGETS[k % 7], SERVE_T[k % 3], SERVE_RANKS[(k // 3) % 3],
+                    SERVE_TYPES[(k + k // 3) % 3]))
+    return out
+
+
+def serving_sample_workload(k: int, spec, weights=None, seed: int = 5, device=None) -> Workload:
+    """Request k of ``serving_sample`` as a Workload whose seed is the seed its
+    proof is made with (5000 + k); ``weights`` caches the frozen W per target."""
+    target, T, r, kind = spec
+    if weights is None:
+        weights = {}
+    if target not in weights:
+        weights[target] = frozen_weight(target, seed=seed)
+    w = serving_request(k, target, T, r, kind, weights[target], seed=seed, device=device)
+    w.seed = 5000 + k
+    return w
+
+
 # --------------------------------------------------------------------------
 # small random groups for parity tests
 # --------------------------------------------------------------------------
