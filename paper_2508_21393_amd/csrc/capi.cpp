@@ -1242,35 +1242,13 @@ void vl_prove_graph_destroy(vl_prove_graph* g) {
 // layout of the partial-eval workspace: [pack][job blob][split partials]
 static uint64_t pe_pack_bytes(uint64_t len) { return align_up(len * 32, 256); }
 static constexpr uint64_t kPeBlob = 1024;
+}  // extern "C"
 
-uint64_t vl_partial_eval_workspace_size(uint32_t rows, uint32_t cols, int32_t contract, int32_t dtype,
-                                        const vl_tuning* tuning) {
-  if (rows == 0 || cols == 0 || !esize(dtype) ||
-      (contract != VL_CONTRACT_ROWS && contract != VL_CONTRACT_COLS))
-    return 0;
-  const bool rws = contract == VL_CONTRACT_ROWS;
-  const uint64_t len = rws ? rows : cols, n_out = rws ? cols : rows;
-  if (check_tuning(tuning) != VL_OK) return 0;
-  const Tuning T = pe_tuning(tuning);
-  // the alignment of M (which picks vector or element loads, and with them
-  // the chunking) is unknown here: the larger of the two plans
-  uint64_t need = 0;
-  for (uintptr_t m : {uintptr_t(0), uintptr_t(2)}) {
-    Plan P;
-    Builder B(P, T, 0, pe_pack_bytes(len) + kPeBlob);
-    B.contract(reinterpret_cast<const void*>(m), dtype, digits_for(dtype), cols, rws, (uint32_t)n_out,
-               (uint32_t)len, nullptr, nullptr, 1, n_out, nullptr);
-    need = std::max(need, B.off);
-  }
-  return align_up(need, 256);
-}
-
-vl_status vl_mle_partial_eval(const void* M, int32_t dtype, uint32_t rows, uint32_t cols, uint64_t ld,
-                              int32_t contract, vl_fr_vec eq, vl_fr_vec out, void* workspace,
-                              uint64_t workspace_bytes, const vl_tuning* tuning, void* stream) {
-  if (!M || !eq.base || !out.base || !workspace) return fail(VL_ERR_INVALID_ARG, "null pointer");
-  if (reinterpret_cast<uintptr_t>(workspace) % 256)
-    return fail(VL_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+namespace vl {
+// Argument checks of a partial evaluation (everything but the workspace).
+vl_status partial_eval_check(const void* M, int32_t dtype, uint32_t rows, uint32_t cols, uint64_t ld,
+                             int32_t contract, vl_fr_vec eq, vl_fr_vec out, const vl_tuning* tuning) {
+  if (!M || !eq.base || !out.base) return fail(VL_ERR_INVALID_ARG, "null pointer");
   if (!esize(dtype)) return fail(VL_ERR_DTYPE, "dtype must be VL_I16/I32/I64");
   if (contract != VL_CONTRACT_ROWS && contract != VL_CONTRACT_COLS)
     return fail(VL_ERR_INVALID_ARG, "contract must be VL_CONTRACT_ROWS or VL_CONTRACT_COLS");
@@ -1281,9 +1259,19 @@ vl_status vl_mle_partial_eval(const void* M, int32_t dtype, uint32_t rows, uint3
   if (eq.n < len || eq.ld < eq.n) return fail(VL_ERR_SHAPE, "eq vector shorter than the contraction");
   if (out.n < n_out || out.ld < out.n) return fail(VL_ERR_SHAPE, "out vector too short");
   if (check_tuning(tuning) != VL_OK) return VL_ERR_INVALID_ARG;
-  if (workspace_bytes < vl_partial_eval_workspace_size(rows, cols, contract, dtype, tuning))
-    return fail(VL_ERR_WORKSPACE, "workspace too small");
+  return VL_OK;
+}
+
+// Enqueues a checked partial evaluation with its scratch at ws (256-byte
+// aligned, at least the workspace size of this shape): the pack table of eq,
+// the job blob (uploaded through kernel arguments) and, for a split
+// contraction, the chunk partials.  Nothing is allocated.
+vl_status partial_eval_launch(const void* M, int32_t dtype, uint32_t rows, uint32_t cols, uint64_t ld,
+                              int32_t contract, vl_fr_vec eq, vl_fr_vec out, void* workspace,
+                              uint64_t workspace_bytes, const vl_tuning* tuning, void* stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool rws = contract == VL_CONTRACT_ROWS;
+  const uint32_t len = rws ? rows : cols, n_out = rws ? cols : rows;
   uint8_t* ws = reinterpret_cast<uint8_t*>(workspace);
   uint32_t* pack = reinterpret_cast<uint32_t*>(ws);
   uint8_t* dblob = ws + pe_pack_bytes(len);
@@ -1310,6 +1298,52 @@ vl_status vl_mle_partial_eval(const void* M, int32_t dtype, uint32_t rows, uint3
     e = launch_finish(reinterpret_cast<const FinishJob*>(dblob + fo), 1, G.fin_blocks, s);
   if (e != hipSuccess) return fail(VL_ERR_HIP, "partial_eval: %s", hipGetErrorString(e));
   return VL_OK;
+}
+}  // namespace vl
+
+extern "C" {
+
+uint64_t vl_partial_eval_workspace_size(uint32_t rows, uint32_t cols, int32_t contract, int32_t dtype,
+                                        const vl_tuning* tuning) {
+  if (rows == 0 || cols == 0 || !esize(dtype) ||
+      (contract != VL_CONTRACT_ROWS && contract != VL_CONTRACT_COLS))
+    return 0;
+  const bool rws = contract == VL_CONTRACT_ROWS;
+  const uint64_t len = rws ? rows : cols, n_out = rws ? cols : rows;
+  if (check_tuning(tuning) != VL_OK) return 0;
+  const Tuning T = pe_tuning(tuning);
+  // the alignment of M and of its leading dimension (which pick vector or
+  // element loads, and with them the chunking) are unknown here: the larger
+  // of the two plans, one with M and ld aligned for every vector width, one
+  // with M misaligned
+  uint64_t need = 0;
+  const uint64_t ld_vec = align_up(cols, 16);
+  for (int k = 0; k < 2; ++k) {
+    const uintptr_t m = k == 0 ? 0 : 2;
+    const uint64_t ld = k == 0 ? ld_vec : cols;
+    Plan P;
+    Builder B(P, T, 0, pe_pack_bytes(len) + kPeBlob);
+    B.contract(reinterpret_cast<const void*>(m), dtype, digits_for(dtype), ld, rws, (uint32_t)n_out,
+               (uint32_t)len, nullptr, nullptr, 1, n_out, nullptr);
+    need = std::max(need, B.off);
+  }
+  return align_up(need, 256);
+}
+
+vl_status vl_mle_partial_eval(const void* M, int32_t dtype, uint32_t rows, uint32_t cols, uint64_t ld,
+                              int32_t contract, vl_fr_vec eq, vl_fr_vec out, void* workspace,
+                              uint64_t workspace_bytes, const vl_tuning* tuning, void* stream) {
+  {
+    const vl_status st = vl::partial_eval_check(M, dtype, rows, cols, ld, contract, eq, out, tuning);
+    if (st != VL_OK) return st;
+  }
+  if (!workspace) return fail(VL_ERR_INVALID_ARG, "null pointer");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(VL_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (workspace_bytes < vl_partial_eval_workspace_size(rows, cols, contract, dtype, tuning))
+    return fail(VL_ERR_WORKSPACE, "workspace too small");
+  return vl::partial_eval_launch(M, dtype, rows, cols, ld, contract, eq, out, workspace, workspace_bytes, tuning,
+                                 stream);
 }
 
 }  // extern "C"

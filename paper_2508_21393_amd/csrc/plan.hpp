@@ -132,6 +132,13 @@ struct StageEvents {
 hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipStream_t s,
                         hipStream_t s2, StageEvents* ev = nullptr, const void* blob_src_dev = nullptr);
 Tuning tuning_for(const vl_prove_opts* o);
+// partial evaluation (vl_mle_partial_eval): argument checks, and the launch
+// with the caller's (or the fixed) scratch
+vl_status partial_eval_check(const void* M, int32_t dtype, uint32_t rows, uint32_t cols, uint64_t ld,
+                             int32_t contract, vl_fr_vec eq, vl_fr_vec out, const vl_tuning* tuning);
+vl_status partial_eval_launch(const void* M, int32_t dtype, uint32_t rows, uint32_t cols, uint64_t ld,
+                              int32_t contract, vl_fr_vec eq, vl_fr_vec out, void* workspace,
+                              uint64_t workspace_bytes, const vl_tuning* tuning, void* stream);
 void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, uint64_t g1,
                  uint64_t seed, uint8_t* ws, bool async, uint8_t* proofs_dev, const uint64_t* offsets,
                  int32_t* status_dev, uint8_t* digests_dev, uint8_t* out);

@@ -228,3 +228,28 @@ def test_header_compiles_as_c_and_cpp():
         r = subprocess.run([cc, "-x", lang, "-fsyntax-only", "-Wall", "-Werror",
                             os.path.join(ROOT, "include", "verilora.h")], capture_output=True, text=True)
         assert r.returncode == 0, r.stderr
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="plans with fake device pointers: CPU-only container")
+@pytest.mark.parametrize("rows,cols,ld,contract,dt,cols_rows", [
+    (130, 777, 784, 1, np.int16, 2), (130, 777, 784, 1, np.int16, 1), (300, 1030, 1032, 1, np.int16, 2),
+    (3000, 65, 72, 0, np.int16, 1), (270, 514, 516, 0, np.int32, 1), (300, 301, 302, 0, np.int64, 1),
+    (33, 515, 520, 1, np.int32, 1), (9, 4093, 4096, 1, np.int64, 1)])
+def test_partial_eval_workspace_size_covers_strided_layouts(rows, cols, ld, contract, dt, cols_rows):
+    # the size query knows only (rows, cols): it must cover the plan for any
+    # leading dimension and alignment.  The call plans on the host and
+    # checks the workspace before any device work; with no GPU here the
+    # first launch then fails with VL_ERR_HIP, never with VL_ERR_WORKSPACE.
+    import ctypes
+    L = _lib_or_skip()
+    tn = B.tuning(cols_rows=cols_rows)
+    need = B.partial_eval_workspace_size(rows, cols, contract, dt, tn)
+    assert need > 0
+    len_ = rows if contract == 0 else cols
+    n_out = cols if contract == 0 else rows
+    eq = B.vl_fr_vec(0x10000, len_, len_)
+    out = B.vl_fr_vec(0x20000, n_out, n_out)
+    st = L.vl_mle_partial_eval(ctypes.c_void_p(0x100000), B.dtype_code(dt), rows, cols, ld, contract, eq, out,
+                               ctypes.c_void_p(0x200000), need, ctypes.byref(tn), None)
+    assert st != B.VL_ERR_WORKSPACE, B.last_error()
+    assert st == B.VL_ERR_HIP
