@@ -209,6 +209,21 @@ vl_status vl_mle_partial_eval(const void* M, int32_t dtype, uint32_t rows, uint3
                               void* workspace, uint64_t workspace_bytes, const vl_tuning* tuning,
                               void* stream);
 
+/* vl_mle_partial_eval for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * allocation): the same operation, arguments and results, with no workspace
+ * argument.  Its scratch is a fixed device array of the library,
+ * VL_NOALLOC_SCRATCH_BYTES per GPU, held by every GPU the library runs on
+ * until the process ends; the call allocates nothing.  A shape whose
+ * vl_partial_eval_workspace_size exceeds that size is refused with
+ * VL_ERR_WORKSPACE before any device work.  Every call on one GPU uses that
+ * GPU's one array: calls that overlap on a GPU (other streams, other host
+ * threads) race and must be ordered by the caller. */
+#define VL_NOALLOC_SCRATCH_BYTES (64ull << 20)
+vl_status vl_mle_partial_eval_noalloc(const void* M, int32_t dtype, uint32_t rows, uint32_t cols,
+                                      uint64_t ld, int32_t contract, vl_fr_vec eq, vl_fr_vec out,
+                                      const vl_tuning* tuning, void* stream);
+
 /* Bytes of one group's proof:
  * 32 * (1 + (n_prods - 1) + sum over products of (3 * n1 + 2)),
  * n1 = ceil(log2 D1).  Layout: c || part claims || per product the round

@@ -31,7 +31,9 @@ STATUS_NAMES = {0: "VL_OK", 1: "VL_ERR_INVALID_ARG", 2: "VL_ERR_SHAPE", 3: "VL_E
 EXPORTED = ("vl_fr_lift", "vl_fr_export", "vl_eq_table", "vl_partial_eval_workspace_size",
             "vl_mle_partial_eval", "vl_proof_size", "vl_workspace_size",
             "vl_sumcheck_matmul_prove", "vl_verify_transcript", "vl_last_error",
-            "vl_prove_graph_create", "vl_prove_graph_launch", "vl_prove_graph_destroy")
+            "vl_prove_graph_create", "vl_prove_graph_launch", "vl_prove_graph_destroy",
+            "vl_mle_partial_eval_noalloc")
+NOALLOC_SCRATCH_BYTES = 64 << 20   # VL_NOALLOC_SCRATCH_BYTES
 
 c_u32, c_u64, c_i32, c_vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p
 
@@ -99,6 +101,8 @@ def lib():
         L.vl_partial_eval_workspace_size.restype = c_u64
         L.vl_mle_partial_eval.argtypes = [c_vp, c_i32, c_u32, c_u32, c_u64, c_i32, vl_fr_vec, vl_fr_vec,
                                           c_vp, c_u64, ctypes.POINTER(vl_tuning), c_vp]
+        L.vl_mle_partial_eval_noalloc.argtypes = [c_vp, c_i32, c_u32, c_u32, c_u64, c_i32, vl_fr_vec, vl_fr_vec,
+                                                  ctypes.POINTER(vl_tuning), c_vp]
         L.vl_proof_size.argtypes = [ctypes.POINTER(vl_group)]
         L.vl_proof_size.restype = c_u64
         L.vl_workspace_size.argtypes = [ctypes.POINTER(vl_group), c_u64, ctypes.POINTER(vl_prove_opts)]
@@ -115,7 +119,7 @@ def lib():
         L.vl_prove_graph_launch.argtypes = [c_vp, c_u64, c_vp]
         L.vl_prove_graph_destroy.argtypes = [c_vp]
         L.vl_prove_graph_destroy.restype = None
-        for f in ("vl_fr_lift", "vl_fr_export", "vl_eq_table", "vl_mle_partial_eval",
+        for f in ("vl_fr_lift", "vl_fr_export", "vl_eq_table", "vl_mle_partial_eval", "vl_mle_partial_eval_noalloc",
                   "vl_sumcheck_matmul_prove", "vl_verify_transcript", "vl_prove_graph_create",
                   "vl_prove_graph_launch"):
             getattr(L, f).restype = c_i32
@@ -265,6 +269,14 @@ def mle_partial_eval(M, contract: int, eq: vl_fr_vec, out: vl_fr_vec, workspace,
     _check(lib().vl_mle_partial_eval(_ptr(M), dtype_code(M.dtype), rows, cols, _row_stride(M), contract,
                                      eq, out, _ptr(workspace), workspace.numel() * workspace.element_size(),
                                      _tun(tuning_), _stream(stream)))
+
+
+def mle_partial_eval_noalloc(M, contract: int, eq: vl_fr_vec, out: vl_fr_vec, stream=None, tuning_=None):
+    """mle_partial_eval with the library's fixed device scratch (no workspace,
+    no allocation); calls overlapping on one GPU race on that scratch."""
+    rows, cols = M.shape
+    _check(lib().vl_mle_partial_eval_noalloc(_ptr(M), dtype_code(M.dtype), rows, cols, _row_stride(M), contract,
+                                             eq, out, _tun(tuning_), _stream(stream)))
 
 
 def proof_size(group: GroupArgs) -> int:
