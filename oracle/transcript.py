@@ -35,6 +35,18 @@ class Transcript:
             msg += struct.pack("<III", d0, d1, d2)
         self.state = sha256(msg)
 
+    @classmethod
+    def from_state(cls, state: bytes) -> "Transcript":
+        """A transcript that continues from a given 32-byte state."""
+        t = cls.__new__(cls)
+        t.state = bytes(state)
+        return t
+
+    def fork(self, label: bytes, k: int) -> "Transcript":
+        """An independent branch: a new transcript whose state is
+        H(st || label || u32 k); this transcript is left unchanged."""
+        return Transcript.from_state(sha256(self.state + label + struct.pack("<I", k)))
+
     def absorb(self, label: bytes, data: bytes) -> None:
         self.state = sha256(self.state + label + data)
 

@@ -156,6 +156,17 @@ def prove_group(prods: Sequence[Tuple[np.ndarray, np.ndarray]], C: np.ndarray, s
 
     tr = Transcript(seed, group_id, shapes)
     u, v = challenges_uv(tr, shapes)
+    proof, details = prove_group_at(prods, C, tr, u, v)
+    return proof, tr.state, details
+
+
+def prove_group_at(prods: Sequence[Tuple[np.ndarray, np.ndarray]], C: np.ndarray, tr: Transcript, u, v):
+    """The sumcheck of a group at a given point (u, v), continuing the
+    transcript tr (which this updates): the steps of prove_group after the
+    challenges.  Used on its own when the point comes from an earlier step
+    of a chained proof.  Returns (proof bytes, details)."""
+    shapes = [(int(A.shape[0]), int(A.shape[1]), int(B.shape[1])) for A, B in prods]
+    group_shapes_ok(shapes)
     c = claim_value(C, u, v)
     tr.absorb(b"claim", enc(c))
 
@@ -190,7 +201,7 @@ def prove_group(prods: Sequence[Tuple[np.ndarray, np.ndarray]], C: np.ndarray, s
 
     pp = ProofParts(c, parts, all_rounds, finals)
     details = dict(u=u, v=v, c=c, sums=sums, r=all_r, finals=finals, rounds=all_rounds)
-    return pp.to_bytes(), tr.state, details
+    return pp.to_bytes(), details
 
 
 def verify_group(proof: bytes, shapes, seed: int, group_id: int,
@@ -205,9 +216,18 @@ def verify_group(proof: bytes, shapes, seed: int, group_id: int,
     """
     shapes = [tuple(int(x) for x in s) for s in shapes]
     group_shapes_ok(shapes)
-    pp = ProofParts.from_bytes(proof, shapes)
     tr = Transcript(seed, group_id, shapes)
     u, v = challenges_uv(tr, shapes)
+    return verify_group_at(proof, shapes, tr, u, v, witness)
+
+
+def verify_group_at(proof: bytes, shapes, tr: Transcript, u, v,
+                    witness: Optional[Tuple[Sequence[Tuple[np.ndarray, np.ndarray]], np.ndarray]] = None):
+    """verify_group at a given point (u, v), continuing the transcript tr
+    (which this updates)."""
+    shapes = [tuple(int(x) for x in s) for s in shapes]
+    group_shapes_ok(shapes)
+    pp = ProofParts.from_bytes(proof, shapes)
     tr.absorb(b"claim", enc(pp.c))
     for s in pp.parts:
         tr.absorb(b"part", enc(s))

@@ -3,7 +3,7 @@
 Only ``oracle`` and ``workloads`` are used: every stored value is what the
 oracle computes for the seeded synthetic inputs.  Usage:
 
-    python tests/golden/make_golden.py [cfg1 cfg1_sweep tiny cfg2 cfg3 cfg4 cfg5] [--procs N]
+    python tests/golden/make_golden.py [cfg1 cfg1_sweep tiny cfg2 cfg3 cfg4 cfg5 chain] [--procs N]
 
 Each config file lists, per group: name, group id, shapes, the SHA-256 of the
 proof bytes and the final transcript state; small configs also keep the full
@@ -130,6 +130,34 @@ def record_cfg5(procs: int):
     return dict(workload="13B-class serving sample (hidden 5120, FFN 13824)", n=N_CFG5, requests=out)
 
 
+CHAIN_TINY = [
+    # (seed, T, d_in, d_out, r): shapes with ragged and unit dimensions
+    (21, 8, 12, 10, 3), (22, 4, 4, 4, 2), (23, 5, 7, 9, 1), (24, 1, 3, 2, 2), (25, 16, 8, 32, 4),
+    (26, 3, 1, 5, 1), (27, 70, 130, 33, 16), (28, 64, 256, 300, 8),
+]
+CHAIN_SEED = 31
+
+
+def record_chain():
+    """Chained layer proofs (oracle/chain.py): the tiny layers in full and
+    the FFN-up layer of the backward-and-update configuration by digest."""
+    from oracle.chain import chain_prove
+    tiny = []
+    for seed, T, d_in, d_out, r in CHAIN_TINY:
+        w = workloads.tiny_layer(seed, T, d_in, d_out, r)
+        t = time.time()
+        proof, state, _ = chain_prove(w, CHAIN_SEED)
+        tiny.append(dict(spec=[seed, T, d_in, d_out, r], proof_hex=proof.hex(), state=state.hex()))
+        print(f"  tiny layer {(T, d_in, d_out, r)} {time.time() - t:6.1f}s", flush=True)
+    w = workloads.chain_layer()
+    t = time.time()
+    proof, state, _ = chain_prove(w, CHAIN_SEED)
+    print(f"  layer {w.dims} {time.time() - t:6.1f}s", flush=True)
+    full = dict(dims=list(w.dims), proof_sha256=hashlib.sha256(proof).hexdigest(), state=state.hex(),
+                proof_len=len(proof))
+    return dict(seed=CHAIN_SEED, F=w.F, eta=w.eta, tiny=tiny, layer=full)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("configs", nargs="*", default=["cfg1", "tiny", "cfg2", "cfg3"])
@@ -138,6 +166,12 @@ def main():
     for name in args.configs:
         t = time.time()
         print(f"{name}: generating", flush=True)
+        if name == "chain":
+            data = record_chain()
+            with open(os.path.join(HERE, "chain.json"), "w") as f:
+                json.dump(data, f, indent=1)
+            print(f"{name}: done in {time.time() - t:.1f}s", flush=True)
+            continue
         if name == "cfg5":
             data = record_cfg5(args.procs)
             with open(os.path.join(HERE, "cfg5.json"), "w") as f:

@@ -241,6 +241,76 @@ def config4(seed: int = 4, T: int = 2048, hidden: int = 4096, ffn: int = 11008, 
 
 
 # --------------------------------------------------------------------------
+# one LoRA layer as a chain of claims (forward, backward and update)
+# --------------------------------------------------------------------------
+CHAIN_F, CHAIN_ETA = 12, 3   # update U = 2^F A - eta dA (eta at scale 2^-12: about 7e-4)
+
+
+@dataclasses.dataclass
+class LayerWitness:
+    """Every tensor of one LoRA layer's training step, as integers.
+
+    Inputs (int16): X (T x d_in), W (d_in x d_out), A (d_in x r), B (r x d_out),
+    dY (T x d_out) and the re-quantised intermediates H = requant(X A) and
+    G = requant(dY B^T) (T x r).  Exact int64 results: Y = X W + H B,
+    C2 = X A, C4 = dY B^T, dA = X^T G, dB = H^T dY, dX = dY W^T + G A^T and the
+    pre-rounding updates UA = 2^F A - eta dA, UB = 2^F B - eta dB."""
+    X: np.ndarray
+    W: np.ndarray
+    A: np.ndarray
+    B: np.ndarray
+    dY: np.ndarray
+    H: np.ndarray
+    G: np.ndarray
+    Y: np.ndarray
+    C2: np.ndarray
+    C4: np.ndarray
+    dA: np.ndarray
+    dB: np.ndarray
+    dX: np.ndarray
+    UA: np.ndarray
+    UB: np.ndarray
+    F: int = CHAIN_F
+    eta: int = CHAIN_ETA
+
+    @property
+    def dims(self):
+        return (int(self.X.shape[0]), int(self.X.shape[1]), int(self.W.shape[1]), int(self.A.shape[1]))
+
+
+def layer_witness(L: "LoraLayer", F: int = CHAIN_F, eta: int = CHAIN_ETA, device=None) -> LayerWitness:
+    """All tensors of one layer's step from a drawn LoraLayer (with dY)."""
+    X, W, A, B, dY, H, G = L.X, L.W, L.A, L.B, L.dY, L.H, L.G
+    mm = lambda a, b: exact_matmul(a, b, device=device)  # noqa: E731
+    C2 = exact_matmul(X, A)
+    C4 = exact_matmul(dY, B.T)
+    Y = mm(X, W) + mm(H, B)
+    dA = mm(X.T, G)
+    dB = mm(H.T, dY)
+    dX = mm(dY, W.T) + mm(G, A.T)
+    UA = (A.astype(np.int64) << F) - eta * dA
+    UB = (B.astype(np.int64) << F) - eta * dB
+    return LayerWitness(X, W, A, B, dY, H, G, Y, C2, C4, dA, dB, dX, UA, UB, F, eta)
+
+
+def chain_layer(seed: int = 3, T: int = 512, d_in: int = 4096, d_out: int = 11008, r: int = 16,
+                device=None) -> LayerWitness:
+    """The FFN-up layer of the backward-and-update configuration (T = 512,
+    4096 -> 11008, rank 16) as one chained step: the same draw order as
+    config3's second layer, from a generator of its own seed."""
+    rng = np.random.default_rng([seed, 77])
+    L = LoraLayer(rng, T, d_in, d_out, r, with_dy=True)
+    return layer_witness(L, device=device)
+
+
+def tiny_layer(seed: int, T: int, d_in: int, d_out: int, r: int) -> LayerWitness:
+    """A small layer with the same distributions (chain parity cases)."""
+    rng = np.random.default_rng([seed, 78])
+    L = LoraLayer(rng, T, d_in, d_out, r, with_dy=True)
+    return layer_witness(L)
+
+
+# --------------------------------------------------------------------------
 # serving requests (13B-class shapes)
 # --------------------------------------------------------------------------
 SERVE_13B = dict(hidden=5120, ffn=13824)
