@@ -311,6 +311,66 @@ vl_status vl_verify_transcript(const uint8_t* proof, uint64_t len, const vl_grou
                                uint64_t seed, vl_fr* reduced, uint64_t reduced_cap,
                                uint64_t* reduced_len, int32_t* fail_round);
 
+/* One LoRA layer's training step (forward, backward and update of one LoRA
+ * target) as a chain of claims in one Fiat-Shamir transcript: the sequential
+ * composition of Sec. IV-B, where each step justifies exactly the
+ * point-value claims the step before it fixed, applied to zkMat's products
+ * and additions and to the update of eq. (grad_update_ab).
+ * Tensors (device pointers, row-major, leading dimension = columns):
+ *   int16: X (T x d_in), W (d_in x d_out), A (d_in x r), B (r x d_out),
+ *          dY (T x d_out), H and G (T x r; the re-quantised X A and dY B^T)
+ *   int64: Y = X W + H B (T x d_out), C2 = X A, C4 = dY B^T (T x r),
+ *          dA = X^T G (d_in x r), dB = H^T dY (r x d_out),
+ *          dX = dY W^T + G A^T (T x d_in),
+ *          UA = 2^F A - eta dA, UB = 2^F B - eta dB (the update before its
+ *          rounding to the next step's int16 parameters)
+ * The proof has four stages: (1) UA~, A~, dA~ at a random point zA and UB~,
+ * B~, dB~ at zB, with UA~ = 2^F A~ - eta dA~ and the same for B (the update
+ * is linear, so it holds iff it holds at a random point); (2) points zY, zX,
+ * z2, z4 for Y, dX, C2 and C4; (3) the sumchecks of eq. (zk-mle-matmul) of
+ * the groups {X^T G} = dA at zA, {H^T dY} = dB at zB, {X W, H B} = Y at zY,
+ * {dY W^T, G A^T} = dX at zX, {X A} = C2 at z2 and {dY B^T} = C4 at z4, each
+ * on its own branch H(st || "fork" || k) of the transcript; (4) the claims
+ * these leave on each of X, W, A, B, dY, H, G reduced to one: a random
+ * combination sum_k rho_k M~(x_k, y_k), one sumcheck over the row variables,
+ * then one over the column variables, ending at a single claim M~(r, s)
+ * (branches H(st || "rfork" || j)).  The claims left at the end (one per
+ * tensor, and those on UA, UB, Y, dX, C2 and C4) are for the openings of
+ * committed tensors (Sec. II-A, out of scope).
+ * Constraints: T + r, d_in + r and d_out + r are at most 2^16 (two 24-bit
+ * digits then hold every int64 result of int16 products); F <= 62.
+ * Blocking call: it synchronises the stream three times (the host squeezes
+ * each stage's points from the proof bytes the kernels wrote) and returns
+ * after the proof (vl_lora_chain_proof_size bytes) and the final transcript
+ * state (digest, 32 bytes, optional) are in host memory.
+ * Errors: VL_ERR_INVALID_ARG, VL_ERR_SHAPE, VL_ERR_WORKSPACE,
+ * VL_ERR_BUFFER_TOO_SMALL, VL_ERR_FALSE_STATEMENT (the update relation or a
+ * product group does not hold), VL_ERR_RANGE, VL_ERR_HIP. */
+typedef struct {
+  uint32_t T, d_in, d_out, r;
+  uint32_t F, eta;
+  const int16_t* X;
+  const int16_t* W;
+  const int16_t* A;
+  const int16_t* B;
+  const int16_t* dY;
+  const int16_t* H;
+  const int16_t* G;
+  const int64_t* Y;
+  const int64_t* C2;
+  const int64_t* C4;
+  const int64_t* dA;
+  const int64_t* dB;
+  const int64_t* dX;
+  const int64_t* UA;
+  const int64_t* UB;
+} vl_lora_layer;
+
+uint64_t vl_lora_chain_proof_size(const vl_lora_layer* layer);
+uint64_t vl_lora_chain_workspace_size(const vl_lora_layer* layer);
+vl_status vl_lora_chain_prove(const vl_lora_layer* layer, uint64_t seed, void* workspace, uint64_t workspace_bytes,
+                              uint8_t* proof, uint64_t proof_len, uint8_t* digest, void* stream);
+
 /* Message for the last non-OK status on this thread. */
 const char* vl_last_error(void);
 

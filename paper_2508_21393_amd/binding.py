@@ -32,7 +32,8 @@ EXPORTED = ("vl_fr_lift", "vl_fr_export", "vl_eq_table", "vl_partial_eval_worksp
             "vl_mle_partial_eval", "vl_proof_size", "vl_workspace_size",
             "vl_sumcheck_matmul_prove", "vl_verify_transcript", "vl_last_error",
             "vl_prove_graph_create", "vl_prove_graph_launch", "vl_prove_graph_destroy",
-            "vl_mle_partial_eval_noalloc")
+            "vl_mle_partial_eval_noalloc", "vl_lora_chain_proof_size", "vl_lora_chain_workspace_size",
+            "vl_lora_chain_prove")
 NOALLOC_SCRATCH_BYTES = 64 << 20   # VL_NOALLOC_SCRATCH_BYTES
 
 c_u32, c_u64, c_i32, c_vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p
@@ -79,6 +80,15 @@ class vl_prove_opts(ctypes.Structure):
                 ("status", c_vp), ("tuning", ctypes.POINTER(vl_tuning)), ("stage_ms", c_vp)]
 
 
+class vl_lora_layer(ctypes.Structure):
+    _fields_ = [("T", c_u32), ("d_in", c_u32), ("d_out", c_u32), ("r", c_u32), ("F", c_u32), ("eta", c_u32)] + \
+        [(n, c_vp) for n in ("X", "W", "A", "B", "dY", "H", "G", "Y", "C2", "C4", "dA", "dB", "dX", "UA", "UB")]
+
+
+LAYER_INT16 = ("X", "W", "A", "B", "dY", "H", "G")
+LAYER_INT64 = ("Y", "C2", "C4", "dA", "dB", "dX", "UA", "UB")
+
+
 class VLError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -103,6 +113,12 @@ def lib():
                                           c_vp, c_u64, ctypes.POINTER(vl_tuning), c_vp]
         L.vl_mle_partial_eval_noalloc.argtypes = [c_vp, c_i32, c_u32, c_u32, c_u64, c_i32, vl_fr_vec, vl_fr_vec,
                                                   ctypes.POINTER(vl_tuning), c_vp]
+        L.vl_lora_chain_proof_size.argtypes = [ctypes.POINTER(vl_lora_layer)]
+        L.vl_lora_chain_proof_size.restype = c_u64
+        L.vl_lora_chain_workspace_size.argtypes = [ctypes.POINTER(vl_lora_layer)]
+        L.vl_lora_chain_workspace_size.restype = c_u64
+        L.vl_lora_chain_prove.argtypes = [ctypes.POINTER(vl_lora_layer), c_u64, c_vp, c_u64, c_vp, c_u64, c_vp, c_vp]
+        L.vl_lora_chain_prove.restype = c_i32
         L.vl_proof_size.argtypes = [ctypes.POINTER(vl_group)]
         L.vl_proof_size.restype = c_u64
         L.vl_workspace_size.argtypes = [ctypes.POINTER(vl_group), c_u64, ctypes.POINTER(vl_prove_opts)]
@@ -381,6 +397,49 @@ class ProveGraph:
             self.close()
         except Exception:
             pass
+
+
+class LayerArgs:
+    """vl_lora_layer over a layer's tensors (objects with the attributes of
+    LAYER_INT16 and LAYER_INT64, and F, eta: device tensors for proving),
+    kept alive as long as the structure is used."""
+
+    def __init__(self, w):
+        self.keep = [getattr(w, n) for n in LAYER_INT16 + LAYER_INT64]
+        T, d_in = w.X.shape
+        d_out, r = w.W.shape[1], w.A.shape[1]
+        for n in LAYER_INT16:
+            assert dtype_code(getattr(w, n).dtype) == VL_I16, n
+        for n in LAYER_INT64:
+            assert dtype_code(getattr(w, n).dtype) == VL_I64, n
+        for x in self.keep:
+            rows, cols = x.shape
+            assert _row_stride(x) == max(cols, 1), "layer tensors must be contiguous"
+        self.struct = vl_lora_layer(T, d_in, d_out, r, int(w.F), int(w.eta),
+                                    *[_ptr(getattr(w, n)) for n in LAYER_INT16 + LAYER_INT64])
+
+
+def lora_chain_proof_size(layer: LayerArgs) -> int:
+    return lib().vl_lora_chain_proof_size(ctypes.byref(layer.struct))
+
+
+def lora_chain_workspace_size(layer: LayerArgs) -> int:
+    return lib().vl_lora_chain_workspace_size(ctypes.byref(layer.struct))
+
+
+def lora_chain_prove(layer: LayerArgs, seed: int, workspace=None, stream=None):
+    """Blocking chained proof of one layer's step: returns (proof bytes,
+    final transcript state)."""
+    import torch
+    if workspace is None:
+        workspace = torch.empty(max(256, lora_chain_workspace_size(layer)), dtype=torch.uint8, device="cuda")
+    n = lora_chain_proof_size(layer)
+    buf = ctypes.create_string_buffer(max(n, 1))
+    dig = ctypes.create_string_buffer(32)
+    _check(lib().vl_lora_chain_prove(ctypes.byref(layer.struct), seed, workspace.data_ptr(),
+                                     workspace.numel() * workspace.element_size(), ctypes.addressof(buf), n,
+                                     ctypes.addressof(dig), _stream(stream)))
+    return buf.raw[:n], dig.raw
 
 
 def verify_transcript(proof: bytes, group: GroupArgs, seed: int):

@@ -154,13 +154,7 @@ static hipError_t upload_blob(void* dst, const void* src, uint64_t bytes, hipStr
 // proofs, status words and digests into (one per host thread and device,
 // grown on demand): no copy back after the call's kernels.
 // (kept for the life of the process, like the staging ring)
-struct PinnedOut {
-  void* host = nullptr;
-  void* dev = nullptr;
-  uint64_t cap = 0;
-};
-
-static hipError_t pinned_out(uint64_t bytes, PinnedOut** out) {
+hipError_t pinned_out(uint64_t bytes, PinnedOut** out) {
   thread_local std::map<int, PinnedOut> bufs;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -429,9 +423,28 @@ void Builder::eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uin
     pts.insert(pts.end(), xm.w, xm.w + 8);
   }
   P.points.push_back(pts);
+  P.point_dev.push_back(nullptr);
   // one thread per 4 entries (one for the whole table below 2 variables);
   // pack_len <= 2^nvars
   const uint32_t threads = std::max<uint32_t>(1, (uint32_t)((1ull << x.size()) / 4));
+  P.eq_threads += std::max(threads, (pack_len + 3) / 4);
+  P.eq.push_back(e);
+}
+
+void Builder::eq_job_dev(uint32_t nvars, const uint32_t* point_dev, uint32_t* eq, uint32_t* pack,
+                         uint32_t pack_len, bool pack_r2, bool eq_canon) {
+  EqJob e{};
+  e.nvars = nvars;
+  e.pack_r2 = pack_r2 ? 1u : 0u;
+  e.eq_canon = eq_canon ? 1u : 0u;
+  e.pack_len = pack_len;
+  e.thread_begin = P.eq_threads;
+  e.eq = eq;
+  e.eq_ld = 1ull << nvars;
+  e.pack = pack;
+  P.points.push_back({});
+  P.point_dev.push_back(point_dev);
+  const uint32_t threads = std::max<uint32_t>(1, (uint32_t)((1ull << nvars) / 4));
   P.eq_threads += std::max(threads, (pack_len + 3) / 4);
   P.eq.push_back(e);
 }
@@ -562,6 +575,10 @@ BlobLayout blob_layout(const Plan& P) {
     L.seg[k].rounds = o;
     o = align_up(o + G.rounds.size() * sizeof(RoundsJob), 64);
   }
+  L.evals = o;
+  o = align_up(o + P.evals.size() * sizeof(EvalJob), 64);
+  L.reduces = o;
+  o = align_up(o + P.reduces.size() * sizeof(ReduceJob), 64);
   L.total = align_up(o, 256);
   return L;
 }
@@ -585,10 +602,17 @@ void fill_blob(Plan& P, const BlobLayout& L, uint8_t* dblob) {
   P.blob.assign(L.total, 0);
   uint64_t po = L.points;
   for (size_t i = 0; i < P.eq.size(); ++i) {
+    if (P.point_dev[i]) {   // written on the device by an earlier kernel
+      P.eq[i].point = P.point_dev[i];
+      continue;
+    }
     P.eq[i].point = reinterpret_cast<const uint32_t*>(dblob + po);
     memcpy(P.blob.data() + po, P.points[i].data(), P.points[i].size() * 4);
     po = align_up(po + P.points[i].size() * 4, 64);
   }
+  if (!P.evals.empty()) memcpy(P.blob.data() + L.evals, P.evals.data(), P.evals.size() * sizeof(EvalJob));
+  if (!P.reduces.empty())
+    memcpy(P.blob.data() + L.reduces, P.reduces.data(), P.reduces.size() * sizeof(ReduceJob));
   memcpy(P.blob.data() + L.eq, P.eq.data(), P.eq.size() * sizeof(EqJob));
   for (size_t k = 0; k < P.seg.size(); ++k) {
     const Segment& G = P.seg[k];
@@ -728,6 +752,12 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
     if (e == hipSuccess) e = hipStreamWaitEvent(s, fork.ev[nseg + 1], 0);
     if (e != hipSuccess) return e;
   }
+  if (!P.evals.empty())
+    VL_STAGE(ev, VL_STAGE_ROUNDS, s,
+             launch_eval(reinterpret_cast<const EvalJob*>(dblob + L.evals), (uint32_t)P.evals.size(), s));
+  if (!P.reduces.empty())
+    VL_STAGE(ev, VL_STAGE_ROUNDS, s,
+             launch_reduce(reinterpret_cast<const ReduceJob*>(dblob + L.reduces), (uint32_t)P.reduces.size(), s));
   return hipSuccess;
 }
 
@@ -776,7 +806,7 @@ static Tuning pe_tuning(const vl_tuning* k) {
 // directly.  ws == nullptr plans for sizing only.
 void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, uint64_t g1,
                  uint64_t seed, uint8_t* ws, bool async, uint8_t* proofs_dev, const uint64_t* offsets,
-                 int32_t* status_dev, uint8_t* digests_dev, uint8_t* out) {
+                 int32_t* status_dev, uint8_t* digests_dev, uint8_t* out, const Challenges* given) {
   P = Plan();
   P.persistent = T.persistent;
   const uint64_t blob = blob_bound(groups + g0, g1 - g0);
@@ -784,7 +814,9 @@ void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, 
   P.n_err = (uint32_t)(g1 - g0);
   const uint64_t n = g1 - g0;
   std::vector<Challenges> ch;
-  if (ws) {
+  if (given) {
+    ch.assign(given, given + n);
+  } else if (ws) {
     all_challenges(groups, g0, g1, seed, ch);
   } else {
     // sizing: the challenges do not change any size, only their count matters

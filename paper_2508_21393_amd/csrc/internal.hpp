@@ -135,7 +135,52 @@ struct RoundsJob {
   RoundsProd prods[VL_MAX_PRODS];
 };
 
+// A matrix MLE value M~(x, y) from the pass-1 partial sums of its dot
+// product (a chained proof's evaluation at a random point): the partials are
+// added and the canonical value written as 32 proof bytes.
+struct EvalJob {
+  const uint32_t* part;       // pass-1 partials (element 0 of each is used)
+  uint32_t nparts;
+  uint32_t pad_;
+  uint8_t* out;               // 32 bytes, canonical little-endian
+  const int32_t* err;         // range flag of the contraction
+  int32_t* status;            // VL_OK, or VL_ERR_RANGE
+};
+
+// One phase of a claim reduction (several claims M~(x_k, y_k) = v_k on one
+// matrix turned into one), run by one workgroup:
+//  phase 1: a sumcheck over the row variables of
+//           sum_k rho_k sum_i eq(x_k, i) t_k(i),  t_k(i) = sum_j M[i][j] eq(y_k, j),
+//           tables a[k] = eq(x_k, .) (Montgomery) and b[k] = t_k (canonical);
+//           then the values t_k(r) are sent and absorbed, sigma_1..sigma_K
+//           squeezed; r (Montgomery), sigma and the state go to io
+//  phase 2: a sumcheck over the column variables of
+//           sum_j M~(r, j) sum_k sigma_k eq(y_k, j),
+//           a[0] = M~(r, .) (Montgomery), b[k] = eq(y_k, .) (canonical), their
+//           sigma-combination built into bsum; then M~(r, s) is sent
+constexpr int kMaxClaims = 4;
+struct ReduceJob {
+  uint32_t st[8];             // phase 1: transcript state after the rho squeezes
+  uint32_t coef[kMaxClaims][8];   // phase 1: rho_k, Montgomery
+  uint32_t phase;             // 1 or 2
+  uint32_t K;                 // claims
+  uint32_t n;                 // rounds (row or column variables)
+  uint32_t pad_;
+  uint64_t ld;                // table stride, 2^n
+  uint32_t* a[kMaxClaims];
+  uint32_t* b[kMaxClaims];
+  uint32_t* bsum;             // phase 2: sum_k sigma_k b[k] (2^n entries)
+  uint32_t* io;               // [state: 8][sigma: kMaxClaims x 8][r: n_rows x 8] words
+  uint8_t* proof;             // this phase's proof bytes
+  uint8_t* digest;            // phase 2: final state of the reduction's branch
+  int32_t* status;            // phase 2: VL_OK when done
+};
+constexpr uint32_t kReduceIoSigma = 8, kReduceIoR = 8 + 8 * kMaxClaims;
+constexpr uint32_t reduce_io_words(uint32_t n_rows) { return kReduceIoR + 8 * n_rows; }
+
 // host launchers (kernels.hip)
+hipError_t launch_eval(const EvalJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
+hipError_t launch_reduce(const ReduceJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
 hipError_t launch_eq(const EqJob* jobs_dev, uint32_t n_jobs, uint32_t n_threads, hipStream_t s);
 hipError_t launch_contract(int kind, const ContractJob* jobs_dev, uint32_t n_jobs, uint32_t n_tasks,
                            hipStream_t s);

@@ -700,6 +700,179 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
   }
 }
 
+// ------------------------------------------------------- chained proofs ----
+// M~(x, y) of a chained proof's evaluation step: the pass-1 partials of its
+// dot product added (one block per value) and written canonical.
+__global__ void __launch_bounds__(256) eval_kernel(const EvalJob* __restrict__ jobs) {
+  const EvalJob& J = jobs[blockIdx.x];
+  if (J.err && *(volatile const int32_t*)J.err) {
+    if (threadIdx.x == 0) *J.status = VL_ERR_RANGE;
+    return;
+  }
+  Fr v[1];
+  v[0] = fr_zero();
+  for (uint32_t i = threadIdx.x; i < J.nparts; i += 256) v[0] = fr_add(v[0], lds_or_global_fr(J.part + 24ull * i));
+  __shared__ uint32_t red[8 * 4];
+  wave_sum<1>(v, kWave);
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) red[j * 4 + wave] = v[0].w[j];
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[0].w[j] = lane < 4 ? red[j * 4 + lane] : 0u;
+    wave_sum<1>(v, 4);
+    if (lane == 0) {
+      put_canon(J.out, v[0]);
+      *J.status = VL_OK;
+    }
+  }
+}
+
+// absorb(label, x_0 .. x_{K-1}) for a run-time K <= kMaxClaims
+template <int LN>
+__device__ __forceinline__ void absorb_k(Transcript& tr, const char (&label)[LN], const Fr* xs, uint32_t K) {
+  switch (K) {
+    case 1: { const Fr a[1] = {xs[0]}; tr_absorb_frs(tr, label, a); break; }
+    case 2: { const Fr a[2] = {xs[0], xs[1]}; tr_absorb_frs(tr, label, a); break; }
+    case 3: { const Fr a[3] = {xs[0], xs[1], xs[2]}; tr_absorb_frs(tr, label, a); break; }
+    default: { const Fr a[4] = {xs[0], xs[1], xs[2], xs[3]}; tr_absorb_frs(tr, label, a); break; }
+  }
+}
+
+// One workgroup per reduction phase (ReduceJob).  Both phases are sumchecks
+// of sum_t sum_k a_k[t] b_k[t] over tables in global memory: the a tables in
+// Montgomery form, the b tables canonical, so every product and round value
+// is canonical (as in the rounds kernel).  Round i > 0 folds the tables by
+// the previous challenge in the same sweep that sums the round's pairs (each
+// thread reads and writes only its own entries).  Wave 0 runs the
+// transcript: it writes g(0), g(1), g(2), absorbs them and squeezes r.
+__global__ void __launch_bounds__(kRoundsBlock) reduce_kernel(const ReduceJob* __restrict__ jobs) {
+  const ReduceJob& J = jobs[blockIdx.x];
+  __shared__ uint32_t red[3 * 8 * (kRoundsBlock / kWave)];
+  __shared__ uint32_t bcast[8];
+  const uint32_t tid = threadIdx.x, NT = blockDim.x;
+  const uint32_t wave = tid >> 6, lane = tid & 63u;
+  const uint32_t K = J.phase == 1 ? J.K : 1;
+  const uint64_t ld = J.ld, len = 1ull << J.n;
+  uint32_t* A[kMaxClaims];
+  uint32_t* Bt[kMaxClaims];
+  for (uint32_t k = 0; k < kMaxClaims; ++k) {
+    A[k] = J.a[k];
+    Bt[k] = J.b[k];
+  }
+  Transcript tr;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) tr.h[i] = J.phase == 1 ? J.st[i] : J.io[i];
+  if (J.phase == 1) {
+    // scale the eq(x_k, .) tables by rho_k: the round sums then need no
+    // per-claim coefficient, and folding keeps the scale
+    for (uint32_t k = 0; k < K; ++k) {
+      const Fr rho = lds_or_global_fr(J.coef[k]);
+      for (uint64_t t = tid; t < len; t += NT) store_sol(A[k], ld, t, fr_mul(rho, load_sol(A[k], ld, t)));
+    }
+  } else {
+    // b = sum_k sigma_k eq(y_k, .), canonical
+    Fr sig[kMaxClaims];
+    for (uint32_t k = 0; k < J.K; ++k) sig[k] = lds_or_global_fr(J.io + kReduceIoSigma + 8 * k);
+    for (uint64_t t = tid; t < len; t += NT) {
+      Fr acc = fr_zero();
+      for (uint32_t k = 0; k < J.K; ++k) acc = fr_add(acc, fr_mul(sig[k], load_sol(J.b[k], ld, t)));
+      store_sol(J.bsum, ld, t, acc);
+    }
+    Bt[0] = J.bsum;
+  }
+  __threadfence_block();
+  __syncthreads();
+  uint8_t* out = J.proof;
+  bool pending = false;
+  Fr r = fr_zero();
+  for (uint32_t rd = 0; rd < J.n; ++rd) {
+    const uint32_t h = 1u << (J.n - 1 - rd);
+    Fr g[3];
+    g[0] = g[1] = g[2] = fr_zero();
+    for (uint32_t t = tid; t < h; t += NT) {
+      for (uint32_t k = 0; k < K; ++k) {
+        Fr a0 = load_sol(A[k], ld, t), a1 = load_sol(A[k], ld, t + h);
+        Fr b0 = load_sol(Bt[k], ld, t), b1 = load_sol(Bt[k], ld, t + h);
+        if (pending) {
+          // entries t, t + h of the folded table come from t, t + 2h and
+          // t + h, t + 3h of the table as it stands (half-size 2h)
+          const Fr rr2[2] = {r, r};
+          const Fr da[2] = {fr_sub(load_sol(A[k], ld, t + 2 * h), a0), fr_sub(load_sol(A[k], ld, t + 3 * h), a1)};
+          const Fr db[2] = {fr_sub(load_sol(Bt[k], ld, t + 2 * h), b0), fr_sub(load_sol(Bt[k], ld, t + 3 * h), b1)};
+          Fr fa[2], fb[2];
+          fr_mul_n<2>(rr2, da, fa);
+          fr_mul_n<2>(rr2, db, fb);
+          a0 = fr_add(a0, fa[0]);
+          a1 = fr_add(a1, fa[1]);
+          b0 = fr_add(b0, fb[0]);
+          b1 = fr_add(b1, fb[1]);
+          store_sol(A[k], ld, t, a0);
+          store_sol(A[k], ld, t + h, a1);
+          store_sol(Bt[k], ld, t, b0);
+          store_sol(Bt[k], ld, t + h, b1);
+        }
+        const Fr x[3] = {a0, a1, at_two(a0, a1)}, y[3] = {b0, b1, at_two(b0, b1)};
+        Fr pr[3];
+        fr_mul_n<3>(x, y, pr);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) g[q] = fr_add(g[q], pr[q]);
+      }
+    }
+    __threadfence_block();   // the folded entries, for the next sweep
+    block_sum_w0<3>(g, red);
+    if (wave == 0) {
+      const Fr rr = round_challenge(tr, g, out, lane);
+      if (lane == 0) {
+        lds_put(bcast, rr);
+        if (J.phase == 1)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) J.io[kReduceIoR + 8 * rd + j] = rr.w[j];   // Montgomery, for eq(r, .)
+      }
+    }
+    out += 96;
+    __syncthreads();
+    r = lds_get(bcast);
+    pending = true;
+  }
+  // the last challenge folds the remaining pair of each table
+  if (tid == 0) {
+    Fr fin[kMaxClaims];
+    for (uint32_t k = 0; k < K; ++k) {
+      if (J.phase == 1) {
+        const Fr b0 = load_sol(Bt[k], ld, 0);
+        fin[k] = pending ? fr_add(b0, fr_mul(r, fr_sub(load_sol(Bt[k], ld, 1), b0))) : b0;
+      } else {
+        const Fr a0 = load_sol(A[k], ld, 0);
+        fin[k] = fr_from_mont(pending ? fr_add(a0, fr_mul(r, fr_sub(load_sol(A[k], ld, 1), a0))) : a0);
+      }
+      put_canon(out + 32 * k, fin[k]);
+    }
+    if (J.phase == 1) {
+      // t_k(r) sent and absorbed; sigma_1..sigma_K squeezed for phase 2
+      absorb_k(tr, VL_LBL_RFINAL, fin, K);
+      for (uint32_t k = 0; k < K; ++k) {
+        const Fr sg = fr_to_mont(tr_squeeze_fixed(tr, VL_LBL_SIGMA));
+#pragma unroll
+        for (int j = 0; j < 8; ++j) J.io[kReduceIoSigma + 8 * k + j] = sg.w[j];
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) J.io[i] = tr.h[i];
+    } else {
+      const Fr f1[1] = {fin[0]};
+      tr_absorb_frs(tr, VL_LBL_FINAL, f1);
+      if (J.digest) {
+        uint8_t d[32];
+        tr_to_bytes(tr, d);
+        for (int i = 0; i < 32; ++i) J.digest[i] = d[i];
+      }
+      if (J.status) *J.status = VL_OK;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- lift ------
 template <typename T>
 __global__ void __launch_bounds__(256) lift_kernel(const T* __restrict__ src, uint64_t n,
@@ -779,6 +952,18 @@ hipError_t launch_pass1(const Pass1Job* jobs, uint32_t n_jobs, uint32_t n_blocks
 hipError_t launch_rounds(const RoundsJob* jobs, uint32_t n_jobs, hipStream_t s) {
   if (n_jobs == 0) return hipSuccess;
   hipLaunchKernelGGL(rounds_kernel, dim3(n_jobs), dim3(kRoundsBlock), 0, s, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(const EvalJob* jobs, uint32_t n_jobs, hipStream_t s) {
+  if (n_jobs == 0) return hipSuccess;
+  hipLaunchKernelGGL(eval_kernel, dim3(n_jobs), dim3(256), 0, s, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const ReduceJob* jobs, uint32_t n_jobs, hipStream_t s) {
+  if (n_jobs == 0) return hipSuccess;
+  hipLaunchKernelGGL(reduce_kernel, dim3(n_jobs), dim3(kRoundsBlock), 0, s, jobs);
   return hipGetLastError();
 }
 

@@ -68,8 +68,12 @@ struct Plan {
   uint32_t eq_threads = 0;
   std::vector<Segment> seg;
   std::vector<std::vector<uint32_t>> points;  // per eq job: (x_j, 1 - x_j) Montgomery
+  std::vector<const uint32_t*> point_dev;     // per eq job: a point already in device memory, or null
   uint32_t n_err = 0;
   uint64_t out_proof_bytes = 0;
+  // launched after every segment, in this order, on the caller's stream
+  std::vector<EvalJob> evals;
+  std::vector<ReduceJob> reduces;
 };
 
 struct SegLayout {
@@ -77,7 +81,7 @@ struct SegLayout {
 };
 
 struct BlobLayout {
-  uint64_t err, eq, points, total;
+  uint64_t err, eq, points, evals, reduces, total;
   std::vector<SegLayout> seg;
 };
 
@@ -104,6 +108,10 @@ struct Builder {
                 const uint32_t* pack, uint32_t* dst, uint64_t dst_ld, uint64_t n_total, int32_t* err);
   void eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_len, bool pack_r2,
               bool eq_canon);
+  // eq job of a point that a kernel earlier on the stream writes to device
+  // memory (nvars Montgomery elements at point_dev)
+  void eq_job_dev(uint32_t nvars, const uint32_t* point_dev, uint32_t* eq, uint32_t* pack, uint32_t pack_len,
+                  bool pack_r2, bool eq_canon);
   // pass-1 job over a, b; returns the partials buffer, sets its block count
   const uint32_t* pass1(const uint32_t* a, uint64_t a_ld, const uint32_t* b, uint64_t b_ld, uint32_t h,
                         bool dot, uint32_t& nparts, uint32_t* ready);
@@ -139,8 +147,19 @@ vl_status partial_eval_check(const void* M, int32_t dtype, uint32_t rows, uint32
 vl_status partial_eval_launch(const void* M, int32_t dtype, uint32_t rows, uint32_t cols, uint64_t ld,
                               int32_t contract, vl_fr_vec eq, vl_fr_vec out, void* workspace,
                               uint64_t workspace_bytes, const vl_tuning* tuning, void* stream);
+// given: optional per-group challenges (transcript state after u and v, and
+// u, v themselves) for groups whose point comes from an earlier step of a
+// chained proof; null squeezes them from (seed, group id, shapes)
 void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, uint64_t g1,
                  uint64_t seed, uint8_t* ws, bool async, uint8_t* proofs_dev, const uint64_t* offsets,
-                 int32_t* status_dev, uint8_t* digests_dev, uint8_t* out);
+                 int32_t* status_dev, uint8_t* digests_dev, uint8_t* out, const Challenges* given = nullptr);
+// pinned host memory of this host thread and device that kernels write
+// outputs into (grown on demand, kept for the process)
+struct PinnedOut {
+  void* host = nullptr;
+  void* dev = nullptr;
+  uint64_t cap = 0;
+};
+hipError_t pinned_out(uint64_t bytes, PinnedOut** out);
 
 }  // namespace vl

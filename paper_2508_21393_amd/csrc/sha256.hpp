@@ -273,6 +273,8 @@ VL_HD void tr_from_bytes(Transcript& t, const uint8_t in[32]) {
 #define VL_LBL_ROUND "round"
 #define VL_LBL_R "r"
 #define VL_LBL_FINAL "final"
+#define VL_LBL_RFINAL "rfinal"
+#define VL_LBL_SIGMA "sigma"
 
 VL_HD void tr_init(Transcript& t, uint64_t seed, uint32_t group_id, uint32_t n_prods,
                    const uint32_t* dims /* 3 per product */) {

@@ -253,3 +253,37 @@ def test_partial_eval_workspace_size_covers_strided_layouts(rows, cols, ld, cont
                                ctypes.c_void_p(0x200000), need, ctypes.byref(tn), None)
     assert st != B.VL_ERR_WORKSPACE, B.last_error()
     assert st == B.VL_ERR_HIP
+
+
+def _layer_host(w):
+    return B.LayerArgs(w)
+
+
+@pytest.mark.parametrize("dims", [(8, 12, 10, 3), (1, 3, 2, 2), (512, 4096, 11008, 16), (2048, 5120, 13824, 64)])
+def test_chain_proof_size_matches_the_oracle(dims):
+    from oracle.chain import chain_proof_len
+    _lib_or_skip()
+    T, d_in, d_out, r = dims
+    st = B.vl_lora_layer(T, d_in, d_out, r, 12, 3, *([0] * 15))
+    assert B.lib().vl_lora_chain_proof_size(ctypes_byref(st)) == chain_proof_len(dims)
+    assert B.lib().vl_lora_chain_workspace_size(ctypes_byref(st)) > 0
+
+
+def ctypes_byref(x):
+    import ctypes
+    return ctypes.byref(x)
+
+
+def test_chain_refuses_bad_layers_before_device_work():
+    import ctypes
+    L = _lib_or_skip()
+    st = B.vl_lora_layer(8, 12, 10, 3, 12, 3, *([0x1000] * 15))
+    buf = ctypes.create_string_buffer(64)
+    # proof buffer too small: refused on the host
+    assert L.vl_lora_chain_prove(ctypes.byref(st), 1, 0x10000, 1 << 20, ctypes.addressof(buf), 64, None,
+                                 None) == B.VL_ERR_BUFFER_TOO_SMALL
+    st2 = B.vl_lora_layer(8, 12, 10, 3, 12, 3, *([0x1000] * 14 + [0]))
+    assert L.vl_lora_chain_prove(ctypes.byref(st2), 1, 0x10000, 1 << 20, ctypes.addressof(buf), 64, None,
+                                 None) == B.VL_ERR_INVALID_ARG
+    st3 = B.vl_lora_layer(70000, 12, 10, 3, 12, 3, *([0x1000] * 15))
+    assert L.vl_lora_chain_proof_size(ctypes.byref(st3)) == 0
