@@ -3,12 +3,13 @@
 Only ``oracle`` and ``workloads`` are used: every stored value is what the
 oracle computes for the seeded synthetic inputs.  Usage:
 
-    python tests/golden/make_golden.py [cfg1 cfg1_sweep tiny cfg2 cfg3 cfg4 cfg5 chain] [--procs N]
+    python tests/golden/make_golden.py [cfg1 cfg1_sweep tiny cfg2 cfg3 cfg4 cfg5 chain bmm] [--procs N]
 
 Each config file lists, per group: name, group id, shapes, the SHA-256 of the
 proof bytes and the final transcript state; small configs also keep the full
 proof in hex.  cfg5 lists the requests of the 13B-class serving sample
-(workloads.serving_sample), each with its seed and its groups.
+(workloads.serving_sample), each with its seed and its groups.  bmm lists
+the per-head batched products (oracle/bmm.py).
 """
 import argparse
 import hashlib
@@ -158,6 +159,75 @@ def record_chain():
     return dict(seed=CHAIN_SEED, F=w.F, eta=w.eta, tiny=tiny, layer=full)
 
 
+BMM_TINY = [
+    # (seed, H, D0, D1, D2, options of workloads.tiny_head_batch)
+    (41, 1, 1, 1, 1, {}),
+    (42, 3, 5, 7, 6, dict(transA=True, b_cols=True, c_cols=True)),
+    (43, 2, 3, 1, 5, dict(a_cols=True)),
+    (44, 5, 1, 4, 1, dict(transB=True)),
+    (45, 8, 2, 2, 4, dict(transA=True, transB=True, a_cols=True, b_cols=True)),
+    (46, 3, 70, 33, 130, dict(c_cols=True)),
+    (47, 6, 40, 257, 65, dict(transA=True)),
+    (48, 32, 64, 16, 64, dict(a_cols=True, b_cols=True, transB=True)),
+    (49, 4, 300, 129, 20, dict(b_cols=True, c_cols=True)),
+    # tables of 2^14 .. 2^15 entries: the first rounds run GPU-wide
+    (50, 8, 3, 2048, 5, dict(b_cols=True)),
+    (51, 2, 2, 16384, 3, dict(transA=True)),
+    (52, 1, 4, 20000, 2, {}),
+]
+ATTN_SMALL = dict(seed=7, T=256, H=4, dh=32)
+ATTN_FULL = dict(seed=6, T=2048, H=32, dh=128)
+BMM_SEED = 41
+
+_BATCHES = None
+
+
+def _prove_batch(i):
+    from oracle.bmm import prove_batch
+    t = time.time()
+    proof, state, _ = prove_batch(_BATCHES[i], BMM_SEED)
+    return i, proof, state, time.time() - t
+
+
+def _bmm_records(batches, keep_hex, procs):
+    global _BATCHES
+    _BATCHES = batches
+    idx = list(range(len(batches)))
+    if procs > 1:
+        with mp.get_context("fork").Pool(min(procs, len(idx))) as pool:
+            res = pool.map(_prove_batch, idx, chunksize=1)
+    else:
+        res = [_prove_batch(i) for i in idx]
+    out = []
+    for i, proof, state, dt in sorted(res):
+        b = batches[i]
+        e = dict(name=b.name, group_id=b.group_id, dims=list(b.dims), proof_sha256=hashlib.sha256(proof).hexdigest(),
+                 state=state.hex(), proof_len=len(proof))
+        if keep_hex:
+            e["proof_hex"] = proof.hex()
+        out.append(e)
+        print(f"  {b.name:12s} {b.dims} {dt:7.1f}s", flush=True)
+    return out
+
+
+def record_bmm(procs: int):
+    """Per-head batched products (oracle/bmm.py): the tiny cases and a small
+    attention layer in full, the 7B-class attention layer (T = 2048, 32 heads
+    of 128) by digest."""
+    tiny = []
+    for k, (seed, H, d0, d1, d2, kw) in enumerate(BMM_TINY):
+        b = workloads.tiny_head_batch(seed, H, d0, d1, d2, name=f"bmm{k}", **kw)
+        b.group_id = k
+        tiny.append(b)
+    data = dict(seed=BMM_SEED, tiny_spec=[[s, H, d0, d1, d2, kw] for s, H, d0, d1, d2, kw in BMM_TINY],
+                tiny=_bmm_records(tiny, True, procs))
+    data["attn_small_spec"] = ATTN_SMALL
+    data["attn_small"] = _bmm_records(workloads.attention_layer(**ATTN_SMALL), True, procs)
+    data["attn_full_spec"] = ATTN_FULL
+    data["attn_full"] = _bmm_records(workloads.attention_layer(**ATTN_FULL), False, procs)
+    return data
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("configs", nargs="*", default=["cfg1", "tiny", "cfg2", "cfg3"])
@@ -169,6 +239,12 @@ def main():
         if name == "chain":
             data = record_chain()
             with open(os.path.join(HERE, "chain.json"), "w") as f:
+                json.dump(data, f, indent=1)
+            print(f"{name}: done in {time.time() - t:.1f}s", flush=True)
+            continue
+        if name == "bmm":
+            data = record_bmm(args.procs)
+            with open(os.path.join(HERE, "bmm.json"), "w") as f:
                 json.dump(data, f, indent=1)
             print(f"{name}: done in {time.time() - t:.1f}s", flush=True)
             continue

@@ -436,3 +436,174 @@ def make_config(name: str, **kw) -> Workload:
     fn: Callable[..., Workload] = {"cfg1": config1, "cfg2": config2, "cfg3": config3,
                                    "cfg4": config4}[name]
     return fn(**kw)
+
+
+# --------------------------------------------------------------------------
+# per-head (batched) products: multi-head attention
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class HeadView:
+    """H matrices of one shape inside one stored, C-contiguous array: head k
+    is the rows x cols matrix at element offset k * head_stride, row-major with
+    leading dimension ld (in elements)."""
+    base: np.ndarray
+    H: int
+    rows: int
+    cols: int
+    head_stride: int
+    ld: int
+
+    def heads(self) -> np.ndarray:
+        flat = self.base.reshape(-1)
+        es = flat.itemsize
+        need = (self.H - 1) * self.head_stride + (self.rows - 1) * self.ld + self.cols
+        assert need <= flat.size and self.cols <= self.ld
+        return np.lib.stride_tricks.as_strided(flat, shape=(self.H, self.rows, self.cols),
+                                               strides=(self.head_stride * es, self.ld * es, es),
+                                               writeable=False)
+
+
+@dataclasses.dataclass
+class HeadBatch:
+    """C_k = op(A_k) op(B_k) for every head k (op: identity or transpose of
+    the stored head matrix)."""
+    name: str
+    A: HeadView
+    B: HeadView
+    C: HeadView
+    transA: bool = False
+    transB: bool = False
+    group_id: int = 0
+
+    def opA_heads(self) -> List[np.ndarray]:
+        return [m.T if self.transA else m for m in self.A.heads()]
+
+    def opB_heads(self) -> List[np.ndarray]:
+        return [m.T if self.transB else m for m in self.B.heads()]
+
+    def C_heads(self) -> List[np.ndarray]:
+        return list(self.C.heads())
+
+    @property
+    def dims(self):
+        a, b = self.opA_heads()[0], self.opB_heads()[0]
+        assert a.shape[1] == b.shape[0]
+        return (self.A.H, int(a.shape[0]), int(a.shape[1]), int(b.shape[1]))
+
+
+def cols_heads(M: np.ndarray, H: int) -> HeadView:
+    """Heads side by side in the columns of a T x (H * dh) matrix."""
+    T, W = M.shape
+    dh = W // H
+    return HeadView(M, H, T, dh, dh, W)
+
+
+def stacked_heads(M: np.ndarray) -> HeadView:
+    """Heads stacked in the leading index of an H x rows x cols array."""
+    H, R, Cc = M.shape
+    return HeadView(M, H, R, Cc, R * Cc, Cc)
+
+
+def _batched_witness(A: HeadView, B: HeadView, transA: bool, transB: bool, out_shape, out_view,
+                     device=None) -> HeadView:
+    C = np.zeros(out_shape, dtype=np.int64)
+    view = out_view(C)
+    ah, bh = A.heads(), B.heads()
+    for k in range(A.H):
+        a = ah[k].T if transA else ah[k]
+        b = bh[k].T if transB else bh[k]
+        res = exact_matmul(np.ascontiguousarray(a), np.ascontiguousarray(b), device=device)
+        flat = C.reshape(-1)
+        for i in range(res.shape[0]):
+            o = k * view.head_stride + i * view.ld
+            flat[o:o + res.shape[1]] = res[i]
+    return view
+
+
+_EXP_TAB = None
+
+
+def int_softmax(S: np.ndarray, dh: int) -> np.ndarray:
+    """Row softmax of S / (2^24 sqrt(dh)) quantised at scale 2^12, in integer
+    arithmetic so that every machine draws the same bytes: the gap to the
+    row maximum is cut to k = floor(256 * gap) (at most 4095), exp(-k / 256)
+    comes from a table of round(2^20 exp(-k / 256)), and each row is
+    normalised by integer division with rounding."""
+    global _EXP_TAB
+    import math
+    if _EXP_TAB is None:
+        _EXP_TAB = np.array([int(round(math.exp(-k / 256.0) * (1 << 20))) for k in range(4096)], dtype=np.int64)
+    q = int(round((1 << 24) * math.sqrt(dh) / 256.0))
+    S = np.asarray(S, dtype=np.int64)
+    k = np.minimum((S.max(axis=1, keepdims=True) - S) // q, 4095)
+    e = _EXP_TAB[k]
+    tot = e.sum(axis=1, keepdims=True)
+    return ((e * (1 << SCALE_BITS) + tot // 2) // tot).astype(np.int16)
+
+
+def attention_layer(seed: int = 6, T: int = 2048, H: int = 32, dh: int = 128, device=None) -> List[HeadBatch]:
+    """The per-head products of one attention layer's forward and backward
+    pass (7B-class: 32 heads of dimension 128): S = Q K^T, O = P V,
+    dP = dO V^T, dV = P^T dO, dQ = dS K, dK = dS^T Q for every head.
+
+    Q, K, V, dO are T x (H dh) int16 activations (sigma = 1 at scale 2^12).
+    P is the row softmax of S / (2^24 sqrt(dh)) quantised at scale 2^12
+    (entries 0..4096, ``int_softmax``); dS is drawn like an activation
+    (H x T x T).  Softmax and
+    its gradient are not proved here (lookup arguments); P and dS are witness
+    inputs.  S and dP are stored H x T x T, O, dV, dQ, dK as T x (H dh)."""
+    rng = np.random.default_rng([seed, 91])
+    Q = quantize_gaussian(rng, (T, H * dh), 1.0)
+    K = quantize_gaussian(rng, (T, H * dh), 1.0)
+    V = quantize_gaussian(rng, (T, H * dh), 1.0)
+    dO = quantize_gaussian(rng, (T, H * dh), 1.0)
+    dS = quantize_gaussian(rng, (H, T, T), 1.0)
+    q, k, v, do = cols_heads(Q, H), cols_heads(K, H), cols_heads(V, H), cols_heads(dO, H)
+    ds = stacked_heads(dS)
+    tt = (H, T, T)
+    S = _batched_witness(q, k, False, True, tt, stacked_heads, device)
+    P = np.empty(tt, dtype=np.int16)
+    for h in range(H):
+        P[h] = int_softmax(S.base[h], dh)
+    p = stacked_heads(P)
+    cols = lambda M: cols_heads(M, H)  # noqa: E731
+    O = _batched_witness(p, v, False, False, (T, H * dh), cols, device)
+    dP = _batched_witness(do, v, False, True, tt, stacked_heads, device)
+    dV = _batched_witness(p, do, True, False, (T, H * dh), cols, device)
+    dQ = _batched_witness(ds, k, False, False, (T, H * dh), cols, device)
+    dK = _batched_witness(ds, q, True, False, (T, H * dh), cols, device)
+    out = [HeadBatch("S=QK^T", q, k, S, False, True), HeadBatch("O=PV", p, v, O, False, False),
+           HeadBatch("dP=dOV^T", do, v, dP, False, True), HeadBatch("dV=P^TdO", p, do, dV, True, False),
+           HeadBatch("dQ=dSK", ds, k, dQ, False, False), HeadBatch("dK=dS^TQ", ds, q, dK, True, False)]
+    for i, b in enumerate(out):
+        b.group_id = i
+    return out
+
+
+def tiny_head_batch(seed: int, H: int, d0: int, d1: int, d2: int, transA: bool = False, transB: bool = False,
+                    a_cols: bool = False, b_cols: bool = False, c_cols: bool = False,
+                    value_bits: Optional[int] = None, name: str = "bmm") -> HeadBatch:
+    """H random heads of op(A) d0 x d1 and op(B) d1 x d2 (int16, uniform, or
+    within +-2^value_bits).  *_cols: that operand's heads sit side by side in
+    the columns of one matrix (as Q, K, V do), else stacked in an
+    H x rows x cols array; the stored head matrix is op's transpose when the
+    trans flag is set."""
+    rng = np.random.default_rng([seed, 92])
+    lo, hi = I16_MIN, I16_MAX
+    if value_bits is not None:
+        lo, hi = -(1 << value_bits), (1 << value_bits) - 1
+
+    def draw(rows, cols, side):
+        if side:
+            M = rng.integers(lo, hi + 1, size=(rows, H * cols), dtype=np.int64).astype(np.int16)
+            return cols_heads(M, H)
+        M = rng.integers(lo, hi + 1, size=(H, rows, cols), dtype=np.int64).astype(np.int16)
+        return stacked_heads(M)
+
+    A = draw(d1, d0, a_cols) if transA else draw(d0, d1, a_cols)
+    B = draw(d2, d1, b_cols) if transB else draw(d1, d2, b_cols)
+    if c_cols:
+        C = _batched_witness(A, B, transA, transB, (d0, H * d2), lambda M: cols_heads(M, H))
+    else:
+        C = _batched_witness(A, B, transA, transB, (H, d0, d2), stacked_heads)
+    return HeadBatch(name, A, B, C, transA, transB)
