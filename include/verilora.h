@@ -371,6 +371,71 @@ uint64_t vl_lora_chain_workspace_size(const vl_lora_layer* layer);
 vl_status vl_lora_chain_prove(const vl_lora_layer* layer, uint64_t seed, void* workspace, uint64_t workspace_bytes,
                               uint8_t* proof, uint64_t proof_len, uint8_t* digest, void* stream);
 
+/* Per-head batched products (multi-head attention, Sec. III-A, eq. (att):
+ * S_h = Q_h K_h^T and O_h = P_h V_h for every head h, and the backward
+ * products dP = dO V^T, dV = P^T dO, dQ = dS K, dK = dS^T Q).  One vl_bmm
+ * states C_h = op(A_h) op(B_h) for h < H; all H are proved by one sumcheck
+ * over the head variables and the inner variables of
+ *     C~(rho, u, v) = sum_h sum_w eq(rho, h) A~(h, u, w) B~(h, w, v),
+ * the multilinear extension of eq. (MLE) over (head, row, column) with the
+ * head index most significant and every dimension zero padded to a power of
+ * two (Sec. II-C), for random rho, u, v (squeezed in that order).  Head
+ * rounds come first and have degree 3; the inner rounds have degree 2 (the
+ * matmul sumcheck of eq. (zk-mle-matmul) scaled by eq(rho, r_h)).
+ * Head h's stored A is the matrix at A + h * head_stride_a elements: D0 x D1
+ * row-major with leading dimension lda, or D1 x D0 if trans_a (op = its
+ * transpose); likewise B (D1 x D2, or D2 x D1 if trans_b) and C (D0 x D2,
+ * ldc).  Heads may sit side by side in the columns of one matrix (Q of
+ * T x (H dh): head_stride = dh, ld = H dh) or stacked (an H x T x T array:
+ * head_stride = T T, ld = T).  Pointers are device memory for proving and
+ * host memory (or NULL) for verification.
+ * Transcript: st = H("VeriLoRA-zkBMat-v1" || u64 seed || u32 group_id ||
+ * u32 H || u32 D0 || u32 D1 || u32 D2), squeezes "h" (nh), "u" (n0), "v"
+ * (n2), absorbs "claim" c, "round" (4 values per head round, 3 per inner
+ * round, challenge "r"), "final" (a_final || b_final).
+ * Proof: c || (g0..g3) per head round || (g0, g1, g2) per inner round ||
+ * a_final || b_final, 32-byte canonical elements; vl_bmm_proof_size bytes.
+ * Limits: H, D0, D1, D2 in 1 .. 2^20, nh + n1 <= 26. */
+typedef struct {
+  const void* A;
+  const void* B;
+  const void* C;
+  int32_t dtype_a, dtype_b, dtype_c;
+  uint32_t H, D0, D1, D2;
+  uint64_t lda, ldb, ldc;
+  uint64_t head_stride_a, head_stride_b, head_stride_c;
+  int32_t trans_a, trans_b;
+  uint32_t group_id;
+} vl_bmm;
+
+uint64_t vl_bmm_proof_size(const vl_bmm* b);
+uint64_t vl_bmm_workspace_size(const vl_bmm* b, uint64_t n);
+/* Prove n batched products with the sumcheck rounds of Sec. II-B.1 over the
+ * statement above (blocking: returns after every proof is in the
+ * host buffer proofs; group k's proof at offsets[k], offsets has n + 1
+ * entries).  digests: optional host buffer of 32 bytes per product (the
+ * final transcript state).  workspace: device memory of at least
+ * vl_bmm_workspace_size bytes, 256-byte aligned.  The proof of a product
+ * depends only on its matrices, seed and group_id.  Errors: VL_ERR_INVALID_ARG,
+ * VL_ERR_SHAPE, VL_ERR_DTYPE, VL_ERR_WORKSPACE, VL_ERR_BUFFER_TOO_SMALL,
+ * VL_ERR_FALSE_STATEMENT (some product's C is not the heads' products),
+ * VL_ERR_RANGE, VL_ERR_HIP. */
+vl_status vl_bmm_prove(const vl_bmm* b, uint64_t n, uint64_t seed, void* workspace, uint64_t workspace_bytes,
+                       uint8_t* proofs, uint64_t proofs_len, uint64_t* offsets, uint8_t* digests, void* stream);
+/* Host verifier (CPU only) of one batched proof: the rounds as above
+ * (g(0) + g(1) equals the running claim; the claim moves to g(r) by
+ * interpolation on {0, 1, 2, 3} or {0, 1, 2}), and the last claim must be
+ * eq(rho, r_h) a_final b_final.  If b's A, B and C are all non-NULL they are
+ * read as host tensors and c = C~(rho, u, v), a_final = A~(r_h, u, r_w),
+ * b_final = B~(r_h, r_w, v) are checked by direct evaluation (standing in for
+ * the commitment openings of Sec. II-A; the same caveat as
+ * vl_verify_transcript: nothing binds C before the challenges).
+ * reduced: optional, canonical: c, rho[nh], u[n0], v[n2], r[nh + n1],
+ * a_final, b_final.  fail_round: 1-based failing round, 0 for a length,
+ * encoding, final or witness failure, -1 on VL_OK. */
+vl_status vl_bmm_verify(const uint8_t* proof, uint64_t len, const vl_bmm* b, uint64_t seed, vl_fr* reduced,
+                        uint64_t reduced_cap, uint64_t* reduced_len, int32_t* fail_round);
+
 /* Message for the last non-OK status on this thread. */
 const char* vl_last_error(void);
 

@@ -33,7 +33,8 @@ EXPORTED = ("vl_fr_lift", "vl_fr_export", "vl_eq_table", "vl_partial_eval_worksp
             "vl_sumcheck_matmul_prove", "vl_verify_transcript", "vl_last_error",
             "vl_prove_graph_create", "vl_prove_graph_launch", "vl_prove_graph_destroy",
             "vl_mle_partial_eval_noalloc", "vl_lora_chain_proof_size", "vl_lora_chain_workspace_size",
-            "vl_lora_chain_prove")
+            "vl_lora_chain_prove", "vl_bmm_proof_size", "vl_bmm_workspace_size", "vl_bmm_prove",
+            "vl_bmm_verify")
 NOALLOC_SCRATCH_BYTES = 64 << 20   # VL_NOALLOC_SCRATCH_BYTES
 
 c_u32, c_u64, c_i32, c_vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p
@@ -85,6 +86,13 @@ class vl_lora_layer(ctypes.Structure):
         [(n, c_vp) for n in ("X", "W", "A", "B", "dY", "H", "G", "Y", "C2", "C4", "dA", "dB", "dX", "UA", "UB")]
 
 
+class vl_bmm(ctypes.Structure):
+    _fields_ = [("A", c_vp), ("B", c_vp), ("C", c_vp), ("dtype_a", c_i32), ("dtype_b", c_i32), ("dtype_c", c_i32),
+                ("H", c_u32), ("D0", c_u32), ("D1", c_u32), ("D2", c_u32), ("lda", c_u64), ("ldb", c_u64),
+                ("ldc", c_u64), ("head_stride_a", c_u64), ("head_stride_b", c_u64), ("head_stride_c", c_u64),
+                ("trans_a", c_i32), ("trans_b", c_i32), ("group_id", c_u32)]
+
+
 LAYER_INT16 = ("X", "W", "A", "B", "dY", "H", "G")
 LAYER_INT64 = ("Y", "C2", "C4", "dA", "dB", "dX", "UA", "UB")
 
@@ -130,6 +138,16 @@ def lib():
                                            ctypes.POINTER(vl_fr), c_u64, ctypes.POINTER(c_u64),
                                            ctypes.POINTER(c_i32)]
         L.vl_last_error.restype = ctypes.c_char_p
+        L.vl_bmm_proof_size.argtypes = [ctypes.POINTER(vl_bmm)]
+        L.vl_bmm_proof_size.restype = c_u64
+        L.vl_bmm_workspace_size.argtypes = [ctypes.POINTER(vl_bmm), c_u64]
+        L.vl_bmm_workspace_size.restype = c_u64
+        L.vl_bmm_prove.argtypes = [ctypes.POINTER(vl_bmm), c_u64, c_u64, c_vp, c_u64, c_vp, c_u64,
+                                   ctypes.POINTER(c_u64), c_vp, c_vp]
+        L.vl_bmm_prove.restype = c_i32
+        L.vl_bmm_verify.argtypes = [c_vp, c_u64, ctypes.POINTER(vl_bmm), c_u64, ctypes.POINTER(vl_fr), c_u64,
+                                    ctypes.POINTER(c_u64), ctypes.POINTER(c_i32)]
+        L.vl_bmm_verify.restype = c_i32
         L.vl_prove_graph_create.argtypes = [ctypes.POINTER(vl_group), c_u64, ctypes.POINTER(vl_prove_opts), c_vp,
                                             c_u64, ctypes.POINTER(c_u64), c_vp, ctypes.POINTER(c_vp)]
         L.vl_prove_graph_launch.argtypes = [c_vp, c_u64, c_vp]
@@ -451,6 +469,72 @@ def verify_transcript(proof: bytes, group: GroupArgs, seed: int):
     buf = ctypes.create_string_buffer(proof, max(len(proof), 1))
     st = lib().vl_verify_transcript(ctypes.addressof(buf), len(proof), ctypes.byref(group.struct), seed,
                                     red, cap, ctypes.byref(rlen), ctypes.byref(fr_))
+    if st not in (VL_OK, VL_ERR_REJECT):
+        _check(st)
+    return st == VL_OK, fr_.value, [fr_to_int(red[i]) for i in range(rlen.value)] if st == VL_OK else []
+
+
+# ------------------------------------------------------- batched products --
+class BmmArgs:
+    """vl_bmm over H head matrices of each operand inside stored tensors
+    (torch tensors on the device for proving, numpy arrays or None on the
+    host for verification): head h of A starts head_stride_a elements after
+    head h - 1, row-major with leading dimension lda (likewise B, C).  The
+    tensors are kept alive as long as the structure is used."""
+
+    def __init__(self, A, B, C, H: int, D0: int, D1: int, D2: int, lda: int, ldb: int, ldc: int,
+                 head_stride_a: int, head_stride_b: int, head_stride_c: int, trans_a: bool = False,
+                 trans_b: bool = False, group_id: int = 0, dtypes=None):
+        self.keep = (A, B, C)
+        dts = dtypes or [dtype_code(x.dtype) for x in (A, B, C)]
+        ptr = lambda x: _ptr(x) if x is not None else None  # noqa: E731
+        self.struct = vl_bmm(ptr(A), ptr(B), ptr(C), dts[0], dts[1], dts[2], H, D0, D1, D2, lda, ldb, ldc,
+                             head_stride_a, head_stride_b, head_stride_c, int(bool(trans_a)), int(bool(trans_b)),
+                             group_id)
+
+    @property
+    def dims(self):
+        s = self.struct
+        return (s.H, s.D0, s.D1, s.D2)
+
+
+def bmm_proof_size(b: BmmArgs) -> int:
+    return lib().vl_bmm_proof_size(ctypes.byref(b.struct))
+
+
+def bmm_workspace_size(batches: Sequence[BmmArgs]) -> int:
+    arr = (vl_bmm * len(batches))(*[b.struct for b in batches])
+    return lib().vl_bmm_workspace_size(arr, len(batches))
+
+
+def bmm_prove(batches: Sequence[BmmArgs], seed: int, workspace=None, stream=None):
+    """Blocking proofs of batched products: returns (proofs, digests), one
+    bytes object each per product."""
+    import torch
+    n = len(batches)
+    arr = (vl_bmm * n)(*[b.struct for b in batches])
+    if workspace is None:
+        workspace = torch.empty(max(256, lib().vl_bmm_workspace_size(arr, n)), dtype=torch.uint8, device="cuda")
+    total = sum(bmm_proof_size(b) for b in batches)
+    buf = ctypes.create_string_buffer(max(total, 1))
+    dig = ctypes.create_string_buffer(32 * n)
+    offs = (c_u64 * (n + 1))()
+    _check(lib().vl_bmm_prove(arr, n, seed, workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                              ctypes.addressof(buf), total, offs, ctypes.addressof(dig), _stream(stream)))
+    raw = buf.raw
+    return [raw[offs[k]:offs[k + 1]] for k in range(n)], [dig.raw[32 * k:32 * k + 32] for k in range(n)]
+
+
+def bmm_verify(proof: bytes, b: BmmArgs, seed: int):
+    """Host verifier of one batched proof.  Returns (ok, fail_round, reduced
+    claims as ints)."""
+    cap = 4096
+    red = (vl_fr * cap)()
+    rlen = c_u64(0)
+    fr_ = c_i32(0)
+    buf = ctypes.create_string_buffer(proof, max(len(proof), 1))
+    st = lib().vl_bmm_verify(ctypes.addressof(buf), len(proof), ctypes.byref(b.struct), seed, red, cap,
+                             ctypes.byref(rlen), ctypes.byref(fr_))
     if st not in (VL_OK, VL_ERR_REJECT):
         _check(st)
     return st == VL_OK, fr_.value, [fr_to_int(red[i]) for i in range(rlen.value)] if st == VL_OK else []

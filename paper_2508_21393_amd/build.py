@@ -16,7 +16,8 @@ LIB = os.path.join(HERE, "libverilora.so")
 PEAK_LIB = os.path.join(HERE, "libvlpeak.so")
 ARCH = "gfx950"
 
-SOURCES = ["contract.hip", "kernels.hip", "capi.cpp", "verify.cpp", "noalloc.hip", "chain.cpp"]
+SOURCES = ["contract.hip", "kernels.hip", "capi.cpp", "verify.cpp", "noalloc.hip", "chain.cpp",
+           "bmm.hip", "bmm.cpp"]
 PEAK_SOURCES = ["peak.hip"]
 
 # packed FP32 instructions stay off in all device code; hipcc's host pass warns

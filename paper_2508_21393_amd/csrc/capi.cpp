@@ -534,6 +534,19 @@ void Builder::group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev,
   (T.persistent ? P.seg[0] : S()).rounds.push_back(rj);
 }
 
+void Builder::zero_fill(uint32_t* dst, uint64_t ld, uint32_t n) {
+  if (!n) return;
+  FinishJob f{};
+  f.n_valid = 0;
+  f.n_total = n;
+  f.out = dst;
+  f.out_ld = ld;
+  f.split = 0;
+  f.block_begin = S().fin_blocks;
+  S().fin_blocks += (n + 255) / 256;
+  S().fin.push_back(f);
+}
+
 const uint32_t* Builder::pass1(const uint32_t* a, uint64_t a_ld, const uint32_t* b, uint64_t b_ld, uint32_t h,
                                bool dot, uint32_t& nparts, uint32_t* ready) {
   Pass1Job j{};
@@ -579,6 +592,13 @@ BlobLayout blob_layout(const Plan& P) {
   o = align_up(o + P.evals.size() * sizeof(EvalJob), 64);
   L.reduces = o;
   o = align_up(o + P.reduces.size() * sizeof(ReduceJob), 64);
+  L.bmms = o;
+  o = align_up(o + P.bmms.size() * sizeof(BmmJob), 64);
+  L.bmm_wide.resize(P.bmm_wide.size());
+  for (size_t k = 0; k < P.bmm_wide.size(); ++k) {
+    L.bmm_wide[k] = o;
+    o = align_up(o + P.bmm_wide[k].size() * sizeof(BmmSweep), 64);
+  }
   L.total = align_up(o, 256);
   return L;
 }
@@ -613,6 +633,9 @@ void fill_blob(Plan& P, const BlobLayout& L, uint8_t* dblob) {
   if (!P.evals.empty()) memcpy(P.blob.data() + L.evals, P.evals.data(), P.evals.size() * sizeof(EvalJob));
   if (!P.reduces.empty())
     memcpy(P.blob.data() + L.reduces, P.reduces.data(), P.reduces.size() * sizeof(ReduceJob));
+  if (!P.bmms.empty()) memcpy(P.blob.data() + L.bmms, P.bmms.data(), P.bmms.size() * sizeof(BmmJob));
+  for (size_t k = 0; k < P.bmm_wide.size(); ++k)
+    memcpy(P.blob.data() + L.bmm_wide[k], P.bmm_wide[k].data(), P.bmm_wide[k].size() * sizeof(BmmSweep));
   memcpy(P.blob.data() + L.eq, P.eq.data(), P.eq.size() * sizeof(EqJob));
   for (size_t k = 0; k < P.seg.size(); ++k) {
     const Segment& G = P.seg[k];
@@ -758,6 +781,18 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
   if (!P.reduces.empty())
     VL_STAGE(ev, VL_STAGE_ROUNDS, s,
              launch_reduce(reinterpret_cast<const ReduceJob*>(dblob + L.reduces), (uint32_t)P.reduces.size(), s));
+  if (!P.bmms.empty()) {
+    const BmmJob* bj = reinterpret_cast<const BmmJob*>(dblob + L.bmms);
+    const uint32_t nb = (uint32_t)P.bmms.size();
+    VL_STAGE(ev, VL_STAGE_PASS1, s, launch_bmm_start(bj, nb, s));
+    for (size_t k = 0; k < P.bmm_wide.size(); ++k) {
+      const BmmSweep* lst = reinterpret_cast<const BmmSweep*>(dblob + L.bmm_wide[k]);
+      const uint32_t nl = (uint32_t)P.bmm_wide[k].size();
+      VL_STAGE(ev, VL_STAGE_PASS1, s, launch_bmm_sweep(bj, lst, nl, P.bmm_wide_blocks[k], (uint32_t)k, s));
+      VL_STAGE(ev, VL_STAGE_ROUNDS, s, launch_bmm_chal(bj, lst, nl, (uint32_t)k, s));
+    }
+    VL_STAGE(ev, VL_STAGE_ROUNDS, s, launch_bmm_rounds(bj, nb, s));
+  }
   return hipSuccess;
 }
 

@@ -178,6 +178,46 @@ struct ReduceJob {
 constexpr uint32_t kReduceIoSigma = 8, kReduceIoR = 8 + 8 * kMaxClaims;
 constexpr uint32_t reduce_io_words(uint32_t n_rows) { return kReduceIoR + 8 * n_rows; }
 
+// One per-head batched product (vl_bmm_prove): C_h = A_h B_h for h < H as
+// one sumcheck over (head, inner) variables of
+//     sum_{h, w} eq(rho, h) a[h, w] b[h, w],  a[h, w] = A~(h, u, w),
+//     b[h, w] = B~(h, w, v),
+// head variables first (rounds of degree 3, eq(rho, .) folded along), then
+// the inner ones (degree 2, scaled by the folded eq value).  Tables: E =
+// eq(rho, .) (2^nh entries, Montgomery), a (Montgomery) and b (canonical)
+// over 2^(nh + n1) entries, head index most significant, so every round
+// value is canonical.  The first `wide` rounds run as GPU-wide sweeps
+// (bmm_sweep_kernel, one launch per round) each followed by a one-wave
+// transcript step (bmm_chal_kernel); the rest run in one workgroup
+// (bmm_rounds_kernel).  io holds the state handed between the launches.
+constexpr uint32_t kBmmSweepPairs = 256;     // pairs per sweep block (one per thread)
+constexpr uint32_t kBmmWidePairs = 4096;     // rounds with at least this many pairs run wide
+constexpr uint32_t kBmmMaxWide = 24;
+// io words: [0] status (VL_OK while running), [8, 16) transcript state,
+// [16, 24) pending challenge r (Montgomery), [24, 32) the claim c (canonical)
+constexpr uint32_t kBmmIoState = 8, kBmmIoR = 16, kBmmIoC = 24, kBmmIoWords = 32;
+struct BmmJob {
+  uint32_t st[8];             // transcript state after squeezing rho, u, v
+  uint32_t nh, n1;            // head and inner variables
+  uint32_t wide;              // rounds done by the sweep/chal launches
+  uint32_t c_nparts;
+  const uint32_t* c_part;     // pass-1 partials of the claim's dot product
+  uint32_t* E;                // ld 2^nh
+  uint32_t* a;                // ld 2^(nh + n1)
+  uint32_t* b;
+  uint32_t* part;             // sweep partials: 4 elements (32 words) per block
+  uint32_t* io;
+  uint8_t* proof;             // device-writable proof bytes
+  uint8_t* digest;            // 32 bytes or null
+  int32_t* status;            // device-writable status word
+  const int32_t* err;         // range flag of the job's contractions
+};
+// a job's part in one wide round: its blocks start at block_begin
+struct BmmSweep {
+  uint32_t job;
+  uint32_t block_begin;
+};
+
 // host launchers (kernels.hip)
 hipError_t launch_eval(const EvalJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
 hipError_t launch_reduce(const ReduceJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
@@ -193,6 +233,13 @@ hipError_t launch_eq_point(const EqPointArgs& a, hipStream_t s);
 hipError_t launch_pack(const uint32_t* eq, uint64_t ld, uint64_t len, uint32_t* pack, hipStream_t s);
 hipError_t launch_upload(void* dst, const void* src, uint64_t bytes, hipStream_t s);
 hipError_t launch_zero_words(uint32_t* p, uint64_t n_words, hipStream_t s);
+// batched products (bmm.hip)
+hipError_t launch_bmm_start(const BmmJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
+hipError_t launch_bmm_sweep(const BmmJob* jobs_dev, const BmmSweep* list_dev, uint32_t n_list, uint32_t n_blocks,
+                            uint32_t round, hipStream_t s);
+hipError_t launch_bmm_chal(const BmmJob* jobs_dev, const BmmSweep* list_dev, uint32_t n_list, uint32_t round,
+                           hipStream_t s);
+hipError_t launch_bmm_rounds(const BmmJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
 // bytes (a multiple of 16, both pointers 16-byte aligned) from pinned host
 // memory, given by its device-side address
 hipError_t launch_copy_in(void* dst, const void* src_dev, uint64_t bytes, hipStream_t s);

@@ -74,6 +74,11 @@ struct Plan {
   // launched after every segment, in this order, on the caller's stream
   std::vector<EvalJob> evals;
   std::vector<ReduceJob> reduces;
+  // per-head batched products: start, wide rounds (per round, the jobs and
+  // their first blocks), the one-workgroup rounds
+  std::vector<BmmJob> bmms;
+  std::vector<std::vector<BmmSweep>> bmm_wide;
+  std::vector<uint32_t> bmm_wide_blocks;
 };
 
 struct SegLayout {
@@ -81,8 +86,9 @@ struct SegLayout {
 };
 
 struct BlobLayout {
-  uint64_t err, eq, points, evals, reduces, total;
+  uint64_t err, eq, points, evals, reduces, bmms, total;
   std::vector<SegLayout> seg;
+  std::vector<uint64_t> bmm_wide;
 };
 
 // Builds jobs; device addresses are base + workspace offset (base 0 = sizing).
@@ -117,6 +123,9 @@ struct Builder {
                         bool dot, uint32_t& nparts, uint32_t* ready);
   void group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev, int32_t* status_dev,
              uint8_t* digest_dev, int32_t* err, uint32_t* ready);
+  // n zero elements of an SoL vector (plane stride ld), written by the
+  // finish launch
+  void zero_fill(uint32_t* dst, uint64_t ld, uint32_t n);
 };
 
 BlobLayout blob_layout(const Plan& P);
@@ -153,6 +162,30 @@ vl_status partial_eval_launch(const void* M, int32_t dtype, uint32_t rows, uint3
 void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, uint64_t g1,
                  uint64_t seed, uint8_t* ws, bool async, uint8_t* proofs_dev, const uint64_t* offsets,
                  int32_t* status_dev, uint8_t* digests_dev, uint8_t* out, const Challenges* given = nullptr);
+// host verifier helpers (verify.cpp): 2^-1 and lifted integers in Montgomery
+// form, an integer entry of a matrix of dtype dt, the eq table of a
+// Montgomery point (index bits most significant first)
+Fr fr_inv2_mont();
+Fr lift_int(int64_t x);
+int64_t get_int(const void* base, int dt, uint64_t idx);
+std::vector<Fr> eq_host(const std::vector<Fr>& x);
+
+// M~(x, y) for an integer matrix given by an accessor over rows x cols
+template <typename F>
+Fr mle2(F get, uint32_t rows, uint32_t cols, const std::vector<Fr>& x, const std::vector<Fr>& y) {
+  const std::vector<Fr> ex = eq_host(x), ey = eq_host(y);
+  Fr total = fr_zero();
+  for (uint32_t i = 0; i < rows; ++i) {
+    Fr row = fr_zero();
+    for (uint32_t k = 0; k < cols; ++k) {
+      const int64_t v = get(i, k);
+      if (v) row = fr_add(row, fr_mul(lift_int(v), ey[k]));
+    }
+    total = fr_add(total, fr_mul(ex[i], row));
+  }
+  return total;
+}
+
 // pinned host memory of this host thread and device that kernels write
 // outputs into (grown on demand, kept for the process)
 struct PinnedOut {

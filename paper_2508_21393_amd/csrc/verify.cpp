@@ -14,13 +14,13 @@
 
 namespace vl {
 
-static Fr fr_inv2_mont() {
+Fr fr_inv2_mont() {
   // (p + 1) / 2 in Montgomery form
   return fr_to_mont(fr_from_limbs(0x80000001u, 0x7fffffffu, 0x7fff2dffu, 0xa9ded201u, 0x04d0ec02u,
                                   0x199cec04u, 0x94cebea4u, 0x39f6d3a9u));
 }
 
-static Fr lift_int(int64_t x) {
+Fr lift_int(int64_t x) {
   const uint64_t mag = x < 0 ? (uint64_t)0 - (uint64_t)x : (uint64_t)x;
   Fr v = fr_zero();
   v.w[0] = (uint32_t)mag;
@@ -29,7 +29,7 @@ static Fr lift_int(int64_t x) {
   return fr_to_mont(v);
 }
 
-static int64_t get_int(const void* base, int dt, uint64_t idx) {
+int64_t get_int(const void* base, int dt, uint64_t idx) {
   switch (dt) {
     case VL_I16: return reinterpret_cast<const int16_t*>(base)[idx];
     case VL_I32: return reinterpret_cast<const int32_t*>(base)[idx];
@@ -38,7 +38,7 @@ static int64_t get_int(const void* base, int dt, uint64_t idx) {
 }
 
 // eq table (Montgomery) of a Montgomery point, index bits most significant first
-static std::vector<Fr> eq_host(const std::vector<Fr>& x) {
+std::vector<Fr> eq_host(const std::vector<Fr>& x) {
   std::vector<Fr> t(1, fr_R());
   for (const Fr& xj : x) {
     std::vector<Fr> n(2 * t.size());
@@ -50,22 +50,6 @@ static std::vector<Fr> eq_host(const std::vector<Fr>& x) {
     t.swap(n);
   }
   return t;
-}
-
-// M~(x, y) for an integer matrix given by an accessor over rows x cols
-template <typename F>
-static Fr mle2(F get, uint32_t rows, uint32_t cols, const std::vector<Fr>& x, const std::vector<Fr>& y) {
-  const std::vector<Fr> ex = eq_host(x), ey = eq_host(y);
-  Fr total = fr_zero();
-  for (uint32_t i = 0; i < rows; ++i) {
-    Fr row = fr_zero();
-    for (uint32_t k = 0; k < cols; ++k) {
-      const int64_t v = get(i, k);
-      if (v) row = fr_add(row, fr_mul(lift_int(v), ey[k]));
-    }
-    total = fr_add(total, fr_mul(ex[i], row));
-  }
-  return total;
 }
 
 }  // namespace vl
