@@ -33,7 +33,8 @@ def dec(b: bytes) -> int:
 
 
 def inv(x: int) -> int:
-    """Multiplicative inverse by Fermat's little theorem."""
+    """Multiplicative inverse (Python's modular inverse, by the extended
+    Euclidean algorithm; equal to x^(p-2) by Fermat's little theorem)."""
     if x % P == 0:
         raise ZeroDivisionError("0 has no inverse")
-    return pow(x, P - 2, P)
+    return pow(x, -1, P)

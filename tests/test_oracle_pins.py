@@ -56,6 +56,8 @@ def test_lift_and_encoding():
     with pytest.raises(ValueError):
         oracle.dec(P.to_bytes(32, "little"))
     assert oracle.inv(2) * 2 % P == 1
+    for x in (2, 3, 12345, P - 1, 2**200 + 7):
+        assert oracle.inv(x) == pow(x, P - 2, P)   # Fermat's little theorem
 
 
 # ---------------------------------------------------------------- hash ------

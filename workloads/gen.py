@@ -607,3 +607,68 @@ def tiny_head_batch(seed: int, H: int, d0: int, d1: int, d2: int, transA: bool =
     else:
         C = _batched_witness(A, B, transA, transB, (H, d0, d2), stacked_heads)
     return HeadBatch(name, A, B, C, transA, transB)
+
+
+# --------------------------------------------------------------------------
+# lookup arguments: entries of a tensor (or pairs of tensors) in a table
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class LookupCase:
+    """Every x_i (with y_i when y is given) is a row of the table
+    (t0 + j, tb_j), j < N: a range check when tb is None, an input/output
+    check of an element-wise function otherwise."""
+    name: str
+    x: np.ndarray
+    y: Optional[np.ndarray]
+    t0: int
+    tb: Optional[np.ndarray]
+    N: int
+    lid: int = 0
+
+
+_SILU_TAB = None
+
+
+def silu_table() -> np.ndarray:
+    """SiLU at scale 2^12 over the int16 range: round(2^12 s sigmoid(s)) for
+    s = x / 2^12, x = -2^15 .. 2^15 - 1 (int32).  Computed with the C
+    library's exp, entry by entry, so that every machine builds the same
+    table."""
+    global _SILU_TAB
+    import math
+    if _SILU_TAB is None:
+        out = np.empty(1 << 16, dtype=np.int32)
+        for j in range(1 << 16):
+            s = (j + I16_MIN) / float(1 << SCALE_BITS)
+            out[j] = int(round(s / (1.0 + math.exp(-s)) * (1 << SCALE_BITS)))
+        _SILU_TAB = out
+    return _SILU_TAB
+
+
+def lookup_range(seed: int, D: int, lid: int = 0) -> LookupCase:
+    """Range check of D quantised activations (sigma = 1 at scale 2^12) against
+    the int16 table -2^15 .. 2^15 - 1 (N = 2^16)."""
+    rng = np.random.default_rng([seed, 93])
+    x = quantize_gaussian(rng, (D,), 1.0)
+    return LookupCase(f"range D={D}", x, None, I16_MIN, None, 1 << 16, lid)
+
+
+def lookup_silu(seed: int, D: int, lid: int = 0) -> LookupCase:
+    """SwiGLU's activation check (input z', output phi(z')) as a two-column
+    lookup into the SiLU table over the int16 range (N = 2^16)."""
+    rng = np.random.default_rng([seed, 94])
+    x = quantize_gaussian(rng, (D,), 1.0)
+    tab = silu_table()
+    y = tab[x.astype(np.int64) - I16_MIN].astype(np.int32)
+    return LookupCase(f"silu D={D}", x, y, I16_MIN, tab, 1 << 16, lid)
+
+
+def tiny_lookup(seed: int, D: int, N: int, t0: int = 0, two_col: bool = False, lid: int = 0) -> LookupCase:
+    """D entries drawn uniformly from a table of N rows starting at t0 (int32;
+    the second column, if any, random int32)."""
+    rng = np.random.default_rng([seed, 95])
+    j = rng.integers(0, N, size=D)
+    x = (t0 + j).astype(np.int32)
+    tb = rng.integers(-(1 << 30), 1 << 30, size=N).astype(np.int32) if two_col else None
+    y = tb[j].astype(np.int32) if two_col else None
+    return LookupCase(f"tiny lookup D={D} N={N}", x, y, t0, tb, N, lid)
