@@ -436,6 +436,66 @@ vl_status vl_bmm_prove(const vl_bmm* b, uint64_t n, uint64_t seed, void* workspa
 vl_status vl_bmm_verify(const uint8_t* proof, uint64_t len, const vl_bmm* b, uint64_t seed, vl_fr* reduced,
                         uint64_t reduced_cap, uint64_t* reduced_len, int32_t* fail_round);
 
+/* Lookup arguments (Protocol 1, Sec. II-D): every entry of a secret tensor
+ * S lies in a public table T.  With m_j the multiplicity of row j in S, the
+ * identity of eq. (rational-function) at a random beta,
+ *     sum_i 1/(beta + s_i) = sum_j m_j/(beta + t_j),
+ * and the inverse relations are proved by the sumcheck of
+ * eq. (lookup-sumcheck) over the D' entries x = (x_H, x_L):
+ *     alpha + alpha^2 = sum_x alpha A(x) eq(u, x) (S(x) + beta) + A(x)
+ *         + (N/D') alpha^2 B(x_L) eq(u_L, x_L) (T(x_L) + beta)
+ *         - (N/D') B(x_L) m(x_L),
+ * A = 1/(beta + S), B = 1/(beta + T), u_L the last log N coordinates of u;
+ * rounds bind the most significant bit first and have degree 3.
+ * Table rows are (t0 + j) for j < N (N a power of two), or with two_col the
+ * pairs (t0 + j, tb[j]), compressed as (t0 + j) + gamma tb[j] and entries as
+ * x_i + gamma y_i (a range check, or the input/output table of an
+ * element-wise function: zkSwiGLU, zkSoftmax, zkElementProd and
+ * zkTranspose of Sec. IV-A build on this).  S is padded to
+ * D' = max(N, 2^ceil(log2 D)) entries with the table's first row.
+ * Transcript: st = H("VeriLoRA-lookup-v1" || u64 seed || u32 id || u64 D ||
+ * u32 N || i32 t0 || u32 two_col), squeezes "gamma" (two_col only),
+ * "beta", "alpha", "u" (log2 D'), absorbs "round" (g(0..3), challenge "r")
+ * and "final" (A(r), S(r), B(r_L), T(r_L), m(r_L)).  The claimed sum is not
+ * sent.  Proof: (g0..g3) per round || the five final values, canonical
+ * 32-byte elements, vl_lookup_proof_size bytes.
+ * x, y: D int16 or int32 entries (dtype, dtype_y); tb: N int32; device pointers for
+ * proving, host pointers (or NULL: shape only) for verification. */
+typedef struct {
+  const void* x;
+  const void* y;
+  const int32_t* tb;
+  int32_t dtype;     /* of x */
+  int32_t dtype_y;   /* of y (two_col) */
+  int32_t t0;
+  int32_t two_col;
+  uint32_t N;
+  uint64_t D;
+  uint32_t id;
+} vl_lookup;
+
+uint64_t vl_lookup_proof_size(const vl_lookup* l);
+uint64_t vl_lookup_workspace_size(const vl_lookup* l, uint64_t n);
+/* Prove n lookups with the sumcheck rounds of Sec. II-B.1 over the sum
+ * above (blocking; proofs, offsets (n + 1) and digests (optional, 32 bytes
+ * each) in host memory; workspace of vl_lookup_workspace_size bytes,
+ * 256-byte aligned).  The multiplicities, inverses, tables and rounds are
+ * computed on the device.  Errors: VL_ERR_INVALID_ARG, VL_ERR_SHAPE,
+ * VL_ERR_DTYPE, VL_ERR_WORKSPACE, VL_ERR_BUFFER_TOO_SMALL,
+ * VL_ERR_FALSE_STATEMENT (an entry is not a row of the table, or beta hit a
+ * pole), VL_ERR_HIP. */
+vl_status vl_lookup_prove(const vl_lookup* l, uint64_t n, uint64_t seed, void* workspace, uint64_t workspace_bytes,
+                          uint8_t* proofs, uint64_t proofs_len, uint64_t* offsets, uint8_t* digests, void* stream);
+/* Host verifier of one lookup proof (Sec. II-B.1 rounds, cubic
+ * interpolation, and the summand of eq. (lookup-sumcheck) at r from the five
+ * final values).  If x (and y, tb with two_col) are host pointers, the
+ * final values are also checked against the multilinear extensions of the
+ * padded S, T, the multiplicities and the inverses (standing in for the
+ * openings of Sec. II-A).  reduced: gamma, beta, alpha, u, r, the five final
+ * values (canonical).  fail_round as for vl_bmm_verify. */
+vl_status vl_lookup_verify(const uint8_t* proof, uint64_t len, const vl_lookup* l, uint64_t seed, vl_fr* reduced,
+                           uint64_t reduced_cap, uint64_t* reduced_len, int32_t* fail_round);
+
 /* Message for the last non-OK status on this thread. */
 const char* vl_last_error(void);
 

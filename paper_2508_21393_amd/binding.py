@@ -34,7 +34,8 @@ EXPORTED = ("vl_fr_lift", "vl_fr_export", "vl_eq_table", "vl_partial_eval_worksp
             "vl_prove_graph_create", "vl_prove_graph_launch", "vl_prove_graph_destroy",
             "vl_mle_partial_eval_noalloc", "vl_lora_chain_proof_size", "vl_lora_chain_workspace_size",
             "vl_lora_chain_prove", "vl_bmm_proof_size", "vl_bmm_workspace_size", "vl_bmm_prove",
-            "vl_bmm_verify")
+            "vl_bmm_verify", "vl_lookup_proof_size", "vl_lookup_workspace_size", "vl_lookup_prove",
+            "vl_lookup_verify")
 NOALLOC_SCRATCH_BYTES = 64 << 20   # VL_NOALLOC_SCRATCH_BYTES
 
 c_u32, c_u64, c_i32, c_vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p
@@ -93,6 +94,11 @@ class vl_bmm(ctypes.Structure):
                 ("trans_a", c_i32), ("trans_b", c_i32), ("group_id", c_u32)]
 
 
+class vl_lookup(ctypes.Structure):
+    _fields_ = [("x", c_vp), ("y", c_vp), ("tb", c_vp), ("dtype", c_i32), ("dtype_y", c_i32), ("t0", c_i32),
+                ("two_col", c_i32), ("N", c_u32), ("D", c_u64), ("id", c_u32)]
+
+
 LAYER_INT16 = ("X", "W", "A", "B", "dY", "H", "G")
 LAYER_INT64 = ("Y", "C2", "C4", "dA", "dB", "dX", "UA", "UB")
 
@@ -148,6 +154,16 @@ def lib():
         L.vl_bmm_verify.argtypes = [c_vp, c_u64, ctypes.POINTER(vl_bmm), c_u64, ctypes.POINTER(vl_fr), c_u64,
                                     ctypes.POINTER(c_u64), ctypes.POINTER(c_i32)]
         L.vl_bmm_verify.restype = c_i32
+        L.vl_lookup_proof_size.argtypes = [ctypes.POINTER(vl_lookup)]
+        L.vl_lookup_proof_size.restype = c_u64
+        L.vl_lookup_workspace_size.argtypes = [ctypes.POINTER(vl_lookup), c_u64]
+        L.vl_lookup_workspace_size.restype = c_u64
+        L.vl_lookup_prove.argtypes = [ctypes.POINTER(vl_lookup), c_u64, c_u64, c_vp, c_u64, c_vp, c_u64,
+                                      ctypes.POINTER(c_u64), c_vp, c_vp]
+        L.vl_lookup_prove.restype = c_i32
+        L.vl_lookup_verify.argtypes = [c_vp, c_u64, ctypes.POINTER(vl_lookup), c_u64, ctypes.POINTER(vl_fr), c_u64,
+                                       ctypes.POINTER(c_u64), ctypes.POINTER(c_i32)]
+        L.vl_lookup_verify.restype = c_i32
         L.vl_prove_graph_create.argtypes = [ctypes.POINTER(vl_group), c_u64, ctypes.POINTER(vl_prove_opts), c_vp,
                                             c_u64, ctypes.POINTER(c_u64), c_vp, ctypes.POINTER(c_vp)]
         L.vl_prove_graph_launch.argtypes = [c_vp, c_u64, c_vp]
@@ -535,6 +551,60 @@ def bmm_verify(proof: bytes, b: BmmArgs, seed: int):
     buf = ctypes.create_string_buffer(proof, max(len(proof), 1))
     st = lib().vl_bmm_verify(ctypes.addressof(buf), len(proof), ctypes.byref(b.struct), seed, red, cap,
                              ctypes.byref(rlen), ctypes.byref(fr_))
+    if st not in (VL_OK, VL_ERR_REJECT):
+        _check(st)
+    return st == VL_OK, fr_.value, [fr_to_int(red[i]) for i in range(rlen.value)] if st == VL_OK else []
+
+
+# --------------------------------------------------------------- lookups --
+class LookupArgs:
+    """vl_lookup over the entries x (and y) of a secret tensor and the table
+    rows (t0 + j[, tb_j]) for j < N: torch tensors on the device for proving,
+    numpy arrays (or None: shape only) on the host for verification.  With
+    two_col the second columns y and tb are used."""
+
+    def __init__(self, x, y, tb, t0: int, N: int, D: int, dtype, two_col: bool, lid: int = 0, dtype_y=None):
+        self.keep = (x, y, tb)
+        ptr = lambda v: _ptr(v) if v is not None else None  # noqa: E731
+        dy = dtype_code(dtype_y) if dtype_y is not None else 0
+        self.struct = vl_lookup(ptr(x), ptr(y), ptr(tb), dtype_code(dtype), dy, t0, int(bool(two_col)), N, D, lid)
+
+
+def lookup_proof_size(a: LookupArgs) -> int:
+    return lib().vl_lookup_proof_size(ctypes.byref(a.struct))
+
+
+def lookup_workspace_size(args: Sequence[LookupArgs]) -> int:
+    arr = (vl_lookup * len(args))(*[a.struct for a in args])
+    return lib().vl_lookup_workspace_size(arr, len(args))
+
+
+def lookup_prove(args: Sequence[LookupArgs], seed: int, workspace=None, stream=None):
+    """Blocking lookup proofs: returns (proofs, digests)."""
+    import torch
+    n = len(args)
+    arr = (vl_lookup * n)(*[a.struct for a in args])
+    if workspace is None:
+        workspace = torch.empty(max(256, lib().vl_lookup_workspace_size(arr, n)), dtype=torch.uint8, device="cuda")
+    total = sum(lookup_proof_size(a) for a in args)
+    buf = ctypes.create_string_buffer(max(total, 1))
+    dig = ctypes.create_string_buffer(32 * n)
+    offs = (c_u64 * (n + 1))()
+    _check(lib().vl_lookup_prove(arr, n, seed, workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                 ctypes.addressof(buf), total, offs, ctypes.addressof(dig), _stream(stream)))
+    raw = buf.raw
+    return [raw[offs[k]:offs[k + 1]] for k in range(n)], [dig.raw[32 * k:32 * k + 32] for k in range(n)]
+
+
+def lookup_verify(proof: bytes, a: LookupArgs, seed: int):
+    """Host verifier of one lookup proof: (ok, fail_round, reduced)."""
+    cap = 4096
+    red = (vl_fr * cap)()
+    rlen = c_u64(0)
+    fr_ = c_i32(0)
+    buf = ctypes.create_string_buffer(proof, max(len(proof), 1))
+    st = lib().vl_lookup_verify(ctypes.addressof(buf), len(proof), ctypes.byref(a.struct), seed, red, cap,
+                                ctypes.byref(rlen), ctypes.byref(fr_))
     if st not in (VL_OK, VL_ERR_REJECT):
         _check(st)
     return st == VL_OK, fr_.value, [fr_to_int(red[i]) for i in range(rlen.value)] if st == VL_OK else []

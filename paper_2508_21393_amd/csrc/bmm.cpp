@@ -229,55 +229,6 @@ vl_status bmm_run(const vl_bmm* bs, uint64_t n, uint64_t seed, uint8_t* ws, uint
   return VL_OK;
 }
 
-// x^e mod p for a Montgomery x, e given as 8 little-endian limbs
-Fr fr_pow_mont(const Fr& x, const uint32_t (&e)[8]) {
-  Fr r = fr_R();
-  for (int i = 255; i >= 0; --i) {
-    r = fr_mul(r, r);
-    if ((e[i >> 5] >> (i & 31)) & 1u) r = fr_mul(r, x);
-  }
-  return r;
-}
-
-Fr fr_inv_mont(const Fr& x) {
-  uint32_t e[8] = {VL_P_LIMBS};
-  e[0] -= 2;   // p - 2 (p's low limb is 1: the borrow propagates)
-  if (e[0] == 0xffffffffu) {
-    int i = 1;
-    while (e[i] == 0) e[i++] = 0xffffffffu;
-    --e[i];
-  }
-  return fr_pow_mont(x, e);
-}
-
-Fr small_mont(int64_t v) { return lift_int(v); }
-
-// the polynomial through (k, g[k]), k < m (m = 3 or 4), at r (Montgomery)
-Fr lagrange_host(const Fr* g, int m, const Fr& r) {
-  Fr total = fr_zero();
-  for (int k = 0; k < m; ++k) {
-    Fr num = fr_R(), den = fr_R();
-    for (int q = 0; q < m; ++q) {
-      if (q == k) continue;
-      num = fr_mul(num, fr_sub(r, small_mont(q)));
-      den = fr_mul(den, small_mont(k - q));
-    }
-    total = fr_add(total, fr_mul(g[k], fr_mul(num, fr_inv_mont(den))));
-  }
-  return total;
-}
-
-// eq(x, y) for Montgomery points of one length
-Fr eq_point(const std::vector<Fr>& x, const std::vector<Fr>& y) {
-  Fr e = fr_R();
-  for (size_t i = 0; i < x.size(); ++i) {
-    const Fr xy = fr_mul(x[i], y[i]);
-    const Fr t = fr_add(xy, fr_sub(fr_sub(fr_R(), x[i]), fr_sub(y[i], xy)));   // xy + (1 - x)(1 - y)
-    e = fr_mul(e, t);
-  }
-  return e;
-}
-
 // sum_h eq(hp, h) M_h~(x, y) of H stored head matrices (accessor per head)
 template <typename G>
 Fr tensor_mle_host(G get, uint32_t H, uint32_t rows, uint32_t cols, const std::vector<Fr>& hp,

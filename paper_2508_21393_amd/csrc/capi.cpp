@@ -599,6 +599,13 @@ BlobLayout blob_layout(const Plan& P) {
     L.bmm_wide[k] = o;
     o = align_up(o + P.bmm_wide[k].size() * sizeof(BmmSweep), 64);
   }
+  L.lookups = o;
+  o = align_up(o + P.lookups.size() * sizeof(LookupJob), 64);
+  L.lk_wide.resize(P.lk_wide.size());
+  for (size_t k = 0; k < P.lk_wide.size(); ++k) {
+    L.lk_wide[k] = o;
+    o = align_up(o + P.lk_wide[k].size() * sizeof(LookupSweep), 64);
+  }
   L.total = align_up(o, 256);
   return L;
 }
@@ -636,6 +643,10 @@ void fill_blob(Plan& P, const BlobLayout& L, uint8_t* dblob) {
   if (!P.bmms.empty()) memcpy(P.blob.data() + L.bmms, P.bmms.data(), P.bmms.size() * sizeof(BmmJob));
   for (size_t k = 0; k < P.bmm_wide.size(); ++k)
     memcpy(P.blob.data() + L.bmm_wide[k], P.bmm_wide[k].data(), P.bmm_wide[k].size() * sizeof(BmmSweep));
+  if (!P.lookups.empty())
+    memcpy(P.blob.data() + L.lookups, P.lookups.data(), P.lookups.size() * sizeof(LookupJob));
+  for (size_t k = 0; k < P.lk_wide.size(); ++k)
+    memcpy(P.blob.data() + L.lk_wide[k], P.lk_wide[k].data(), P.lk_wide[k].size() * sizeof(LookupSweep));
   memcpy(P.blob.data() + L.eq, P.eq.data(), P.eq.size() * sizeof(EqJob));
   for (size_t k = 0; k < P.seg.size(); ++k) {
     const Segment& G = P.seg[k];
@@ -792,6 +803,22 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
       VL_STAGE(ev, VL_STAGE_ROUNDS, s, launch_bmm_chal(bj, lst, nl, (uint32_t)k, s));
     }
     VL_STAGE(ev, VL_STAGE_ROUNDS, s, launch_bmm_rounds(bj, nb, s));
+  }
+  if (!P.lookups.empty()) {
+    const LookupJob* lj = reinterpret_cast<const LookupJob*>(dblob + L.lookups);
+    const uint32_t nl = (uint32_t)P.lookups.size();
+    for (const auto& z : P.lookup_zero) VL_STAGE(ev, VL_STAGE_FINISH, s, launch_zero_words(z.first, z.second, s));
+    VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_hist(lj, nl, P.lk_hist_blocks, s));
+    VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_table(lj, nl, P.lk_tab_blocks, s));
+    VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_prep(lj, nl, P.lk_prep_blocks, s));
+    VL_STAGE(ev, VL_STAGE_PASS1, s, launch_lookup_start(lj, nl, s));
+    for (size_t k = 0; k < P.lk_wide.size(); ++k) {
+      const LookupSweep* lst = reinterpret_cast<const LookupSweep*>(dblob + L.lk_wide[k]);
+      const uint32_t nw = (uint32_t)P.lk_wide[k].size();
+      VL_STAGE(ev, VL_STAGE_PASS1, s, launch_lookup_sweep(lj, lst, nw, P.lk_wide_blocks[k], (uint32_t)k, s));
+      VL_STAGE(ev, VL_STAGE_ROUNDS, s, launch_lookup_chal(lj, lst, nw, (uint32_t)k, s));
+    }
+    VL_STAGE(ev, VL_STAGE_ROUNDS, s, launch_lookup_rounds(lj, nl, s));
   }
   return hipSuccess;
 }

@@ -218,6 +218,61 @@ struct BmmSweep {
   uint32_t block_begin;
 };
 
+// One lookup argument (vl_lookup_prove, Protocol 1 with the sum of
+// eq. (lookup-sumcheck)): every entry (x_i[, y_i]) of a secret tensor is a
+// row (t0 + j[, tb_j]) of a table of N = 2^nL rows.  S is padded to
+// 2^(nH + nL) entries with the table's first row.  Tables (SoL, Montgomery):
+// over the padded entries A = 1/(beta + S), Sb = S + beta, E = eq(u, .);
+// over the table rows B = 1/(beta + T), Tb = T + beta, M = multiplicities,
+// EL = eq(u_L, .).  Rounds bind the high index bits first (only A, Sb, E
+// depend on them; the table rows' terms add a constant K per round), then
+// the low bits (all seven tables).  As for batched products, the first
+// `wide` rounds run as GPU-wide sweeps and a one-wave transcript step.
+constexpr uint32_t kLookupInvChunk = 16;       // table rows per thread in the batch inversion
+constexpr uint32_t kLookupSweepPairs = 256;
+constexpr uint32_t kLookupWidePairs = 4096;
+constexpr uint32_t kLookupMaxWide = 32;
+constexpr uint32_t kLookupParts = 14;          // sweep partial elements per block
+// io words: [0] status, [8, 16) state, [16, 24) pending r, [24, 32) K
+constexpr uint32_t kLkIoState = 8, kLkIoR = 16, kLkIoK = 24, kLkIoWords = 32;
+struct LookupJob {
+  uint32_t st[8];             // transcript state after gamma, beta, alpha, u
+  uint32_t gamma[8], beta[8], alpha[8], c1[8], c2[8];   // Montgomery
+  uint32_t claim[8];          // alpha + alpha^2, Montgomery
+  const void* x;              // D entries, dtype
+  const void* y;              // second column or null
+  const int32_t* tb;          // table's second column or null
+  int32_t dtype, dtype_y;
+  int32_t t0;
+  uint32_t pad_;
+  uint64_t D;
+  uint32_t nH, nL;
+  uint32_t wide;
+  uint32_t hist_begin;        // block prefixes: histogram launch (D entries),
+  uint32_t prep_begin;        // preparation launch (padded entries),
+  uint32_t tab_begin;         // table launch (chunks of table rows)
+  uint32_t nkparts;           // table-launch blocks (partials of sum_j B_j m_j)
+  uint32_t* cnt;              // N counts, zeroed by the plan
+  uint32_t* A;                // ld 2^(nH + nL)
+  uint32_t* S;
+  uint32_t* E;
+  uint32_t* B;                // ld 2^nL
+  uint32_t* T;
+  uint32_t* M;
+  uint32_t* EL;
+  uint32_t* kpart;
+  uint32_t* part;             // sweep partials, kLookupParts elements per block
+  uint32_t* io;
+  int32_t* flag;              // set when an entry is not in the table
+  uint8_t* proof;
+  uint8_t* digest;
+  int32_t* status;
+};
+struct LookupSweep {
+  uint32_t job;
+  uint32_t block_begin;
+};
+
 // host launchers (kernels.hip)
 hipError_t launch_eval(const EvalJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
 hipError_t launch_reduce(const ReduceJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
@@ -240,6 +295,16 @@ hipError_t launch_bmm_sweep(const BmmJob* jobs_dev, const BmmSweep* list_dev, ui
 hipError_t launch_bmm_chal(const BmmJob* jobs_dev, const BmmSweep* list_dev, uint32_t n_list, uint32_t round,
                            hipStream_t s);
 hipError_t launch_bmm_rounds(const BmmJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
+// lookup arguments (lookup.hip)
+hipError_t launch_lookup_hist(const LookupJob* jobs_dev, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s);
+hipError_t launch_lookup_table(const LookupJob* jobs_dev, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s);
+hipError_t launch_lookup_prep(const LookupJob* jobs_dev, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s);
+hipError_t launch_lookup_start(const LookupJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
+hipError_t launch_lookup_sweep(const LookupJob* jobs_dev, const LookupSweep* list_dev, uint32_t n_list,
+                               uint32_t n_blocks, uint32_t round, hipStream_t s);
+hipError_t launch_lookup_chal(const LookupJob* jobs_dev, const LookupSweep* list_dev, uint32_t n_list,
+                              uint32_t round, hipStream_t s);
+hipError_t launch_lookup_rounds(const LookupJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
 // bytes (a multiple of 16, both pointers 16-byte aligned) from pinned host
 // memory, given by its device-side address
 hipError_t launch_copy_in(void* dst, const void* src_dev, uint64_t bytes, hipStream_t s);

@@ -79,6 +79,13 @@ struct Plan {
   std::vector<BmmJob> bmms;
   std::vector<std::vector<BmmSweep>> bmm_wide;
   std::vector<uint32_t> bmm_wide_blocks;
+  // lookup arguments: count buffers to zero, the entry-wise and table
+  // launches, wide rounds, the one-workgroup rounds
+  std::vector<LookupJob> lookups;
+  std::vector<std::pair<uint32_t*, uint64_t>> lookup_zero;
+  uint32_t lk_hist_blocks = 0, lk_prep_blocks = 0, lk_tab_blocks = 0;
+  std::vector<std::vector<LookupSweep>> lk_wide;
+  std::vector<uint32_t> lk_wide_blocks;
 };
 
 struct SegLayout {
@@ -86,9 +93,9 @@ struct SegLayout {
 };
 
 struct BlobLayout {
-  uint64_t err, eq, points, evals, reduces, bmms, total;
+  uint64_t err, eq, points, evals, reduces, bmms, lookups, total;
   std::vector<SegLayout> seg;
-  std::vector<uint64_t> bmm_wide;
+  std::vector<uint64_t> bmm_wide, lk_wide;
 };
 
 // Builds jobs; device addresses are base + workspace offset (base 0 = sizing).
@@ -169,6 +176,11 @@ Fr fr_inv2_mont();
 Fr lift_int(int64_t x);
 int64_t get_int(const void* base, int dt, uint64_t idx);
 std::vector<Fr> eq_host(const std::vector<Fr>& x);
+// x^-1 (Montgomery in and out; Fermat), the polynomial through (k, g[k]),
+// k < m, at r (Montgomery), and eq(x, y) of two Montgomery points
+Fr fr_inv_host(const Fr& x);
+Fr lagrange_host(const Fr* g, int m, const Fr& r);
+Fr eq_point(const std::vector<Fr>& x, const std::vector<Fr>& y);
 
 // M~(x, y) for an integer matrix given by an accessor over rows x cols
 template <typename F>

@@ -3,7 +3,7 @@
 Only ``oracle`` and ``workloads`` are used: every stored value is what the
 oracle computes for the seeded synthetic inputs.  Usage:
 
-    python tests/golden/make_golden.py [cfg1 cfg1_sweep tiny cfg2 cfg3 cfg4 cfg5 chain bmm] [--procs N]
+    python tests/golden/make_golden.py [cfg1 cfg1_sweep tiny cfg2 cfg3 cfg4 cfg5 chain bmm lookup lookup_full] [--procs N]
 
 Each config file lists, per group: name, group id, shapes, the SHA-256 of the
 proof bytes and the final transcript state; small configs also keep the full
@@ -228,6 +228,68 @@ def record_bmm(procs: int):
     return data
 
 
+LOOKUP_TINY = [
+    # (seed, D, N, t0, two_col)
+    (61, 20, 8, -3, True), (62, 8, 8, 5, False), (63, 64, 4, 0, False), (64, 3, 16, -100, True),
+    (65, 37, 2, 7, False), (66, 1, 1, 2, False), (67, 5000, 64, -32, True), (68, 20000, 16, 1000, False),
+    (69, 9000, 16384, -8192, True),
+]
+LOOKUP_MID = [("range", 71, 1 << 16), ("silu", 72, 1 << 18)]
+LOOKUP_FULL = [("range", 73, 1 << 23), ("silu", 74, 1 << 23)]
+LOOKUP_SEED = 61
+
+_LOOKUPS = None
+
+
+def _prove_lookup(i):
+    from oracle.lookup import prove_case
+    t = time.time()
+    proof, state, _ = prove_case(_LOOKUPS[i], LOOKUP_SEED)
+    return i, proof, state, time.time() - t
+
+
+def _lookup_records(cases, keep_hex, procs):
+    global _LOOKUPS
+    _LOOKUPS = cases
+    idx = sorted(range(len(cases)), key=lambda i: -len(cases[i].x))
+    if procs > 1:
+        with mp.get_context("fork").Pool(min(procs, len(idx))) as pool:
+            res = pool.map(_prove_lookup, idx, chunksize=1)
+    else:
+        res = [_prove_lookup(i) for i in idx]
+    out = []
+    for i, proof, state, dt in sorted(res):
+        c = cases[i]
+        e = dict(name=c.name, D=len(c.x), N=c.N, proof_sha256=hashlib.sha256(proof).hexdigest(), state=state.hex(),
+                 proof_len=len(proof))
+        if keep_hex:
+            e["proof_hex"] = proof.hex()
+        out.append(e)
+        print(f"  {c.name:24s} {dt:7.1f}s", flush=True)
+    return out
+
+
+def _lookup_case(kind, seed, D, lid):
+    return (workloads.lookup_range if kind == "range" else workloads.lookup_silu)(seed, D, lid)
+
+
+def record_lookup(procs: int, full: bool):
+    """Lookup arguments (oracle/lookup.py): tiny cases in full, two
+    mid-size cases (a range check of 2^16 activations, the SiLU input/output
+    check of 2^18) in full, and with ``full`` the 7B-class cases (2^23
+    activations: range check and SiLU check) by digest."""
+    tiny = [workloads.tiny_lookup(s, D, N, t0, two, lid=k) for k, (s, D, N, t0, two) in enumerate(LOOKUP_TINY)]
+    data = dict(seed=LOOKUP_SEED, tiny_spec=LOOKUP_TINY, tiny=_lookup_records(tiny, True, procs))
+    mid = [_lookup_case(kind, s, D, k) for k, (kind, s, D) in enumerate(LOOKUP_MID)]
+    data["mid_spec"] = LOOKUP_MID
+    data["mid"] = _lookup_records(mid, True, procs)
+    if full:
+        big = [_lookup_case(kind, s, D, k) for k, (kind, s, D) in enumerate(LOOKUP_FULL)]
+        data["full_spec"] = LOOKUP_FULL
+        data["full"] = _lookup_records(big, False, procs)
+    return data
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("configs", nargs="*", default=["cfg1", "tiny", "cfg2", "cfg3"])
@@ -239,6 +301,17 @@ def main():
         if name == "chain":
             data = record_chain()
             with open(os.path.join(HERE, "chain.json"), "w") as f:
+                json.dump(data, f, indent=1)
+            print(f"{name}: done in {time.time() - t:.1f}s", flush=True)
+            continue
+        if name in ("lookup", "lookup_full"):
+            path = os.path.join(HERE, "lookup.json")
+            data = record_lookup(args.procs, name == "lookup_full")
+            if name == "lookup" and os.path.exists(path):
+                old = json.load(open(path))
+                if "full" in old:
+                    data["full_spec"], data["full"] = old["full_spec"], old["full"]
+            with open(path, "w") as f:
                 json.dump(data, f, indent=1)
             print(f"{name}: done in {time.time() - t:.1f}s", flush=True)
             continue
