@@ -304,6 +304,79 @@ def serving_leg(B, n_requests, pool_size=6, n_slots=4, seed=5):
             "peak_in_flight": srv.peak_in_flight}
 
 
+def attention_leg(B, reps, seed=6):
+    """Per-head batched products of one 7B-class attention layer (T = 2048,
+    32 heads of 128): S = Q K^T, O = P V, dP = dO V^T, dV = P^T dO, dQ = dS K,
+    dK = dS^T Q, proved in one vl_bmm_prove call (blocking) with the tensors
+    resident in HBM.  Every proof is compared with the first call's bytes."""
+    import torch
+    import workloads
+    layer = workloads.attention_layer(seed=seed, T=2048, H=32, dh=128, device="cuda")
+    keep = []
+
+    def dev(a):
+        t = torch.from_numpy(a).to("cuda")
+        keep.append(t)
+        return t
+
+    args = [B.BmmArgs(dev(hb.A.base), dev(hb.B.base), dev(hb.C.base), *hb.dims, hb.A.ld, hb.B.ld, hb.C.ld,
+                      hb.A.head_stride, hb.B.head_stride, hb.C.head_stride, hb.transA, hb.transB, hb.group_id)
+            for hb in layer]
+    ws = torch.empty(B.bmm_workspace_size(args), dtype=torch.uint8, device="cuda")
+    ref, _ = B.bmm_prove(args, seed, workspace=ws)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        pr, _ = B.bmm_prove(args, seed, workspace=ws)
+        times.append(time.perf_counter() - t0)
+        assert pr == ref, "attention proofs changed between calls"
+    ms = 1e3 * sorted(times)[len(times) // 2]
+    macs = sum(H * (d0 * d1 + d1 * d2 + d0 * d2) for (H, d0, d1, d2) in (hb.dims for hb in layer))
+    nbytes = sum(hb.A.base.nbytes + hb.B.base.nbytes + hb.C.base.nbytes for hb in layer)
+    return {"workload": "7B-class attention layer, T=2048, 32 heads x 128: S=QK^T, O=PV, dP=dOV^T, dV=P^TdO, "
+                        "dQ=dSK, dK=dS^TQ (per-head batched sumchecks, one call)",
+            "products": len(layer), "heads": 32, "ms_per_call": ms, "calls": reps,
+            "Fr_MAC_per_s": macs / (ms * 1e-3), "algorithmic_macs": macs,
+            "operand_bytes": nbytes, "operand_GBps": nbytes / (ms * 1e-3) / 1e9}
+
+
+def lookup_leg(B, reps, seed=61):
+    """Lookup arguments at 7B-class size: a range check of 2^23 int16
+    activations (T = 2048 x hidden 4096) against the int16 table (2^16 rows)
+    and the SiLU input/output check of 2^23 entries against its 2^16-row
+    table, proved in one vl_lookup_prove call (blocking)."""
+    import torch
+    import workloads
+    cases = [workloads.lookup_range(73, 1 << 23, 0), workloads.lookup_silu(74, 1 << 23, 1)]
+    keep = []
+
+    def dev(a):
+        if a is None:
+            return None
+        t = torch.from_numpy(a).to("cuda")
+        keep.append(t)
+        return t
+
+    args = [B.LookupArgs(dev(c.x), dev(c.y), dev(c.tb), c.t0, c.N, len(c.x), c.x.dtype, c.y is not None, c.lid,
+                         dtype_y=c.y.dtype if c.y is not None else None) for c in cases]
+    ws = torch.empty(B.lookup_workspace_size(args), dtype=torch.uint8, device="cuda")
+    ref, _ = B.lookup_prove(args, seed, workspace=ws)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        pr, _ = B.lookup_prove(args, seed, workspace=ws)
+        times.append(time.perf_counter() - t0)
+        assert pr == ref, "lookup proofs changed between calls"
+    ms = 1e3 * sorted(times)[len(times) // 2]
+    entries = sum(len(c.x) for c in cases)
+    return {"workload": "lookup arguments, 7B-class: range check of 2^23 int16 activations and SiLU "
+                        "input/output check of 2^23 entries, tables of 2^16 rows (one call)",
+            "lookups": len(cases), "entries": entries, "ms_per_call": ms, "calls": reps,
+            "entries_per_s": entries / (ms * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -328,6 +401,12 @@ def main():
                     help="requests in the serving leg at 13B-class shapes (0: skip it)")
     ap.add_argument("--autotune", action="store_true",
                     help="time a grid of launch shapes first and bench the fastest")
+    ap.add_argument("--attention-reps", type=int, default=5,
+                    help="calls of the attention-layer leg (per-head batched products; 0: skip it)")
+    ap.add_argument("--lookup-reps", type=int, default=3,
+                    help="calls of the lookup-argument leg (0: skip it)")
+    ap.add_argument("--legs-only", action="store_true",
+                    help="run only the attention and lookup legs (for profiling them)")
     args = ap.parse_args()
     ws = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or ws != 1:
@@ -344,6 +423,15 @@ def main():
     B.lib()
     mode = {"batched": B.VL_MODE_BATCHED, "per_instance": B.VL_MODE_PER_INSTANCE,
             "persistent": B.VL_MODE_PERSISTENT}[args.mode]
+    if args.legs_only:
+        legs = {}
+        if args.attention_reps > 0:
+            legs["attention"] = attention_leg(B, args.attention_reps)
+            torch.cuda.empty_cache()
+        if args.lookup_reps > 0:
+            legs["lookup"] = lookup_leg(B, args.lookup_reps)
+        print(json.dumps(legs), flush=True)
+        return
     t_gen = time.perf_counter()
     w = workloads.config4(T=args.T, device="cuda")
     groups = w.groups
@@ -518,6 +606,12 @@ def main():
         del slots, workspace, batch, gas
         torch.cuda.empty_cache()
         out["serving"] = serving_leg(B, args.serve_requests)
+    if args.attention_reps > 0:
+        torch.cuda.empty_cache()
+        out["attention"] = attention_leg(B, args.attention_reps)
+    if args.lookup_reps > 0:
+        torch.cuda.empty_cache()
+        out["lookup"] = lookup_leg(B, args.lookup_reps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
