@@ -407,8 +407,12 @@ void Builder::contract(const void* M, int dtype, int nd, uint64_t ld, bool rows,
 }
 
 void Builder::eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_len, bool pack_r2,
-                     bool eq_canon) {
+                     bool eq_canon, const Fr* scale) {
   EqJob e{};
+  if (scale) {
+    e.scaled = 1;
+    memcpy(e.scale, scale->w, 32);
+  }
   e.nvars = (uint32_t)x.size();
   e.pack_r2 = pack_r2 ? 1u : 0u;
   e.eq_canon = eq_canon ? 1u : 0u;
@@ -601,10 +605,12 @@ BlobLayout blob_layout(const Plan& P) {
   }
   L.lookups = o;
   o = align_up(o + P.lookups.size() * sizeof(LookupJob), 64);
-  L.lk_wide.resize(P.lk_wide.size());
-  for (size_t k = 0; k < P.lk_wide.size(); ++k) {
-    L.lk_wide[k] = o;
-    o = align_up(o + P.lk_wide[k].size() * sizeof(LookupSweep), 64);
+  for (int lo = 0; lo < 2; ++lo) {
+    L.lk_wide[lo].resize(P.lk_wide[lo].size());
+    for (size_t k = 0; k < P.lk_wide[lo].size(); ++k) {
+      L.lk_wide[lo][k] = o;
+      o = align_up(o + P.lk_wide[lo][k].size() * sizeof(LookupSweep), 64);
+    }
   }
   L.total = align_up(o, 256);
   return L;
@@ -645,8 +651,11 @@ void fill_blob(Plan& P, const BlobLayout& L, uint8_t* dblob) {
     memcpy(P.blob.data() + L.bmm_wide[k], P.bmm_wide[k].data(), P.bmm_wide[k].size() * sizeof(BmmSweep));
   if (!P.lookups.empty())
     memcpy(P.blob.data() + L.lookups, P.lookups.data(), P.lookups.size() * sizeof(LookupJob));
-  for (size_t k = 0; k < P.lk_wide.size(); ++k)
-    memcpy(P.blob.data() + L.lk_wide[k], P.lk_wide[k].data(), P.lk_wide[k].size() * sizeof(LookupSweep));
+  for (int lo = 0; lo < 2; ++lo)
+    for (size_t k = 0; k < P.lk_wide[lo].size(); ++k)
+      if (!P.lk_wide[lo][k].empty())
+        memcpy(P.blob.data() + L.lk_wide[lo][k], P.lk_wide[lo][k].data(),
+               P.lk_wide[lo][k].size() * sizeof(LookupSweep));
   memcpy(P.blob.data() + L.eq, P.eq.data(), P.eq.size() * sizeof(EqJob));
   for (size_t k = 0; k < P.seg.size(); ++k) {
     const Segment& G = P.seg[k];
@@ -812,11 +821,16 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
     VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_table(lj, nl, P.lk_tab_blocks, s));
     VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_prep(lj, nl, P.lk_prep_blocks, s));
     VL_STAGE(ev, VL_STAGE_PASS1, s, launch_lookup_start(lj, nl, s));
-    for (size_t k = 0; k < P.lk_wide.size(); ++k) {
-      const LookupSweep* lst = reinterpret_cast<const LookupSweep*>(dblob + L.lk_wide[k]);
-      const uint32_t nw = (uint32_t)P.lk_wide[k].size();
-      VL_STAGE(ev, VL_STAGE_PASS1, s, launch_lookup_sweep(lj, lst, nw, P.lk_wide_blocks[k], (uint32_t)k, s));
-      VL_STAGE(ev, VL_STAGE_ROUNDS, s, launch_lookup_chal(lj, lst, nw, (uint32_t)k, s));
+    const size_t nk = std::max(P.lk_wide[0].size(), P.lk_wide[1].size());
+    for (size_t k = 0; k < nk; ++k) {
+      for (int lo = 0; lo < 2; ++lo) {
+        if (k >= P.lk_wide[lo].size() || P.lk_wide[lo][k].empty()) continue;
+        const LookupSweep* lst = reinterpret_cast<const LookupSweep*>(dblob + L.lk_wide[lo][k]);
+        const uint32_t nw = (uint32_t)P.lk_wide[lo][k].size();
+        VL_STAGE(ev, VL_STAGE_PASS1, s,
+                 launch_lookup_sweep(lj, lst, nw, P.lk_wide_blocks[lo][k], (uint32_t)k, lo == 1, s));
+        VL_STAGE(ev, VL_STAGE_ROUNDS, s, launch_lookup_chal(lj, lst, nw, (uint32_t)k, s));
+      }
     }
     VL_STAGE(ev, VL_STAGE_ROUNDS, s, launch_lookup_rounds(lj, nl, s));
   }

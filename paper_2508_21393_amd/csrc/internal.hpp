@@ -23,11 +23,12 @@ struct EqJob {
   uint32_t pack_r2;           // 1: pack holds e * R^2 (contractions land in Montgomery
                               // form); 0: e * R (they land in canonical form)
   uint32_t eq_canon;          // 1: eq holds canonical values, 0: Montgomery form
-  uint32_t pad_;
+  uint32_t scaled;            // 1: every entry multiplied by scale
   const uint32_t* point;      // device: nvars Montgomery elements x_j (8 words each)
   uint32_t* eq;               // SoL output, may be null
   uint64_t eq_ld;
   uint32_t* pack;             // pack_len * 8 words, may be null
+  uint32_t scale[8];          // Montgomery
 };
 
 // eq table of a point passed by value (at most 20 variables)
@@ -230,14 +231,14 @@ struct BmmSweep {
 // `wide` rounds run as GPU-wide sweeps and a one-wave transcript step.
 constexpr uint32_t kLookupInvChunk = 16;       // table rows per thread in the batch inversion
 constexpr uint32_t kLookupSweepPairs = 256;
-constexpr uint32_t kLookupWidePairs = 4096;
+constexpr uint32_t kLookupWidePairs = 1024;
 constexpr uint32_t kLookupMaxWide = 32;
 constexpr uint32_t kLookupParts = 14;          // sweep partial elements per block
 // io words: [0] status, [8, 16) state, [16, 24) pending r, [24, 32) K
 constexpr uint32_t kLkIoState = 8, kLkIoR = 16, kLkIoK = 24, kLkIoWords = 32;
 struct LookupJob {
   uint32_t st[8];             // transcript state after gamma, beta, alpha, u
-  uint32_t gamma[8], beta[8], alpha[8], c1[8], c2[8];   // Montgomery
+  uint32_t gamma[8], beta[8], alpha[8], c1[8], c2[8];   // Montgomery (c1 = alpha^2 N / D', c2 = N / D')
   uint32_t claim[8];          // alpha + alpha^2, Montgomery
   const void* x;              // D entries, dtype
   const void* y;              // second column or null
@@ -301,7 +302,7 @@ hipError_t launch_lookup_table(const LookupJob* jobs_dev, uint32_t n_jobs, uint3
 hipError_t launch_lookup_prep(const LookupJob* jobs_dev, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s);
 hipError_t launch_lookup_start(const LookupJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
 hipError_t launch_lookup_sweep(const LookupJob* jobs_dev, const LookupSweep* list_dev, uint32_t n_list,
-                               uint32_t n_blocks, uint32_t round, hipStream_t s);
+                               uint32_t n_blocks, uint32_t round, bool low, hipStream_t s);
 hipError_t launch_lookup_chal(const LookupJob* jobs_dev, const LookupSweep* list_dev, uint32_t n_list,
                               uint32_t round, hipStream_t s);
 hipError_t launch_lookup_rounds(const LookupJob* jobs_dev, uint32_t n_jobs, hipStream_t s);

@@ -41,9 +41,13 @@ __global__ void __launch_bounds__(256) eq_kernel(const EqJob* __restrict__ jobs,
     return x;
   };
   Fr e[4];
+  Fr sc = fr_R();
+  if (J.scaled)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sc.w[k] = J.scale[k];
   if (n < 2) {
-    e[0] = n == 0 ? fr_R() : fr_sub(fr_R(), point(0));
-    e[1] = n == 0 ? fr_zero() : point(0);
+    e[0] = n == 0 ? sc : fr_mul(sc, fr_sub(fr_R(), point(0)));
+    e[1] = n == 0 ? fr_zero() : fr_mul(sc, point(0));
     e[2] = e[3] = fr_zero();
   } else {
     // factor j is x_j for bit 1 and 1 - x_j for bit 0 (b_1 the most
@@ -55,6 +59,7 @@ __global__ void __launch_bounds__(256) eq_kernel(const EqJob* __restrict__ jobs,
       const Fr f = ((t >> (n - 3 - j)) & 1u) ? x : fr_sub(fr_R(), x);
       base = j == 0 ? f : fr_mul(base, f);
     }
+    if (J.scaled) base = n > 2 ? fr_mul(base, sc) : sc;
     const Fr xa = point(n - 2), xb = point(n - 1);
     const Fr bb[2] = {base, base}, fa[2] = {fr_sub(fr_R(), xa), xa}, fb[2] = {fr_sub(fr_R(), xb), xb};
     Fr h[2], q0[2], q1[2];

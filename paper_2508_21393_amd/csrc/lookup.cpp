@@ -128,8 +128,10 @@ void plan_lookup(Builder& B, const vl_lookup& L, const LookupChallenges& ch, uin
   j.T = B.dev<uint32_t>(B.take(32 * N));
   j.M = B.dev<uint32_t>(B.take(32 * N));
   j.EL = B.dev<uint32_t>(B.take(32 * N));
-  B.eq_job(ch.u, j.E, nullptr, 0, false, false);                                          // eq(u, .)
-  B.eq_job(std::vector<Fr>(ch.u.begin() + nH, ch.u.end()), j.EL, nullptr, 0, false, false);   // eq(u_L, .)
+  // E' = alpha eq(u, .) and EL' = c1 eq(u_L, .): the constant factors of
+  // their terms built into the tables (neither is sent)
+  B.eq_job(ch.u, j.E, nullptr, 0, false, false, &am);
+  B.eq_job(std::vector<Fr>(ch.u.begin() + nH, ch.u.end()), j.EL, nullptr, 0, false, false, &c1);
   const uint64_t chunks = (N + kLookupInvChunk - 1) / kLookupInvChunk;
   j.nkparts = (uint32_t)((chunks + 255) / 256);
   j.kpart = B.dev<uint32_t>(B.take(128ull * j.nkparts));
@@ -150,14 +152,16 @@ void plan_lookup(Builder& B, const vl_lookup& L, const LookupChallenges& ch, uin
   if (wide) j.part = B.dev<uint32_t>(B.take(((Dp / 2 + kLookupSweepPairs - 1) / kLookupSweepPairs) * 128));
   const uint32_t idx = (uint32_t)B.P.lookups.size();
   B.P.lookups.push_back(j);
-  if (B.P.lk_wide.size() < wide) {
-    B.P.lk_wide.resize(wide);
-    B.P.lk_wide_blocks.resize(wide, 0);
-  }
+  for (int lo = 0; lo < 2; ++lo)
+    if (B.P.lk_wide[lo].size() < wide) {
+      B.P.lk_wide[lo].resize(wide);
+      B.P.lk_wide_blocks[lo].resize(wide, 0);
+    }
   for (uint32_t k = 0; k < wide; ++k) {
     const uint64_t h = Dp >> (k + 1);
-    B.P.lk_wide[k].push_back(LookupSweep{idx, B.P.lk_wide_blocks[k]});
-    B.P.lk_wide_blocks[k] += (uint32_t)((h + kLookupSweepPairs - 1) / kLookupSweepPairs);
+    const int lo = k >= nH ? 1 : 0;
+    B.P.lk_wide[lo][k].push_back(LookupSweep{idx, B.P.lk_wide_blocks[lo][k]});
+    B.P.lk_wide_blocks[lo][k] += (uint32_t)((h + kLookupSweepPairs - 1) / kLookupSweepPairs);
   }
 }
 

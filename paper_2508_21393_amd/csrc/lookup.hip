@@ -22,7 +22,10 @@
 //   lookup_rounds_kernel the remaining rounds in one workgroup, and the
 //                        final values A(r), S(r), B(r_L), T(r_L), m(r_L)
 // Every table is in Montgomery form; round values are converted to
-// canonical form for the proof.
+// canonical form for the proof.  The constant factors of the sum are folded
+// into tables that are never sent: E' = alpha eq(u, .), EL' = c1 eq(u_L, .)
+// (both built scaled by the eq kernel) and M' = c2 m (m(r_L) is recovered
+// as 2^nH M'(r_L)), so a round's terms add up without further products.
 #include "device.hpp"
 #include "rounds_dev.hpp"
 #include "sha256.hpp"
@@ -86,98 +89,85 @@ __device__ __forceinline__ void lk_fold(const Fr& r, Fr& x0, Fr& x1, const Fr& x
 }
 
 // entries t, t + h of a table of 2h entries (4h before a pending fold,
-// which is done and stored); its values on the line at X = 0, 1, 2, 3
-__device__ __forceinline__ void lk_line(uint32_t* tab, uint64_t ld, uint64_t h, uint64_t t, bool fold, const Fr& r,
-                                        Fr (&v)[4]) {
-  Fr x0 = load_sol(tab, ld, t), x1 = load_sol(tab, ld, t + h);
+// which is done and stored): the table's line at X = 0 and X = 1
+__device__ __forceinline__ void lk_load(uint32_t* tab, uint64_t ld, uint64_t h, uint64_t t, bool fold, const Fr& r,
+                                        Fr& x0, Fr& x1) {
+  x0 = load_sol(tab, ld, t);
+  x1 = load_sol(tab, ld, t + h);
   if (fold) {
     lk_fold(r, x0, x1, load_sol(tab, ld, t + 2 * h), load_sol(tab, ld, t + 3 * h));
     store_sol(tab, ld, t, x0);
     store_sol(tab, ld, t + h, x1);
   }
+}
+
+// the line at X, X + 1 moved on to X + 2, X + 3
+__device__ __forceinline__ void lk_adv(Fr& x0, Fr& x1) {
   const Fr d = fr_sub(x1, x0);
-  v[0] = x0;
-  v[1] = x1;
-  v[2] = fr_add(x1, d);
-  v[3] = fr_add(v[2], d);
+  x0 = fr_add(x1, d);
+  x1 = fr_add(x0, d);
 }
 
-// elementwise products of two lines at the four points
-__device__ __forceinline__ void lk_mul4(const Fr (&x)[4], const Fr (&y)[4], Fr (&z)[4]) {
-  {
-    const Fr a[2] = {x[0], x[1]}, b[2] = {y[0], y[1]};
-    Fr c[2];
-    fr_mul_n<2>(a, b, c);
-    z[0] = c[0];
-    z[1] = c[1];
-  }
-  {
-    const Fr a[2] = {x[2], x[3]}, b[2] = {y[2], y[3]};
-    Fr c[2];
-    fr_mul_n<2>(a, b, c);
-    z[2] = c[0];
-    z[3] = c[1];
-  }
+__device__ __forceinline__ void lk_mul2(const Fr& x0, const Fr& x1, const Fr& y0, const Fr& y1, Fr& z0, Fr& z1) {
+  const Fr a[2] = {x0, x1}, b[2] = {y0, y1};
+  Fr c[2];
+  fr_mul_n<2>(a, b, c);
+  z0 = c[0];
+  z1 = c[1];
 }
 
-// per-thread sums of one round's terms
-struct LkAcc {
-  Fr q[4];      // E A Sb
-  Fr rr[4];     // B EL Tb (low rounds)
-  Fr mm[4];     // B m (low rounds)
-  Fr a0, a1;    // the A line's end points
-};
-
-__device__ __forceinline__ void lk_acc_zero(LkAcc& s) {
+// One pair t < h of a round whose variable is a high index bit: only A, Sb
+// and E' = alpha eq(u, .) depend on it.  Adds alpha E A Sb + A at X = 0..3
+// to g, two points at a time.  pending: fold by r first.
+__device__ __forceinline__ void lk_pair_high(const LookupJob& J, uint64_t h, uint64_t t, bool pending, const Fr& r,
+                                             Fr (&g)[4]) {
+  const uint64_t ldD = 1ull << (J.nH + J.nL);
+  Fr e0, e1, a0, a1, s0, s1;
+  lk_load(J.E, ldD, h, t, pending, r, e0, e1);
+  lk_load(J.A, ldD, h, t, pending, r, a0, a1);
+  lk_load(J.S, ldD, h, t, pending, r, s0, s1);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) s.q[k] = s.rr[k] = s.mm[k] = fr_zero();
-  s.a0 = s.a1 = fr_zero();
-}
-
-// one pair t < h of round rd.  pending: fold by r first (r bound a high bit
-// if rd - 1 < nH: then only A, Sb, E depend on it)
-__device__ __forceinline__ void lk_pair(const LookupJob& J, uint64_t h, uint64_t t, uint32_t rd, bool pending,
-                                        const Fr& r, LkAcc& s) {
-  const uint64_t ldD = 1ull << (J.nH + J.nL), ldN = 1ull << J.nL;
-  const bool high = rd < J.nH;
-  const bool pend_low = pending && rd - 1 >= J.nH;
-  Fr e[4], a[4], sb[4], ea[4], q[4];
-  lk_line(J.E, ldD, h, t, pending, r, e);
-  lk_line(J.A, ldD, h, t, pending, r, a);
-  lk_line(J.S, ldD, h, t, pending, r, sb);
-  lk_mul4(e, a, ea);
-  lk_mul4(ea, sb, q);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) s.q[k] = fr_add(s.q[k], q[k]);
-  s.a0 = fr_add(s.a0, a[0]);
-  s.a1 = fr_add(s.a1, a[1]);
-  if (high) return;
-  Fr b[4], el[4], tt[4], m[4], be[4], rr[4], bm[4];
-  lk_line(J.B, ldN, h, t, pend_low, r, b);
-  lk_line(J.EL, ldN, h, t, pend_low, r, el);
-  lk_line(J.T, ldN, h, t, pend_low, r, tt);
-  lk_line(J.M, ldN, h, t, pend_low, r, m);
-  lk_mul4(b, el, be);
-  lk_mul4(be, tt, rr);
-  lk_mul4(b, m, bm);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    s.rr[k] = fr_add(s.rr[k], rr[k]);
-    s.mm[k] = fr_add(s.mm[k], bm[k]);
+  for (int half = 0; half < 2; ++half) {
+    if (half) {
+      lk_adv(e0, e1);
+      lk_adv(a0, a1);
+      lk_adv(s0, s1);
+    }
+    Fr p0, p1, q0, q1;
+    lk_mul2(e0, e1, a0, a1, p0, p1);
+    lk_mul2(p0, p1, s0, s1, q0, q1);
+    g[2 * half] = fr_add(g[2 * half], fr_add(q0, a0));
+    g[2 * half + 1] = fr_add(g[2 * half + 1], fr_add(q1, a1));
   }
 }
 
-// a thread's sums combined into its part of g(0..3) (without the constant of
-// the high rounds): alpha q + A line + c1 (B EL Tb) - c2 (B m)
-__device__ __forceinline__ void lk_combine(const LookupJob& J, const LkAcc& s, bool high, Fr (&g)[4]) {
-  const Fr alpha = lk_fr(J.alpha), c1 = lk_fr(J.c1), c2 = lk_fr(J.c2);
-  const Fr da = fr_sub(s.a1, s.a0);
-  Fr al = s.a0;
+// One pair of a round whose variable is a low index bit: every table.  Adds
+// alpha E A Sb + A + c1 B EL Tb - c2 B m (EL' = c1 eq(u_L, .), M' = c2 m).
+// pend_hi: the pending challenge bound a high bit (only A, Sb, E fold).
+__device__ __forceinline__ void lk_pair_low(const LookupJob& J, uint64_t h, uint64_t t, bool pending, bool pend_hi,
+                                            const Fr& r, Fr (&g)[4]) {
+  lk_pair_high(J, h, t, pending, r, g);
+  const uint64_t ldN = 1ull << J.nL;
+  const bool fold = pending && !pend_hi;
+  Fr b0, b1, l0, l1, t0, t1, m0, m1;
+  lk_load(J.B, ldN, h, t, fold, r, b0, b1);
+  lk_load(J.EL, ldN, h, t, fold, r, l0, l1);
+  lk_load(J.T, ldN, h, t, fold, r, t0, t1);
+  lk_load(J.M, ldN, h, t, fold, r, m0, m1);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    g[k] = fr_add(fr_mul(alpha, s.q[k]), al);
-    if (!high) g[k] = fr_add(g[k], fr_sub(fr_mul(c1, s.rr[k]), fr_mul(c2, s.mm[k])));
-    al = fr_add(al, da);
+  for (int half = 0; half < 2; ++half) {
+    if (half) {
+      lk_adv(b0, b1);
+      lk_adv(l0, l1);
+      lk_adv(t0, t1);
+      lk_adv(m0, m1);
+    }
+    Fr p0, p1, q0, q1, w0, w1;
+    lk_mul2(b0, b1, l0, l1, p0, p1);
+    lk_mul2(p0, p1, t0, t1, q0, q1);
+    lk_mul2(b0, b1, m0, m1, w0, w1);
+    g[2 * half] = fr_add(g[2 * half], fr_sub(q0, w0));
+    g[2 * half + 1] = fr_add(g[2 * half + 1], fr_sub(q1, w1));
   }
 }
 
@@ -203,9 +193,9 @@ __device__ __forceinline__ bool lk_transcript(const LookupJob& J, uint32_t rd, F
   return true;
 }
 
-// block sum of 4 elements over 256 threads into out (32 words)
-__device__ __forceinline__ void lk_block_out(Fr (&g)[4], uint32_t* out) {
-  __shared__ uint32_t red[4 * 8 * 4];
+// sum of 4 elements over a 256-thread block; the total lands in the lanes
+// of wave 0
+__device__ __forceinline__ void lk_block_sum(Fr (&g)[4], uint32_t* red /* 4 * 8 * 4 words of LDS */) {
   wave_sum<4>(g, kWave);
   const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
   if (lane == 0)
@@ -220,12 +210,18 @@ __device__ __forceinline__ void lk_block_out(Fr (&g)[4], uint32_t* out) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) g[k].w[j] = lane < 4 ? red[(k * 8 + j) * 4 + lane] : 0u;
     wave_sum<4>(g, 4);
-    if (lane == 0)
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) out[k * 8 + j] = g[k].w[j];
   }
+}
+
+// block sum of 4 elements over 256 threads into out (32 words)
+__device__ __forceinline__ void lk_block_out(Fr (&g)[4], uint32_t* out) {
+  __shared__ uint32_t red[4 * 8 * 4];
+  lk_block_sum(g, red);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) out[k * 8 + j] = g[k].w[j];
 }
 
 template <typename Get>
@@ -261,8 +257,8 @@ __global__ void __launch_bounds__(256) lookup_hist_kernel(const LookupJob* __res
 
 // Table rows: Tb_j = t0 + j + gamma tb_j + beta, B_j = 1/Tb_j by a batch
 // inversion over each thread's kLookupInvChunk rows (prefix products, one
-// inversion, back-substitution), m_j in the field, and per block the sum of
-// B_j m_j.  A zero Tb_j (beta at a pole, probability N/p) sets the flag.
+// inversion, back-substitution), M'_j = c2 m_j, and per block the sum of
+// B_j M'_j.  A zero Tb_j (beta at a pole, probability N/p) sets the flag.
 __global__ void __launch_bounds__(256) lookup_table_kernel(const LookupJob* __restrict__ jobs, uint32_t n_jobs,
                                                            uint32_t n_blocks) {
   const uint32_t blk = blockIdx.x;
@@ -275,7 +271,7 @@ __global__ void __launch_bounds__(256) lookup_table_kernel(const LookupJob* __re
 #pragma unroll
   for (int k = 0; k < 4; ++k) g[k] = fr_zero();
   if (j0 < N) {
-    const Fr gamma = lk_fr(J.gamma), beta = lk_fr(J.beta);
+    const Fr gamma = lk_fr(J.gamma), beta = lk_fr(J.beta), c2r2 = fr_mul(lk_fr(J.c2), fr_R2());
     Fr acc = fr_R();
     for (uint64_t j = j0; j < j1; ++j) {
       const Fr tb = compress_mont(J.t0 + (int64_t)j, J.tb ? J.tb[j] : 0, J.tb != nullptr, gamma, beta);
@@ -292,7 +288,7 @@ __global__ void __launch_bounds__(256) lookup_table_kernel(const LookupJob* __re
       store_sol(J.B, N, j, b);
       Fr m = fr_zero();
       m.w[0] = J.cnt[j];
-      m = fr_to_mont(m);
+      m = fr_mul(c2r2, m);            // c2 m in Montgomery form (c2 R^2 times the count)
       store_sol(J.M, N, j, m);
       g[0] = fr_add(g[0], fr_mul(b, m));
     }
@@ -322,8 +318,9 @@ __global__ void __launch_bounds__(256) lookup_prep_kernel(const LookupJob* __res
   store_sol(J.A, Dp, i, load_sol(J.B, N, (uint64_t)j));
 }
 
-// Status and the constant of the high rounds: K = c1 - c2 sum_j B_j m_j (the
-// table rows' terms summed over x_L; sum_j eq(u_L, j) = 1 and B_j Tb_j = 1).
+// Status and the constant of the high rounds: K = c1 - sum_j B_j M'_j with
+// M' = c2 m (the table rows' terms summed over x_L; sum_j eq(u_L, j) = 1 and
+// B_j Tb_j = 1).
 __global__ void __launch_bounds__(64) lookup_start_kernel(const LookupJob* __restrict__ jobs) {
   const LookupJob& J = jobs[blockIdx.x];
   const uint32_t lane = threadIdx.x;
@@ -339,7 +336,7 @@ __global__ void __launch_bounds__(64) lookup_start_kernel(const LookupJob* __res
   for (uint32_t i = lane; i < J.nkparts; i += kWave) s[0] = fr_add(s[0], lds_or_global_fr(J.kpart + 32ull * i));
   wave_sum<1>(s, kWave);
   if (lane == 0) {
-    const Fr K = fr_sub(lk_fr(J.c1), fr_mul(lk_fr(J.c2), s[0]));
+    const Fr K = fr_sub(lk_fr(J.c1), s[0]);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       J.io[kLkIoK + i] = K.w[i];
@@ -349,7 +346,9 @@ __global__ void __launch_bounds__(64) lookup_start_kernel(const LookupJob* __res
   }
 }
 
-// One wide round over every job of its list (one pair per thread).
+// One wide round over every job of its list (one pair per thread), high or
+// low index bit (separate kernels: the high one keeps three tables live).
+template <bool LOW>
 __global__ void __launch_bounds__(256) lookup_sweep_kernel(const LookupJob* __restrict__ jobs,
                                                            const LookupSweep* __restrict__ list, uint32_t n_list,
                                                            uint32_t n_blocks, uint32_t rd) {
@@ -361,14 +360,14 @@ __global__ void __launch_bounds__(256) lookup_sweep_kernel(const LookupJob* __re
   const uint32_t n = J.nH + J.nL;
   const uint64_t h = 1ull << (n - 1 - rd);
   const uint64_t t = (uint64_t)(blk - S.block_begin) * kLookupSweepPairs + threadIdx.x;
-  LkAcc s;
-  lk_acc_zero(s);
+  Fr g[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) g[k] = fr_zero();
   if (t < h) {
     const Fr r = rd > 0 ? lds_or_global_fr(J.io + kLkIoR) : fr_zero();
-    lk_pair(J, h, t, rd, rd > 0, r, s);
+    if (LOW) lk_pair_low(J, h, t, rd > 0, rd > 0 && rd - 1 < J.nH, r, g);
+    else lk_pair_high(J, h, t, rd > 0, r, g);
   }
-  Fr g[4];
-  lk_combine(J, s, rd < J.nH, g);
   lk_block_out(g, J.part + (uint64_t)(blk - S.block_begin) * 32);
 }
 
@@ -405,10 +404,12 @@ __global__ void __launch_bounds__(64) lookup_chal_kernel(const LookupJob* __rest
   }
 }
 
-// The remaining rounds in one workgroup, then the final values.
-__global__ void __launch_bounds__(kRoundsBlock) lookup_rounds_kernel(const LookupJob* __restrict__ jobs) {
+// The remaining rounds in one workgroup of 256 threads (one wave per SIMD,
+// so the pair arithmetic and the hashing lane keep their registers), then
+// the final values.
+__global__ void __launch_bounds__(256) lookup_rounds_kernel(const LookupJob* __restrict__ jobs) {
   const LookupJob& J = jobs[blockIdx.x];
-  __shared__ uint32_t red[4 * 8 * (kRoundsBlock / kWave)];
+  __shared__ uint32_t red[4 * 8 * 4];
   __shared__ uint32_t bcast[8];
   __shared__ uint32_t dead_s;
   const uint32_t tid = threadIdx.x, NT = blockDim.x;
@@ -425,13 +426,17 @@ __global__ void __launch_bounds__(kRoundsBlock) lookup_rounds_kernel(const Looku
   Fr r = pending ? lds_or_global_fr(J.io + kLkIoR) : fr_zero();
   for (uint32_t rd = J.wide; rd < n; ++rd) {
     const uint64_t h = 1ull << (n - 1 - rd);
-    LkAcc s;
-    lk_acc_zero(s);
-    for (uint64_t t = tid; t < h; t += NT) lk_pair(J, h, t, rd, pending, r, s);
     Fr g[4];
-    lk_combine(J, s, rd < J.nH, g);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g[k] = fr_zero();
+    if (rd < J.nH) {
+      for (uint64_t t = tid; t < h; t += NT) lk_pair_high(J, h, t, pending, r, g);
+    } else {
+      const bool pend_hi = pending && rd - 1 < J.nH;
+      for (uint64_t t = tid; t < h; t += NT) lk_pair_low(J, h, t, pending, pend_hi, r, g);
+    }
     __threadfence_block();   // the folded entries, for the next sweep
-    block_sum_w0<4>(g, red);
+    lk_block_sum(g, red);
     if (tid == 0) {
       dead_s = 0;
       Fr rr;
@@ -460,17 +465,19 @@ __global__ void __launch_bounds__(kRoundsBlock) lookup_rounds_kernel(const Looku
   }
   if (n == 0) {
     // no rounds (one entry, one row): the guard is the summand itself
-    const Fr alpha = lk_fr(J.alpha), c1 = lk_fr(J.c1), c2 = lk_fr(J.c2);
-    const Fr f = fr_add(fr_add(fr_mul(alpha, fr_mul(fr_mul(v[2], v[0]), v[1])), v[0]),
-                        fr_sub(fr_mul(c1, fr_mul(fr_mul(v[3], v[6]), v[4])), fr_mul(c2, fr_mul(v[3], v[5]))));
+    const Fr f = fr_add(fr_add(fr_mul(fr_mul(v[2], v[0]), v[1]), v[0]),
+                        fr_sub(fr_mul(fr_mul(v[3], v[6]), v[4]), fr_mul(v[3], v[5])));
     if (!fr_eq(f, lk_fr(J.claim))) {
       *J.status = VL_ERR_FALSE_STATEMENT;
       return;
     }
   }
+  // m(r_L) = M'(r_L) / c2 = 2^nH M'(r_L)
+  Fr mv = v[5];
+  for (uint32_t i = 0; i < J.nH; ++i) mv = fr_double(mv);
   const Fr beta = lk_fr(J.beta);
   const Fr fin[5] = {fr_from_mont(v[0]), fr_from_mont(fr_sub(v[1], beta)), fr_from_mont(v[3]),
-                     fr_from_mont(fr_sub(v[4], beta)), fr_from_mont(v[5])};
+                     fr_from_mont(fr_sub(v[4], beta)), fr_from_mont(mv)};
   uint8_t* out = J.proof + 128ull * n;
   for (int k = 0; k < 5; ++k) put_canon(out + 32 * k, fin[k]);
   tr_absorb_frs(tr, VL_LBL_FINAL, fin);
@@ -507,9 +514,12 @@ hipError_t launch_lookup_start(const LookupJob* jobs, uint32_t n_jobs, hipStream
 }
 
 hipError_t launch_lookup_sweep(const LookupJob* jobs, const LookupSweep* list, uint32_t n_list, uint32_t n_blocks,
-                               uint32_t round, hipStream_t s) {
+                               uint32_t round, bool low, hipStream_t s) {
   if (n_blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(lookup_sweep_kernel, dim3(n_blocks), dim3(256), 0, s, jobs, list, n_list, n_blocks, round);
+  if (low)
+    hipLaunchKernelGGL(lookup_sweep_kernel<true>, dim3(n_blocks), dim3(256), 0, s, jobs, list, n_list, n_blocks, round);
+  else
+    hipLaunchKernelGGL(lookup_sweep_kernel<false>, dim3(n_blocks), dim3(256), 0, s, jobs, list, n_list, n_blocks, round);
   return hipGetLastError();
 }
 
@@ -522,7 +532,7 @@ hipError_t launch_lookup_chal(const LookupJob* jobs, const LookupSweep* list, ui
 
 hipError_t launch_lookup_rounds(const LookupJob* jobs, uint32_t n_jobs, hipStream_t s) {
   if (n_jobs == 0) return hipSuccess;
-  hipLaunchKernelGGL(lookup_rounds_kernel, dim3(n_jobs), dim3(kRoundsBlock), 0, s, jobs);
+  hipLaunchKernelGGL(lookup_rounds_kernel, dim3(n_jobs), dim3(256), 0, s, jobs);
   return hipGetLastError();
 }
 

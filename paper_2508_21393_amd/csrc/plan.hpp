@@ -84,8 +84,8 @@ struct Plan {
   std::vector<LookupJob> lookups;
   std::vector<std::pair<uint32_t*, uint64_t>> lookup_zero;
   uint32_t lk_hist_blocks = 0, lk_prep_blocks = 0, lk_tab_blocks = 0;
-  std::vector<std::vector<LookupSweep>> lk_wide;
-  std::vector<uint32_t> lk_wide_blocks;
+  std::vector<std::vector<LookupSweep>> lk_wide[2];   // per round: jobs binding a high [0] / low [1] bit
+  std::vector<uint32_t> lk_wide_blocks[2];
 };
 
 struct SegLayout {
@@ -95,7 +95,7 @@ struct SegLayout {
 struct BlobLayout {
   uint64_t err, eq, points, evals, reduces, bmms, lookups, total;
   std::vector<SegLayout> seg;
-  std::vector<uint64_t> bmm_wide, lk_wide;
+  std::vector<uint64_t> bmm_wide, lk_wide[2];
 };
 
 // Builds jobs; device addresses are base + workspace offset (base 0 = sizing).
@@ -120,7 +120,7 @@ struct Builder {
   void contract(const void* M, int dtype, int nd, uint64_t ld, bool rows, uint32_t n_out, uint32_t len,
                 const uint32_t* pack, uint32_t* dst, uint64_t dst_ld, uint64_t n_total, int32_t* err);
   void eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_len, bool pack_r2,
-              bool eq_canon);
+              bool eq_canon, const Fr* scale = nullptr);
   // eq job of a point that a kernel earlier on the stream writes to device
   // memory (nvars Montgomery elements at point_dev)
   void eq_job_dev(uint32_t nvars, const uint32_t* point_dev, uint32_t* eq, uint32_t* pack, uint32_t pack_len,
