@@ -14,7 +14,7 @@
 //   bmm_start_kernel   the claim c from its pass-1 partials, absorbed
 //   bmm_sweep_kernel   one round over large tables across the GPU: fold by
 //                      the previous challenge and the round's partial sums
-//   bmm_chal_kernel    one wave per job: the round values, the prover guard
+//   bmm_chal_kernel    one block per job: the round values, the prover guard
 //                      (round 1: g(0) + g(1) = c), transcript, challenge,
 //                      and the fold of E in a head round
 //   bmm_rounds_kernel  one workgroup per job: the remaining rounds and the
@@ -122,16 +122,29 @@ __device__ __forceinline__ void bmm_pair(const BmmJob& J, uint64_t ld, uint64_t 
   }
 }
 
-// absorb("round", g(0..K-1)) and squeeze r (canonical result, one lane)
-__device__ __forceinline__ Fr bmm_transcript_round(Transcript& tr, const Fr (&g)[4], bool head) {
+// an inner round's values times e* = E[0] (the folded eq(rho, .)), uniform
+__device__ __forceinline__ void bmm_scale_inner(const BmmJob& J, bool head, Fr (&g)[4]) {
+  if (head) return;
+  const Fr es = load_sol(J.E, 1ull << J.nh, 0);
+  const Fr x[3] = {es, es, es}, y[3] = {g[0], g[1], g[2]};
+  Fr s[3];
+  fr_mul_n<3>(x, y, s);
+  g[0] = s[0];
+  g[1] = s[1];
+  g[2] = s[2];
+}
+
+// round rd's values written to the proof, absorbed ("round", four values in a
+// head round, three in an inner round) and r squeezed, by wave 0
+__device__ __forceinline__ Fr bmm_round_msg(const BmmJob& J, uint32_t rd, bool head, const Fr (&g)[4],
+                                            Transcript& tr, uint32_t lane) {
+  uint8_t* out = J.proof + bmm_round_off(J, rd);
   if (head) {
     const Fr m[4] = {g[0], g[1], g[2], g[3]};
-    tr_absorb_frs(tr, VL_LBL_ROUND, m);
-  } else {
-    const Fr m[3] = {g[0], g[1], g[2]};
-    tr_absorb_frs(tr, VL_LBL_ROUND, m);
+    return round_challenge_k<4>(tr, m, out, lane);
   }
-  return tr_squeeze_fixed(tr, VL_LBL_R);
+  const Fr m[3] = {g[0], g[1], g[2]};
+  return round_challenge_k<3>(tr, m, out, lane);
 }
 
 }  // namespace
@@ -187,31 +200,22 @@ __global__ void __launch_bounds__(256) bmm_sweep_kernel(const BmmJob* __restrict
   if (bmm_io_status(J) != VL_OK) return;
   const uint32_t nv = J.nh + J.n1;
   const uint64_t ld = 1ull << nv, h = 1ull << (nv - 1 - rd);
-  const uint64_t t = (uint64_t)(blk - S.block_begin) * kBmmSweepPairs + threadIdx.x;
+  const uint64_t base = (uint64_t)(blk - S.block_begin) * kBmmSweepPairs;
   const bool head = rd < J.nh;
   Fr g[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) g[k] = fr_zero();
-  if (t < h) {
+  {
     Fr r = fr_zero();
     if (rd > 0) r = lds_or_global_fr(J.io + kBmmIoR);
-    bmm_pair(J, ld, h, t, head, rd > 0, r, g);
+#pragma unroll 1
+    for (uint64_t t = base + threadIdx.x; t < h && t < base + kBmmSweepPairs; t += 256)
+      bmm_pair(J, ld, h, t, head, rd > 0, r, g);
   }
   __shared__ uint32_t red[4 * 8 * 4];
-  wave_sum<4>(g, kWave);
-  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) red[(k * 8 + j) * 4 + wave] = g[k].w[j];
-  __syncthreads();
-  if (wave == 0) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) g[k].w[j] = lane < 4 ? red[(k * 8 + j) * 4 + lane] : 0u;
-    wave_sum<4>(g, 4);
+  block256_sum4(g, red);
+  const uint32_t lane = threadIdx.x & 63u;
+  if (threadIdx.x < 64) {
     if (lane == 0) {
       uint32_t* o = J.part + (uint64_t)(blk - S.block_begin) * 32;
 #pragma unroll
@@ -222,61 +226,63 @@ __global__ void __launch_bounds__(256) bmm_sweep_kernel(const BmmJob* __restrict
   }
 }
 
-// The transcript step after a wide round, one wave per job: the partials
-// added, an inner round's values scaled by e* = E[0], the prover guard in
-// round 1, the values written and absorbed, r squeezed (kept in io in
-// Montgomery form for the next fold), and in a head round E folded by r.
-__global__ void __launch_bounds__(64) bmm_chal_kernel(const BmmJob* __restrict__ jobs,
-                                                      const BmmSweep* __restrict__ list, uint32_t rd) {
+// The transcript step after a wide round, one 256-thread block per job:
+// the partials added, an inner round's values scaled by e* = E[0], the
+// prover guard in round 1, the values written and absorbed by wave 0, r
+// squeezed (kept in io in Montgomery form for the next fold), and in a head
+// round E folded by r.
+__global__ void __launch_bounds__(256) bmm_chal_kernel(const BmmJob* __restrict__ jobs,
+                                                       const BmmSweep* __restrict__ list, uint32_t rd) {
   const BmmJob& J = jobs[list[blockIdx.x].job];
-  const uint32_t lane = threadIdx.x;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u;
   if (bmm_io_status(J) != VL_OK) return;
   const uint32_t nv = J.nh + J.n1;
   const uint64_t h = 1ull << (nv - 1 - rd);
   const uint32_t nblocks = (uint32_t)((h + kBmmSweepPairs - 1) / kBmmSweepPairs);
   const bool head = rd < J.nh;
+  __shared__ uint32_t red[4 * 8 * 4];
+  __shared__ uint32_t bcast[8];
+  __shared__ uint32_t dead_s;
   Fr g[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) g[k] = fr_zero();
-  for (uint32_t i = lane; i < nblocks; i += kWave)
+  for (uint32_t i = tid; i < nblocks; i += 256)
 #pragma unroll
     for (int k = 0; k < 4; ++k) g[k] = fr_add(g[k], lds_or_global_fr(J.part + 32ull * i + 8 * k));
-  wave_sum<4>(g, kWave);
-  Fr r = fr_zero();
-  uint32_t dead = 0;
-  if (lane == 0) {
-    if (!head) {
-      const Fr es = load_sol(J.E, 1ull << J.nh, 0);
-      const Fr x[3] = {es, es, es}, y[3] = {g[0], g[1], g[2]};
-      Fr s[3];
-      fr_mul_n<3>(x, y, s);
-      g[0] = s[0];
-      g[1] = s[1];
-      g[2] = s[2];
-    }
-    if (rd == 0 && !fr_eq(fr_add(g[0], g[1]), lds_or_global_fr(J.io + kBmmIoC))) {
-      dead = 1;
-      J.io[0] = (uint32_t)VL_ERR_FALSE_STATEMENT;
-      *J.status = VL_ERR_FALSE_STATEMENT;
+  block256_sum4(g, red);
+  if (tid < 64) {
+    Fr gt[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) gt[k] = readlane_fr(g[k], 0);
+    bmm_scale_inner(J, head, gt);
+    const bool dead = rd == 0 && !fr_eq(fr_add(gt[0], gt[1]), lds_or_global_fr(J.io + kBmmIoC));
+    if (dead) {
+      if (lane == 0) {
+        J.io[0] = (uint32_t)VL_ERR_FALSE_STATEMENT;
+        *J.status = VL_ERR_FALSE_STATEMENT;
+        dead_s = 1;
+      }
     } else {
-      uint8_t* out = J.proof + bmm_round_off(J, rd);
-      for (int k = 0; k < (head ? 4 : 3); ++k) put_canon(out + 32 * k, g[k]);
       Transcript tr;
 #pragma unroll
       for (int i = 0; i < 8; ++i) tr.h[i] = J.io[kBmmIoState + i];
-      r = fr_to_mont(bmm_transcript_round(tr, g, head));
+      const Fr r = bmm_round_msg(J, rd, head, gt, tr, lane);
+      if (lane == 0) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        J.io[kBmmIoState + i] = tr.h[i];
-        J.io[kBmmIoR + i] = r.w[i];
+        for (int i = 0; i < 8; ++i) {
+          J.io[kBmmIoState + i] = tr.h[i];
+          J.io[kBmmIoR + i] = r.w[i];
+        }
+        lds_put(bcast, r);
+        dead_s = 0;
       }
     }
   }
-  dead = __builtin_amdgcn_readlane(dead, 0);
-  if (dead || !head) return;
-  r = readlane_fr(r, 0);
+  __syncthreads();
+  if (dead_s || !head) return;
+  const Fr r = lds_get(bcast);
   const uint64_t eld = 1ull << J.nh, hh = 1ull << (J.nh - 1 - rd);
-  for (uint64_t t = lane; t < hh; t += kWave) {
+  for (uint64_t t = tid; t < hh; t += 256) {
     const Fr e0 = load_sol(J.E, eld, t);
     store_sol(J.E, eld, t, fr_add(e0, fr_mul(r, fr_sub(load_sol(J.E, eld, t + hh), e0))));
   }
@@ -311,27 +317,26 @@ __global__ void __launch_bounds__(kRoundsBlock) bmm_rounds_kernel(const BmmJob* 
     Fr g[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) g[k] = fr_zero();
+#pragma unroll 1
     for (uint64_t t = tid; t < h; t += NT) bmm_pair(J, ld, h, t, head, pending, r, g);
     __threadfence_block();   // the folded entries, for the next sweep
     block_sum_w0<4>(g, red);
-    if (tid == 0) {
-      dead_s = 0;
-      if (!head) {
-        const Fr es = load_sol(J.E, eld, 0);
-        const Fr x[3] = {es, es, es}, y[3] = {g[0], g[1], g[2]};
-        Fr s[3];
-        fr_mul_n<3>(x, y, s);
-        g[0] = s[0];
-        g[1] = s[1];
-        g[2] = s[2];
-      }
-      if (rd == 0 && !fr_eq(fr_add(g[0], g[1]), lds_or_global_fr(J.io + kBmmIoC))) {
-        dead_s = 1;
-        *J.status = VL_ERR_FALSE_STATEMENT;
+    if (wave == 0) {
+      Fr gt[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) gt[k] = readlane_fr(g[k], 0);
+      bmm_scale_inner(J, head, gt);
+      if (rd == 0 && !fr_eq(fr_add(gt[0], gt[1]), lds_or_global_fr(J.io + kBmmIoC))) {
+        if (lane == 0) {
+          dead_s = 1;
+          *J.status = VL_ERR_FALSE_STATEMENT;
+        }
       } else {
-        uint8_t* out = J.proof + bmm_round_off(J, rd);
-        for (int k = 0; k < (head ? 4 : 3); ++k) put_canon(out + 32 * k, g[k]);
-        lds_put(bcast, fr_to_mont(bmm_transcript_round(tr, g, head)));
+        const Fr rr = bmm_round_msg(J, rd, head, gt, tr, lane);
+        if (lane == 0) {
+          dead_s = 0;
+          lds_put(bcast, rr);
+        }
       }
     }
     __syncthreads();
@@ -388,7 +393,7 @@ hipError_t launch_bmm_sweep(const BmmJob* jobs, const BmmSweep* list, uint32_t n
 hipError_t launch_bmm_chal(const BmmJob* jobs, const BmmSweep* list, uint32_t n_list, uint32_t round,
                            hipStream_t s) {
   if (n_list == 0) return hipSuccess;
-  hipLaunchKernelGGL(bmm_chal_kernel, dim3(n_list), dim3(kWave), 0, s, jobs, list, round);
+  hipLaunchKernelGGL(bmm_chal_kernel, dim3(n_list), dim3(256), 0, s, jobs, list, round);
   return hipGetLastError();
 }
 

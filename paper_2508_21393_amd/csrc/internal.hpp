@@ -192,7 +192,7 @@ constexpr uint32_t reduce_io_words(uint32_t n_rows) { return kReduceIoR + 8 * n_
 // transcript step (bmm_chal_kernel); the rest run in one workgroup
 // (bmm_rounds_kernel).  io holds the state handed between the launches.
 constexpr uint32_t kBmmSweepPairs = 256;     // pairs per sweep block (one per thread)
-constexpr uint32_t kBmmWidePairs = 4096;     // rounds with at least this many pairs run wide
+constexpr uint32_t kBmmWidePairs = 1024;     // rounds with at least this many pairs run wide
 constexpr uint32_t kBmmMaxWide = 24;
 // io words: [0] status (VL_OK while running), [8, 16) transcript state,
 // [16, 24) pending challenge r (Montgomery), [24, 32) the claim c (canonical)
@@ -230,8 +230,8 @@ struct BmmSweep {
 // the low bits (all seven tables).  As for batched products, the first
 // `wide` rounds run as GPU-wide sweeps and a one-wave transcript step.
 constexpr uint32_t kLookupInvChunk = 16;       // table rows per thread in the batch inversion
-constexpr uint32_t kLookupSweepPairs = 256;
-constexpr uint32_t kLookupWidePairs = 1024;
+constexpr uint32_t kLookupSweepPairs = 256;    // pairs per sweep block (one per thread)
+constexpr uint32_t kLookupWidePairs = 512;
 constexpr uint32_t kLookupMaxWide = 32;
 constexpr uint32_t kLookupParts = 14;          // sweep partial elements per block
 // io words: [0] status, [8, 16) state, [16, 24) pending r, [24, 32) K

@@ -17,7 +17,7 @@
 //                        m in the field, partial sums of B m
 //   lookup_prep_kernel   Sb = S + beta and A = B[row of the entry]
 //   lookup_start_kernel  the constant K of the high rounds, the status
-//   lookup_sweep/chal    the first rounds across the GPU, then a one-wave
+//   lookup_sweep/chal    the first rounds across the GPU, then a one-block
 //                        transcript step
 //   lookup_rounds_kernel the remaining rounds in one workgroup, and the
 //                        final values A(r), S(r), B(r_L), T(r_L), m(r_L)
@@ -171,52 +171,34 @@ __device__ __forceinline__ void lk_pair_low(const LookupJob& J, uint64_t h, uint
   }
 }
 
-// g(0..3) of a round from its summed parts: the high rounds add
-// 2^(nH - rd - 1) K; the guard of round 1 (g(0) + g(1) = alpha + alpha^2);
-// the values written canonical, absorbed, and r squeezed (Montgomery).
-// Returns false if the guard fails.
-__device__ __forceinline__ bool lk_transcript(const LookupJob& J, uint32_t rd, Fr (&g)[4], Transcript& tr, Fr& r) {
+// Round rd by wave 0 (all lanes; the block totals in lane 0): a high round
+// adds the constant 2^(nH - rd - 1) K; round 1 checks the guard
+// g(0) + g(1) = alpha + alpha^2; the values are written canonical, absorbed
+// and r squeezed (Montgomery, every lane).  Returns false, in every lane, if
+// the guard fails.
+__device__ __forceinline__ bool lk_round_wave(const LookupJob& J, uint32_t rd, const Fr (&g)[4], Transcript& tr,
+                                              Fr& r, uint32_t lane) {
+  Fr gt[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) gt[q] = readlane_fr(g[q], 0);
   if (rd < J.nH) {
     Fr k = lds_or_global_fr(J.io + kLkIoK);
     for (uint32_t i = 0; i + 1 < J.nH - rd; ++i) k = fr_double(k);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) g[q] = fr_add(g[q], k);
+    for (int q = 0; q < 4; ++q) gt[q] = fr_add(gt[q], k);
   }
-  if (rd == 0 && !fr_eq(fr_add(g[0], g[1]), lk_fr(J.claim))) return false;
+  if (rd == 0 && !fr_eq(fr_add(gt[0], gt[1]), lk_fr(J.claim))) return false;
   Fr gc[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) gc[q] = fr_from_mont(g[q]);
-  uint8_t* out = J.proof + 128ull * rd;
-  for (int q = 0; q < 4; ++q) put_canon(out + 32 * q, gc[q]);
-  tr_absorb_frs(tr, VL_LBL_ROUND, gc);
-  r = fr_to_mont(tr_squeeze_fixed(tr, VL_LBL_R));
+  for (int q = 0; q < 4; ++q) gc[q] = fr_from_mont(gt[q]);
+  r = round_challenge_k<4>(tr, gc, J.proof + 128ull * rd, lane);
   return true;
-}
-
-// sum of 4 elements over a 256-thread block; the total lands in the lanes
-// of wave 0
-__device__ __forceinline__ void lk_block_sum(Fr (&g)[4], uint32_t* red /* 4 * 8 * 4 words of LDS */) {
-  wave_sum<4>(g, kWave);
-  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) red[(k * 8 + j) * 4 + wave] = g[k].w[j];
-  __syncthreads();
-  if (wave == 0) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) g[k].w[j] = lane < 4 ? red[(k * 8 + j) * 4 + lane] : 0u;
-    wave_sum<4>(g, 4);
-  }
 }
 
 // block sum of 4 elements over 256 threads into out (32 words)
 __device__ __forceinline__ void lk_block_out(Fr (&g)[4], uint32_t* out) {
   __shared__ uint32_t red[4 * 8 * 4];
-  lk_block_sum(g, red);
+  block256_sum4(g, red);
   if (threadIdx.x == 0)
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -346,8 +328,9 @@ __global__ void __launch_bounds__(64) lookup_start_kernel(const LookupJob* __res
   }
 }
 
-// One wide round over every job of its list (one pair per thread), high or
-// low index bit (separate kernels: the high one keeps three tables live).
+// One wide round over every job of its list (kLookupSweepPairs pairs per
+// 256-thread block), high or low index bit (separate kernels: the high one
+// keeps three tables live).
 template <bool LOW>
 __global__ void __launch_bounds__(256) lookup_sweep_kernel(const LookupJob* __restrict__ jobs,
                                                            const LookupSweep* __restrict__ list, uint32_t n_list,
@@ -359,49 +342,54 @@ __global__ void __launch_bounds__(256) lookup_sweep_kernel(const LookupJob* __re
   if (lk_io_status(J) != VL_OK) return;
   const uint32_t n = J.nH + J.nL;
   const uint64_t h = 1ull << (n - 1 - rd);
-  const uint64_t t = (uint64_t)(blk - S.block_begin) * kLookupSweepPairs + threadIdx.x;
+  const uint64_t base = (uint64_t)(blk - S.block_begin) * kLookupSweepPairs;
   Fr g[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) g[k] = fr_zero();
-  if (t < h) {
-    const Fr r = rd > 0 ? lds_or_global_fr(J.io + kLkIoR) : fr_zero();
+  const Fr r = rd > 0 ? lds_or_global_fr(J.io + kLkIoR) : fr_zero();
+#pragma unroll 1
+  for (uint64_t t = base + threadIdx.x; t < h && t < base + kLookupSweepPairs; t += 256) {
     if (LOW) lk_pair_low(J, h, t, rd > 0, rd > 0 && rd - 1 < J.nH, r, g);
     else lk_pair_high(J, h, t, rd > 0, r, g);
   }
   lk_block_out(g, J.part + (uint64_t)(blk - S.block_begin) * 32);
 }
 
-// The transcript step after a wide round, one wave per job.
-__global__ void __launch_bounds__(64) lookup_chal_kernel(const LookupJob* __restrict__ jobs,
-                                                         const LookupSweep* __restrict__ list, uint32_t rd) {
+// The transcript step after a wide round, one 256-thread block per job.
+__global__ void __launch_bounds__(256) lookup_chal_kernel(const LookupJob* __restrict__ jobs,
+                                                          const LookupSweep* __restrict__ list, uint32_t rd) {
   const LookupJob& J = jobs[list[blockIdx.x].job];
-  const uint32_t lane = threadIdx.x;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u;
   if (lk_io_status(J) != VL_OK) return;
   const uint32_t n = J.nH + J.nL;
   const uint64_t h = 1ull << (n - 1 - rd);
   const uint32_t nblocks = (uint32_t)((h + kLookupSweepPairs - 1) / kLookupSweepPairs);
+  __shared__ uint32_t red[4 * 8 * 4];
   Fr g[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) g[k] = fr_zero();
-  for (uint32_t i = lane; i < nblocks; i += kWave)
+  for (uint32_t i = tid; i < nblocks; i += 256)
 #pragma unroll
     for (int k = 0; k < 4; ++k) g[k] = fr_add(g[k], lds_or_global_fr(J.part + 32ull * i + 8 * k));
-  wave_sum<4>(g, kWave);
-  if (lane != 0) return;
+  block256_sum4(g, red);
+  if (tid >= 64) return;
   Transcript tr;
 #pragma unroll
   for (int i = 0; i < 8; ++i) tr.h[i] = J.io[kLkIoState + i];
   Fr r;
-  if (!lk_transcript(J, rd, g, tr, r)) {
-    J.io[0] = (uint32_t)VL_ERR_FALSE_STATEMENT;
-    *J.status = VL_ERR_FALSE_STATEMENT;
+  if (!lk_round_wave(J, rd, g, tr, r, lane)) {
+    if (lane == 0) {
+      J.io[0] = (uint32_t)VL_ERR_FALSE_STATEMENT;
+      *J.status = VL_ERR_FALSE_STATEMENT;
+    }
     return;
   }
+  if (lane == 0)
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    J.io[kLkIoState + i] = tr.h[i];
-    J.io[kLkIoR + i] = r.w[i];
-  }
+    for (int i = 0; i < 8; ++i) {
+      J.io[kLkIoState + i] = tr.h[i];
+      J.io[kLkIoR + i] = r.w[i];
+    }
 }
 
 // The remaining rounds in one workgroup of 256 threads (one wave per SIMD,
@@ -430,21 +418,22 @@ __global__ void __launch_bounds__(256) lookup_rounds_kernel(const LookupJob* __r
 #pragma unroll
     for (int k = 0; k < 4; ++k) g[k] = fr_zero();
     if (rd < J.nH) {
+#pragma unroll 1
       for (uint64_t t = tid; t < h; t += NT) lk_pair_high(J, h, t, pending, r, g);
     } else {
       const bool pend_hi = pending && rd - 1 < J.nH;
+#pragma unroll 1
       for (uint64_t t = tid; t < h; t += NT) lk_pair_low(J, h, t, pending, pend_hi, r, g);
     }
     __threadfence_block();   // the folded entries, for the next sweep
-    lk_block_sum(g, red);
-    if (tid == 0) {
-      dead_s = 0;
+    block256_sum4(g, red);
+    if (tid < 64) {
       Fr rr;
-      if (!lk_transcript(J, rd, g, tr, rr)) {
-        dead_s = 1;
-        *J.status = VL_ERR_FALSE_STATEMENT;
-      } else {
-        lds_put(bcast, rr);
+      const bool ok = lk_round_wave(J, rd, g, tr, rr, tid);
+      if (tid == 0) {
+        dead_s = ok ? 0 : 1;
+        if (ok) lds_put(bcast, rr);
+        else *J.status = VL_ERR_FALSE_STATEMENT;
       }
     }
     __syncthreads();
@@ -526,7 +515,7 @@ hipError_t launch_lookup_sweep(const LookupJob* jobs, const LookupSweep* list, u
 hipError_t launch_lookup_chal(const LookupJob* jobs, const LookupSweep* list, uint32_t n_list, uint32_t round,
                               hipStream_t s) {
   if (n_list == 0) return hipSuccess;
-  hipLaunchKernelGGL(lookup_chal_kernel, dim3(n_list), dim3(kWave), 0, s, jobs, list, round);
+  hipLaunchKernelGGL(lookup_chal_kernel, dim3(n_list), dim3(256), 0, s, jobs, list, round);
   return hipGetLastError();
 }
 
