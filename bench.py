@@ -231,26 +231,27 @@ def autotune(B, gas, seed, mode, reps=3):
     return best[1], table
 
 
-def serving_leg(B, n_requests, pool_size=6, n_slots=4, seed=5):
-    """Continuous batching at 13B-class shapes: a resident pool of proof
-    requests (LoRA layers of hidden 5120 / FFN 13824, mixed T, rank and
-    fwd/bwd/upd type), Poisson arrivals at the serial service rate, served by
-    paper_2508_21393_amd.serve.  Each arrival proves a pooled witness with its
-    own seed; three results are checked against a solo prove."""
+def serving_leg(B, n_requests, n_slots=4, seed=5, loads=(0.5, 0.8, 0.95), pool_n=14):
+    """Continuous batching at 13B-class shapes (hidden 5120, FFN 13824): a
+    resident pool of proof requests that covers every target, T in
+    {128, 512, 2048}, rank in {8, 16, 64} and type in {fwd, bwd, upd}
+    (workloads.serving_sample), served by paper_2508_21393_amd.serve.  The
+    saturated rate is measured first (the whole stream queued at once); then
+    Poisson arrivals at each fraction of it in `loads`, n_requests each, each
+    arrival proving a pooled witness with its own seed.  Three results per
+    load are checked against a solo prove of the same request and seed."""
     import numpy as np
     import torch
     import workloads
     from paper_2508_21393_amd import serve
     dev = lambda x: x if torch.is_tensor(x) else torch.from_numpy(x).to("cuda")  # noqa: E731
-    kinds = workloads.serving_stream(pool_size, 1.0, seed=seed)
     weights, pool, shapes = {}, [], []
-    for k, (_, target, T, r, kind) in enumerate(kinds):
-        if target not in weights:
-            weights[target] = workloads.frozen_weight(target, seed=seed)
-        wl = workloads.serving_request(k, target, T, r, kind, weights[target], seed=seed, device="cuda")
+    for k, spec in enumerate(workloads.serving_sample(pool_n)):
+        wl = workloads.serving_sample_workload(k, spec, weights, seed=seed, device="cuda")
         gas = [B.GroupArgs(g.group_id, [(dev(p.A), dev(p.B), p.transA, p.transB) for p in g.products], dev(g.C))
                for g in wl.groups]
         pool.append(gas)
+        target, T, r, kind = spec
         shapes.append(f"{kind} {target} T={T} r={r}")
     torch.cuda.synchronize()
     solo = []
@@ -260,48 +261,54 @@ def serving_leg(B, n_requests, pool_size=6, n_slots=4, seed=5):
         B.sumcheck_matmul_prove(gas, 2, mode=B.VL_MODE_BATCHED)
         solo.append(time.perf_counter() - t0)
     mean_solo = sum(solo) / len(solo)
-    rate = 1.0 / mean_solo                     # offered load: the one-at-a-time service rate
-    gaps = np.random.default_rng([seed, 11]).exponential(1.0 / rate, size=n_requests)
-    arrivals = [(float(t), i % pool_size) for i, t in enumerate(np.cumsum(gaps))]
+    rng = np.random.default_rng([seed, 11])
+    picks = rng.integers(0, len(pool), size=n_requests)       # which pooled request each arrival proves
     srv = serve.ProofServer(n_slots=n_slots, hbm_budget_bytes=64 << 30)
     # warm the server (each slot's pinned buffers, the allocator's blocks):
     # every pooled request once per slot, back to back, not timed
-    for i in range(n_slots * pool_size):
-        srv.submit(serve.Request(-1 - i, pool[i % pool_size], 1))
+    for i in range(n_slots * len(pool)):
+        srv.submit(serve.Request(-1 - i, pool[i % len(pool)], 1))
     srv.drain()
     srv.done.clear()
     for slot in srv.slots:   # every slot's pinned buffers at the pool's largest request
         slot.host_buffers(torch, max(sum(B.proof_size(g) for g in gas) for gas in pool), max(len(gas) for gas in pool))
-    # no garbage-collector pass inside the timed loops
+    n_products = sum(sum(len(g.prods) for g in pool[k]) for k in picks)
     gc.collect()
-    gc.disable()
+    gc.disable()   # no garbage-collector pass inside the timed loops
+    rows = []
     try:
-        results, wall = serve.run_open_loop(srv, arrivals,
-                                            lambda i, k: serve.Request(i, pool[k], 7000 + i))
-        # capacity: the same requests all queued at once (a standing backlog)
-        done_poisson = dict(srv.done)
-        srv.done.clear()
-        _, sat_wall = serve.run_open_loop(srv, [(0.0, k) for _, k in arrivals],
+        # capacity: the whole stream queued at once (a standing backlog)
+        _, sat_wall = serve.run_open_loop(srv, [(0.0, int(k)) for k in picks],
                                           lambda i, k: serve.Request(i, pool[k], 9000 + i))
+        srv.done.clear()
+        sat_rate = n_requests / sat_wall
+        for li, frac in enumerate(loads):
+            rate = frac * sat_rate
+            gaps = np.random.default_rng([seed, 12, li]).exponential(1.0 / rate, size=n_requests)
+            arrivals = [(float(t), int(k)) for t, k in zip(np.cumsum(gaps), picks)]
+            base = 100000 * (li + 1)
+            results, wall = serve.run_open_loop(srv, arrivals, lambda i, k: serve.Request(i, pool[k], base + i))
+            srv.done.clear()
+            gc.enable()
+            for res in results[:: max(1, len(results) // 3)][:3]:
+                ref, _ = B.sumcheck_matmul_prove(pool[arrivals[res.rid][1]], base + res.rid, mode=B.VL_MODE_BATCHED)
+                assert res.proofs == ref and not any(res.status), "a served proof differs from the solo prove"
+            gc.disable()
+            summ = serve.latency_summary(results)
+            worst = max(results, key=lambda r: r.latency)
+            rows.append({"load": frac, "arrival_rate_per_s": rate, "requests": n_requests,
+                         "p50_ms": summ["p50_ms"], "p99_ms": summ["p99_ms"], "mean_ms": summ["mean_ms"],
+                         "requests_per_s": n_requests / wall, "products_per_s": n_products / wall,
+                         "worst_request_ms": {"queued": 1e3 * (worst.t_admit - worst.t_arrive),
+                                              "in_flight": 1e3 * (worst.t_done - worst.t_admit)},
+                         "peak_in_flight": srv.peak_in_flight})
     finally:
         gc.enable()
-    assert len(done_poisson) == n_requests
-    for r in results[:3]:
-        ref, _ = B.sumcheck_matmul_prove(pool[arrivals[r.rid][1]], 7000 + r.rid, mode=B.VL_MODE_BATCHED)
-        assert r.proofs == ref and not any(r.status), "a served proof differs from the solo prove"
-    summ = serve.latency_summary(results)
-    n_products = sum(sum(len(g.prods) for g in pool[k]) for _, k in arrivals)
-    worst = max(results, key=lambda r: r.latency)
-    return {"workload": "13B-class LoRA layer requests (hidden 5120, FFN 13824; T in {128, 512, 2048}, "
-                        "rank in {8, 16, 64}; fwd/bwd/upd)",
-            "pool": shapes, "requests": n_requests, "slots": n_slots, "arrival": "poisson",
-            "arrival_rate_per_s": rate, "solo_mean_ms": 1e3 * mean_solo,
-            "p50_ms": summ["p50_ms"], "p99_ms": summ["p99_ms"], "mean_ms": summ["mean_ms"],
-            "requests_per_s": n_requests / wall, "products_per_s": n_products / wall,
-            "saturated_requests_per_s": n_requests / sat_wall, "saturated_products_per_s": n_products / sat_wall,
-            "worst_request_ms": {"queued": 1e3 * (worst.t_admit - worst.t_arrive),
-                                 "in_flight": 1e3 * (worst.t_done - worst.t_admit)},
-            "peak_in_flight": srv.peak_in_flight}
+    return {"workload": "13B-class LoRA layer requests (hidden 5120, FFN 13824; every target, T in "
+                        "{128, 512, 2048}, rank in {8, 16, 64}, fwd/bwd/upd)",
+            "pool": shapes, "slots": n_slots, "arrival": "poisson", "solo_mean_ms": 1e3 * mean_solo,
+            "saturated_requests_per_s": sat_rate, "saturated_products_per_s": n_products / sat_wall,
+            "loads": rows}
 
 
 def attention_leg(B, reps, seed=6):
@@ -397,8 +404,8 @@ def main():
                     help="proofs in flight in the throughput phase (asynchronous entry point)")
     ap.add_argument("--graph", type=int, default=1,
                     help="1: the throughput phase replays one captured HIP graph per slot (vl_prove_graph)")
-    ap.add_argument("--serve-requests", type=int, default=48,
-                    help="requests in the serving leg at 13B-class shapes (0: skip it)")
+    ap.add_argument("--serve-requests", type=int, default=600,
+                    help="requests per offered load in the serving leg at 13B-class shapes (0: skip it)")
     ap.add_argument("--autotune", action="store_true",
                     help="time a grid of launch shapes first and bench the fastest")
     ap.add_argument("--attention-reps", type=int, default=5,
