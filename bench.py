@@ -208,30 +208,7 @@ def streaming_read_GBps(nbytes=4 << 30):
     return v if v > 0 else None
 
 
-def autotune(B, gas, seed, mode, reps=3):
-    """Time each launch shape of a small grid (results are identical for
-    all of them) and return the fastest with the table of timings."""
-    import torch
-    grid = [(lm, sg, cr) for lm in (4096, 8192, 16384) for sg in (1, 2, 4) for cr in (1, 2)]
-    best, table = None, []
-    for lm, sg, cr in grid:
-        t = B.tuning(lane_macs=lm, segments=sg, cols_rows=cr)
-        ws = torch.empty(B.workspace_size(gas, mode, tuning_=t), dtype=torch.uint8, device="cuda")
-        B.sumcheck_matmul_prove(gas, seed, mode=mode, workspace=ws, tuning_=t)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            B.sumcheck_matmul_prove(gas, seed, mode=mode, workspace=ws, tuning_=t)
-        ms = 1e3 * (time.perf_counter() - t0) / reps
-        table.append({"lane_macs": lm, "segments": sg, "cols_rows": cr, "ms": round(ms, 3)})
-        print(json.dumps(table[-1]), file=sys.stderr, flush=True)
-        if best is None or ms < best[0]:
-            best = (ms, t)
-        del ws
-    return best[1], table
-
-
-def serving_leg(B, n_requests, n_slots=4, seed=5, loads=(0.5, 0.8, 0.95), pool_n=14):
+def serving_leg(B, n_requests, n_slots=4, seed=5, loads=(0.5, 0.8, 0.95), pool_n=14, planner=None):
     """Continuous batching at 13B-class shapes (hidden 5120, FFN 13824): a
     resident pool of proof requests that covers every target, T in
     {128, 512, 2048}, rank in {8, 16, 64} and type in {fwd, bwd, upd}
@@ -239,7 +216,9 @@ def serving_leg(B, n_requests, n_slots=4, seed=5, loads=(0.5, 0.8, 0.95), pool_n
     saturated rate is measured first (the whole stream queued at once); then
     Poisson arrivals at each fraction of it in `loads`, n_requests each, each
     arrival proving a pooled witness with its own seed.  Three results per
-    load are checked against a solo prove of the same request and seed."""
+    load are checked against a solo prove of the same request and seed.  The
+    planner (if given) picks each pooled shape's launch shapes before the
+    timed runs; the server uses its cached choices."""
     import numpy as np
     import torch
     import workloads
@@ -254,6 +233,11 @@ def serving_leg(B, n_requests, n_slots=4, seed=5, loads=(0.5, 0.8, 0.95), pool_n
         target, T, r, kind = spec
         shapes.append(f"{kind} {target} T={T} r={r}")
     torch.cuda.synchronize()
+    planned = 0
+    if planner is not None:
+        for gas in pool:
+            rec = planner.plan(gas, 1)
+            planned += rec["lane_macs"] != 0
     solo = []
     for gas in pool:
         B.sumcheck_matmul_prove(gas, 1, mode=B.VL_MODE_BATCHED)
@@ -263,7 +247,7 @@ def serving_leg(B, n_requests, n_slots=4, seed=5, loads=(0.5, 0.8, 0.95), pool_n
     mean_solo = sum(solo) / len(solo)
     rng = np.random.default_rng([seed, 11])
     picks = rng.integers(0, len(pool), size=n_requests)       # which pooled request each arrival proves
-    srv = serve.ProofServer(n_slots=n_slots, hbm_budget_bytes=64 << 30)
+    srv = serve.ProofServer(n_slots=n_slots, hbm_budget_bytes=64 << 30, planner=planner)
     # warm the server (each slot's pinned buffers, the allocator's blocks):
     # every pooled request once per slot, back to back, not timed
     for i in range(n_slots * len(pool)):
@@ -307,6 +291,7 @@ def serving_leg(B, n_requests, n_slots=4, seed=5, loads=(0.5, 0.8, 0.95), pool_n
     return {"workload": "13B-class LoRA layer requests (hidden 5120, FFN 13824; every target, T in "
                         "{128, 512, 2048}, rank in {8, 16, 64}, fwd/bwd/upd)",
             "pool": shapes, "slots": n_slots, "arrival": "poisson", "solo_mean_ms": 1e3 * mean_solo,
+            "planned_shapes_off_default": planned,
             "saturated_requests_per_s": sat_rate, "saturated_products_per_s": n_products / sat_wall,
             "loads": rows}
 
@@ -406,8 +391,10 @@ def main():
                     help="1: the throughput phase replays one captured HIP graph per slot (vl_prove_graph)")
     ap.add_argument("--serve-requests", type=int, default=600,
                     help="requests per offered load in the serving leg at 13B-class shapes (0: skip it)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="time a grid of launch shapes first and bench the fastest")
+    ap.add_argument("--no-plan", action="store_true",
+                    help="use the library's default launch shapes instead of the planner's choice")
+    ap.add_argument("--plan-cache", default=None,
+                    help="JSON file of the planner's choices per shape signature (read and updated)")
     ap.add_argument("--attention-reps", type=int, default=5,
                     help="calls of the attention-layer leg (per-head batched products; 0: skip it)")
     ap.add_argument("--lookup-reps", type=int, default=3,
@@ -452,9 +439,13 @@ def main():
     macs = algorithmic_macs(shapes)
     n_products = sum(len(s) for s in shapes)
     tun = B.tuning(args.lane_macs, args.min_tasks, args.segments, args.cols_rows, 0, args.claim_order)
-    tried = None
-    if args.autotune:
-        tun, tried = autotune(B, batch, w.seed, mode)
+    from paper_2508_21393_amd import tune
+    planner = None if args.no_plan else tune.Planner(cache_path=args.plan_cache)
+    plan_rec = None
+    knobs = (args.lane_macs, args.min_tasks, args.segments, args.cols_rows, args.claim_order)
+    if planner is not None and not any(knobs) and mode == B.VL_MODE_BATCHED:
+        plan_rec = planner.plan(batch, w.seed, mode)
+        tun = planner.tuning(batch, w.seed, mode)
     workspace = torch.empty(B.workspace_size(batch, mode, tuning_=tun), dtype=torch.uint8, device="cuda")
 
     def step(stage=None):
@@ -605,14 +596,18 @@ def main():
         "tuning": {"lane_macs": tun.lane_macs, "min_tasks": tun.min_tasks, "segments": tun.segments,
                    "cols_rows": tun.cols_rows, "claim_order": tun.claim_order},
     }
-    if tried is not None:
-        out["autotune"] = tried
+    if plan_rec is not None:
+        out["plan"] = {"signature": tune.signature(batch, mode),
+                       "chosen": {k: plan_rec[k] for k in ("lane_macs", "segments", "cols_rows", "claim_order")},
+                       "blocking_ms_chosen": plan_rec["ms"], "blocking_ms_default": plan_rec["default_ms"],
+                       "candidates": len(plan_rec["grid"]),
+                       "note": "0 = the library default for that knob; timed on this block's inputs"}
     if args.serve_requests > 0:
         for sl in slots:
             sl.graph = None
         del slots, workspace, batch, gas
         torch.cuda.empty_cache()
-        out["serving"] = serving_leg(B, args.serve_requests)
+        out["serving"] = serving_leg(B, args.serve_requests, planner=planner)
     if args.attention_reps > 0:
         torch.cuda.empty_cache()
         out["attention"] = attention_leg(B, args.attention_reps)

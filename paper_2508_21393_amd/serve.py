@@ -35,6 +35,7 @@ class Request:
     t_arrive: float = 0.0
     witness_bytes: int = 0          # counted against the budget while in flight (0 = resident pool)
     mode: int = B.VL_MODE_BATCHED
+    tuning: object = None           # vl_tuning; None: the server planner's cached choice, else defaults
 
 
 @dataclasses.dataclass
@@ -75,9 +76,10 @@ class _Slot:
 
 
 class ProofServer:
-    def __init__(self, n_slots: int = 4, hbm_budget_bytes: int = 32 << 30):
+    def __init__(self, n_slots: int = 4, hbm_budget_bytes: int = 32 << 30, planner=None):
         import torch
         self.torch = torch
+        self.planner = planner                 # tune.Planner: launch shapes per shape signature (cached only)
         self.slots = [_Slot(torch, i) for i in range(n_slots)]
         self.budget = hbm_budget_bytes
         self.in_use = 0
@@ -86,10 +88,14 @@ class ProofServer:
         self.peak_in_flight = 0
 
     # -- sizing ---------------------------------------------------------------
-    @staticmethod
-    def request_bytes(req: Request) -> int:
+    def _tuning(self, req: Request):
+        if req.tuning is None and self.planner is not None:
+            req.tuning = self.planner.lookup(req.groups, req.mode)
+        return req.tuning
+
+    def request_bytes(self, req: Request) -> int:
         """HBM bytes a request holds while in flight (its outputs are in host memory)."""
-        return B.workspace_size(req.groups, req.mode, async_=True) + req.witness_bytes
+        return B.workspace_size(req.groups, req.mode, async_=True, tuning_=self._tuning(req)) + req.witness_bytes
 
     # -- queue ----------------------------------------------------------------
     def submit(self, req: Request):
@@ -118,8 +124,9 @@ class ProofServer:
             # the workspace comes from the slot's stream: freed when the slot
             # is released, its block is at once reusable by the slot's next
             # request (no cross-stream event, no new device allocation)
+            tun = self._tuning(req)
             with torch.cuda.stream(slot.stream):
-                ws = torch.empty(max(256, B.workspace_size(req.groups, req.mode, async_=True)),
+                ws = torch.empty(max(256, B.workspace_size(req.groups, req.mode, async_=True, tuning_=tun)),
                                  dtype=torch.uint8, device="cuda")
             total = sum(B.proof_size(g) for g in req.groups)
             # the slot is free, so nothing still writes its pinned buffers
@@ -128,7 +135,7 @@ class ProofServer:
             # the slot's stream must see the witnesses made on the current stream
             slot.stream.wait_stream(torch.cuda.current_stream())
             slot.offs = B.sumcheck_matmul_prove_async(req.groups, req.seed, proofs, status, ws,
-                                                      mode=req.mode, stream=slot.stream)
+                                                      mode=req.mode, stream=slot.stream, tuning_=tun)
             ev = torch.cuda.Event()
             ev.record(slot.stream)
             slot.req, slot.event, slot.bufs, slot.bytes = req, ev, (ws, proofs, status), need

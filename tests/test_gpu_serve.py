@@ -75,8 +75,9 @@ def test_budget_limits_admission(env):
         g = workloads.tiny_random_group(300 + i, [(64, 128, 32)], name=f"b{i}")
         host.append(([g], 2000 + i))
     reqs = [([device_group(g, B) for g in gs], seed) for gs, seed in host]
-    need = serve.ProofServer.request_bytes(serve.Request(0, *reqs[0]))
-    assert all(serve.ProofServer.request_bytes(serve.Request(0, *r)) == need for r in reqs)
+    sizer = serve.ProofServer(n_slots=1)
+    need = sizer.request_bytes(serve.Request(0, *reqs[0]))
+    assert all(sizer.request_bytes(serve.Request(0, *r)) == need for r in reqs)
     srv = serve.ProofServer(n_slots=4, hbm_budget_bytes=need)
     for i, (gs, seed) in enumerate(reqs):
         srv.submit(serve.Request(i, gs, seed))
@@ -143,3 +144,23 @@ def test_server_refuses_persistent_mode(env):
     srv = serve.ProofServer(n_slots=1)
     with pytest.raises(ValueError):
         srv.submit(serve.Request(0, *reqs[0], mode=B.VL_MODE_PERSISTENT))
+
+
+def test_planner_choice_is_used_and_bytes_unchanged(env):
+    # the planner times launch shapes for a request's shape signature once;
+    # the server then proves that shape with the cached choice, and the
+    # proof bytes are the oracle's whatever the choice
+    B, serve = env
+    from paper_2508_21393_amd import tune
+    g = workloads.tiny_random_group(41, [(70, 1030, 129)], name="plan")
+    gs = [device_group(g, B)]
+    planner = tune.Planner(grid=[(4096, 1, 2, 1), (16384, 2, 1, 0)], reps=1)
+    rec = planner.plan(gs, 5)
+    assert {"lane_macs", "segments", "cols_rows", "claim_order", "ms", "default_ms", "grid"} <= set(rec)
+    assert planner.lookup(gs) is not None
+    srv = serve.ProofServer(n_slots=2, planner=planner)
+    for i in range(3):
+        srv.submit(serve.Request(i, gs, 50 + i))
+    srv.drain()
+    for i in range(3):
+        assert srv.done[i].proofs == [prove_workload_group(g, 50 + i)[0]]
