@@ -497,6 +497,77 @@ vl_status vl_lookup_verify(const uint8_t* proof, uint64_t len, const vl_lookup* 
                            uint64_t reduced_cap, uint64_t* reduced_len, int32_t* fail_round);
 
 /* Message for the last non-OK status on this thread. */
+/* Hyrax commitments to matrix MLEs: the polynomial commitments of Sec. II-A,
+ * with the scheme the paper's implementation uses (Hyrax; its commitment
+ * times and sizes are those of Table t2).  The multilinear extension of an
+ * R x m integer matrix M (eq. (MLE), rows indexed by the first log2 R
+ * variables, both dimensions zero padded to powers of two) is committed row
+ * by row with Pedersen vector commitments in G1 of BLS12-381, the group of
+ * order p (the order of Fr):
+ *     C_i = sum_{j < m} M[i][j] G_j            (i < R; padded rows commit to 0)
+ * and opened at a point (x, y) with w = sum_i eq(x, i) M[i][.] (m elements:
+ * the partial evaluation vl_mle_partial_eval computes with
+ * VL_CONTRACT_ROWS); the verifier checks
+ *     sum_j w_j G_j = sum_i eq(x, i) C_i
+ * and takes M~(x, y) = sum_j w_j eq(y, j).  Commitments are binding, not
+ * hiding (no blinding term).
+ * Generators: G_j by try-and-increment hashing to the curve y^2 = x^3 + 4:
+ * for ctr = 0, 1, ..: X = LE(H(t || 0) || H(t || 1)) mod q with
+ * t = "VeriLoRA-hyrax-v1" || u32 j || u32 ctr and H = SHA-256; the first
+ * ctr for which X^3 + 4 is a square gives the point (X, y) with y its even
+ * square root, and G_j = 0xd201000000010001 (X, y) (cofactor clearing into
+ * the order-p subgroup).
+ * Points are 96 bytes: x then y, each 48 bytes little-endian canonical; the
+ * point at infinity is 96 zero bytes. */
+#define VL_HYRAX_POINT_BYTES 96
+
+/* Device bytes of the fixed-base table of m generators and W windows:
+ * m * W * 128 * 96 (0 for m outside 1 .. 2^20 or W outside 1 .. 8). */
+uint64_t vl_hyrax_table_size(uint32_t m, uint32_t windows);
+
+/* Computes the public parameters on the device: for j < m, w < W and
+ * k = 1..128 the affine point k 256^w G_j (Montgomery coordinates), point
+ * ((j W + w) 128 + k - 1) of table.  A table of W windows commits entries of
+ * up to W bytes (int16: 2, int32: 4, int64: 8) with one mixed addition per
+ * nonzero signed base-256 digit.  table: device memory of
+ * vl_hyrax_table_size bytes, 16-byte aligned, owned by the caller.
+ * Asynchronous on stream.  Errors: VL_ERR_SHAPE, VL_ERR_INVALID_ARG,
+ * VL_ERR_BUFFER_TOO_SMALL, VL_ERR_HIP. */
+vl_status vl_hyrax_setup(uint32_t m, uint32_t windows, void* table, uint64_t table_bytes, void* stream);
+
+/* Device workspace bytes of vl_hyrax_commit for R rows, m columns and the
+ * given split (0 = the library's choice); 0 for a bad shape. */
+uint64_t vl_hyrax_commit_workspace_size(uint32_t R, uint32_t m, uint32_t split);
+
+/* Commits to the rows of M (device, R x m, row-major, leading dimension
+ * ld >= m, dtype VL_I16/I32/I64; negative entries are x mod p) with a table
+ * from vl_hyrax_setup of table_m >= m generators and windows >= the entry's
+ * byte size.  commits: device memory of R * 96 bytes (4-byte aligned),
+ * row i's commitment at 96 i.  split: column slices per row, 0 = the
+ * library's choice, else 1 .. ceil(m / 64); it changes how the work is cut,
+ * never the bytes.  workspace: vl_hyrax_commit_workspace_size bytes,
+ * 256-byte aligned.  Asynchronous on stream.  Errors: VL_ERR_INVALID_ARG,
+ * VL_ERR_SHAPE, VL_ERR_DTYPE, VL_ERR_WORKSPACE, VL_ERR_HIP. */
+vl_status vl_hyrax_commit(const void* M, int32_t dtype, uint32_t R, uint32_t m, uint64_t ld, const void* table,
+                          uint32_t table_m, uint32_t windows, uint32_t split, void* commits, void* workspace,
+                          uint64_t workspace_bytes, void* stream);
+
+/* Host: the generators G_0 .. G_{m-1} as 96-byte points into out (host,
+ * 96 m bytes).  Computed on the host (and kept for later calls), so a
+ * verifier does not trust the prover's table. */
+vl_status vl_hyrax_generators(uint32_t m, uint8_t* out);
+
+/* Host verifier of an opening.  commits: R points (host, 96 R bytes); x:
+ * ceil(log2 R) and y: ceil(log2 m) canonical elements (NULL when there are
+ * none); w: m canonical elements.  Checks that every commitment is a
+ * canonical point of the curve in the order-p subgroup (or 96 zero bytes)
+ * and that sum_j w_j G_j = sum_i eq(x, i) C_i (both multi-scalar products
+ * by Pippenger's bucket method), then writes M~(x, y) = sum_j w_j eq(y, j)
+ * to value (optional).  Returns VL_OK or VL_ERR_REJECT (message in
+ * vl_last_error); VL_ERR_INVALID_ARG / VL_ERR_SHAPE for bad arguments. */
+vl_status vl_hyrax_verify_open(const uint8_t* commits, uint32_t R, uint32_t m, const vl_fr* x, const vl_fr* y,
+                               const vl_fr* w, vl_fr* value);
+
 const char* vl_last_error(void);
 
 #ifdef __cplusplus

@@ -35,7 +35,8 @@ EXPORTED = ("vl_fr_lift", "vl_fr_export", "vl_eq_table", "vl_partial_eval_worksp
             "vl_mle_partial_eval_noalloc", "vl_lora_chain_proof_size", "vl_lora_chain_workspace_size",
             "vl_lora_chain_prove", "vl_bmm_proof_size", "vl_bmm_workspace_size", "vl_bmm_prove",
             "vl_bmm_verify", "vl_lookup_proof_size", "vl_lookup_workspace_size", "vl_lookup_prove",
-            "vl_lookup_verify")
+            "vl_lookup_verify", "vl_hyrax_table_size", "vl_hyrax_setup", "vl_hyrax_commit_workspace_size",
+            "vl_hyrax_commit", "vl_hyrax_generators", "vl_hyrax_verify_open")
 NOALLOC_SCRATCH_BYTES = 64 << 20   # VL_NOALLOC_SCRATCH_BYTES
 
 c_u32, c_u64, c_i32, c_vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p
@@ -164,6 +165,20 @@ def lib():
         L.vl_lookup_verify.argtypes = [c_vp, c_u64, ctypes.POINTER(vl_lookup), c_u64, ctypes.POINTER(vl_fr), c_u64,
                                        ctypes.POINTER(c_u64), ctypes.POINTER(c_i32)]
         L.vl_lookup_verify.restype = c_i32
+        L.vl_hyrax_table_size.argtypes = [c_u32, c_u32]
+        L.vl_hyrax_table_size.restype = c_u64
+        L.vl_hyrax_setup.argtypes = [c_u32, c_u32, c_vp, c_u64, c_vp]
+        L.vl_hyrax_setup.restype = c_i32
+        L.vl_hyrax_commit_workspace_size.argtypes = [c_u32, c_u32, c_u32]
+        L.vl_hyrax_commit_workspace_size.restype = c_u64
+        L.vl_hyrax_commit.argtypes = [c_vp, c_i32, c_u32, c_u32, c_u64, c_vp, c_u32, c_u32, c_u32, c_vp, c_vp, c_u64,
+                                      c_vp]
+        L.vl_hyrax_commit.restype = c_i32
+        L.vl_hyrax_generators.argtypes = [c_u32, c_vp]
+        L.vl_hyrax_generators.restype = c_i32
+        L.vl_hyrax_verify_open.argtypes = [c_vp, c_u32, c_u32, ctypes.POINTER(vl_fr), ctypes.POINTER(vl_fr),
+                                           ctypes.POINTER(vl_fr), ctypes.POINTER(vl_fr)]
+        L.vl_hyrax_verify_open.restype = c_i32
         L.vl_prove_graph_create.argtypes = [ctypes.POINTER(vl_group), c_u64, ctypes.POINTER(vl_prove_opts), c_vp,
                                             c_u64, ctypes.POINTER(c_u64), c_vp, ctypes.POINTER(c_vp)]
         L.vl_prove_graph_launch.argtypes = [c_vp, c_u64, c_vp]
@@ -608,3 +623,90 @@ def lookup_verify(proof: bytes, a: LookupArgs, seed: int):
     if st not in (VL_OK, VL_ERR_REJECT):
         _check(st)
     return st == VL_OK, fr_.value, [fr_to_int(red[i]) for i in range(rlen.value)] if st == VL_OK else []
+
+
+# ---------------------------------------------------------------- Hyrax ------
+HYRAX_POINT_BYTES = 96
+
+
+def hyrax_windows(dtype) -> int:
+    """Table windows an entry type needs: its size in bytes."""
+    return {VL_I16: 2, VL_I32: 4, VL_I64: 8}[dtype_code(dtype)]
+
+
+def hyrax_table_size(m: int, windows: int) -> int:
+    return lib().vl_hyrax_table_size(m, windows)
+
+
+class HyraxTable:
+    """Device fixed-base table (public parameters) of m generators and the
+    given windows, filled by vl_hyrax_setup on the current stream."""
+
+    def __init__(self, m: int, windows: int = 2, stream=None):
+        import torch
+        self.m, self.windows = m, windows
+        n = hyrax_table_size(m, windows)
+        if n == 0:
+            raise VLError(VL_ERR_SHAPE, "bad Hyrax table shape")
+        self.buf = torch.empty(n, dtype=torch.uint8, device="cuda")
+        _check(lib().vl_hyrax_setup(m, windows, self.buf.data_ptr(), n, _stream(stream)))
+
+
+def hyrax_commit_workspace_size(R: int, m: int, split: int = 0) -> int:
+    return lib().vl_hyrax_commit_workspace_size(R, m, split)
+
+
+def hyrax_commit(M, table: HyraxTable, out=None, workspace=None, split: int = 0, stream=None):
+    """Row commitments of the device matrix M (R x m int16/int32/int64) as a
+    device uint8 tensor of R x 96 bytes (asynchronous on the stream)."""
+    import torch
+    R, m = M.shape
+    if out is None:
+        out = torch.empty((R, HYRAX_POINT_BYTES), dtype=torch.uint8, device=M.device)
+    need = hyrax_commit_workspace_size(R, m, split)
+    if workspace is None:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=M.device)
+    _check(lib().vl_hyrax_commit(_ptr(M), dtype_code(M.dtype), R, m, _row_stride(M), table.buf.data_ptr(), table.m,
+                                 table.windows, split, _ptr(out), _ptr(workspace),
+                                 workspace.numel() * workspace.element_size(), _stream(stream)))
+    return out
+
+
+def hyrax_generators(m: int) -> bytes:
+    """The generators G_0 .. G_{m-1} computed on the host (96 bytes each)."""
+    buf = ctypes.create_string_buffer(HYRAX_POINT_BYTES * m)
+    _check(lib().vl_hyrax_generators(m, ctypes.addressof(buf)))
+    return buf.raw
+
+
+def hyrax_open(M, x: Sequence[int], stream=None) -> List[int]:
+    """The opening message w = sum_i eq(x, i) M[i][.] of a device matrix,
+    computed by the device partial evaluation (eq table, VL_CONTRACT_ROWS,
+    export to canonical form); returns the m canonical values."""
+    import torch
+    R, m = M.shape
+    n_eq = 1 << len(x)
+    eq = torch.empty((8, max(n_eq, R)), dtype=torch.int32, device=M.device)
+    eq_table(x, fr_vec(eq, n_eq), stream)
+    out = torch.empty((8, m), dtype=torch.int32, device=M.device)
+    ws_n = partial_eval_workspace_size(R, m, VL_CONTRACT_ROWS, M.dtype)
+    ws = torch.empty(max(ws_n, 256), dtype=torch.uint8, device=M.device)
+    mle_partial_eval(M, VL_CONTRACT_ROWS, fr_vec(eq, max(n_eq, R)), fr_vec(out), ws, stream)
+    canon = torch.empty((m, 8), dtype=torch.int32, device=M.device)
+    fr_export(fr_vec(out), m, canon, stream)
+    torch.cuda.synchronize()
+    words = canon.cpu().numpy().astype("uint32")
+    return [sum(int(words[j, k]) << (32 * k) for k in range(8)) for j in range(m)]
+
+
+def hyrax_verify_open(commits: bytes, R: int, m: int, x: Sequence[int], y: Sequence[int], w: Sequence[int]):
+    """Host check of an opening: (ok, value, message)."""
+    xa = (vl_fr * max(1, len(x)))(*[int_to_fr(v) for v in x])
+    ya = (vl_fr * max(1, len(y)))(*[int_to_fr(v) for v in y])
+    wa = (vl_fr * max(1, len(w)))(*[int_to_fr(v) for v in w])
+    val = vl_fr()
+    buf = ctypes.create_string_buffer(bytes(commits), max(len(commits), 1))
+    st = lib().vl_hyrax_verify_open(ctypes.addressof(buf), R, m, xa, ya, wa, ctypes.byref(val))
+    if st not in (VL_OK, VL_ERR_REJECT):
+        _check(st)
+    return st == VL_OK, (fr_to_int(val) if st == VL_OK else None), ("" if st == VL_OK else last_error())

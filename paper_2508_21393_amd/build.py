@@ -17,7 +17,7 @@ PEAK_LIB = os.path.join(HERE, "libvlpeak.so")
 ARCH = "gfx950"
 
 SOURCES = ["contract.hip", "kernels.hip", "capi.cpp", "verify.cpp", "noalloc.hip", "chain.cpp",
-           "bmm.hip", "bmm.cpp", "lookup.hip", "lookup.cpp"]
+           "bmm.hip", "bmm.cpp", "lookup.hip", "lookup.cpp", "hyrax.hip", "hyrax.cpp"]
 PEAK_SOURCES = ["peak.hip"]
 
 # packed FP32 instructions stay off in all device code; hipcc's host pass warns

@@ -306,6 +306,13 @@ hipError_t launch_lookup_sweep(const LookupJob* jobs_dev, const LookupSweep* lis
 hipError_t launch_lookup_chal(const LookupJob* jobs_dev, const LookupSweep* list_dev, uint32_t n_list,
                               uint32_t round, hipStream_t s);
 hipError_t launch_lookup_rounds(const LookupJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
+// Hyrax: generators and fixed-base tables of windows W for m generators;
+// commitments of R rows of an int16/int32/int64 matrix in n_split column
+// slices of chunk columns (partials: R n_split XYZZ points)
+hipError_t launch_hyrax_setup(uint32_t m, uint32_t W, uint32_t* table, hipStream_t s);
+hipError_t launch_hyrax_commit(const void* M, int dtype, uint64_t ld, uint32_t R, uint32_t m, uint32_t W,
+                               const uint32_t* table, uint32_t n_split, uint32_t chunk, uint32_t* partials,
+                               uint32_t* commits, hipStream_t s);
 // bytes (a multiple of 16, both pointers 16-byte aligned) from pinned host
 // memory, given by its device-side address
 hipError_t launch_copy_in(void* dst, const void* src_dev, uint64_t bytes, hipStream_t s);

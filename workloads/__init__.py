@@ -13,5 +13,5 @@ from .gen import (  # noqa: F401
     LayerWitness, layer_witness, chain_layer, tiny_layer, CHAIN_F, CHAIN_ETA,
     serving_request, serving_stream, frozen_weight, serving_sample, serving_sample_workload, tiny_random_group, CONFIG_NAMES, make_config,
     HeadView, HeadBatch, cols_heads, stacked_heads, attention_layer, tiny_head_batch,
-    LookupCase, silu_table, lookup_range, lookup_silu, tiny_lookup,
+    LookupCase, silu_table, lookup_range, lookup_silu, tiny_lookup, block_weights,
 )

@@ -240,6 +240,23 @@ def config4(seed: int = 4, T: int = 2048, hidden: int = 4096, ffn: int = 11008, 
     return Workload(f"7B block T={T} h{hidden} ffn{ffn} r{r}", seed, _number(groups))
 
 
+def block_weights(seed: int = 4, hidden: int = 4096, ffn: int = 11008, only=None):
+    """The frozen weights of one 7B-class decoder block, the matrices a
+    commitment covers: W_q, W_k, W_v, W_o (hidden x hidden), W_gate, W_up
+    (hidden x ffn) and W_down (ffn x hidden), int16 quantised Gaussians with
+    sigma 0.02 at scale 2^12 (as the LoRA layers above).  ``only``: a subset
+    of the names (each matrix has a generator of its own, seeded by
+    (seed, index), so a subset draws the same values)."""
+    shapes = [("q", hidden, hidden), ("k", hidden, hidden), ("v", hidden, hidden), ("o", hidden, hidden),
+              ("gate", hidden, ffn), ("up", hidden, ffn), ("down", ffn, hidden)]
+    out = []
+    for k, (name, r, c) in enumerate(shapes):
+        if only is not None and name not in only:
+            continue
+        out.append((name, quantize_gaussian(np.random.default_rng([seed, k]), (r, c), 0.02)))
+    return out
+
+
 # --------------------------------------------------------------------------
 # one LoRA layer as a chain of claims (forward, backward and update)
 # --------------------------------------------------------------------------
