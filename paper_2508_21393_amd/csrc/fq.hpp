@@ -179,6 +179,67 @@ __device__ __forceinline__ Fq fq_mul_dev(const Fq& a, const Fq& b) {
   for (int j = 0; j < 12; ++j) r.w[j] = u[j];
   return fq_reduce_once(r);
 }
+// N (2 or 3) independent products with their partial products interleaved
+// instruction by instruction (the multiply-adds of fr_macn / fr_macns carry
+// one step of every product), so that the products' dependency chains and
+// carry hazards overlap; the same results as N calls of fq_mul_dev.
+template <int N>
+__device__ __forceinline__ void fq_mul_dev_n(const Fq (&a)[N], const Fq (&b)[N], Fq (&r)[N]) {
+  uint32_t m[N][12], u[N][12];
+  uint64_t acc[N];
+  uint32_t top[N];
+#pragma unroll
+  for (int c = 0; c < N; ++c) { acc[c] = 0; top[c] = 0; }
+  static_for<0, 23>([&](auto K) {
+    constexpr int k = decltype(K)::value;
+    static_for<0, 12>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr int j = k - i;
+      if constexpr (j >= 0 && j < 12) {
+        uint32_t x[N], y[N];
+#pragma unroll
+        for (int c = 0; c < N; ++c) { x[c] = a[c].w[i]; y[c] = b[c].w[j]; }
+        fr_macn<N>(acc, top, x, y);
+      }
+    });
+    static_for<0, 12>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr int j = k - i;
+      if constexpr (i < k && j >= 1 && j < 12) {
+        uint32_t x[N];
+#pragma unroll
+        for (int c = 0; c < N; ++c) x[c] = m[c][i];
+        fr_macns<N>(acc, top, x, q_limb(j));
+      }
+    });
+    if constexpr (k < 12) {
+      uint32_t x[N];
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        m[c][k] = (uint32_t)acc[c] * kQInv32;
+        x[c] = m[c][k];
+      }
+      fr_macns<N>(acc, top, x, q_limb(0));
+    } else {
+#pragma unroll
+      for (int c = 0; c < N; ++c) u[c][k - 12] = (uint32_t)acc[c];
+    }
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      acc[c] = (acc[c] >> 32) | ((uint64_t)top[c] << 32);
+      top[c] = 0;
+    }
+  });
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    u[c][11] = (uint32_t)acc[c];
+    Fq t;
+#pragma unroll
+    for (int j = 0; j < 12; ++j) t.w[j] = u[c][j];
+    r[c] = fq_reduce_once(t);
+  }
+}
+
 // one out-of-line copy for the code outside the commitment loop (setup,
 // reductions, normalisation): inlining every product there makes the kernels
 // many times larger and slow to compile; the loop's mixed addition inlines

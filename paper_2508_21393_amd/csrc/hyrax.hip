@@ -138,22 +138,29 @@ __device__ __forceinline__ G1z g1_dbl_affine_inl(const G1a& a) {
 
 __device__ __forceinline__ G1z g1_add_affine_inl(const G1z& p, const G1a& a) {
   if (g1_is_inf(p)) return g1_from_affine(a);
-  const Fq U2 = fq_mul_dev(a.x, p.ZZ);
-  const Fq S2 = fq_mul_dev(a.y, p.ZZZ);
-  const Fq P = fq_sub(U2, p.X);
-  const Fq R = fq_sub(S2, p.Y);
+  // the ten products in four rounds of independent ones, each round's
+  // products interleaved (fq_mul_dev_n)
+  Fq t2[2];
+  fq_mul_dev_n<2>({a.x, a.y}, {p.ZZ, p.ZZZ}, t2);                 // U2, S2
+  const Fq P = fq_sub(t2[0], p.X);
+  const Fq R = fq_sub(t2[1], p.Y);
   if (fq_is_zero(P)) {
     if (fq_is_zero(R)) return g1_dbl_affine_inl(a);
     return g1_infinity();
   }
-  const Fq PP = fq_mul_dev(P, P);
-  const Fq PPP = fq_mul_dev(P, PP);
-  const Fq Qv = fq_mul_dev(p.X, PP);
+  Fq sq[2];
+  fq_mul_dev_n<2>({P, R}, {P, R}, sq);                              // PP, R^2
+  Fq t3[3];
+  fq_mul_dev_n<3>({P, p.X, p.ZZ}, {sq[0], sq[0], sq[0]}, t3);      // PPP, Q, ZZ PP
+  const Fq& PPP = t3[0];
+  const Fq& Qv = t3[1];
   G1z r;
-  r.X = fq_sub(fq_sub(fq_sub(fq_mul_dev(R, R), PPP), Qv), Qv);
-  r.Y = fq_sub(fq_mul_dev(R, fq_sub(Qv, r.X)), fq_mul_dev(p.Y, PPP));
-  r.ZZ = fq_mul_dev(p.ZZ, PP);
-  r.ZZZ = fq_mul_dev(p.ZZZ, PPP);
+  r.X = fq_sub(fq_sub(fq_sub(sq[1], PPP), Qv), Qv);
+  Fq t4[3];
+  fq_mul_dev_n<3>({R, p.Y, p.ZZZ}, {fq_sub(Qv, r.X), PPP, PPP}, t4);  // R (Q - X3), Y PPP, ZZZ PPP
+  r.Y = fq_sub(t4[0], t4[1]);
+  r.ZZ = t3[2];
+  r.ZZZ = t4[2];
   return r;
 }
 
@@ -214,19 +221,67 @@ __device__ __forceinline__ int digit_of(int64_t v, uint32_t w, int carry, int& c
   return (int)(v >> (8 * (WD - 1))) + carry;
 }
 
+// A lane's nonzero terms (entry t, window w, digit d) in order.  Every
+// madd of the commitment loop is executed by the whole wave, so a lane must
+// not spend an iteration on a zero digit while the others add: each lane
+// walks its own entries to its next nonzero digit (quantised weights mostly
+// have a zero top digit), and the loop runs as many iterations as the lane
+// with the most nonzero terms.  Entry t + 1 is loaded while entry t is in
+// use.
+template <typename T>
+struct NonzeroTerms {
+  static constexpr int WD = (int)sizeof(T);
+  const T* row;
+  uint32_t j0, je, cnt;   // the lane's entries j0 + 64 t, t < cnt, of a slice ending at je
+  uint32_t t, w;          // the next term to examine
+  int c;                  // carry into window w
+  int64_t v;              // entry t
+  T vn;                   // entry t + 1
+
+  __device__ __forceinline__ T load(uint32_t k) const {
+    return __builtin_nontemporal_load(row + min(j0 + 64 * k, je - 1));   // clamped: always in the slice
+  }
+  __device__ __forceinline__ void init(const T* r, uint32_t j0_, uint32_t je_, uint32_t cnt_) {
+    row = r; j0 = j0_; je = je_; cnt = cnt_; t = 0; w = 0; c = 0;
+    v = (int64_t)load(0);
+    vn = load(1);
+  }
+  __device__ __forceinline__ bool next(int& d, uint32_t& j, uint32_t& win) {
+    while (t < cnt) {
+      int co;
+      const int x = digit_of<WD>(v, w, c, co);
+      const uint32_t jj = j0 + 64 * t, ww = w;
+      if (w + 1 < (uint32_t)WD) {
+        c = co;
+        ++w;
+      } else {
+        w = 0;
+        c = 0;
+        ++t;
+        v = (int64_t)vn;
+        vn = load(t + 1);
+      }
+      if (x != 0) {
+        d = x;
+        j = jj;
+        win = ww;
+        return true;
+      }
+    }
+    return false;
+  }
+};
+
 // Task t = s R + i (slice-major, so the waves running together read the same
 // generators' tables) sums M[i][j] G_j over the slice j in [s chunk, (s + 1)
-// chunk) of columns; lane l takes j = s chunk + l + 64 t.  The terms (entry
-// t, window w) are walked in a wave-uniform order; each iteration recodes
-// the next term's digit and loads its table point (always a valid address:
-// a zero digit or a lane past its entries loads the slice's first point and
-// is not added), then adds the current one.  Entries are loaded one entry
-// ahead.
+// chunk) of columns; lane l takes j = s chunk + l + 64 t.  Each iteration
+// finds every lane's next nonzero term and loads its table point (a lane
+// without one loads the slice's first point and adds nothing), then adds the
+// current points.
 template <typename T>
 __global__ void __launch_bounds__(256) hyrax_commit_kernel(const T* __restrict__ M, uint64_t ld, uint32_t R,
                                                            uint32_t m, uint32_t W, const uint32_t* __restrict__ table,
                                                            uint32_t n_split, uint32_t chunk, uint32_t* partials) {
-  constexpr int WD = (int)sizeof(T);
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t task = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (task >= (uint64_t)R * n_split) return;
@@ -234,39 +289,21 @@ __global__ void __launch_bounds__(256) hyrax_commit_kernel(const T* __restrict__
   const uint32_t jb = sl * chunk;
   const uint32_t je = min(m, jb + chunk);
   const uint32_t j0 = jb + lane;
-  const uint32_t cnt = j0 < je ? (je - j0 + 63) / 64 : 0;     // this lane's entries
-  const uint32_t n_terms = (je - jb + 63) / 64 * WD;            // wave-uniform
-  const T* row = M + (uint64_t)i * ld;
+  const uint32_t cnt = j0 < je ? (je - j0 + 63) / 64 : 0;
   const uint32_t* safe = table + table_index(jb, W, 0, 1);
 
-  // entry t's load (clamped to the slice; whether t < cnt is applied to its
-  // digits, so that the load is not waited for until the digits are needed)
-  // (kept as T until used: a widening right after the load would wait for it)
-  auto entry = [&](uint32_t t) -> T { return __builtin_nontemporal_load(row + min(j0 + 64 * t, je - 1)); };
-  int64_t v = (int64_t)entry(0);
-  T vn = entry(1);
-  int c_next;
-  int dn = cnt > 0 ? digit_of<WD>(v, 0, 0, c_next) : 0;
-  G1a nxt = load_point(dn != 0 ? table + table_index(j0, W, 0, (uint32_t)abs(dn)) : safe);
+  NonzeroTerms<T> ts;
+  ts.init(M + (uint64_t)i * ld, j0, je, cnt);
+  int dn = 0;
+  uint32_t jn = 0, wn = 0;
+  bool have = ts.next(dn, jn, wn);
+  G1a nxt = load_point(have ? table + table_index(jn, W, wn, (uint32_t)abs(dn)) : safe);
   G1z acc = g1_infinity();
-  for (uint32_t s = 0; s < n_terms; ++s) {
-    const uint32_t t = s / WD, w = s % WD;
+  while (__ballot(have) != 0) {
     const G1a cur = nxt;
-    const int d = dn;
-    const int c = c_next;
-    uint32_t jn, wn;
-    if (w + 1 < (uint32_t)WD) {
-      dn = t < cnt ? digit_of<WD>(v, w + 1, c, c_next) : 0;
-      jn = j0 + 64 * t;
-      wn = w + 1;
-    } else {
-      v = (int64_t)vn;
-      vn = entry(t + 2);
-      dn = t + 1 < cnt ? digit_of<WD>(v, 0, 0, c_next) : 0;
-      jn = j0 + 64 * (t + 1);
-      wn = 0;
-    }
-    nxt = load_point(dn != 0 ? table + table_index(jn, W, wn, (uint32_t)abs(dn)) : safe);
+    const int d = have ? dn : 0;
+    have = ts.next(dn, jn, wn);
+    nxt = load_point(have ? table + table_index(jn, W, wn, (uint32_t)abs(dn)) : safe);
     if (d != 0) {
       G1a p = cur;
       if (d < 0) p.y = fq_neg(p.y);
@@ -278,21 +315,64 @@ __global__ void __launch_bounds__(256) hyrax_commit_kernel(const T* __restrict__
   if (lane == 0) store_z(partials + task * kZWords, acc);
 }
 
-// C_i = the sum of row i's slices, as 96 canonical bytes (24 words)
+__device__ __forceinline__ Fq fq_shfl_up(const Fq& a, int d) {
+  Fq r;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) r.w[k] = __shfl_up(a.w[k], d);
+  return r;
+}
+__device__ __forceinline__ Fq fq_shfl_down(const Fq& a, int d) {
+  Fq r;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) r.w[k] = __shfl_down(a.w[k], d);
+  return r;
+}
+__device__ __forceinline__ Fq fq_shfl(const Fq& a, int src) {
+  Fq r;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) r.w[k] = __shfl(a.w[k], src);
+  return r;
+}
+
+// C_i = the sum of row i's slices, as 96 canonical bytes (24 words).  One
+// wave per 64 rows: the affine conversions need 1 / (ZZ ZZZ) per row, which
+// Montgomery's simultaneous inversion gets from one inversion per wave (the
+// product of all 64 values, by prefix and suffix products across the lanes;
+// every lane inverts the same value, so the inversion's branches do not
+// diverge).
 __global__ void __launch_bounds__(64) hyrax_final_kernel(uint32_t R, uint32_t n_split, const uint32_t* partials,
                                                          uint32_t* commits) {
-  const uint32_t i = blockIdx.x * 64 + threadIdx.x;
-  if (i >= R) return;
-  G1z acc = load_z(partials + (uint64_t)i * kZWords);
-  for (uint32_t s = 1; s < n_split; ++s) acc = g1_add(acc, load_z(partials + ((uint64_t)s * R + i) * kZWords));
+  const int lane = (int)threadIdx.x;
+  const uint32_t i = blockIdx.x * 64 + lane;
+  const bool valid = i < R;
+  G1z acc = g1_infinity();
+  if (valid) {
+    acc = load_z(partials + (uint64_t)i * kZWords);
+    for (uint32_t s = 1; s < n_split; ++s) acc = g1_add(acc, load_z(partials + ((uint64_t)s * R + i) * kZWords));
+  }
+  const bool fin = valid && !g1_is_inf(acc);
+  const Fq a = fin ? fq_mul(acc.ZZ, acc.ZZZ) : fq_one();
+  Fq P = a, S = a;                       // inclusive prefix and suffix products
+  for (int off = 1; off < 64; off <<= 1) {
+    const Fq tp = fq_shfl_up(P, off);
+    const Fq ts = fq_shfl_down(S, off);
+    if (lane >= off) P = fq_mul(P, tp);
+    if (lane + off < 64) S = fq_mul(S, ts);
+  }
+  const Fq inv = fq_inv(fq_shfl(P, 63));
+  Fq pre = fq_shfl_up(P, 1), suf = fq_shfl_down(S, 1);
+  if (lane == 0) pre = fq_one();
+  if (lane == 63) suf = fq_one();
+  const Fq ainv = fq_mul(fq_mul(pre, suf), inv);   // 1 / (ZZ ZZZ) of this row
+  if (!valid) return;
   uint32_t* out = commits + (uint64_t)i * 24;
-  if (g1_is_inf(acc)) {
+  if (!fin) {
 #pragma unroll
     for (int k = 0; k < 24; ++k) out[k] = 0;
     return;
   }
-  const G1a a = g1_to_affine(acc);
-  const Fq x = fq_from_mont(a.x), y = fq_from_mont(a.y);
+  const Fq x = fq_from_mont(fq_mul(acc.X, fq_mul(ainv, acc.ZZZ)));
+  const Fq y = fq_from_mont(fq_mul(acc.Y, fq_mul(ainv, acc.ZZ)));
 #pragma unroll
   for (int k = 0; k < 12; ++k) {
     out[k] = x.w[k];
