@@ -38,6 +38,8 @@ EXPORTED = ("vl_fr_lift", "vl_fr_export", "vl_eq_table", "vl_partial_eval_worksp
             "vl_lookup_verify", "vl_hyrax_table_size", "vl_hyrax_setup", "vl_hyrax_commit_workspace_size",
             "vl_hyrax_commit", "vl_hyrax_generators", "vl_hyrax_verify_open")
 NOALLOC_SCRATCH_BYTES = 64 << 20   # VL_NOALLOC_SCRATCH_BYTES
+# the library's field Fr: the BLS12-381 scalar field (for drawing points)
+FR_MODULUS = 0x73eda753299d7d483339d80809a1d80553bda402fffe5bfeffffffff00000001
 
 c_u32, c_u64, c_i32, c_vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p
 
