@@ -23,6 +23,17 @@ from . import binding as B
 # 0 keeps the library default for that knob
 DEFAULT_GRID = [(lm, sg, cr, co) for lm in (4096, 8192, 16384) for sg in (1, 2) for cr in (1, 2)
                 for co in (0, 1)]
+# the library's defaults for those knobs (vl_tuning fields left at 0); a
+# persistent call defaults to 4 segments
+LIBRARY_DEFAULTS = (8192, 1, 1, 0)
+
+
+def _defaults(mode: int) -> tuple:
+    return (8192, 4, 1, 0) if mode == B.VL_MODE_PERSISTENT else LIBRARY_DEFAULTS
+
+
+def _resolved(c, mode: int) -> tuple:
+    return tuple(v if v else d for v, d in zip(c, _defaults(mode)))
 
 
 def signature(groups: Sequence[B.GroupArgs], mode: int) -> str:
@@ -87,18 +98,28 @@ class Planner:
             return rec
         batch = groups if isinstance(groups, B.GroupBatch) else B.GroupBatch(list(groups))
         self._time(batch, seed, mode, None)      # first call of these shapes: warms caches and allocator
-        table: List[dict] = []
-        best = None
-        for lm, sg, cr, co in self.grid:
-            t = B.tuning(lane_macs=lm, segments=sg, cols_rows=cr, claim_order=co)
-            ms = self._time(batch, seed, mode, t)
-            row = {"lane_macs": lm, "segments": sg, "cols_rows": cr, "claim_order": co, "ms": round(ms, 4)}
-            table.append(row)
-            if best is None or ms < best["ms"]:
-                best = row
-        default_ms = self._time(batch, seed, mode, None)
+        # candidates that resolve to the defaults are the defaults; the
+        # defaults and every other candidate are timed in two interleaved
+        # passes (best of both), so drift over the sweep biases none of them
+        cands = []
+        for c in self.grid:
+            r = _resolved(c, mode)
+            if r != _defaults(mode) and r not in [_resolved(x, mode) for x in cands]:
+                cands.append(c)
+        times = {None: float("inf")}
+        for c in cands:
+            times[c] = float("inf")
+        for _ in range(2):
+            times[None] = min(times[None], self._time(batch, seed, mode, None))
+            for c in cands:
+                t = B.tuning(lane_macs=c[0], segments=c[1], cols_rows=c[2], claim_order=c[3])
+                times[c] = min(times[c], self._time(batch, seed, mode, t))
+        default_ms = times[None]
+        table: List[dict] = [{"lane_macs": c[0], "segments": c[1], "cols_rows": c[2], "claim_order": c[3],
+                              "ms": round(times[c], 4)} for c in cands]
+        best = min(table, key=lambda r: r["ms"]) if table else None
         # the defaults unless a candidate is faster by more than the timing noise
-        if best["ms"] >= 0.98 * default_ms:
+        if best is None or best["ms"] >= 0.98 * default_ms:
             best = {"lane_macs": 0, "segments": 0, "cols_rows": 0, "claim_order": 0, "ms": round(default_ms, 4)}
         rec = dict(best)
         rec["default_ms"] = round(default_ms, 4)
