@@ -94,7 +94,7 @@ def contraction_bytes(groups, cols_rows=1, claim_order=0):
     return {B.STAGE_NAMES.index(n): v for n, v in k.items() if v[1]}
 
 
-CONTRACT_SOURCES = ("contract.hip", "device.hpp", "internal.hpp", "fr.hpp")
+CONTRACT_SOURCES = ("contract.hip", "device.hpp", "contract_job.hpp", "fr.hpp")
 
 
 def contract_source_sha256():
@@ -654,7 +654,9 @@ def main():
                                                 if stage_avg[k] > 0 else None,
                                                 "valu_frac": (e * MAD_PER_ENTRY[B.STAGE_NAMES[k]] /
                                                               (stage_avg[k] * 1e-3) / (CU * LANES_PER_CLK * CLOCK_HZ))
-                                                if stage_avg[k] > 0 else None}
+                                                if stage_avg[k] > 0 else None,
+                                                "traffic_ratio": (measured_traffic(B.STAGE_NAMES[k]) / b
+                                                                  if measured_traffic(B.STAGE_NAMES[k]) else None)}
                              for k, (b, e) in kinds.items()}}
     if not args.no_peak:
         rd = streaming_read_GBps()
