@@ -534,6 +534,35 @@ void Builder::group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev,
                             : pass1(a, L1, b, L1, 1, true, rj.prods[k].g_nparts, ready);
     rj.ready_target += rj.prods[k].g_nparts;
   }
+  // wide rounds for product 0 while its half-table has >= kMatWidePairs pairs
+  // (round 2 at least); not in persistent mode, whose rounds workgroups are
+  // resident before the contractions run
+  const uint32_t n1w = rj.prods[0].n1;
+  if (!T.persistent && n1w >= 2 && (1ull << (n1w - 2)) >= kMatWidePairs) {
+    uint32_t W = 1;
+    while (W < kMatMaxWide && W + 1 < n1w && (1ull << (n1w - 1 - W)) >= kMatWidePairs) ++W;
+    const uint32_t nb1 = (uint32_t)(((1ull << (n1w - 2)) + kMatSweepPairs - 1) / kMatSweepPairs);
+    rj.wide = W;
+    rj.io = nullptr;   // a slot of the descriptor blob, set when the blob is filled
+    rj.wpart_stride = (uint64_t)nb1 * 24;
+    rj.wpart = dev<uint32_t>(take((uint64_t)nb1 * 96 * 2));
+    Segment& G = S();
+    const uint32_t idx = (uint32_t)G.rounds.size();
+    P.n_wide += 1;
+    if (G.wide.size() < W) {
+      G.wide.resize(W);
+      G.wide_blocks.resize(W, 0);
+    }
+    for (uint32_t rd = 0; rd < W; ++rd) {
+      MatSweep m{};
+      m.job = idx;
+      m.block_begin = G.wide_blocks[rd];
+      G.wide[rd].push_back(m);
+      if (rd > 0)
+        G.wide_blocks[rd] +=
+            (uint32_t)(((1ull << (n1w - 1 - rd)) + kMatSweepPairs - 1) / kMatSweepPairs);
+    }
+  }
   // persistent mode: one resident launch for every group (segment 0's list)
   (T.persistent ? P.seg[0] : S()).rounds.push_back(rj);
 }
@@ -591,7 +620,14 @@ BlobLayout blob_layout(const Plan& P) {
     o = align_up(o + G.pass1.size() * sizeof(Pass1Job), 64);
     L.seg[k].rounds = o;
     o = align_up(o + G.rounds.size() * sizeof(RoundsJob), 64);
+    L.seg[k].wide.resize(G.wide.size());
+    for (size_t rd = 0; rd < G.wide.size(); ++rd) {
+      L.seg[k].wide[rd] = o;
+      o = align_up(o + G.wide[rd].size() * sizeof(MatSweep), 64);
+    }
   }
+  L.mat_io = o;
+  o = align_up(o + 4ull * kMatIoWords * P.n_wide, 64);
   L.evals = o;
   o = align_up(o + P.evals.size() * sizeof(EvalJob), 64);
   L.reduces = o;
@@ -626,7 +662,9 @@ uint64_t blob_bound(const vl_group* groups, uint64_t n) {
   // of its CK_COUNT + 3 arrays to 64 bytes
   return align_up(8 * n + 64 + 2 * n * (sizeof(EqJob) + 64) +
                       cj * (sizeof(ContractJob) + sizeof(FinishJob) + sizeof(Pass1Job) + 128) +
-                      n * (sizeof(RoundsJob) + 64) + pts + 64 * (CK_COUNT + 3) * (n + 1) + 1024,
+                      n * (sizeof(RoundsJob) + 64) + pts + 64 * (CK_COUNT + 3) * (n + 1) + 1024 +
+                      kMatMaxWide * (n * sizeof(MatSweep) + 64ull * (kMaxSegments + 1)) +
+                      n * 4ull * kMatIoWords + 64,
                   256);
 }
 
@@ -657,6 +695,12 @@ void fill_blob(Plan& P, const BlobLayout& L, uint8_t* dblob) {
         memcpy(P.blob.data() + L.lk_wide[lo][k], P.lk_wide[lo][k].data(),
                P.lk_wide[lo][k].size() * sizeof(LookupSweep));
   memcpy(P.blob.data() + L.eq, P.eq.data(), P.eq.size() * sizeof(EqJob));
+  // wide rounds' io slots: zeros in the blob, so every call starts its counts
+  // and status afresh
+  uint32_t slot = 0;
+  for (auto& G : P.seg)
+    for (auto& rj : G.rounds)
+      if (rj.wide) rj.io = reinterpret_cast<uint32_t*>(dblob + L.mat_io + 4ull * kMatIoWords * slot++);
   for (size_t k = 0; k < P.seg.size(); ++k) {
     const Segment& G = P.seg[k];
     for (int c = 0; c < CK_COUNT; ++c)
@@ -667,6 +711,9 @@ void fill_blob(Plan& P, const BlobLayout& L, uint8_t* dblob) {
       memcpy(P.blob.data() + L.seg[k].pass1, G.pass1.data(), G.pass1.size() * sizeof(Pass1Job));
     if (!G.rounds.empty())
       memcpy(P.blob.data() + L.seg[k].rounds, G.rounds.data(), G.rounds.size() * sizeof(RoundsJob));
+    for (size_t rd = 0; rd < G.wide.size(); ++rd)
+      if (!G.wide[rd].empty())
+        memcpy(P.blob.data() + L.seg[k].wide[rd], G.wide[rd].data(), G.wide[rd].size() * sizeof(MatSweep));
   }
 }
 
@@ -785,9 +832,15 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
       if (e == hipSuccess) e = hipStreamWaitEvent(s2, fork.ev[k], 0);
       if (e != hipSuccess) return e;
     }
-    VL_STAGE(ev, VL_STAGE_ROUNDS, s2,
-             launch_rounds(reinterpret_cast<const RoundsJob*>(dblob + L.seg[k].rounds),
-                           (uint32_t)G.rounds.size(), s2));
+    const RoundsJob* rjobs = reinterpret_cast<const RoundsJob*>(dblob + L.seg[k].rounds);
+    // wide rounds 2, 3, ..: one sweep launch each (round 1 is in pass 1)
+    for (size_t rd = 1; rd < G.wide.size(); ++rd) {
+      if (G.wide[rd].empty()) continue;
+      const MatSweep* lst = reinterpret_cast<const MatSweep*>(dblob + L.seg[k].wide[rd]);
+      VL_STAGE(ev, VL_STAGE_ROUNDS, s2,
+               launch_mat_sweep(rjobs, lst, (uint32_t)G.wide[rd].size(), G.wide_blocks[rd], (uint32_t)rd, s2));
+    }
+    VL_STAGE(ev, VL_STAGE_ROUNDS, s2, launch_rounds(rjobs, (uint32_t)G.rounds.size(), s2));
   }
   if (two) {
     // join: the caller's stream sees every rounds launch

@@ -70,6 +70,26 @@ struct RoundsProd {
   const uint32_t* g_part;
 };
 
+// Wide rounds: a group whose first product's half-table has at least
+// kMatWidePairs pairs in round 2 sums that product's first `wide` rounds
+// across the GPU before its rounds workgroup starts: round 1 in pass 1 as
+// always, each later one in a launch of mat_sweep_kernel (fold by the previous
+// challenge, the round's partial sums, kMatSweepPairs pairs per block) whose
+// every block first takes the previous round's transcript step from the
+// previous launch's partials; the rounds workgroup takes the last wide
+// round's step.  io (in the descriptor blob, so every call starts from
+// zeros): [0] status, [8..23] transcript state after round k in slot k & 1,
+// [24..39] r_k in slot k & 1 (Montgomery).  Sweep partials: two buffers of
+// wpart_stride words, round k's in buffer k & 1.
+constexpr uint32_t kMatSweepPairs = 256;
+constexpr uint32_t kMatWidePairs = 1024;
+constexpr uint32_t kMatMaxWide = 16;          // n1 <= 20 needs at most 10
+constexpr uint32_t kMatIoState = 8, kMatIoR = 24, kMatIoWords = 48;
+struct MatSweep {
+  uint32_t job;               // index in the launch's RoundsJob array
+  uint32_t block_begin;       // prefix sum of sweep blocks within the launch
+};
+
 // The sumcheck rounds of one group, run by one workgroup.
 struct RoundsJob {
   uint32_t st[8];             // transcript state (digest words) after squeezing u and v
@@ -84,7 +104,10 @@ struct RoundsJob {
   uint32_t ready_target;      // persistent mode: pass-1 blocks of this group
   const uint32_t* ready;      // persistent mode: readiness counter, else null
   uint32_t spin_limit;        // polls of `ready` before giving up (VL_ERR_TIMEOUT)
-  uint32_t pad2_;
+  uint32_t wide;              // product 0's rounds summed by wide launches (0: none, else >= 2)
+  uint32_t* io;               // wide rounds: status, transcript states, challenges
+  uint32_t* wpart;            // wide rounds: sweep partials, 3 elements per block, two buffers
+  uint64_t wpart_stride;      // words per partials buffer
   RoundsProd prods[VL_MAX_PRODS];
 };
 
@@ -235,6 +258,9 @@ hipError_t launch_contract(int kind, const ContractJob* jobs_dev, uint32_t n_job
 hipError_t launch_finish(const FinishJob* jobs_dev, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s);
 hipError_t launch_pass1(const Pass1Job* jobs_dev, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s);
 hipError_t launch_rounds(const RoundsJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
+hipError_t launch_mat_sweep(const RoundsJob* jobs_dev, const MatSweep* list_dev, uint32_t n_list, uint32_t n_blocks,
+                            uint32_t round, hipStream_t s);
+
 hipError_t launch_lift(const void* src, int dtype, uint64_t n, uint32_t* dst, uint64_t ld, hipStream_t s);
 hipError_t launch_export(const uint32_t* src, uint64_t ld, uint64_t n, uint32_t* dst, hipStream_t s);
 hipError_t launch_eq_point(const EqPointArgs& a, hipStream_t s);

@@ -196,18 +196,188 @@ __device__ __forceinline__ void absorb_round_lanes(Transcript& tr, const Fr (&gc
 // proof; the wave absorbs the three values (all 64 lanes must be active:
 // lanes 1 and 2 hold message schedules) and lane 0 squeezes r.  Returns r in
 // Montgomery form in every lane of wave 0.
-__device__ __forceinline__ Fr round_challenge(Transcript& tr, const Fr (&g)[3], uint8_t* out, uint32_t lane) {
+__device__ __forceinline__ Fr round_challenge(Transcript& tr, const Fr (&g)[3], uint8_t* out, uint32_t lane,
+                                              bool write = true) {
   Fr gc[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) gc[k] = readlane_fr(g[k], 0);
   Fr mine;   // word by word: a select of whole values goes through scratch memory
 #pragma unroll
   for (int j = 0; j < 8; ++j) mine.w[j] = lane == 0 ? gc[0].w[j] : (lane == 1 ? gc[1].w[j] : gc[2].w[j]);
-  if (lane < 3) put_canon(out + 32 * lane, mine);
+  if (write && lane < 3) put_canon(out + 32 * lane, mine);
   Fr r = fr_zero();
   absorb_round_lanes(tr, gc, lane);
   if (lane == 0) r = fr_to_mont(tr_squeeze_fixed(tr, VL_LBL_R));
   return readlane_fr(r, 0);
+}
+
+// ------------------------------------------------------- wide rounds ------
+// The transcript step of wide round k of a group (its values from partial
+// sums, absorbed; r_k squeezed), computed by a 256-thread block.  Every block
+// of the launch that needs r_k computes the step itself from the same
+// partials, so no block waits for another and no fence is needed; only the
+// launch's first block of the group (write) stores the proof bytes and io.
+// Round 0 (k = 0): the range flag, c = C~(u, v) and every product's round-1
+// values from the pass-1 partials, the prover guard, the claim and the part
+// claims, as the rounds kernel does without wide rounds; a failure is
+// reported (by the writing block) and every block returns false.  Later
+// rounds: the partials of sweep k (buffer k & 1), the state after round
+// k - 1 (io slot (k - 1) & 1).  r_k is returned in every thread.
+__device__ bool mat_step_block(const RoundsJob& J, uint32_t k, bool write, Fr& r_out) {
+  __shared__ uint32_t red[4 * 8 * 4];
+  __shared__ uint32_t first[VL_MAX_PRODS][3][8];
+  __shared__ uint32_t bcast[8];
+  __shared__ int32_t verdict;
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
+  uint8_t* out = J.proof + 32ull * J.n_prods + 96ull * k;
+  Transcript tr;
+  Fr g[4];
+  g[0] = g[1] = g[2] = g[3] = fr_zero();
+  if (k == 0) {
+    const int32_t bad = J.err && *(volatile const int32_t*)J.err;
+    if (bad) {
+      if (write && tid == 0) {
+        J.io[0] = (uint32_t)VL_ERR_RANGE;
+        *J.status = VL_ERR_RANGE;
+      }
+      return false;
+    }
+    Fr v[4];
+    v[0] = v[1] = v[2] = v[3] = fr_zero();
+    for (uint32_t i = tid; i < J.c_nparts; i += 256) v[0] = fr_add(v[0], lds_or_global_fr(J.c_part + 24ull * i));
+    block256_sum4(v, red);
+    const Fr c = v[0];   // valid in thread 0
+    __syncthreads();
+    Fr total = fr_zero();
+    for (uint32_t p = 0; p < J.n_prods; ++p) {
+      const RoundsProd& P = J.prods[p];
+      Fr gp[4];
+      gp[0] = gp[1] = gp[2] = gp[3] = fr_zero();
+      for (uint32_t i = tid; i < P.g_nparts; i += 256)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) gp[q] = fr_add(gp[q], lds_or_global_fr(P.g_part + 24ull * i + 8 * q));
+      block256_sum4(gp, red);
+      if (tid == 0)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) lds_put(first[p][q], gp[q]);
+      total = fr_add(total, fr_add(gp[0], gp[1]));
+      __syncthreads();
+    }
+    if (tid == 0) verdict = fr_eq(total, c) ? 1 : 0;
+    __syncthreads();
+    if (!verdict) {
+      if (write && tid == 0) {
+        J.io[0] = (uint32_t)VL_ERR_FALSE_STATEMENT;
+        *J.status = VL_ERR_FALSE_STATEMENT;
+      }
+      return false;
+    }
+    if (tid == 0) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) tr.h[i] = J.st[i];
+      const Fr cc[1] = {c};
+      if (write) put_canon(J.proof, cc[0]);
+      tr_absorb_frs(tr, VL_LBL_CLAIM, cc);
+      for (uint32_t p = 0; p + 1 < J.n_prods; ++p) {
+        const Fr sc[1] = {fr_add(lds_get(first[p][0]), lds_get(first[p][1]))};
+        if (write) put_canon(J.proof + 32 * (1 + p), sc[0]);
+        tr_absorb_frs(tr, VL_LBL_PART, sc);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) g[q] = lds_get(first[0][q]);
+  } else {
+    const uint32_t h = 1u << (J.prods[0].n1 - 1 - k);
+    const uint32_t nb = (h + kMatSweepPairs - 1) / kMatSweepPairs;
+    const uint32_t* part = J.wpart + (uint64_t)(k & 1) * J.wpart_stride;
+    for (uint32_t i = tid; i < nb; i += 256)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) g[q] = fr_add(g[q], lds_or_global_fr(part + 24ull * i + 8 * q));
+    block256_sum4(g, red);   // valid in thread 0
+    if (tid == 0)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) tr.h[i] = J.io[kMatIoState + 8 * ((k - 1) & 1) + i];
+  }
+  if (wave == 0) {
+    const Fr g3[3] = {g[0], g[1], g[2]};
+    const Fr r = round_challenge(tr, g3, out, lane, write);
+    if (lane == 0) {
+      if (write)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          J.io[kMatIoState + 8 * (k & 1) + i] = tr.h[i];
+          J.io[kMatIoR + 8 * (k & 1) + i] = r.w[i];
+        }
+      lds_put(bcast, r);
+    }
+  }
+  __syncthreads();
+  r_out = lds_get(bcast);
+  return true;
+}
+
+// Wide round rd >= 1 of product 0 across the GPU: every block first takes
+// round rd - 1's transcript step (mat_step_block) for r_{rd-1}; then every
+// thread takes one pair t < h of round rd, folds the entries t, t + h,
+// t + 2h, t + 3h of the tables by r_{rd-1} into t and t + h (as the rounds
+// kernel's sweeps do; each thread reads and writes only its own entries)
+// and adds the pair's three products; a block writes its sums to the
+// partials buffer rd & 1.
+__global__ void __launch_bounds__(256) mat_sweep_kernel(const RoundsJob* __restrict__ jobs,
+                                                        const MatSweep* __restrict__ list, uint32_t n_list,
+                                                        uint32_t n_blocks, uint32_t rd) {
+  const uint32_t blk = blockIdx.x;
+  if (blk >= n_blocks) return;
+  uint32_t lo = 0, hi = n_list;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (list[mid].block_begin <= blk) lo = mid; else hi = mid;
+  }
+  const MatSweep& S = list[lo];
+  const RoundsJob& J = jobs[S.job];
+  if (*reinterpret_cast<volatile const int32_t*>(J.io) != VL_OK) return;
+  Fr r;
+  if (!mat_step_block(J, rd - 1, blk == S.block_begin, r)) return;
+  const RoundsProd& P = J.prods[0];
+  uint32_t* a = P.a;
+  uint32_t* b = P.b;
+  const uint64_t ld = P.ld;
+  const uint32_t h = 1u << (P.n1 - 1 - rd);
+  const uint32_t t = (blk - S.block_begin) * kMatSweepPairs + threadIdx.x;
+  Fr g[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) g[k] = fr_zero();
+  if (t < h) {
+    const Fr a00 = load_sol(a, ld, t), a01 = load_sol(a, ld, t + 2 * h);
+    const Fr a10 = load_sol(a, ld, t + h), a11 = load_sol(a, ld, t + 3 * h);
+    const Fr b00 = load_sol(b, ld, t), b01 = load_sol(b, ld, t + 2 * h);
+    const Fr b10 = load_sol(b, ld, t + h), b11 = load_sol(b, ld, t + 3 * h);
+    const Fr rr2[2] = {r, r}, da[2] = {fr_sub(a01, a00), fr_sub(a11, a10)};
+    const Fr db[2] = {fr_sub(b01, b00), fr_sub(b11, b10)};
+    Fr fa[2], fb[2];
+    fr_mul_n<2>(rr2, da, fa);
+    fr_mul_n<2>(rr2, db, fb);
+    const Fr a0 = fr_add(a00, fa[0]), a1 = fr_add(a10, fa[1]);
+    const Fr b0 = fr_add(b00, fb[0]), b1 = fr_add(b10, fb[1]);
+    store_sol(a, ld, t, a0);
+    store_sol(a, ld, t + h, a1);
+    store_sol(b, ld, t, b0);
+    store_sol(b, ld, t + h, b1);
+    const Fr x[3] = {a0, a1, at_two(a0, a1)}, y[3] = {b0, b1, at_two(b0, b1)};
+    Fr pr[3];
+    fr_mul_n<3>(x, y, pr);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g[k] = pr[k];
+  }
+  __shared__ uint32_t red[4 * 8 * 4];
+  block256_sum4(g, red);
+  if (threadIdx.x == 0) {
+    uint32_t* o = J.wpart + (uint64_t)(rd & 1) * J.wpart_stride + (uint64_t)(blk - S.block_begin) * 24;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) o[k * 8 + j] = g[k].w[j];
+  }
 }
 
 // Pass 1: the claim's dot product and round 1 of every product as partial
@@ -324,18 +494,29 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
       return;
     }
   }
-  if (J.err && *(volatile const int32_t*)J.err) {
+  if (J.wide) {
+    // the range flag, the claim, the prover guard and product 0's first
+    // J.wide rounds ran as wide launches, which left their status in io
+    const int32_t st = *reinterpret_cast<volatile const int32_t*>(J.io);
+    if (st != VL_OK) {
+      if (tid == 0) *J.status = st;
+      return;
+    }
+  } else if (J.err && *(volatile const int32_t*)J.err) {
     if (tid == 0) *J.status = VL_ERR_RANGE;
     return;
   }
   // c = C~(u, v) from the pass-1 partials of its dot product (canonical:
   // one factor in Montgomery form, the other canonical)
-  Fr v1[1];
-  v1[0] = fr_zero();
-  for (uint32_t i = tid; i < J.c_nparts; i += NT) v1[0] = fr_add(v1[0], lds_or_global_fr(J.c_part + 24ull * i));
-  block_sum_w0<1>(v1, red);
-  const Fr c = v1[0];   // valid in lane 0 of wave 0
-  __syncthreads();      // red is reused by the next sum
+  Fr c = fr_zero();
+  if (!J.wide) {
+    Fr v1[1];
+    v1[0] = fr_zero();
+    for (uint32_t i = tid; i < J.c_nparts; i += NT) v1[0] = fr_add(v1[0], lds_or_global_fr(J.c_part + 24ull * i));
+    block_sum_w0<1>(v1, red);
+    c = v1[0];          // valid in lane 0 of wave 0
+    __syncthreads();    // red is reused by the next sum
+  }
 
   // round 1 of every product from its partials; its g(0) + g(1) is
   // sum_w a_p[w] b_p[w]
@@ -354,17 +535,24 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
     total = fr_add(total, fr_add(g[0], g[1]));
     __syncthreads();   // red is reused by the next sum
   }
-  if (tid == 0) verdict = fr_eq(total, c) ? 1 : 0;
-  __syncthreads();
-  if (!verdict) {
-    if (tid == 0) *J.status = VL_ERR_FALSE_STATEMENT;
-    return;
+  if (!J.wide) {
+    if (tid == 0) verdict = fr_eq(total, c) ? 1 : 0;
+    __syncthreads();
+    if (!verdict) {
+      if (tid == 0) *J.status = VL_ERR_FALSE_STATEMENT;
+      return;
+    }
   }
 
   // the transcript lives in thread 0; every thread keeps the same proof cursor
   Transcript tr;
   uint8_t* out = J.proof;
-  if (tid == 0) {
+  if (J.wide) {
+    // the state after round wide - 2, the last step a wide launch took
+    if (tid == 0)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) tr.h[i] = J.io[kMatIoState + 8 * ((J.wide - 2) & 1) + i];
+  } else if (tid == 0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) tr.h[i] = J.st[i];
     const Fr cc[1] = {c};
@@ -391,6 +579,31 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
     // the round's pair.  Each thread reads and writes only its own entries.
     bool pending = false;   // tables still to be folded by r
     Fr r = fr_zero();
+    if (p == 0 && J.wide) {
+      // rounds 0 .. wide - 1 were summed by wide launches, which also took
+      // the transcript steps of rounds 0 .. wide - 2; take round wide - 1's
+      // step here (its values from the last sweep's partials), then resume
+      // with the tables still to be folded by its challenge
+      const uint32_t k = J.wide - 1;
+      const uint32_t hk = 1u << (P.n1 - 1 - k);
+      const uint32_t nb = (hk + kMatSweepPairs - 1) / kMatSweepPairs;
+      const uint32_t* part = J.wpart + (uint64_t)(k & 1) * J.wpart_stride;
+      Fr g[3];
+      g[0] = g[1] = g[2] = fr_zero();
+      for (uint32_t i = tid; i < nb; i += NT)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) g[q] = fr_add(g[q], lds_or_global_fr(part + 24ull * i + 8 * q));
+      block_sum_w0<3>(g, red);
+      if (wave == 0) {
+        const Fr rr = round_challenge(tr, g, out + 96ull * k, lane);
+        if (lane == 0) lds_put(bcast, rr);
+      }
+      __syncthreads();
+      r = lds_get(bcast);
+      rd = J.wide;
+      pending = true;
+      out += 96ull * J.wide;
+    }
     for (; rd < P.n1; ++rd) {
       const uint32_t h = 1u << (P.n1 - 1 - rd);
       if (h <= kWave) break;
@@ -455,7 +668,7 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
       const uint32_t rd0 = rd;
       uint32_t h = 1u << (P.n1 - 1 - rd0);
       Fr A0 = fr_zero(), A1 = fr_zero(), B0 = fr_zero(), B1 = fr_zero();
-      if (wave == 1) {
+      if (wave >= 1 && wave <= 3) {
         if (lane < h) {
           A0 = load_sol(a, ld, lane);
           A1 = load_sol(a, ld, lane + h);
@@ -474,39 +687,39 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
             B1 = fr_add(B1, fb[1]);
           }
         }
-        // round rd0's values directly, as constant quadratics
-        Fr g[3];   // lanes >= h hold zeros
-        {
-          const Fr x[3] = {A0, A1, at_two(A0, A1)}, y[3] = {B0, B1, at_two(B0, B1)};
-          fr_mul_n<3>(x, y, g);
-        }
-        wave_sum<3>(g, h);
-        if (lane == 0)
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            lds_put(coef[rd0 & 1][k][0], g[k]);
-            lds_put(coef[rd0 & 1][k][1], fr_zero());
-            lds_put(coef[rd0 & 1][k][2], fr_zero());
+        // round rd0's values directly, as constant quadratics (wave 1)
+        if (wave == 1) {
+          Fr g[3];   // lanes >= h hold zeros
+          {
+            const Fr x[3] = {A0, A1, at_two(A0, A1)}, y[3] = {B0, B1, at_two(B0, B1)};
+            fr_mul_n<3>(x, y, g);
           }
+          wave_sum<3>(g, h);
+          if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              lds_put(coef[rd0 & 1][k][0], g[k]);
+              lds_put(coef[rd0 & 1][k][1], g[k]);   // c1 = [1] - [0] - [2] = 0
+              lds_put(coef[rd0 & 1][k][2], fr_zero());
+            }
+        }
       }
       __syncthreads();
       for (uint32_t j = rd0; j < P.n1; ++j, h >>= 1) {
         if (wave == 0) {
           const Fr rp = j > rd0 ? lds_get(rbuf[(j - 1) & 1]) : fr_zero();
-          // g_k = c0 + r (c1 + r c2), the three in step
-          Fr g[3], c2[3], t[3];
-          const Fr rp3[3] = {rp, rp, rp};
+          // g_k = c0 + r (c1 + r c2) with c1 = [1] - c0 - c2, lane k < 3
+          // evaluating value k (the three side by side), then gathered
+          const uint32_t kk = lane < 3 ? lane : 2u;
+          const Fr c0 = lds_get(coef[j & 1][kk][0]), c2 = lds_get(coef[j & 1][kk][2]);
+          const Fr c1 = fr_sub(fr_sub(lds_get(coef[j & 1][kk][1]), c0), c2);
+          const Fr mine = fr_add(c0, fr_mul(rp, fr_add(c1, fr_mul(rp, c2))));
+          Fr g[3];
 #pragma unroll
-          for (int k = 0; k < 3; ++k) c2[k] = lds_get(coef[j & 1][k][2]);
-          fr_mul_n<3>(rp3, c2, t);
-#pragma unroll
-          for (int k = 0; k < 3; ++k) t[k] = fr_add(lds_get(coef[j & 1][k][1]), t[k]);
-          fr_mul_n<3>(rp3, t, g);
-#pragma unroll
-          for (int k = 0; k < 3; ++k) g[k] = fr_add(lds_get(coef[j & 1][k][0]), g[k]);
+          for (int k = 0; k < 3; ++k) g[k] = readlane_fr(mine, k);
           const Fr rj = round_challenge(tr, g, out, lane);
           if (lane == 0) lds_put(rbuf[j & 1], rj);
-        } else if (wave == 1) {
+        } else if (wave >= 1 && wave <= 3) {
           if (j > rd0) {
             // fold by r_{j-1}; entry t + h of the folded table comes from lane t + h
             const Fr rp = lds_get(rbuf[(j - 1) & 1]);
@@ -549,29 +762,24 @@ __global__ void __launch_bounds__(kRoundsBlock) rounds_kernel(const RoundsJob* _
             xb[1] = qb0; yb[1] = fr_sub(qb1, qb0);
             xa[2] = at_two(xa[0], xa[1]); ya[2] = at_two(ya[0], ya[1]);
             xb[2] = at_two(xb[0], xb[1]); yb[2] = at_two(yb[0], yb[1]);
-            Fr c[9];
-            Fr p0[3], p2[3], pm[3], sa[3], sb[3];
+            // Karatsuba's three products split over waves 1, 2, 3: the sums of
+            // x x' (term 0), (x + y)(x' + y') (term 1) and y y' (term 2);
+            // wave 0 forms c1 = [1] - [0] - [2]
+            const uint32_t role = wave - 1;
+            Fr ua[3], ub[3], pr[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-              sa[k] = fr_add(xa[k], ya[k]);
-              sb[k] = fr_add(xb[k], yb[k]);
+              ua[k] = role == 0 ? xa[k] : (role == 2 ? ya[k] : fr_add(xa[k], ya[k]));
+              ub[k] = role == 0 ? xb[k] : (role == 2 ? yb[k] : fr_add(xb[k], yb[k]));
             }
-            fr_mul_n<3>(xa, xb, p0);
-            fr_mul_n<3>(ya, yb, p2);
-            fr_mul_n<3>(sa, sb, pm);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-              c[3 * k] = p0[k];
-              c[3 * k + 1] = fr_sub(fr_sub(pm[k], p0[k]), p2[k]);
-              c[3 * k + 2] = p2[k];
-            }
+            fr_mul_n<3>(ua, ub, pr);
             if (lane >= hh)
 #pragma unroll
-              for (int k = 0; k < 9; ++k) c[k] = fr_zero();
-            wave_sum<9>(c, hh);
+              for (int k = 0; k < 3; ++k) pr[k] = fr_zero();
+            wave_sum<3>(pr, hh);
             if (lane == 0)
 #pragma unroll
-              for (int k = 0; k < 9; ++k) lds_put(coef[(j + 1) & 1][k / 3][k % 3], c[k]);
+              for (int k = 0; k < 3; ++k) lds_put(coef[(j + 1) & 1][k][role], pr[k]);
           }
         }
         out += 96;
@@ -865,6 +1073,13 @@ hipError_t launch_pack(const uint32_t* eq, uint64_t ld, uint64_t len, uint32_t* 
 hipError_t launch_pass1(const Pass1Job* jobs, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s) {
   if (n_blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(pass1_kernel, dim3(n_blocks), dim3(256), 0, s, jobs, n_jobs, n_blocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_mat_sweep(const RoundsJob* jobs, const MatSweep* list, uint32_t n_list, uint32_t n_blocks,
+                            uint32_t round, hipStream_t s) {
+  if (!n_blocks) return hipSuccess;
+  hipLaunchKernelGGL(mat_sweep_kernel, dim3(n_blocks), dim3(256), 0, s, jobs, list, n_list, n_blocks, round);
   return hipGetLastError();
 }
 

@@ -58,6 +58,10 @@ struct Segment {
   std::vector<Pass1Job> pass1;
   uint32_t pass1_blocks = 0;
   std::vector<RoundsJob> rounds;
+  // wide rounds, per round rd: the groups (indices into rounds) and, for
+  // rd >= 1, the sweep blocks of the launch
+  std::vector<std::vector<MatSweep>> wide;
+  std::vector<uint32_t> wide_blocks;
 };
 
 struct Plan {
@@ -70,6 +74,7 @@ struct Plan {
   std::vector<std::vector<uint32_t>> points;  // per eq job: (x_j, 1 - x_j) Montgomery
   std::vector<const uint32_t*> point_dev;     // per eq job: a point already in device memory, or null
   uint32_t n_err = 0;
+  uint32_t n_wide = 0;            // groups with wide rounds (one io slot each in the blob)
   uint64_t out_proof_bytes = 0;
   // launched after every segment, in this order, on the caller's stream
   std::vector<EvalJob> evals;
@@ -90,10 +95,11 @@ struct Plan {
 
 struct SegLayout {
   uint64_t cj[CK_COUNT], fin, pass1, rounds;
+  std::vector<uint64_t> wide;
 };
 
 struct BlobLayout {
-  uint64_t err, eq, points, evals, reduces, bmms, lookups, total;
+  uint64_t err, eq, points, mat_io, evals, reduces, bmms, lookups, total;
   std::vector<SegLayout> seg;
   std::vector<uint64_t> bmm_wide, lk_wide[2];
 };
