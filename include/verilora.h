@@ -96,7 +96,15 @@ typedef struct {
 /* A group: products sharing D0 and D2 whose sum is the claimed C (D0 x D2,
  * ldc >= D2).  A group of one product is a plain matmul; more products prove
  * a sum of products (zkMat covers additions, Sec. IV-B).  group_id and the
- * seed key the group's own Fiat-Shamir transcript. */
+ * seed key the group's own Fiat-Shamir transcript.
+ * bind: NULL, or 32 host bytes that the transcript absorbs (label "bind")
+ * right after its initial state, before the challenges u and v: a digest of
+ * the caller's commitments to the group's matrices (for instance SHA-256 of
+ * their vl_hyrax_commit points).  Sec. II-C has the verifier draw its point
+ * only after the commitments of Sec. II-A; with a bind the point depends on
+ * them, so C cannot be chosen after u and v are known.  Read during the
+ * call (vl_prove_graph_create copies it); the verifier is given the same
+ * digest. */
 typedef struct {
   const vl_product* prods;
   uint32_t n_prods;      /* 1 .. VL_MAX_PRODS */
@@ -104,6 +112,7 @@ typedef struct {
   const void* C;
   int32_t dtype_c;
   uint64_t ldc;
+  const uint8_t* bind;   /* optional 32-byte commitment digest, see above */
 } vl_group;
 
 #define VL_MAX_PRODS 8
@@ -261,9 +270,9 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n_groups, ui
  *   the workspace, proofs, opts->status and digests addresses fixed; the
  *   caller keeps those buffers, and the matrices the groups point to, alive
  *   and unused by other work until destroy.  The group and product
- *   descriptors are copied (deep): the caller may free or reuse its vl_group
- *   and vl_product arrays after create; a launch reads the matrices at the
- *   same addresses.
+ *   descriptors are copied (deep, bind digests included): the caller may
+ *   free or reuse its vl_group and vl_product arrays and bind buffers after
+ *   create; a launch reads the matrices at the same addresses.
  * launch: proves the groups' current matrix contents for seed on stream,
  *   asynchronously, with bytes identical to vl_sumcheck_matmul_prove.  The
  *   host rebuilds the descriptor blob (challenges depend on the seed and
@@ -279,6 +288,13 @@ vl_status vl_prove_graph_create(const vl_group* groups, uint64_t n_groups, const
                                 uint8_t* proofs, uint64_t proofs_len, uint64_t* offsets, uint8_t* digests,
                                 vl_prove_graph** graph);
 vl_status vl_prove_graph_launch(vl_prove_graph* graph, uint64_t seed, void* stream);
+
+/* Replaces the bind digests of a prove graph's groups for its next launches
+ * (new data comes with new commitments, Sec. II-C): binds is NULL (no group
+ * binds) or 32 host bytes per group in the order given to create, copied
+ * here.  Not concurrent with a launch of the same handle.  Errors:
+ * VL_ERR_INVALID_ARG. */
+vl_status vl_prove_graph_bind(vl_prove_graph* graph, const uint8_t* binds);
 void vl_prove_graph_destroy(vl_prove_graph* graph);
 
 /* Host-side verifier (CPU only) of the sumcheck of eq. (zk-mle-matmul)
@@ -294,13 +310,15 @@ void vl_prove_graph_destroy(vl_prove_graph* graph);
  * c = C~(u, v), a_final = A~(u, r), b_final = B~(r, v) are also checked by
  * direct evaluation of eq. (MLE), standing in for the commitment openings of
  * Sec. II-A, which are out of scope.
- * Soundness without commitments: u and v are squeezed from (seed, group_id,
- * shapes) alone, before any message that depends on C, A or B.  In the paper
- * the verifier draws them after the prover has committed to the matrices
- * (Sec. II-A, II-C).  Here nothing binds C before u and v are known, so the
- * witness check does not rule out a false C' = AB + D with D~(u, v) = 0 that
- * a prover chose after seeing u and v; it binds the proof to the matrices only
- * once a commitment (or a digest of the witness) is absorbed before u and v.
+ * Commitments: the group's bind digest, if any, enters the transcript before
+ * u and v, as in the prover.  In the paper the verifier draws u and v after
+ * the prover has committed to the matrices (Sec. II-A, II-C).  Without a
+ * bind, u and v follow from (seed, group_id, shapes) alone, nothing ties C
+ * to them, and the witness check does not rule out a false C' = AB + D with
+ * D~(u, v) = 0 chosen after seeing u and v.  With a bind of commitments to
+ * A, B and C, the verifier checks the reduced claims below by openings
+ * (vl_hyrax_verify_open: A at (u, r), B at (r, v), C at (u, v)) instead of
+ * the witness.
  *   reduced : optional host output of the reduced claims, canonical:
  *             c, u[n0], v[n2], then per product r[n1], a_final, b_final
  *   reduced_len : elements written (or needed, on VL_ERR_BUFFER_TOO_SMALL)
@@ -496,7 +514,6 @@ vl_status vl_lookup_prove(const vl_lookup* l, uint64_t n, uint64_t seed, void* w
 vl_status vl_lookup_verify(const uint8_t* proof, uint64_t len, const vl_lookup* l, uint64_t seed, vl_fr* reduced,
                            uint64_t reduced_cap, uint64_t* reduced_len, int32_t* fail_round);
 
-/* Message for the last non-OK status on this thread. */
 /* Hyrax commitments to matrix MLEs: the polynomial commitments of Sec. II-A,
  * with the scheme the paper's implementation uses (Hyrax; its commitment
  * times and sizes are those of Table t2).  The multilinear extension of an
@@ -568,6 +585,7 @@ vl_status vl_hyrax_generators(uint32_t m, uint8_t* out);
 vl_status vl_hyrax_verify_open(const uint8_t* commits, uint32_t R, uint32_t m, const vl_fr* x, const vl_fr* y,
                                const vl_fr* w, vl_fr* value);
 
+/* Message for the last non-OK status on this thread. */
 const char* vl_last_error(void);
 
 #ifdef __cplusplus

@@ -20,9 +20,13 @@ Readings of the paper taken here (the paper is silent or inconsistent):
     is a sum of k products shares one transcript and one (u, v); the prover
     sends the part claims s_1..s_{k-1} and then runs the k sumchecks in order,
     the last claim being c - sum of the parts.
-  * Each group has its own transcript keyed by (seed, group id, shapes); there
-    are no commitments, so challenges depend only on public data and on the
-    prover's messages.
+  * Each group has its own transcript keyed by (seed, group id, shapes).
+  * Commitments before challenges (Sec. II-C: the verifier draws its point
+    only after the prover has committed to the matrices, Sec. II-A): a
+    caller that holds commitments passes a 32-byte digest of them as
+    ``bind``, absorbed with label "bind" right after the initial state and
+    before u and v.  Without one the challenges depend only on public data
+    and on the prover's messages, and nothing ties C to them.
 
 Proof bytes: c || s_1..s_{k-1} || for each product (g0, g1, g2) per round ||
 a_final || b_final, each a 32-byte canonical little-endian field element.
@@ -140,10 +144,23 @@ def interpolate_quadratic(g0: int, g1: int, g2: int, r: int) -> int:
     return (g0 * l0 + g1 * l1 + g2 * l2) % P
 
 
+def group_transcript(seed: int, group_id: int, shapes, bind: Optional[bytes] = None) -> Transcript:
+    """A group's transcript before its challenges: the initial state, then
+    the commitments' digest when one is given (Sec. II-C after II-A)."""
+    tr = Transcript(seed, group_id, shapes)
+    if bind is not None:
+        bind = bytes(bind)
+        if len(bind) != 32:
+            raise ValueError("a bind digest is 32 bytes")
+        tr.absorb(b"bind", bind)
+    return tr
+
+
 def prove_group(prods: Sequence[Tuple[np.ndarray, np.ndarray]], C: np.ndarray, seed: int,
-                group_id: int):
+                group_id: int, bind: Optional[bytes] = None):
     """Prove C = sum_k A_k B_k.  ``prods`` holds the integer factors as they
-    enter the product (transposed views already applied).
+    enter the product (transposed views already applied); ``bind`` the
+    optional 32-byte digest of the caller's commitments.
 
     Returns (proof bytes, final transcript state, details dict).
     Raises FalseStatement if the products do not sum to C.
@@ -154,7 +171,7 @@ def prove_group(prods: Sequence[Tuple[np.ndarray, np.ndarray]], C: np.ndarray, s
         assert A.shape[1] == B.shape[0]
     assert C.shape == (shapes[0][0], shapes[0][2])
 
-    tr = Transcript(seed, group_id, shapes)
+    tr = group_transcript(seed, group_id, shapes, bind)
     u, v = challenges_uv(tr, shapes)
     proof, details = prove_group_at(prods, C, tr, u, v)
     return proof, tr.state, details
@@ -205,18 +222,21 @@ def prove_group_at(prods: Sequence[Tuple[np.ndarray, np.ndarray]], C: np.ndarray
 
 
 def verify_group(proof: bytes, shapes, seed: int, group_id: int,
-                 witness: Optional[Tuple[Sequence[Tuple[np.ndarray, np.ndarray]], np.ndarray]] = None):
+                 witness: Optional[Tuple[Sequence[Tuple[np.ndarray, np.ndarray]], np.ndarray]] = None,
+                 bind: Optional[bytes] = None):
     """Check a proof; returns the reduced claims, raises Reject.
 
     Without a witness this checks the sumcheck itself: g(0) + g(1) equals the
     running claim each round, the claim moves to g(r), and the last claim is
     a_final * b_final.  With a witness ((A_k, B_k) list, C) it also checks
     c = C~(u, v), a_final = A~(u, r) and b_final = B~(r, v) by direct
-    evaluation, which stands in for commitment openings (not in scope).
+    evaluation, which stands in for commitment openings.  ``bind``: the
+    digest the prover bound (the verifier recomputes it from the commitments
+    it holds and then checks the reduced claims by openings).
     """
     shapes = [tuple(int(x) for x in s) for s in shapes]
     group_shapes_ok(shapes)
-    tr = Transcript(seed, group_id, shapes)
+    tr = group_transcript(seed, group_id, shapes, bind)
     u, v = challenges_uv(tr, shapes)
     return verify_group_at(proof, shapes, tr, u, v, witness)
 
@@ -261,10 +281,10 @@ def verify_group_at(proof: bytes, shapes, tr: Transcript, u, v,
     return dict(u=u, v=v, c=pp.c, r=all_r, finals=pp.finals, state=tr.state, parts=pp.parts)
 
 
-def prove_workload_group(group, seed: int):
+def prove_workload_group(group, seed: int, bind: Optional[bytes] = None):
     """Convenience: prove a ``workloads.Group`` (op views applied here)."""
     prods = [(p.opA(), p.opB()) for p in group.products]
-    return prove_group(prods, group.C, seed, group.group_id)
+    return prove_group(prods, group.C, seed, group.group_id, bind)
 
 
 def lifted(M: np.ndarray) -> List[List[int]]:

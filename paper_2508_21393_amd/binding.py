@@ -31,7 +31,7 @@ STATUS_NAMES = {0: "VL_OK", 1: "VL_ERR_INVALID_ARG", 2: "VL_ERR_SHAPE", 3: "VL_E
 EXPORTED = ("vl_fr_lift", "vl_fr_export", "vl_eq_table", "vl_partial_eval_workspace_size",
             "vl_mle_partial_eval", "vl_proof_size", "vl_workspace_size",
             "vl_sumcheck_matmul_prove", "vl_verify_transcript", "vl_last_error",
-            "vl_prove_graph_create", "vl_prove_graph_launch", "vl_prove_graph_destroy",
+            "vl_prove_graph_create", "vl_prove_graph_launch", "vl_prove_graph_bind", "vl_prove_graph_destroy",
             "vl_mle_partial_eval_noalloc", "vl_lora_chain_proof_size", "vl_lora_chain_workspace_size",
             "vl_lora_chain_prove", "vl_bmm_proof_size", "vl_bmm_workspace_size", "vl_bmm_prove",
             "vl_bmm_verify", "vl_lookup_proof_size", "vl_lookup_workspace_size", "vl_lookup_prove",
@@ -60,7 +60,7 @@ class vl_product(ctypes.Structure):
 
 class vl_group(ctypes.Structure):
     _fields_ = [("prods", ctypes.POINTER(vl_product)), ("n_prods", c_u32), ("group_id", c_u32),
-                ("C", c_vp), ("dtype_c", c_i32), ("ldc", c_u64)]
+                ("C", c_vp), ("dtype_c", c_i32), ("ldc", c_u64), ("bind", c_vp)]
 
 
 class vl_tuning(ctypes.Structure):
@@ -184,11 +184,12 @@ def lib():
         L.vl_prove_graph_create.argtypes = [ctypes.POINTER(vl_group), c_u64, ctypes.POINTER(vl_prove_opts), c_vp,
                                             c_u64, ctypes.POINTER(c_u64), c_vp, ctypes.POINTER(c_vp)]
         L.vl_prove_graph_launch.argtypes = [c_vp, c_u64, c_vp]
+        L.vl_prove_graph_bind.argtypes = [c_vp, c_vp]
         L.vl_prove_graph_destroy.argtypes = [c_vp]
         L.vl_prove_graph_destroy.restype = None
         for f in ("vl_fr_lift", "vl_fr_export", "vl_eq_table", "vl_mle_partial_eval", "vl_mle_partial_eval_noalloc",
                   "vl_sumcheck_matmul_prove", "vl_verify_transcript", "vl_prove_graph_create",
-                  "vl_prove_graph_launch"):
+                  "vl_prove_graph_launch", "vl_prove_graph_bind"):
             getattr(L, f).restype = c_i32
         _lib = L
     return _lib
@@ -256,12 +257,24 @@ def _stream(stream) -> Optional[int]:
     return getattr(stream, "cuda_stream", stream)
 
 
+def _bind_buffer(bind):
+    """A 32-byte host buffer holding a bind digest (None stays None)."""
+    if bind is None:
+        return None
+    bind = bytes(bind)
+    if len(bind) != 32:
+        raise ValueError("a bind digest is 32 bytes")
+    return ctypes.create_string_buffer(bind, 32)
+
+
 class GroupArgs:
-    """vl_group built from (A, B, transA, transB) operands and C; keeps the
+    """vl_group built from (A, B, transA, transB) operands and C, with an
+    optional 32-byte bind digest of the caller's commitments; keeps the
     Python objects alive as long as the structure is used."""
 
-    def __init__(self, group_id: int, prods: Sequence[Tuple[object, object, bool, bool]], C):
+    def __init__(self, group_id: int, prods: Sequence[Tuple[object, object, bool, bool]], C, bind=None):
         self.keep = [C] + [x for p in prods for x in p[:2]]
+        self._bind = _bind_buffer(bind)
         arr = (vl_product * len(prods))()
         for k, (A, B, ta, tb) in enumerate(prods):
             a_rows, a_cols = A.shape
@@ -272,7 +285,25 @@ class GroupArgs:
             arr[k] = vl_product(_ptr(A), _ptr(B), dtype_code(A.dtype), dtype_code(B.dtype), D0, D1, D2,
                                 _row_stride(A), _row_stride(B), int(ta), int(tb))
         self.prods = arr
-        self.struct = vl_group(arr, len(prods), group_id, _ptr(C), dtype_code(C.dtype), _row_stride(C))
+        self.struct = vl_group(arr, len(prods), group_id, _ptr(C), dtype_code(C.dtype), _row_stride(C),
+                               ctypes.addressof(self._bind) if self._bind is not None else None)
+
+    @classmethod
+    def shapes_only(cls, group_id: int, shapes: Sequence[Tuple[int, int, int]], dtype_a="int16",
+                    dtype_b="int16", dtype_c="int64", bind=None) -> "GroupArgs":
+        """A group of the given (D0, D1, D2) products with no matrices (NULL
+        pointers, plain layouts): for the verifier without a witness, whose
+        reduced claims are then checked by commitment openings."""
+        g = cls.__new__(cls)
+        g.keep = []
+        g._bind = _bind_buffer(bind)
+        arr = (vl_product * len(shapes))()
+        for k, (D0, D1, D2) in enumerate(shapes):
+            arr[k] = vl_product(None, None, dtype_code(dtype_a), dtype_code(dtype_b), D0, D1, D2, D1, D2, 0, 0)
+        g.prods = arr
+        g.struct = vl_group(arr, len(shapes), group_id, None, dtype_code(dtype_c), shapes[0][2],
+                            ctypes.addressof(g._bind) if g._bind is not None else None)
+        return g
 
     @property
     def shapes(self):
@@ -431,6 +462,18 @@ class ProveGraph:
 
     def launch(self, seed: int, stream=None):
         _check(lib().vl_prove_graph_launch(self.handle, seed, _stream(stream)))
+
+    def bind(self, binds=None):
+        """New bind digests for the next launches: None, or one 32-byte
+        digest per group in the order given at create."""
+        if binds is None:
+            _check(lib().vl_prove_graph_bind(self.handle, None))
+            return
+        raw = b"".join(bytes(b) for b in binds)
+        if len(raw) != 32 * len(self.batch):
+            raise ValueError("one 32-byte digest per group")
+        buf = ctypes.create_string_buffer(raw, len(raw))
+        _check(lib().vl_prove_graph_bind(self.handle, ctypes.addressof(buf)))
 
     def close(self):
         if self.handle is not None and self.handle.value:

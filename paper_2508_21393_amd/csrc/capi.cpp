@@ -276,6 +276,8 @@ void group_challenges(const vl_group& g, uint64_t seed, Transcript& tr, std::vec
     dims.push_back(g.prods[k].D2);
   }
   tr_init(tr, seed, g.group_id, g.n_prods, dims.data());
+  // the caller's commitments before the challenges (Sec. II-C after II-A)
+  if (g.bind) tr_absorb32(tr, VL_LBL_BIND, g.bind);
   const uint32_t n0 = nvars_of(g.prods[0].D0), n2 = nvars_of(g.prods[0].D2);
   u.resize(n0);
   v.resize(n2);
@@ -1251,6 +1253,7 @@ struct vl_prove_graph {
   int device = 0;
   std::vector<vl_group> groups;
   std::vector<vl_product> prods;   // the groups' products, owned by the handle
+  std::vector<uint8_t> binds;      // 32 bytes per group: the bind digests, owned by the handle
   vl_prove_opts opts{};
   vl_tuning tuning{};
   bool has_tuning = false;
@@ -1320,6 +1323,12 @@ vl_status vl_prove_graph_create(const vl_group* groups, uint64_t n, const vl_pro
       g->prods.insert(g->prods.end(), groups[i].prods, groups[i].prods + groups[i].n_prods);
       g->groups[i].prods = g->prods.data() + at;   // no reallocation: reserved above
     }
+    g->binds.assign(32 * n, 0);
+    for (uint64_t i = 0; i < n; ++i)
+      if (groups[i].bind) {
+        memcpy(g->binds.data() + 32 * i, groups[i].bind, 32);
+        g->groups[i].bind = g->binds.data() + 32 * i;
+      }
   }
   g->opts = *o;
   if (o->tuning) {
@@ -1392,6 +1401,14 @@ vl_status vl_prove_graph_launch(vl_prove_graph* g, uint64_t seed, void* stream) 
   if (e == hipSuccess) e = hipEventRecord(g->done, s);
   if (e != hipSuccess) return fail(VL_ERR_HIP, "prove graph launch: %s", hipGetErrorString(e));
   g->launched = true;
+  return VL_OK;
+}
+
+vl_status vl_prove_graph_bind(vl_prove_graph* g, const uint8_t* binds) {
+  if (!g) return fail(VL_ERR_INVALID_ARG, "null prove graph");
+  const uint64_t n = g->groups.size();
+  if (binds) memcpy(g->binds.data(), binds, 32 * n);
+  for (uint64_t i = 0; i < n; ++i) g->groups[i].bind = binds ? g->binds.data() + 32 * i : nullptr;
   return VL_OK;
 }
 

@@ -275,6 +275,7 @@ VL_HD void tr_from_bytes(Transcript& t, const uint8_t in[32]) {
 #define VL_LBL_FINAL "final"
 #define VL_LBL_RFINAL "rfinal"
 #define VL_LBL_SIGMA "sigma"
+#define VL_LBL_BIND "bind"
 
 VL_HD void tr_init(Transcript& t, uint64_t seed, uint32_t group_id, uint32_t n_prods,
                    const uint32_t* dims /* 3 per product */) {
@@ -342,6 +343,18 @@ VL_HD void tr_absorb_frs(Transcript& t, const char (&label)[LN], const Fr (&xs)[
     if (k < 32 + L) return (uint8_t)label[k - 32];
     const int e = (k - 32 - L) >> 5, b = (k - 32 - L) & 31;
     return fr_byte(xs[e], b);
+  });
+}
+
+// absorb(label, d): st = H(st || label || d) for a 32-byte message d
+template <int LN>
+VL_HD void tr_absorb32(Transcript& t, const char (&label)[LN], const uint8_t* d) {
+  constexpr int L = LN - 1;
+  const Transcript old = t;
+  sha256_gen<32 + L + 32>(t.h, [&](int k) -> uint32_t {
+    if (k < 32) return state_byte(old, k);
+    if (k < 32 + L) return (uint8_t)label[k - 32];
+    return d[k - 32 - L];
   });
 }
 
