@@ -65,15 +65,15 @@ class vl_group(ctypes.Structure):
 
 class vl_tuning(ctypes.Structure):
     _fields_ = [("lane_macs", c_u32), ("min_tasks", c_u32), ("segments", c_u32), ("cols_rows", c_u32),
-                ("spin_limit", c_u32), ("claim_order", c_u32)]
+                ("spin_limit", c_u32), ("claim_order", c_u32), ("contract_streams", c_u32)]
 
 
 def tuning(lane_macs: int = 0, min_tasks: int = 0, segments: int = 0, cols_rows: int = 0,
-           spin_limit: int = 0, claim_order: int = 0) -> vl_tuning:
+           spin_limit: int = 0, claim_order: int = 0, contract_streams: int = 0) -> vl_tuning:
     """Launch-shape knobs (0 = library default); results never depend on them
     (a spin limit too small for the work makes persistent-mode groups fail
     with VL_ERR_TIMEOUT instead)."""
-    return vl_tuning(lane_macs, min_tasks, segments, cols_rows, spin_limit, claim_order)
+    return vl_tuning(lane_macs, min_tasks, segments, cols_rows, spin_limit, claim_order, contract_streams)
 
 
 def _tun(t):

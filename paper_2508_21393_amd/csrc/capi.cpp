@@ -200,21 +200,23 @@ static vl_status device_writable(void* p, const char* what) {
 // the library holds stays bounded however many caller streams come and go.
 // Two callers that share a rounds stream stay correct (every call forks and
 // joins through events); their rounds stages then run one after the other.
+// The side streams of the contraction fork come from a second pool of the
+// same kind.
 constexpr int kRoundsStreams = 8;
 
-hipError_t rounds_stream_for(hipStream_t s, hipStream_t* out) {
+static hipError_t pool_stream_for(int pool, hipStream_t s, hipStream_t* out) {
   struct Pool {
     hipStream_t st[kRoundsStreams] = {};
     std::map<hipStream_t, int> of;   // caller stream -> pool index
     int next = 0;
   };
   static std::mutex mu;
-  static std::map<int, Pool> pools;
+  static std::map<std::pair<int, int>, Pool> pools;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   std::lock_guard<std::mutex> lock(mu);
-  Pool& P = pools[dev];
+  Pool& P = pools[{dev, pool}];
   auto it = P.of.find(s);
   int k;
   if (it != P.of.end()) {
@@ -235,6 +237,9 @@ hipError_t rounds_stream_for(hipStream_t s, hipStream_t* out) {
   *out = P.st[k];
   return hipSuccess;
 }
+
+hipError_t rounds_stream_for(hipStream_t s, hipStream_t* out) { return pool_stream_for(0, s, out); }
+static hipError_t side_stream_for(hipStream_t s, hipStream_t* out) { return pool_stream_for(1, s, out); }
 
 // Persistent mode's resident rounds workgroups spin until the contractions of
 // their groups have run.  That needs the contractions to be dispatched while
@@ -399,6 +404,7 @@ void Builder::contract(const void* M, int dtype, int nd, uint64_t ld, bool rows,
     f.part = part;
   }
   S().cj_tasks[kind] += out_waves * n_chunks;
+  S().cj_bytes[kind] += (uint64_t)n_out * len * es;
   S().cj[kind].push_back(j);
   if (f.part || f.n_total > f.n_valid) {
     f.split = (f.part && n_chunks >= kFinishSplitChunks) ? 1u : 0u;
@@ -778,19 +784,41 @@ struct ForkEvents {
   }
 };
 
+// The contraction kinds of a segment write disjoint outputs, and the int16
+// kinds are held by latency rather than by HBM: split over two streams they
+// overlap, and the launch gaps between them close.  Worth it when at least
+// two kinds each stream 8 MB or more.
+constexpr uint64_t kForkMinBytes = 8ull << 20;
+
+bool fork_contractions(const Segment& G) {
+  int big = 0;
+  for (int c = 0; c < CK_COUNT; ++c) big += !G.cj[c].empty() && G.cj_bytes[c] >= kForkMinBytes;
+  return big >= 2;
+}
+
+bool plan_forks(const Plan& P) {
+  if (!P.fork) return false;
+  for (const Segment& G : P.seg)
+    if (fork_contractions(G)) return true;
+  return false;
+}
+
 hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipStream_t s,
-                        hipStream_t s2, StageEvents* ev, const void* blob_src_dev) {
+                        hipStream_t s2, StageEvents* ev, const void* blob_src_dev, hipStream_t s3) {
   thread_local std::map<int, ForkEvents> forks;   // per host thread and device
   const size_t nseg = P.seg.size();
   const bool two = s2 != s;
+  const bool side = s3 && s3 != s && !ev && P.fork;
   int dev = 0;
-  if (two) {
+  if (two || side) {
     const hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
   }
   ForkEvents& fork = forks[dev];
-  if (two) {
-    const hipError_t e = fork.need(nseg + 2);
+  if (two || side) {
+    // [0, nseg): rounds forks; nseg, nseg + 1: rounds start and join;
+    // nseg + 2 + 2k, nseg + 3 + 2k: segment k's contraction fork and join
+    const hipError_t e = fork.need(3 * nseg + 2);
     if (e != hipSuccess) return e;
   }
   VL_STAGE(ev, VL_STAGE_UPLOAD, s,
@@ -814,11 +842,40 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
   }
   for (size_t k = 0; k < nseg; ++k) {
     const Segment& G = P.seg[k];
-    for (int c = 0; c < CK_COUNT; ++c) {
+    const bool fk = side && fork_contractions(G);
+    if (fk) {
+      hipError_t e = hipEventRecord(fork.ev[nseg + 2 + 2 * k], s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s3, fork.ev[nseg + 2 + 2 * k], 0);
+      if (e != hipSuccess) return e;
+    }
+    // streams: kinds largest first, each to the stream with fewer bytes so
+    // far; then each stream runs its kinds smallest first, so that the
+    // narrower kinds (the int16 ones, held by latency) run beside the
+    // largest one (the claim, which saturates HBM on its own)
+    int order[CK_COUNT], which[CK_COUNT] = {};
+    for (int c = 0; c < CK_COUNT; ++c) order[c] = c;
+    std::stable_sort(order, order + CK_COUNT, [&](int a, int b) { return G.cj_bytes[a] > G.cj_bytes[b]; });
+    uint64_t load[2] = {0, 0};
+    for (int i = 0; i < CK_COUNT; ++i) {
+      const int c = order[i];
       if (G.cj[c].empty()) continue;
-      VL_STAGE(ev, VL_STAGE_CONTRACT + c, s,
-               launch_contract(c, reinterpret_cast<const ContractJob*>(dblob + L.seg[k].cj[c]),
-                               (uint32_t)G.cj[c].size(), G.cj_tasks[c], s));
+      which[c] = (fk && load[1] < load[0]) ? 1 : 0;
+      load[which[c]] += G.cj_bytes[c];
+    }
+    // (the caller's stream first: its kinds wait on nothing)
+    for (int w = 0; w < 2; ++w)
+      for (int i = CK_COUNT - 1; i >= 0; --i) {
+        const int c = order[i];
+        if (G.cj[c].empty() || which[c] != w) continue;
+        hipStream_t sc = w ? s3 : s;
+        VL_STAGE(ev, VL_STAGE_CONTRACT + c, sc,
+                 launch_contract(c, reinterpret_cast<const ContractJob*>(dblob + L.seg[k].cj[c]),
+                                 (uint32_t)G.cj[c].size(), G.cj_tasks[c], sc));
+      }
+    if (fk) {
+      hipError_t e = hipEventRecord(fork.ev[nseg + 3 + 2 * k], s3);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, fork.ev[nseg + 3 + 2 * k], 0);
+      if (e != hipSuccess) return e;
     }
     if (!G.fin.empty())
       VL_STAGE(ev, VL_STAGE_FINISH, s,
@@ -901,6 +958,7 @@ static void apply_tuning(Tuning& t, const vl_tuning* k) {
   if (k->cols_rows) t.cols_rows = k->cols_rows;
   if (k->spin_limit) t.spin_limit = k->spin_limit;
   if (k->claim_order) t.claim_order = k->claim_order;
+  if (k->contract_streams) t.contract_streams = k->contract_streams;
 }
 
 static vl_status check_tuning(const vl_tuning* k) {
@@ -910,6 +968,8 @@ static vl_status check_tuning(const vl_tuning* k) {
     return fail(VL_ERR_INVALID_ARG, "vl_tuning.segments must be <= %u", kMaxSegments);
   if (k->lane_macs && k->lane_macs < 64) return fail(VL_ERR_INVALID_ARG, "vl_tuning.lane_macs must be >= 64");
   if (k->cols_rows > 2) return fail(VL_ERR_INVALID_ARG, "vl_tuning.cols_rows must be 0, 1 or 2");
+  if (k->contract_streams > 2)
+    return fail(VL_ERR_INVALID_ARG, "vl_tuning.contract_streams must be 0, 1 or 2");
   return VL_OK;
 }
 
@@ -940,6 +1000,7 @@ void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, 
                  int32_t* status_dev, uint8_t* digests_dev, uint8_t* out, const Challenges* given) {
   P = Plan();
   P.persistent = T.persistent;
+  P.fork = !T.persistent && T.contract_streams == 2;
   const uint64_t blob = blob_bound(groups + g0, g1 - g0);
   Builder B(P, T, reinterpret_cast<uint64_t>(ws), blob);
   P.n_err = (uint32_t)(g1 - g0);
@@ -1171,12 +1232,16 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
                   (unsigned long long)o->workspace_bytes, (unsigned long long)align_up(P.data_end, 256));
     const BlobLayout L = blob_layout(P);
     fill_blob(P, L, ws);
-    hipStream_t s2 = s;
+    hipStream_t s2 = s, s3 = nullptr;
     if (P.seg.size() > 1 || P.persistent) {
       const hipError_t e2 = rounds_stream_for(s, &s2);
       if (e2 != hipSuccess) return fail(VL_ERR_HIP, "rounds stream: %s", hipGetErrorString(e2));
     }
-    hipError_t e = enqueue_plan(P, L, ws, s, s2, ev);
+    if (!ev && plan_forks(P)) {
+      const hipError_t e3 = side_stream_for(s, &s3);
+      if (e3 != hipSuccess) return fail(VL_ERR_HIP, "side stream: %s", hipGetErrorString(e3));
+    }
+    hipError_t e = enqueue_plan(P, L, ws, s, s2, ev, nullptr, s3);
     if (e == hipSuccess && gate) {
       // the caller's stream has joined the rounds stream: its position now
       // marks the end of this persistent call
@@ -1188,6 +1253,7 @@ vl_status vl_sumcheck_matmul_prove(const vl_group* groups, uint64_t n, uint64_t 
       // (the pinned buffer the next blocking call reuses): let it finish
       (void)hipStreamSynchronize(s);
       if (s2 != s) (void)hipStreamSynchronize(s2);
+      if (s3) (void)hipStreamSynchronize(s3);
       return fail(VL_ERR_HIP, "launch: %s", hipGetErrorString(e));
     }
     return async ? VL_OK : fetch(g0, g1);
@@ -1354,23 +1420,25 @@ vl_status vl_prove_graph_create(const vl_group* groups, uint64_t n, const vl_pro
   // private stream for the rounds, created before the capture starts: not one
   // of the shared rounds streams, which other threads may be using for eager
   // calls while this one captures)
-  hipStream_t cs = nullptr, s2 = nullptr, own2 = nullptr;
+  hipStream_t cs = nullptr, s2 = nullptr, own2 = nullptr, own3 = nullptr;
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   s2 = cs;
   if (e == hipSuccess && (P.seg.size() > 1 || P.persistent)) {
     e = hipStreamCreateWithFlags(&own2, hipStreamNonBlocking);
     if (e == hipSuccess) s2 = own2;
   }
+  if (e == hipSuccess && plan_forks(P)) e = hipStreamCreateWithFlags(&own3, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
   if (e == hipSuccess) {
     const hipError_t e1 = enqueue_plan(P, L, reinterpret_cast<uint8_t*>(g->opts.workspace), cs, s2, nullptr,
-                                       g->pinned_dev);
+                                       g->pinned_dev, own3);
     const hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
     e = e1 != hipSuccess ? e1 : e2;
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
   if (cs) (void)hipStreamDestroy(cs);
   if (own2) (void)hipStreamDestroy(own2);
+  if (own3) (void)hipStreamDestroy(own3);
   if (e != hipSuccess) {
     graph_free(g);
     return fail(VL_ERR_HIP, "prove graph: %s", hipGetErrorString(e));

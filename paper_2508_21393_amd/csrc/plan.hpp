@@ -44,6 +44,7 @@ struct Tuning {
   uint32_t claim_order = 0;       // claim contraction: 0 auto, 1 by columns, 2 by rows
   bool persistent = false;        // rounds launched first, waiting on readiness counters
   uint32_t spin_limit = 1u << 24; // persistent mode: polls before VL_ERR_TIMEOUT
+  uint32_t contract_streams = 2;  // 2: large contraction kinds split over two streams
 };
 
 // Jobs of one pipeline segment: its groups' contractions, finish jobs and
@@ -53,6 +54,7 @@ struct Tuning {
 struct Segment {
   std::vector<ContractJob> cj[CK_COUNT];
   uint32_t cj_tasks[CK_COUNT] = {};
+  uint64_t cj_bytes[CK_COUNT] = {};   // matrix bytes each kind streams
   std::vector<FinishJob> fin;
   uint32_t fin_blocks = 0;
   std::vector<Pass1Job> pass1;
@@ -67,6 +69,7 @@ struct Segment {
 struct Plan {
   std::vector<uint8_t> blob;      // host image of [err flags][eq jobs][points][segments]
   bool persistent = false;        // rounds launched before the contractions
+  bool fork = false;              // contraction kinds may use a side stream
   uint64_t data_end = 0;          // workspace bytes used
   std::vector<EqJob> eq;
   uint32_t eq_threads = 0;
@@ -159,8 +162,15 @@ struct StageEvents {
 // after segment k's contractions (s2 may equal s: then everything is serial).
 // blob_src_dev: device-side address of a pinned host buffer the blob is
 // copied from (graph capture), else the blob goes through the staging ring.
+// s3: a side stream for the contraction kinds of a segment (forked after the
+// eq tables, joined before the finish pass; see fork_contractions), or null;
+// unused when ev is given, so that stage times are each kernel's own.
 hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipStream_t s,
-                        hipStream_t s2, StageEvents* ev = nullptr, const void* blob_src_dev = nullptr);
+                        hipStream_t s2, StageEvents* ev = nullptr, const void* blob_src_dev = nullptr,
+                        hipStream_t s3 = nullptr);
+// whether a segment's contraction kinds are split over two streams
+bool fork_contractions(const Segment& G);
+bool plan_forks(const Plan& P);
 Tuning tuning_for(const vl_prove_opts* o);
 // partial evaluation (vl_mle_partial_eval): argument checks, and the launch
 // with the caller's (or the fixed) scratch
