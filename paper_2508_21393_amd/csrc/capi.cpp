@@ -13,6 +13,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <condition_variable>
+#include <functional>
 #include <cstdarg>
 #include <map>
 #include <mutex>
@@ -290,31 +293,105 @@ void group_challenges(const vl_group& g, uint64_t seed, Transcript& tr, std::vec
   for (uint32_t i = 0; i < n2; ++i) v[i] = tr_squeeze_fixed(tr, VL_LBL_V);
 }
 
+// A few host threads kept for the life of the process, for the per-group
+// hashing of large calls: starting threads per call costs about as much as
+// the hashing it would spread (tens of microseconds).  run(n, fn) calls
+// fn(i) for every i < n on the workers and the calling thread and returns
+// when all are done; a call that finds the pool busy (another host thread
+// planning) does its work alone.
+class HostPool {
+ public:
+  static HostPool& get() {
+    static HostPool pool;
+    return pool;
+  }
+  void run(uint64_t n, const std::function<void(uint64_t)>& fn) {
+    std::unique_lock<std::mutex> busy(run_mu_, std::try_to_lock);
+    if (!busy.owns_lock() || th_.empty()) {
+      for (uint64_t i = 0; i < n; ++i) fn(i);
+      return;
+    }
+    Job job;
+    job.fn = &fn;
+    job.n = n;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      job_ = &job;
+      ++gen_;
+    }
+    cv_.notify_all();
+    work(job);
+    // every index is taken; wait for the workers still inside this job (no
+    // worker joins it once job_ is cleared)
+    std::unique_lock<std::mutex> lk(mu_);
+    job_ = nullptr;
+    idle_cv_.wait(lk, [&] { return active_ == 0; });
+  }
+  ~HostPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+
+ private:
+  struct Job {
+    const std::function<void(uint64_t)>* fn = nullptr;
+    uint64_t n = 0;
+    std::atomic<uint64_t> next{0};
+  };
+  HostPool() {
+    const unsigned hw = std::thread::hardware_concurrency();
+    const unsigned nw = hw > 1 ? std::min(7u, hw - 1) : 0u;
+    for (unsigned k = 0; k < nw; ++k) th_.emplace_back([this] { loop(); });
+  }
+  static void work(Job& j) {
+    for (uint64_t i = j.next.fetch_add(1); i < j.n; i = j.next.fetch_add(1)) (*j.fn)(i);
+  }
+  void loop() {
+    uint64_t seen = 0;
+    for (;;) {
+      Job* j;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return stop_ || (job_ && gen_ != seen); });
+        if (stop_) return;
+        seen = gen_;
+        j = job_;
+        ++active_;
+      }
+      work(*j);
+      std::lock_guard<std::mutex> lk(mu_);
+      if (--active_ == 0) idle_cv_.notify_all();
+    }
+  }
+  std::mutex run_mu_, mu_;
+  std::condition_variable cv_, idle_cv_;
+  Job* job_ = nullptr;
+  uint64_t gen_ = 0;
+  uint32_t active_ = 0;
+  bool stop_ = false;
+  std::vector<std::thread> th_;
+};
+
 // Challenges of groups [g0, g1): transcript state after u and v.  Each group
-// is independent (its own transcript), so large calls split the hashing over
-// a few host threads.
+// is independent (its own transcript); a group costs a few microseconds of
+// hashing (tens of blocks), so calls of a dozen groups or more spread them
+// over the host pool.
 void all_challenges(const vl_group* groups, uint64_t g0, uint64_t g1, uint64_t seed,
                     std::vector<Challenges>& out) {
   const uint64_t n = g1 - g0;
   out.assign(n, Challenges());
-  auto work = [&](uint64_t lo, uint64_t hi) {
-    for (uint64_t i = lo; i < hi; ++i) group_challenges(groups[g0 + i], seed, out[i].tr, out[i].u, out[i].v);
+  const std::function<void(uint64_t)> one = [&](uint64_t i) {
+    group_challenges(groups[g0 + i], seed, out[i].tr, out[i].u, out[i].v);
   };
-  // a group costs a few microseconds of hashing (tens of blocks): threads
-  // only pay off for a dozen groups or more each
-  const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
-  const uint64_t nt = std::min<uint64_t>(hw, n / 12);
-  if (nt <= 1) {
-    work(0, n);
+  if (n < 12) {
+    for (uint64_t i = 0; i < n; ++i) one(i);
     return;
   }
-  std::vector<std::thread> th;
-  const uint64_t per = (n + nt - 1) / nt;
-  for (uint64_t t = 0; t < nt; ++t) {
-    const uint64_t lo = t * per, hi = std::min(n, lo + per);
-    if (lo < hi) th.emplace_back(work, lo, hi);
-  }
-  for (auto& x : th) x.join();
+  HostPool::get().run(n, one);
 }
 
 // ---------------------------------------------------------------- planning --
