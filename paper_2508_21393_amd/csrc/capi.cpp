@@ -620,10 +620,10 @@ void Builder::group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev,
     rj.ready_target += rj.prods[k].g_nparts;
   }
   // wide rounds for product 0 while its half-table has >= kMatWidePairs pairs
-  // (round 2 at least); not in persistent mode, whose rounds workgroups are
-  // resident before the contractions run
+  // (from round 2, when that has >= kMatWideStart); not in persistent mode,
+  // whose rounds workgroups are resident before the contractions run
   const uint32_t n1w = rj.prods[0].n1;
-  if (!T.persistent && n1w >= 2 && (1ull << (n1w - 2)) >= kMatWidePairs) {
+  if (!T.persistent && n1w >= 2 && (1ull << (n1w - 2)) >= kMatWideStart) {
     uint32_t W = 1;
     while (W < kMatMaxWide && W + 1 < n1w && (1ull << (n1w - 1 - W)) >= kMatWidePairs) ++W;
     const uint32_t nb1 = (uint32_t)(((1ull << (n1w - 2)) + kMatSweepPairs - 1) / kMatSweepPairs);

@@ -82,6 +82,10 @@ struct RoundsProd {
 // [24..39] r_k in slot k & 1 (Montgomery).  Sweep partials: two buffers of
 // wpart_stride words, round k's in buffer k & 1.
 constexpr uint32_t kMatSweepPairs = 256;
+// a product goes wide when its round 2 has kMatWideStart pairs or more (at
+// 1024 a sweep launch costs more than the round on one workgroup), and stays
+// wide while a round has kMatWidePairs or more
+constexpr uint32_t kMatWideStart = 2048;
 constexpr uint32_t kMatWidePairs = 1024;
 constexpr uint32_t kMatMaxWide = 16;          // n1 <= 20 needs at most 10
 constexpr uint32_t kMatIoState = 8, kMatIoR = 24, kMatIoWords = 48;

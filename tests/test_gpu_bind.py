@@ -114,9 +114,8 @@ def test_bound_async_and_graph_rebind(B):
 
 def test_commit_prove_open_on_the_device(B):
     # Hyrax row commitments of A, B and C on the device, a proof bound to
-    # their digest (D1 = 4096: the first rounds run wide), the host
-    # verifier without a witness, and each reduced claim checked by a device
-    # opening against its commitment
+    # their digest, the host verifier without a witness, and each reduced
+    # claim checked by a device opening against its commitment
     import torch
     rng = np.random.default_rng(41)
     D0, D1, D2 = 8, 4096, 4

@@ -1,7 +1,8 @@
 """Parity of the wide matmul rounds with the CPU oracle (needs a gfx950 GPU).
 
-A group whose first product has an inner dimension of 4096 or more (padded)
-proves its first rounds across the whole GPU: one sweep launch per round,
+A group whose first product has an inner dimension of 8192 or more (padded:
+its round 2 then has 2048 pairs or more) proves its first rounds across the
+whole GPU: one sweep launch per round,
 whose blocks each take the previous round's transcript step, fold the
 tables and sum the next round's pairs.  The proof bytes must not change:
 every case here compares them, exactly, with the oracle's proof of the same
@@ -22,12 +23,12 @@ from gpu_util import device_group
 pytestmark = pytest.mark.gpu
 
 # (dims of the products, dtype, transposed views, value bits): first
-# products with D1 = 4096 .. 16384 (two to four wide rounds), a ragged D1,
+# products with D1 = 8192 .. 16384 (three or four wide rounds), ragged D1,
 # a second narrow product in the group, and every entry type (value bits
 # keep every claim entry within |x| < 2^47)
 WIDE_CASES = [
     ([(3, 8192, 5)], np.int16, (False, False), None),
-    ([(4, 4096, 3), (4, 16, 3)], np.int16, (False, False), None),
+    ([(4, 8192, 3), (4, 16, 3)], np.int16, (False, False), None),
     ([(5, 5000, 7)], np.int32, (True, False), 14),
     ([(2, 16384, 2)], np.int16, (False, True), None),
     ([(6, 4100, 4), (6, 4100, 4)], np.int64, (True, True), 16),
@@ -101,7 +102,7 @@ def test_wide_range_error_on_oversized_claim_entry(B):
     # int16 factors: C is contracted in two 24-bit digits, so an entry
     # beyond |x| < 2^47 is refused (int64 factors take three digits, which
     # cover every int64 entry: there the same C is a false statement)
-    g = workloads.tiny_random_group(32, [(4, 4096, 3)])
+    g = workloads.tiny_random_group(32, [(4, 8192, 3)])
     g.C = g.C.copy()
     g.C[3, 0] = 1 << 60
     _say("wide range error")
@@ -116,9 +117,9 @@ def test_wide_async_mixed_batch_statuses(B):
     import torch
     cases = [
         ([(3, 8192, 5)], np.int16, (False, False), None),     # valid, wide
-        ([(2, 4096, 2)], np.int16, (False, False), None),     # false claim, wide
+        ([(2, 8192, 2)], np.int16, (False, False), None),     # false claim, wide
         ([(8, 8, 8)], np.int16, (False, False), None),        # valid, narrow
-        ([(4, 4096, 3)], np.int16, (False, False), None),     # range error, wide
+        ([(4, 8192, 3)], np.int16, (False, False), None),     # range error, wide
         ([(5, 5000, 7)], np.int32, (True, False), 14),        # valid, wide
     ]
     groups = _groups(cases, seed0=200)
