@@ -11,6 +11,7 @@
 // group; batched mode runs each stage once for all groups (one launch per
 // stage and contraction kind); both write identical bytes.
 #include <hip/hip_runtime.h>
+#include <pthread.h>
 
 #include <algorithm>
 #include <atomic>
@@ -301,11 +302,18 @@ void group_challenges(const vl_group& g, uint64_t seed, Transcript& tr, std::vec
 // planning) does its work alone.
 class HostPool {
  public:
+  // never destroyed: the workers stay blocked on the condition variable
+  // until the process ends (destroying it under waiters would block, also in
+  // a forked child, whose copy still counts the parent's workers)
   static HostPool& get() {
-    static HostPool pool;
-    return pool;
+    static HostPool* pool = new HostPool();
+    return *pool;
   }
   void run(uint64_t n, const std::function<void(uint64_t)>& fn) {
+    if (forked_) {   // a child process: the workers stayed in the parent
+      for (uint64_t i = 0; i < n; ++i) fn(i);
+      return;
+    }
     std::unique_lock<std::mutex> busy(run_mu_, std::try_to_lock);
     if (!busy.owns_lock() || th_.empty()) {
       for (uint64_t i = 0; i < n; ++i) fn(i);
@@ -327,15 +335,6 @@ class HostPool {
     job_ = nullptr;
     idle_cv_.wait(lk, [&] { return active_ == 0; });
   }
-  ~HostPool() {
-    {
-      std::lock_guard<std::mutex> lk(mu_);
-      stop_ = true;
-    }
-    cv_.notify_all();
-    for (auto& t : th_) t.join();
-  }
-
  private:
   struct Job {
     const std::function<void(uint64_t)>* fn = nullptr;
@@ -346,6 +345,7 @@ class HostPool {
     const unsigned hw = std::thread::hardware_concurrency();
     const unsigned nw = hw > 1 ? std::min(7u, hw - 1) : 0u;
     for (unsigned k = 0; k < nw; ++k) th_.emplace_back([this] { loop(); });
+    pthread_atfork(nullptr, nullptr, [] { HostPool::get().forked_ = true; });
   }
   static void work(Job& j) {
     for (uint64_t i = j.next.fetch_add(1); i < j.n; i = j.next.fetch_add(1)) (*j.fn)(i);
@@ -356,8 +356,7 @@ class HostPool {
       Job* j;
       {
         std::unique_lock<std::mutex> lk(mu_);
-        cv_.wait(lk, [&] { return stop_ || (job_ && gen_ != seen); });
-        if (stop_) return;
+        cv_.wait(lk, [&] { return job_ && gen_ != seen; });
         seen = gen_;
         j = job_;
         ++active_;
@@ -372,7 +371,7 @@ class HostPool {
   Job* job_ = nullptr;
   uint64_t gen_ = 0;
   uint32_t active_ = 0;
-  bool stop_ = false;
+  bool forked_ = false;
   std::vector<std::thread> th_;
 };
 
