@@ -383,8 +383,15 @@ void all_challenges(const vl_group* groups, uint64_t g0, uint64_t g1, uint64_t s
                     std::vector<Challenges>& out) {
   const uint64_t n = g1 - g0;
   out.assign(n, Challenges());
+  // (with u and v in Montgomery form for the eq jobs, converted here on the
+  // pool rather than by the serial job builder)
   const std::function<void(uint64_t)> one = [&](uint64_t i) {
-    group_challenges(groups[g0 + i], seed, out[i].tr, out[i].u, out[i].v);
+    Challenges& c = out[i];
+    group_challenges(groups[g0 + i], seed, c.tr, c.u, c.v);
+    c.um.resize(8 * c.u.size());
+    c.vm.resize(8 * c.v.size());
+    for (size_t k = 0; k < c.u.size(); ++k) memcpy(c.um.data() + 8 * k, fr_to_mont(c.u[k]).w, 32);
+    for (size_t k = 0; k < c.v.size(); ++k) memcpy(c.vm.data() + 8 * k, fr_to_mont(c.v[k]).w, 32);
   };
   if (n < 12) {
     for (uint64_t i = 0; i < n; ++i) one(i);
@@ -491,7 +498,7 @@ void Builder::contract(const void* M, int dtype, int nd, uint64_t ld, bool rows,
 }
 
 void Builder::eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_len, bool pack_r2,
-                     bool eq_canon, const Fr* scale) {
+                     bool eq_canon, const Fr* scale, const std::vector<uint32_t>* mont) {
   EqJob e{};
   if (scale) {
     e.scaled = 1;
@@ -505,12 +512,17 @@ void Builder::eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uin
   e.eq = eq;
   e.eq_ld = 1ull << x.size();
   e.pack = pack;
-  std::vector<uint32_t> pts;
-  for (const Fr& xi : x) {
-    const Fr xm = fr_to_mont(xi);
-    pts.insert(pts.end(), xm.w, xm.w + 8);
+  if (mont && mont->size() == 8 * x.size()) {
+    P.points.push_back(*mont);
+  } else {
+    std::vector<uint32_t> pts;
+    pts.reserve(8 * x.size());
+    for (const Fr& xi : x) {
+      const Fr xm = fr_to_mont(xi);
+      pts.insert(pts.end(), xm.w, xm.w + 8);
+    }
+    P.points.push_back(std::move(pts));
   }
-  P.points.push_back(pts);
   P.point_dev.push_back(nullptr);
   // one thread per 4 entries (one for the whole table below 2 variables);
   // pack_len <= 2^nvars
@@ -577,15 +589,15 @@ void Builder::group(const vl_group& g, const Challenges& ch, uint8_t* proof_dev,
   if (by_rows) {
     uint32_t* eqV = dev<uint32_t>(take(8 * L2 * 4));
     uint32_t* svec = dev<uint32_t>(take(8 * L2 * 4));
-    eq_job(u, nullptr, packU, D0, true, false);
-    eq_job(v, eqV, packV, D2, false, true);
+    eq_job(u, nullptr, packU, D0, true, false, nullptr, &ch.um);
+    eq_job(v, eqV, packV, D2, false, true, nullptr, &ch.vm);
     contract(g.C, g.dtype_c, ndc, g.ldc, true, D2, D0, packU, svec, L2, L2, err);
     rj.c_part = pass1(eqV, L2, svec, L2, (uint32_t)L2, true, rj.c_nparts, ready);
   } else {
     uint32_t* eqU = dev<uint32_t>(take(8 * L0 * 4));
     uint32_t* tvec = dev<uint32_t>(take(8 * L0 * 4));
-    eq_job(u, eqU, packU, D0, true, false);
-    eq_job(v, nullptr, packV, D2, false, false);
+    eq_job(u, eqU, packU, D0, true, false, nullptr, &ch.um);
+    eq_job(v, nullptr, packV, D2, false, false, nullptr, &ch.vm);
     contract(g.C, g.dtype_c, ndc, g.ldc, false, D0, D2, packV, tvec, L0, L0, err);
     rj.c_part = pass1(eqU, L0, tvec, L0, (uint32_t)L0, true, rj.c_nparts, ready);
   }

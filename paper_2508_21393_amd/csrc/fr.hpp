@@ -176,8 +176,51 @@ __device__ __forceinline__ void fr_mac96s(uint64_t& acc, uint32_t& top, uint32_t
 
 #endif
 
+#if !defined(__HIP_DEVICE_COMPILE__)
+// Host Montgomery product with 64-bit limbs (CIOS, 128-bit partial
+// products): 32 multiplications instead of the 128 of 32-bit limbs.  R is
+// 2^256 either way, so the result is the same field element.
+inline Fr fr_mul_host64(const Fr& a, const Fr& b) {
+  typedef unsigned __int128 u128;
+  constexpr uint64_t P[4] = {0xffffffff00000001ull, 0x53bda402fffe5bfeull, 0x3339d80809a1d805ull,
+                             0x73eda753299d7d48ull};
+  constexpr uint64_t kPInv64 = 0xfffffffeffffffffull;   // -p^-1 mod 2^64
+  uint64_t A[4], Bv[4], t[6] = {0, 0, 0, 0, 0, 0};
+  for (int j = 0; j < 4; ++j) {
+    A[j] = (uint64_t)a.w[2 * j] | ((uint64_t)a.w[2 * j + 1] << 32);
+    Bv[j] = (uint64_t)b.w[2 * j] | ((uint64_t)b.w[2 * j + 1] << 32);
+  }
+  for (int i = 0; i < 4; ++i) {
+    u128 C = 0;
+    for (int j = 0; j < 4; ++j) {
+      C = (u128)A[j] * Bv[i] + t[j] + (uint64_t)(C >> 64);
+      t[j] = (uint64_t)C;
+    }
+    u128 s = (u128)t[4] + (uint64_t)(C >> 64);
+    t[4] = (uint64_t)s;
+    t[5] = (uint64_t)(s >> 64);
+    const uint64_t m = t[0] * kPInv64;
+    C = (u128)m * P[0] + t[0];
+    for (int j = 1; j < 4; ++j) {
+      C = (u128)m * P[j] + t[j] + (uint64_t)(C >> 64);
+      t[j - 1] = (uint64_t)C;
+    }
+    s = (u128)t[4] + (uint64_t)(C >> 64);
+    t[3] = (uint64_t)s;
+    t[4] = t[5] + (uint64_t)(s >> 64);
+  }
+  Fr r;
+  for (int j = 0; j < 4; ++j) {
+    r.w[2 * j] = (uint32_t)t[j];
+    r.w[2 * j + 1] = (uint32_t)(t[j] >> 32);
+  }
+  return fr_reduce_once(r);
+}
+#endif
+
 // Montgomery product a*b*R^-1 mod p (inputs < p, output < p).  The device
-// build uses the product-scanning form above; the host build uses CIOS.
+// build uses the product-scanning form above; the host build the 64-bit
+// CIOS form.
 VL_HD Fr fr_mul(const Fr& a, const Fr& b) {
 #if defined(__HIP_DEVICE_COMPILE__)
   uint32_t m[8], u[8];
@@ -213,33 +256,7 @@ VL_HD Fr fr_mul(const Fr& a, const Fr& b) {
   for (int j = 0; j < 8; ++j) r.w[j] = u[j];
   return fr_reduce_once(r);
 #else
-  uint32_t t[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) t[j] = 0;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const uint32_t bi = b.w[i];
-    // t += a * b_i, keeping the carry word A
-    uint64_t s = (uint64_t)a.w[0] * bi + t[0];
-    uint32_t A = (uint32_t)(s >> 32);
-    t[0] = (uint32_t)s;
-    const uint32_t m = 0u - t[0];          // m = t0 * (-p^-1) mod 2^32
-    // t0 + m * p0 = t0 + m: low word is 0, carry is (t0 != 0)
-    uint32_t C = t[0] != 0u ? 1u : 0u;
-#pragma unroll
-    for (int j = 1; j < 8; ++j) {
-      uint64_t s1 = (uint64_t)a.w[j] * bi + t[j] + A;
-      A = (uint32_t)(s1 >> 32);
-      uint64_t s2 = (uint64_t)m * p_limb(j) + (uint32_t)s1 + C;
-      C = (uint32_t)(s2 >> 32);
-      t[j - 1] = (uint32_t)s2;
-    }
-    t[7] = A + C;
-  }
-  Fr r;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) r.w[j] = t[j];
-  return fr_reduce_once(r);
+  return fr_mul_host64(a, b);
 #endif
 }
 

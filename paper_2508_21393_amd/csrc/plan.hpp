@@ -25,6 +25,7 @@ void group_challenges(const vl_group& g, uint64_t seed, Transcript& tr, std::vec
 struct Challenges {
   Transcript tr;
   std::vector<Fr> u, v;
+  std::vector<uint32_t> um, vm;   // u and v in Montgomery form, 8 words each (empty: not computed)
 };
 
 constexpr uint32_t kMaxSegments = 8;
@@ -129,7 +130,8 @@ struct Builder {
   void contract(const void* M, int dtype, int nd, uint64_t ld, bool rows, uint32_t n_out, uint32_t len,
                 const uint32_t* pack, uint32_t* dst, uint64_t dst_ld, uint64_t n_total, int32_t* err);
   void eq_job(const std::vector<Fr>& x, uint32_t* eq, uint32_t* pack, uint32_t pack_len, bool pack_r2,
-              bool eq_canon, const Fr* scale = nullptr);
+              bool eq_canon, const Fr* scale = nullptr,
+              const std::vector<uint32_t>* mont = nullptr);
   // eq job of a point that a kernel earlier on the stream writes to device
   // memory (nvars Montgomery elements at point_dev)
   void eq_job_dev(uint32_t nvars, const uint32_t* point_dev, uint32_t* eq, uint32_t* pack, uint32_t pack_len,
