@@ -28,6 +28,14 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# Hardware queues for this process, read when the runtime starts (before any
+# GPU call): HIP gives a stream a queue at its first launch, and with its
+# default of 4 the proofs in flight, the caller's stream and the library's
+# side stream share queues, so one proof's sumcheck rounds can hold up
+# another's contractions.  16 gives every stream its own queue (a larger
+# value set by the caller is kept).
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < 16:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 METRIC = "Fr MACs/s + matmul-sumcheck proofs/s; batched vs per-instance; p50/p99 latency"
 CU, LANES_PER_CLK, CLOCK_HZ = 256, 64, 2.4e9   # MI355X: CUs, VALU lanes per CU per clock, peak clock
@@ -482,12 +490,12 @@ def main():
     ap.add_argument("--lane-macs", type=int, default=0, help="vl_tuning.lane_macs (0: library default)")
     ap.add_argument("--min-tasks", type=int, default=0, help="vl_tuning.min_tasks (0: library default)")
     ap.add_argument("--contract-streams", type=int, default=0,
-                    help="vl_tuning.contract_streams (0: library default, two streams; 1: one stream)")
+                    help="vl_tuning.contract_streams (0: library default; 1: one stream; 2: two)")
     ap.add_argument("--segments", type=int, default=0, help="vl_tuning.segments (0: library default)")
     ap.add_argument("--cols-rows", type=int, default=0, help="vl_tuning.cols_rows (0: library default)")
     ap.add_argument("--claim-order", type=int, default=0,
                     help="vl_tuning.claim_order (0: library default, 1: C by columns, 2: C by rows)")
-    ap.add_argument("--inflight", type=int, default=3,
+    ap.add_argument("--inflight", type=int, default=8,
                     help="proofs in flight in the throughput phase (asynchronous entry point)")
     ap.add_argument("--graph", type=int, default=1,
                     help="1: the throughput phase replays one captured HIP graph per slot (vl_prove_graph)")

@@ -136,11 +136,13 @@ typedef struct {
                               has >= 256 columns, else by columns; 1 = always by
                               columns, t[i] = sum_j C[i][j] eq(v, j); 2 = always
                               by rows, s[j] = sum_i eq(u, i) C[i][j]              */
-  uint32_t contract_streams; /* batched mode: 2 (default) = the contraction kinds
-                              of a pipeline segment with two or more large kinds
-                              run on two streams (joined before the finish
-                              pass); 1 = one stream.  Calls that ask for stage
-                              times always use one                               */
+  uint32_t contract_streams; /* batched mode: 2 = the contraction kinds of a
+                              pipeline segment with two or more large kinds run
+                              on two streams (joined before the finish pass);
+                              1 = one stream.  Default: 2 for blocking calls, 1
+                              for asynchronous calls and prove graphs (several
+                              proofs in flight share the hardware queues).
+                              Calls that ask for stage times always use one      */
 } vl_tuning;
 
 typedef struct {

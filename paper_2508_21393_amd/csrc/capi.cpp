@@ -1067,6 +1067,12 @@ Tuning tuning_for(const vl_prove_opts* o) {
   t.persistent = o && o->mode == VL_MODE_PERSISTENT;
   t.min_tasks = t.per_instance ? 1024 : 1;
   t.segments = t.per_instance ? 1 : (t.persistent ? kPersistentSegments : kDefaultSegments);
+  // the contraction fork by default only in blocking calls: asynchronous
+  // calls and prove graphs are made to have several proofs in flight, which
+  // then share the GPU's few hardware queues, and a second stream per proof
+  // made their throughput depend on how the runtime happened to map streams
+  // to queues (one proof's rounds kernel holding up another's contractions)
+  t.contract_streams = (o && !o->async) ? 2 : 1;
   if (o) apply_tuning(t, o->tuning);
   return t;
 }

@@ -45,7 +45,7 @@ struct Tuning {
   uint32_t claim_order = 0;       // claim contraction: 0 auto, 1 by columns, 2 by rows
   bool persistent = false;        // rounds launched first, waiting on readiness counters
   uint32_t spin_limit = 1u << 24; // persistent mode: polls before VL_ERR_TIMEOUT
-  uint32_t contract_streams = 2;  // 2: large contraction kinds split over two streams
+  uint32_t contract_streams = 1;  // 2: large contraction kinds split over two streams
 };
 
 // Jobs of one pipeline segment: its groups' contractions, finish jobs and

@@ -256,7 +256,8 @@ def test_two_rows_per_lane_tiny_cases(B):
 
 
 @pytest.mark.parametrize("knobs", [dict(cols_rows=2, claim_order=1), dict(lane_macs=4096),
-                                   dict(lane_macs=16384)])
+                                   dict(lane_macs=16384), dict(contract_streams=1),
+                                   dict(contract_streams=2, segments=3)])
 def test_tuned_launch_shapes_full_size_cfg3(B, knobs):
     # launch shapes the autotuner may pick, at full size: the proof bytes
     # must still be the oracle's
@@ -338,6 +339,7 @@ def test_async_refuses_pageable_host_buffers(B):
 
 @pytest.mark.parametrize("cfg", ["cfg2", "cfg3", "cfg4"])
 def test_full_size_config_matches_oracle(B, cfg):
+    # blocking calls: the large contraction kinds run on two streams
     _say(f"{cfg}: generating")
     # the 7B block's witness products run as float64 GEMMs on the GPU (exact:
     # all partial sums are integers below 2^53); the others on the host
@@ -385,19 +387,23 @@ def test_prove_graph_replays_match_eager(B, segments):
                     assert raw[G.offsets[i]:G.offsets[i + 1]].hex() == gold["proof_hex"]
 
 
-def test_prove_graph_full_size_cfg3(B):
+@pytest.mark.parametrize("streams", [0, 2])
+def test_prove_graph_full_size_cfg3(B, streams):
+    # streams 2: the contraction kinds (each above 100 MB here) forked over
+    # two streams inside the captured graph; 0: the default (one stream)
     import torch
-    _say("cfg3 graph: generating")
+    _say(f"cfg3 graph streams={streams}: generating")
     w = workloads.make_config("cfg3")
     gold = golden("cfg3")
     gs = [device_group(g, B) for g in w.groups]
     total = sum(B.proof_size(g) for g in gs)
     proofs = torch.empty(total, dtype=torch.uint8, pin_memory=True)
     status = torch.empty(len(gs), dtype=torch.int32, pin_memory=True)
-    ws = torch.empty(B.workspace_size(gs, 1, async_=True), dtype=torch.uint8, device="cuda")
-    with B.ProveGraph(gs, ws, proofs, status) as G:
+    tn = B.tuning(contract_streams=streams)
+    ws = torch.empty(B.workspace_size(gs, 1, async_=True, tuning_=tn), dtype=torch.uint8, device="cuda")
+    with B.ProveGraph(gs, ws, proofs, status, tuning_=tn) as G:
         for rep in range(3):
-            _say(f"cfg3 graph: replay {rep}")
+            _say(f"cfg3 graph streams={streams}: replay {rep}")
             proofs.numpy()[:] = 0
             G.launch(w.seed)
             torch.cuda.synchronize()
