@@ -18,6 +18,12 @@ released.
 The arithmetic is untouched: a request's proof bytes depend only on its
 matrices, its seed and its group ids, so a result is identical alone and in
 any mix (the serving tests check this).
+
+Hardware queues: HIP gives each stream one of GPU_MAX_HW_QUEUES queues (4 by
+default) at its first launch; slots whose streams share a queue run one
+after the other there, one request's sumcheck rounds in front of the next
+one's contractions.  A process serving n slots should set GPU_MAX_HW_QUEUES
+to at least n + 2 before the GPU is first used (bench.py sets 16).
 """
 import collections
 import dataclasses
