@@ -216,7 +216,7 @@ def streaming_read_GBps(nbytes=4 << 30):
     return v if v > 0 else None
 
 
-def serving_leg(B, n_requests, n_slots=4, seed=5, loads=(0.5, 0.8, 0.95), pool_n=14, planner=None):
+def serving_leg(B, n_requests, n_slots=8, seed=5, loads=(0.5, 0.8, 0.95), pool_n=14, planner=None):
     """Continuous batching at 13B-class shapes (hidden 5120, FFN 13824): a
     resident pool of proof requests that covers every target, T in
     {128, 512, 2048}, rank in {8, 16, 64} and type in {fwd, bwd, upd}
@@ -499,6 +499,7 @@ def main():
                     help="proofs in flight in the throughput phase (asynchronous entry point)")
     ap.add_argument("--graph", type=int, default=1,
                     help="1: the throughput phase replays one captured HIP graph per slot (vl_prove_graph)")
+    ap.add_argument("--serve-slots", type=int, default=8, help="slots of the serving leg's proof server")
     ap.add_argument("--serve-requests", type=int, default=600,
                     help="requests per offered load in the serving leg at 13B-class shapes (0: skip it)")
     ap.add_argument("--no-plan", action="store_true",
@@ -737,7 +738,7 @@ def main():
             sl.graph = None
         del slots, workspace, batch, gas
         torch.cuda.empty_cache()
-        out["serving"] = serving_leg(B, args.serve_requests, planner=planner)
+        out["serving"] = serving_leg(B, args.serve_requests, n_slots=args.serve_slots, planner=planner)
     if args.attention_reps > 0:
         torch.cuda.empty_cache()
         out["attention"] = attention_leg(B, args.attention_reps)
