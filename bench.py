@@ -563,10 +563,14 @@ def main():
     if planner is not None and not any(knobs) and mode == B.VL_MODE_BATCHED:
         plan_rec = planner.plan(batch, w.seed, mode)
         tun = planner.tuning(batch, w.seed, mode)
-    workspace = torch.empty(B.workspace_size(batch, mode, tuning_=tun), dtype=torch.uint8, device="cuda")
+    one_seg = B.tuning(tun.lane_macs, tun.min_tasks, tun.segments or 1, tun.cols_rows, 0, tun.claim_order,
+                       tun.contract_streams)
+    workspace = torch.empty(max(B.workspace_size(batch, mode, tuning_=tun),
+                                B.workspace_size(batch, mode, tuning_=one_seg)), dtype=torch.uint8, device="cuda")
 
-    def step(stage=None):
-        return B.sumcheck_matmul_prove(batch, w.seed, mode=mode, workspace=workspace, stage_ms=stage, tuning_=tun)
+    def step(stage=None, tuning_=None):
+        return B.sumcheck_matmul_prove(batch, w.seed, mode=mode, workspace=workspace, stage_ms=stage,
+                                       tuning_=tuning_ or tun)
 
     for _ in range(args.warmup):
         ref, ref_dig = step()
@@ -648,14 +652,18 @@ def main():
     lat_ms = sorted(1e3 * x for x in lat)
     p50 = lat_ms[len(lat_ms) // 2]
     p99 = lat_ms[min(len(lat_ms) - 1, int(math.ceil(0.99 * len(lat_ms))) - 1)]
-    # Stage times: the same blocking calls with HIP events around every
-    # launch (the events add host work per launch, so these calls are not
-    # the ones timed for latency)
+    # Stage times: blocking calls with HIP events around every launch (the
+    # events add host work per launch, so these calls are not the ones timed
+    # for latency), in one pipeline segment (unless one was asked for) so
+    # that each contraction kind is one launch per proof, whose time is the
+    # kernel's own (the library runs them on one stream when stage times are
+    # asked for)
+    stage_tun = one_seg
     stage_sum, ilat = [0.0] * B.VL_STAGE_COUNT, []
     for _ in range(args.steps):
         s0 = time.perf_counter()
         st = []
-        proofs, dig = step(st)
+        proofs, dig = step(st, stage_tun)
         ilat.append(time.perf_counter() - s0)
         stage_sum = [a + b for a, b in zip(stage_sum, st)]
         assert dig == ref_dig, "proofs changed between steps"

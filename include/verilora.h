@@ -126,7 +126,8 @@ typedef struct {
   uint32_t min_tasks;      /* halve a contraction's chunk until it has this many
                               wave tasks (chunks stay >= 256 entries)               */
   uint32_t segments;       /* batched mode: pipeline segments, 1..8; the rounds of
-                              one segment overlap the contractions of the next     */
+                              one segment overlap the contractions of the next
+                              (default 2 in blocking calls, 1 otherwise)          */
   uint32_t cols_rows;      /* rows per lane in the vector cols kernels (int16 and
                               |x| < 2^47 int64): 1 or 2                            */
   uint32_t spin_limit;     /* persistent mode: polls (about 0.2 us each) of a

@@ -974,7 +974,10 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
                launch_pass1(reinterpret_cast<const Pass1Job*>(dblob + L.seg[k].pass1), (uint32_t)G.pass1.size(),
                             G.pass1_blocks, s));
     if (G.rounds.empty() || P.persistent) continue;
-    if (two) {
+    // the last segment's rounds on the caller's stream (nothing follows its
+    // contractions there), beside the earlier segments' on the rounds stream
+    hipStream_t sr = (two && k + 1 < nseg) ? s2 : s;
+    if (sr != s) {
       hipError_t e = hipEventRecord(fork.ev[k], s);
       if (e == hipSuccess) e = hipStreamWaitEvent(s2, fork.ev[k], 0);
       if (e != hipSuccess) return e;
@@ -984,10 +987,10 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
     for (size_t rd = 1; rd < G.wide.size(); ++rd) {
       if (G.wide[rd].empty()) continue;
       const MatSweep* lst = reinterpret_cast<const MatSweep*>(dblob + L.seg[k].wide[rd]);
-      VL_STAGE(ev, VL_STAGE_ROUNDS, s2,
-               launch_mat_sweep(rjobs, lst, (uint32_t)G.wide[rd].size(), G.wide_blocks[rd], (uint32_t)rd, s2));
+      VL_STAGE(ev, VL_STAGE_ROUNDS, sr,
+               launch_mat_sweep(rjobs, lst, (uint32_t)G.wide[rd].size(), G.wide_blocks[rd], (uint32_t)rd, sr));
     }
-    VL_STAGE(ev, VL_STAGE_ROUNDS, s2, launch_rounds(rjobs, (uint32_t)G.rounds.size(), s2));
+    VL_STAGE(ev, VL_STAGE_ROUNDS, sr, launch_rounds(rjobs, (uint32_t)G.rounds.size(), sr));
   }
   if (two) {
     // join: the caller's stream sees every rounds launch
@@ -1067,6 +1070,11 @@ Tuning tuning_for(const vl_prove_opts* o) {
   t.persistent = o && o->mode == VL_MODE_PERSISTENT;
   t.min_tasks = t.per_instance ? 1024 : 1;
   t.segments = t.per_instance ? 1 : (t.persistent ? kPersistentSegments : kDefaultSegments);
+  // a blocking call proves one batch at a time: two segments let the longest
+  // sumchecks start while the last groups' contractions run (1.55 -> 1.50 ms
+  // on the 7B block); with several proofs in flight the other proofs fill the
+  // GPU instead, and one segment gave 2-3% more throughput
+  if (!t.per_instance && !t.persistent && o && !o->async) t.segments = kBlockingSegments;
   // the contraction fork by default only in blocking calls: asynchronous
   // calls and prove graphs are made to have several proofs in flight, which
   // then share the GPU's few hardware queues, and a second stream per proof
@@ -1082,6 +1090,72 @@ static Tuning pe_tuning(const vl_tuning* k) {
   t.min_tasks = 1024;
   apply_tuning(t, k);
   return t;
+}
+
+// Time model of a group for pipeline segments (µs, measured on MI355X): its
+// rounds chain, a base of about 50 µs plus 13 µs per round held in
+// registers (half-table of 64 pairs or fewer) and 24 µs per round swept in
+// memory, per product in order; and its contraction bytes at about 4.5 TB/s.
+static double rounds_us(const vl_group& g) {
+  double t = 50.0;
+  for (uint32_t k = 0; k < g.n_prods; ++k) {
+    const double n1 = nvars_of(g.prods[k].D1);
+    t += 13.0 * std::min(n1, 7.0) + 24.0 * std::max(0.0, n1 - 7.0) + (k ? 15.0 : 0.0);
+  }
+  return t;
+}
+
+// Segment boundaries over the groups in order (longest chains first):
+// segment k holds positions [cut[k], cut[k + 1]).  Segment k's rounds start
+// once its contractions (all earlier segments' too, on the caller's stream)
+// and its finish pass are done; the rounds of segments 0 .. nseg - 2 run one
+// after another on the rounds stream, the last segment's on the caller's
+// stream beside them.  Two or three segments: the cuts that minimise the
+// modelled end of the call (over all cuts; few groups per call); otherwise,
+// and in persistent mode, equal numbers of groups.
+static std::vector<uint64_t> segment_cuts(const std::vector<uint64_t>& order, const std::vector<double>& chain,
+                                          const std::vector<double>& bytes, uint32_t nseg, bool persistent) {
+  const uint64_t n = order.size();
+  std::vector<uint64_t> cut(nseg + 1);
+  for (uint32_t k = 0; k <= nseg; ++k) cut[k] = (uint64_t)k * n / nseg;
+  if (persistent || nseg < 2 || nseg > 3 || n > 512) return cut;
+  constexpr double kBytesPerUs = 4.5e6, kFinishUs = 60.0;
+  std::vector<double> pre(n + 1, 0.0);   // contraction time of positions [0, i)
+  for (uint64_t i = 0; i < n; ++i) pre[i + 1] = pre[i] + bytes[order[i]] / kBytesPerUs;
+  auto end_of = [&](const std::vector<uint64_t>& c) {
+    double rs = 0.0, end = 0.0;   // the rounds stream's free time; the call's end
+    for (uint32_t k = 0; k < nseg; ++k) {
+      const double ready = pre[c[k + 1]] + kFinishUs * (k + 1);
+      const double r = chain[order[c[k]]];   // the segment's longest chain
+      if (k + 1 < nseg) {
+        rs = std::max(rs, ready) + r;
+        end = std::max(end, rs);
+      } else {
+        end = std::max(end, ready + r);
+      }
+    }
+    return end;
+  };
+  double best = end_of(cut);
+  std::vector<uint64_t> c(nseg + 1);
+  c[0] = 0;
+  c[nseg] = n;
+  if (nseg == 2) {
+    for (uint64_t a = 1; a < n; ++a) {
+      c[1] = a;
+      const double e = end_of(c);
+      if (e < best) best = e, cut = c;
+    }
+  } else {
+    for (uint64_t a = 1; a + 1 < n; ++a)
+      for (uint64_t b = a + 1; b < n; ++b) {
+        c[1] = a;
+        c[2] = b;
+        const double e = end_of(c);
+        if (e < best) best = e, cut = c;
+      }
+  }
+  return cut;
 }
 
 // Plans groups [g0, g1) with the blob at workspace offset 0 and data after it.
@@ -1119,20 +1193,25 @@ void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, 
   // rounds overlap the contractions of the groups after them
   std::vector<uint64_t> order(n);
   for (uint64_t i = 0; i < n; ++i) order[i] = i;
-  auto rounds_cost = [&](uint64_t i) {
-    uint64_t c = 0;
-    for (uint32_t k = 0; k < groups[g0 + i].n_prods; ++k) {
-      const uint32_t n1 = nvars_of(groups[g0 + i].prods[k].D1);
-      c += (5ull << n1) + 20000ull * n1;   // field products plus per-round hashing
+  std::vector<double> chain(n), bytes(n);
+  for (uint64_t i = 0; i < n; ++i) {
+    const vl_group& g = groups[g0 + i];
+    chain[i] = rounds_us(g);
+    bytes[i] = (double)g.prods[0].D0 * g.prods[0].D2 * (double)esize(g.dtype_c);
+    for (uint32_t k = 0; k < g.n_prods; ++k) {
+      const vl_product& p = g.prods[k];
+      bytes[i] += (double)p.D1 * ((double)p.D0 * esize(p.dtype_a) + (double)p.D2 * esize(p.dtype_b));
     }
-    return c;
-  };
-  std::stable_sort(order.begin(), order.end(),
-                   [&](uint64_t a, uint64_t b) { return rounds_cost(a) > rounds_cost(b); });
+  }
+  std::stable_sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) { return chain[a] > chain[b]; });
   const uint32_t nseg = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(T.segments, n));
   P.seg.assign(nseg, Segment());
   std::vector<uint32_t> seg_of(n);
-  for (uint64_t r = 0; r < n; ++r) seg_of[order[r]] = (uint32_t)(r * nseg / n);
+  const std::vector<uint64_t> cut = segment_cuts(order, chain, bytes, nseg, T.persistent);
+  for (uint64_t r = 0, k = 0; r < n; ++r) {
+    while (k + 1 < nseg && r >= cut[k + 1]) ++k;
+    seg_of[order[r]] = (uint32_t)k;
+  }
   uint64_t rel = 0;
   for (uint64_t i = g0; i < g1; ++i) {
     uint8_t* pd;

@@ -34,6 +34,7 @@ constexpr uint32_t kMaxSegments = 8;
 // run on the rest
 constexpr uint64_t kMaxPersistentGroups = 128;
 constexpr uint32_t kDefaultSegments = 1;
+constexpr uint32_t kBlockingSegments = 2;   // blocking calls: latency over throughput
 constexpr uint32_t kPersistentSegments = 4;
 
 struct Tuning {

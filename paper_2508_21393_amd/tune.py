@@ -23,9 +23,9 @@ from . import binding as B
 # 0 keeps the library default for that knob
 DEFAULT_GRID = [(lm, sg, cr, co) for lm in (4096, 8192, 16384) for sg in (1, 2) for cr in (1, 2)
                 for co in (0, 1)]
-# the library's defaults for those knobs (vl_tuning fields left at 0); a
-# persistent call defaults to 4 segments
-LIBRARY_DEFAULTS = (8192, 1, 1, 0)
+# the library's defaults for those knobs (vl_tuning fields left at 0) in the
+# blocking calls the planner times; a persistent call defaults to 4 segments
+LIBRARY_DEFAULTS = (8192, 2, 1, 0)
 
 
 def _defaults(mode: int) -> tuple:

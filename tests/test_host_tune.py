@@ -6,7 +6,9 @@ from paper_2508_21393_amd import tune
 
 def test_candidates_equal_to_the_defaults_are_not_timed_twice():
     assert tune._resolved((0, 0, 0, 0), B.VL_MODE_BATCHED) == tune.LIBRARY_DEFAULTS
-    assert tune._resolved((8192, 1, 1, 0), B.VL_MODE_BATCHED) == tune._defaults(B.VL_MODE_BATCHED)
+    # blocking batched calls default to two segments
+    assert tune._resolved((8192, 2, 1, 0), B.VL_MODE_BATCHED) == tune._defaults(B.VL_MODE_BATCHED)
+    assert tune._resolved((8192, 1, 1, 0), B.VL_MODE_BATCHED) != tune._defaults(B.VL_MODE_BATCHED)
     # persistent calls default to four segments
     assert tune._resolved((8192, 1, 1, 0), B.VL_MODE_PERSISTENT) != tune._defaults(B.VL_MODE_PERSISTENT)
     assert tune._resolved((0, 0, 0, 0), B.VL_MODE_PERSISTENT) == tune._defaults(B.VL_MODE_PERSISTENT)
