@@ -335,11 +335,53 @@ class HostPool {
     job_ = nullptr;
     idle_cv_.wait(lk, [&] { return active_ == 0; });
   }
+  // fn(i) for every i < n on the workers and the calling thread, and
+  // consume(i) on the calling thread in order of i, each as soon as fn(i) is
+  // done (while it waits, the calling thread takes indices itself)
+  void run_ordered(uint64_t n, const std::function<void(uint64_t)>& fn,
+                   const std::function<void(uint64_t)>& consume) {
+    std::unique_lock<std::mutex> busy(run_mu_, std::defer_lock);
+    if (forked_ || th_.empty() || !busy.try_lock()) {
+      for (uint64_t i = 0; i < n; ++i) {
+        fn(i);
+        consume(i);
+      }
+      return;
+    }
+    std::vector<std::atomic<uint8_t>> done(n);
+    for (auto& d : done) d.store(0, std::memory_order_relaxed);
+    Job job;
+    job.fn = &fn;
+    job.n = n;
+    job.done = done.data();
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      job_ = &job;
+      ++gen_;
+    }
+    cv_.notify_all();
+    for (uint64_t i = 0; i < n; ++i) {
+      while (!done[i].load(std::memory_order_acquire)) {
+        const uint64_t j = job.next.fetch_add(1);
+        if (j < n) {
+          fn(j);
+          done[j].store(1, std::memory_order_release);
+        } else {
+          std::this_thread::yield();   // index i is on a worker
+        }
+      }
+      consume(i);
+    }
+    std::unique_lock<std::mutex> lk(mu_);
+    job_ = nullptr;
+    idle_cv_.wait(lk, [&] { return active_ == 0; });
+  }
  private:
   struct Job {
     const std::function<void(uint64_t)>* fn = nullptr;
     uint64_t n = 0;
     std::atomic<uint64_t> next{0};
+    std::atomic<uint8_t>* done = nullptr;   // run_ordered: index i finished
   };
   HostPool() {
     const unsigned hw = std::thread::hardware_concurrency();
@@ -348,7 +390,10 @@ class HostPool {
     pthread_atfork(nullptr, nullptr, [] { HostPool::get().forked_ = true; });
   }
   static void work(Job& j) {
-    for (uint64_t i = j.next.fetch_add(1); i < j.n; i = j.next.fetch_add(1)) (*j.fn)(i);
+    for (uint64_t i = j.next.fetch_add(1); i < j.n; i = j.next.fetch_add(1)) {
+      (*j.fn)(i);
+      if (j.done) j.done[i].store(1, std::memory_order_release);
+    }
   }
   void loop() {
     uint64_t seen = 0;
@@ -379,20 +424,21 @@ class HostPool {
 // is independent (its own transcript); a group costs a few microseconds of
 // hashing (tens of blocks), so calls of a dozen groups or more spread them
 // over the host pool.
+// (with u and v in Montgomery form for the eq jobs, converted with the
+// challenges, on the pool, rather than by the serial job builder)
+static void challenges_of(const vl_group& g, uint64_t seed, Challenges& c) {
+  group_challenges(g, seed, c.tr, c.u, c.v);
+  c.um.resize(8 * c.u.size());
+  c.vm.resize(8 * c.v.size());
+  for (size_t k = 0; k < c.u.size(); ++k) memcpy(c.um.data() + 8 * k, fr_to_mont(c.u[k]).w, 32);
+  for (size_t k = 0; k < c.v.size(); ++k) memcpy(c.vm.data() + 8 * k, fr_to_mont(c.v[k]).w, 32);
+}
+
 void all_challenges(const vl_group* groups, uint64_t g0, uint64_t g1, uint64_t seed,
                     std::vector<Challenges>& out) {
   const uint64_t n = g1 - g0;
   out.assign(n, Challenges());
-  // (with u and v in Montgomery form for the eq jobs, converted here on the
-  // pool rather than by the serial job builder)
-  const std::function<void(uint64_t)> one = [&](uint64_t i) {
-    Challenges& c = out[i];
-    group_challenges(groups[g0 + i], seed, c.tr, c.u, c.v);
-    c.um.resize(8 * c.u.size());
-    c.vm.resize(8 * c.v.size());
-    for (size_t k = 0; k < c.u.size(); ++k) memcpy(c.um.data() + 8 * k, fr_to_mont(c.u[k]).w, 32);
-    for (size_t k = 0; k < c.v.size(); ++k) memcpy(c.vm.data() + 8 * k, fr_to_mont(c.v[k]).w, 32);
-  };
+  const std::function<void(uint64_t)> one = [&](uint64_t i) { challenges_of(groups[g0 + i], seed, out[i]); };
   if (n < 12) {
     for (uint64_t i = 0; i < n; ++i) one(i);
     return;
@@ -1173,13 +1219,15 @@ void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, 
   Builder B(P, T, reinterpret_cast<uint64_t>(ws), blob);
   P.n_err = (uint32_t)(g1 - g0);
   const uint64_t n = g1 - g0;
+  // challenges: given, computed with the groups' jobs below (ws), or for
+  // sizing zeros (they change no size, only their count matters)
   std::vector<Challenges> ch;
+  const bool stream_ch = !given && ws;
   if (given) {
     ch.assign(given, given + n);
   } else if (ws) {
-    all_challenges(groups, g0, g1, seed, ch);
+    ch.assign(n, Challenges());
   } else {
-    // sizing: the challenges do not change any size, only their count matters
     ch.assign(n, Challenges());
     for (uint64_t i = 0; i < n; ++i) {
       ch[i].u.assign(nvars_of(groups[g0 + i].prods[0].D0), fr_zero());
@@ -1213,7 +1261,10 @@ void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, 
     seg_of[order[r]] = (uint32_t)k;
   }
   uint64_t rel = 0;
-  for (uint64_t i = g0; i < g1; ++i) {
+  // group jobs in group order, each as soon as its challenges are known:
+  // the host pool hashes the groups' transcripts while this thread builds
+  const std::function<void(uint64_t)> build = [&](uint64_t li) {
+    const uint64_t i = g0 + li;
     uint8_t* pd;
     int32_t* sd;
     uint8_t* dd;
@@ -1224,14 +1275,23 @@ void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, 
     } else {
       uint8_t* base = out;
       pd = base + rel;
-      sd = reinterpret_cast<int32_t*>(base + align_up(proof_total, 256)) + (i - g0);
-      dd = base + align_up(proof_total, 256) + align_up(4 * n, 256) + 32 * (i - g0);
+      sd = reinterpret_cast<int32_t*>(base + align_up(proof_total, 256)) + li;
+      dd = base + align_up(proof_total, 256) + align_up(4 * n, 256) + 32 * li;
     }
     rel += 32 * proof_elems(groups[i]);
-    int32_t* err = reinterpret_cast<int32_t*>(ws + 4 * (i - g0));  // blob starts with the flags
-    uint32_t* ready = T.persistent ? reinterpret_cast<uint32_t*>(ws + 4 * (n + (i - g0))) : nullptr;
-    B.cur = seg_of[i - g0];
-    B.group(groups[i], ch[i - g0], pd, sd, dd, err, ready);
+    int32_t* err = reinterpret_cast<int32_t*>(ws + 4 * li);  // blob starts with the flags
+    uint32_t* ready = T.persistent ? reinterpret_cast<uint32_t*>(ws + 4 * (n + li)) : nullptr;
+    B.cur = seg_of[li];
+    B.group(groups[i], ch[li], pd, sd, dd, err, ready);
+  };
+  if (stream_ch && n >= 12) {
+    const std::function<void(uint64_t)> hash = [&](uint64_t li) { challenges_of(groups[g0 + li], seed, ch[li]); };
+    HostPool::get().run_ordered(n, hash, build);
+  } else {
+    for (uint64_t li = 0; li < n; ++li) {
+      if (stream_ch) challenges_of(groups[g0 + li], seed, ch[li]);
+      build(li);
+    }
   }
   P.data_end = B.off;
 }
