@@ -517,9 +517,9 @@ def main():
     args = ap.parse_args()
     ws = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or ws != 1:
-        print("bench.py measures one GPU: the prover's groups are independent and this build "
-              "runs on a single MI355X (see DESIGN.md for how the groups would shard); "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the prover's groups are independent (each has its own "
+              "transcript), so a multi-GPU prover would shard the groups across GPUs; this benchmark "
+              "runs on a single MI355X: run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
