@@ -229,9 +229,9 @@ contract_kernel(const ContractJob* __restrict__ jobs, uint32_t n_jobs, uint32_t 
       const uint32_t row = owave * 64u + 8 * i + lrow;
       return row < n_out ? lbase + (uint64_t)(8 * i) * ldv : (gptr<u32x4>)(Mg + (uint64_t)(n_out - 1) * ld + m0);
     };
-    auto ldst = [&](uint32_t st, u32x4 (&b)[NP]) {
+    auto ldst = [&](uint32_t st, u32x4 (&b)[NP]) {   // nontemporal: read once
 #pragma unroll
-      for (uint32_t i = 0; i < NP; ++i) b[i] = lrowp(i)[min(st * NP + lpiece, nvec - 1)];
+      for (uint32_t i = 0; i < NP; ++i) b[i] = __builtin_nontemporal_load(&lrowp(i)[min(st * NP + lpiece, nvec - 1)]);
     };
     u32x4 r[NP];
     ldst(0, r);
@@ -368,7 +368,11 @@ contract_kernel(const ContractJob* __restrict__ jobs, uint32_t n_jobs, uint32_t 
     const uint32_t nc = min(n0, ((n_out - 1) / OPL) * OPL);
     const gptr<T> base = Mg + (uint64_t)m0 * ld + nc;
     const uint32_t rows = m1 - m0;
-    auto row = [&](uint32_t r) -> LT { return *(gptr<LT>)(base + (uint64_t)min(r, rows - 1) * ld); };
+    // nontemporal loads: each row segment is read once, so the caches may
+    // treat it as streaming data
+    auto row = [&](uint32_t r) -> LT {
+      return __builtin_nontemporal_load((gptr<LT>)(base + (uint64_t)min(r, rows - 1) * ld));
+    };
     uint32_t bad_o[OPL];
 #pragma unroll
     for (int o = 0; o < OPL; ++o) bad_o[o] = 0;
