@@ -951,8 +951,9 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
   ForkEvents& fork = forks[dev];
   if (two || side) {
     // [0, nseg): rounds forks; nseg, nseg + 1: rounds start and join;
-    // nseg + 2 + 2k, nseg + 3 + 2k: segment k's contraction fork and join
-    const hipError_t e = fork.need(3 * nseg + 2);
+    // nseg + 2 + 2k, nseg + 3 + 2k: segment k's contraction fork and join;
+    // 3 nseg + 2 + k: the end of segment k's wide rounds
+    const hipError_t e = fork.need(4 * nseg + 2);
     if (e != hipSuccess) return e;
   }
   VL_STAGE(ev, VL_STAGE_UPLOAD, s,
@@ -974,8 +975,19 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
                  launch_rounds(reinterpret_cast<const RoundsJob*>(dblob + L.seg[k].rounds),
                                (uint32_t)P.seg[k].rounds.size(), s2));
   }
+  bool wide_wait = false;   // the previous segment's wide rounds run on the rounds stream
   for (size_t k = 0; k < nseg; ++k) {
     const Segment& G = P.seg[k];
+    if (wide_wait) {
+      // this segment's contractions start after the previous segment's wide
+      // rounds: those are on the path to its rounds kernel (the chain that
+      // ends the call), and beside HBM-bound contractions a sweep took up to
+      // 1.7 times as long; the contractions then overlap the rounds kernel,
+      // which holds one CU per group
+      const hipError_t e = hipStreamWaitEvent(s, fork.ev[3 * nseg + 2 + k - 1], 0);
+      if (e != hipSuccess) return e;
+      wide_wait = false;
+    }
     const bool fk = side && fork_contractions(G);
     if (fk) {
       hipError_t e = hipEventRecord(fork.ev[nseg + 2 + 2 * k], s);
@@ -1035,6 +1047,11 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
       const MatSweep* lst = reinterpret_cast<const MatSweep*>(dblob + L.seg[k].wide[rd]);
       VL_STAGE(ev, VL_STAGE_ROUNDS, sr,
                launch_mat_sweep(rjobs, lst, (uint32_t)G.wide[rd].size(), G.wide_blocks[rd], (uint32_t)rd, sr));
+    }
+    if (sr != s && G.wide.size() > 1 && k + 1 < nseg) {
+      const hipError_t e = hipEventRecord(fork.ev[3 * nseg + 2 + k], sr);
+      if (e != hipSuccess) return e;
+      wide_wait = true;
     }
     VL_STAGE(ev, VL_STAGE_ROUNDS, sr, launch_rounds(rjobs, (uint32_t)G.rounds.size(), sr));
   }
