@@ -243,7 +243,7 @@ static hipError_t pool_stream_for(int pool, hipStream_t s, hipStream_t* out) {
 }
 
 hipError_t rounds_stream_for(hipStream_t s, hipStream_t* out) { return pool_stream_for(0, s, out); }
-static hipError_t side_stream_for(hipStream_t s, hipStream_t* out) { return pool_stream_for(1, s, out); }
+hipError_t side_stream_for(hipStream_t s, hipStream_t* out) { return pool_stream_for(1, s, out); }
 
 // Persistent mode's resident rounds workgroups spin until the contractions of
 // their groups have run.  That needs the contractions to be dispatched while
@@ -937,30 +937,57 @@ bool plan_forks(const Plan& P) {
   return false;
 }
 
+// whether the eq tables of a plan are read by its lookups alone (then the
+// eq kernel may run beside the lookups' first kernels)
+static bool eq_only_for_lookups(const Plan& P) {
+  if (P.lookups.empty() || !P.bmms.empty() || !P.evals.empty() || !P.reduces.empty()) return false;
+  for (const Segment& G : P.seg) {
+    if (!G.fin.empty() || !G.pass1.empty() || !G.rounds.empty()) return false;
+    for (int c = 0; c < CK_COUNT; ++c)
+      if (!G.cj[c].empty()) return false;
+  }
+  return true;
+}
+
 hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipStream_t s,
                         hipStream_t s2, StageEvents* ev, const void* blob_src_dev, hipStream_t s3) {
   thread_local std::map<int, ForkEvents> forks;   // per host thread and device
   const size_t nseg = P.seg.size();
   const bool two = s2 != s;
   const bool side = s3 && s3 != s && !ev && P.fork;
+  const bool eq_side = s3 && s3 != s && !ev && P.eq_fork && eq_only_for_lookups(P);
   int dev = 0;
-  if (two || side) {
+  if (two || side || eq_side) {
     const hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
   }
   ForkEvents& fork = forks[dev];
-  if (two || side) {
+  if (two || side || eq_side) {
     // [0, nseg): rounds forks; nseg, nseg + 1: rounds start and join;
     // nseg + 2 + 2k, nseg + 3 + 2k: segment k's contraction fork and join;
-    // 3 nseg + 2 + k: the end of segment k's wide rounds
-    const hipError_t e = fork.need(4 * nseg + 2);
+    // 3 nseg + 2 + k: the end of segment k's wide rounds; 4 nseg + 2,
+    // 4 nseg + 3: the eq fork and join
+    const hipError_t e = fork.need(4 * nseg + 4);
     if (e != hipSuccess) return e;
   }
   VL_STAGE(ev, VL_STAGE_UPLOAD, s,
            blob_src_dev ? launch_copy_in(dblob, blob_src_dev, L.total, s)
                         : upload_blob(dblob, P.blob.data(), L.total, s));
-  VL_STAGE(ev, VL_STAGE_EQ, s,
-           launch_eq(reinterpret_cast<const EqJob*>(dblob + L.eq), (uint32_t)P.eq.size(), P.eq_threads, s));
+  if (eq_side) {
+    // lookups: the eq tables are first read by the sweeps, after the
+    // multiplicities, the table inverses and the entries' terms; the eq
+    // kernel (bound by its field products) runs beside those (bound by
+    // atomics, one inversion chain per thread, and memory)
+    hipError_t e = hipEventRecord(fork.ev[4 * nseg + 2], s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s3, fork.ev[4 * nseg + 2], 0);
+    if (e == hipSuccess)
+      e = launch_eq(reinterpret_cast<const EqJob*>(dblob + L.eq), (uint32_t)P.eq.size(), P.eq_threads, s3);
+    if (e == hipSuccess) e = hipEventRecord(fork.ev[4 * nseg + 3], s3);
+    if (e != hipSuccess) return e;
+  } else {
+    VL_STAGE(ev, VL_STAGE_EQ, s,
+             launch_eq(reinterpret_cast<const EqJob*>(dblob + L.eq), (uint32_t)P.eq.size(), P.eq_threads, s));
+  }
   if (two) {
     // the rounds stream starts after everything queued before this call
     hipError_t e = hipEventRecord(fork.ev[nseg], s);
@@ -1086,6 +1113,10 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
     VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_hist(lj, nl, P.lk_hist_blocks, s));
     VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_table(lj, nl, P.lk_tab_blocks, s));
     VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_prep(lj, nl, P.lk_prep_blocks, s));
+    if (eq_side) {
+      const hipError_t e = hipStreamWaitEvent(s, fork.ev[4 * nseg + 3], 0);
+      if (e != hipSuccess) return e;
+    }
     VL_STAGE(ev, VL_STAGE_PASS1, s, launch_lookup_start(lj, nl, s));
     const size_t nk = std::max(P.lk_wide[0].size(), P.lk_wide[1].size());
     for (size_t k = 0; k < nk; ++k) {

@@ -72,6 +72,7 @@ struct Plan {
   std::vector<uint8_t> blob;      // host image of [err flags][eq jobs][points][segments]
   bool persistent = false;        // rounds launched before the contractions
   bool fork = false;              // contraction kinds may use a side stream
+  bool eq_fork = false;           // eq tables on a side stream beside the lookups' table kernels
   uint64_t data_end = 0;          // workspace bytes used
   std::vector<EqJob> eq;
   uint32_t eq_threads = 0;
@@ -166,11 +167,16 @@ struct StageEvents {
 // blob_src_dev: device-side address of a pinned host buffer the blob is
 // copied from (graph capture), else the blob goes through the staging ring.
 // s3: a side stream for the contraction kinds of a segment (forked after the
-// eq tables, joined before the finish pass; see fork_contractions), or null;
-// unused when ev is given, so that stage times are each kernel's own.
+// eq tables, joined before the finish pass; see fork_contractions) and, with
+// P.eq_fork, for the eq tables of a lookup plan (joined before the first
+// kernel that reads them), or null; unused when ev is given, so that stage
+// times are each kernel's own.
 hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipStream_t s,
                         hipStream_t s2, StageEvents* ev = nullptr, const void* blob_src_dev = nullptr,
                         hipStream_t s3 = nullptr);
+// the calling stream's internal side stream (one per device and caller
+// stream, kept for the process)
+hipError_t side_stream_for(hipStream_t s, hipStream_t* out);
 // whether a segment's contraction kinds are split over two streams
 bool fork_contractions(const Segment& G);
 bool plan_forks(const Plan& P);
