@@ -937,9 +937,9 @@ bool plan_forks(const Plan& P) {
   return false;
 }
 
-// whether the eq tables of a plan are read by its lookups alone (then the
-// eq kernel may run beside the lookups' first kernels)
-static bool eq_only_for_lookups(const Plan& P) {
+// whether a plan holds lookups alone (then its eq tables are first read by
+// the lookup sweeps, and the table kernels may use the internal streams)
+static bool lookups_only(const Plan& P) {
   if (P.lookups.empty() || !P.bmms.empty() || !P.evals.empty() || !P.reduces.empty()) return false;
   for (const Segment& G : P.seg) {
     if (!G.fin.empty() || !G.pass1.empty() || !G.rounds.empty()) return false;
@@ -955,7 +955,8 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
   const size_t nseg = P.seg.size();
   const bool two = s2 != s;
   const bool side = s3 && s3 != s && !ev && P.fork;
-  const bool eq_side = s3 && s3 != s && !ev && P.eq_fork && eq_only_for_lookups(P);
+  const bool eq_side = s3 && s3 != s && !ev && P.eq_fork && lookups_only(P);
+  const bool inv_side = two && !ev && lookups_only(P);
   int dev = 0;
   if (two || side || eq_side) {
     const hipError_t e = hipGetDevice(&dev);
@@ -966,8 +967,9 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
     // [0, nseg): rounds forks; nseg, nseg + 1: rounds start and join;
     // nseg + 2 + 2k, nseg + 3 + 2k: segment k's contraction fork and join;
     // 3 nseg + 2 + k: the end of segment k's wide rounds; 4 nseg + 2,
-    // 4 nseg + 3: the eq fork and join
-    const hipError_t e = fork.need(4 * nseg + 4);
+    // 4 nseg + 3: the eq fork and join; 4 nseg + 4, 4 nseg + 5: the fork and
+    // join of the lookups' table inversions
+    const hipError_t e = fork.need(4 * nseg + 6);
     if (e != hipSuccess) return e;
   }
   VL_STAGE(ev, VL_STAGE_UPLOAD, s,
@@ -1110,8 +1112,22 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
     const LookupJob* lj = reinterpret_cast<const LookupJob*>(dblob + L.lookups);
     const uint32_t nl = (uint32_t)P.lookups.size();
     for (const auto& z : P.lookup_zero) VL_STAGE(ev, VL_STAGE_FINISH, s, launch_zero_words(z.first, z.second, s));
-    VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_hist(lj, nl, P.lk_hist_blocks, s));
-    VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_table(lj, nl, P.lk_tab_blocks, s));
+    if (inv_side) {
+      // the table inversions (one chain of field products per thread, a few
+      // dozen blocks) read no count: they run on the rounds stream beside
+      // the count kernel, joined before the multiplicities
+      hipError_t e = hipEventRecord(fork.ev[4 * nseg + 4], s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s2, fork.ev[4 * nseg + 4], 0);
+      if (e == hipSuccess) e = launch_lookup_inv(lj, nl, P.lk_tab_blocks, s2);
+      if (e == hipSuccess) e = hipEventRecord(fork.ev[4 * nseg + 5], s2);
+      if (e == hipSuccess) e = launch_lookup_hist(lj, nl, P.lk_hist_blocks, s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, fork.ev[4 * nseg + 5], 0);
+      if (e != hipSuccess) return e;
+    } else {
+      VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_hist(lj, nl, P.lk_hist_blocks, s));
+      VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_inv(lj, nl, P.lk_tab_blocks, s));
+    }
+    VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_mult(lj, nl, P.lk_tab_blocks, s));
     VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_prep(lj, nl, P.lk_prep_blocks, s));
     if (eq_side) {
       const hipError_t e = hipStreamWaitEvent(s, fork.ev[4 * nseg + 3], 0);

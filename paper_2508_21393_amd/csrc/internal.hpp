@@ -280,7 +280,8 @@ hipError_t launch_bmm_chal(const BmmJob* jobs_dev, const BmmSweep* list_dev, uin
 hipError_t launch_bmm_rounds(const BmmJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
 // lookup arguments (lookup.hip)
 hipError_t launch_lookup_hist(const LookupJob* jobs_dev, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s);
-hipError_t launch_lookup_table(const LookupJob* jobs_dev, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s);
+hipError_t launch_lookup_inv(const LookupJob* jobs_dev, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s);
+hipError_t launch_lookup_mult(const LookupJob* jobs_dev, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s);
 hipError_t launch_lookup_prep(const LookupJob* jobs_dev, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s);
 hipError_t launch_lookup_start(const LookupJob* jobs_dev, uint32_t n_jobs, hipStream_t s);
 hipError_t launch_lookup_sweep(const LookupJob* jobs_dev, const LookupSweep* list_dev, uint32_t n_list,

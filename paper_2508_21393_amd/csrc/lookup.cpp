@@ -206,16 +206,20 @@ vl_status lookup_run(const vl_lookup* ls, uint64_t n, uint64_t seed, uint8_t* ws
                 (unsigned long long)align_up(P.data_end, 256));
   const BlobLayout BL = blob_layout(P);
   fill_blob(P, BL, ws);
-  // the eq tables on the internal side stream, beside the table kernels
-  hipStream_t s3 = nullptr;
-  hipError_t e = side_stream_for(s, &s3);
-  if (e != hipSuccess) return fail(VL_ERR_HIP, "side stream: %s", hipGetErrorString(e));
+  // the eq tables on the internal side stream and the table inversions on
+  // the internal rounds stream, beside the count kernel
+  hipStream_t s2 = nullptr, s3 = nullptr;
+  hipError_t e = rounds_stream_for(s, &s2);
+  if (e == hipSuccess) e = side_stream_for(s, &s3);
+  if (e != hipSuccess) return fail(VL_ERR_HIP, "internal streams: %s", hipGetErrorString(e));
   P.eq_fork = true;
-  e = enqueue_plan(P, BL, ws, s, s, nullptr, nullptr, s3);
+  e = enqueue_plan(P, BL, ws, s, s2, nullptr, nullptr, s3);
   const hipError_t e2 = hipStreamSynchronize(s);
-  const hipError_t e3 = hipStreamSynchronize(s3);   // joined into s unless the enqueue failed
+  // both are joined into s unless the enqueue failed
+  const hipError_t e3 = hipStreamSynchronize(s2), e4 = hipStreamSynchronize(s3);
   if (e == hipSuccess) e = e2;
   if (e == hipSuccess) e = e3;
+  if (e == hipSuccess) e = e4;
   if (e != hipSuccess) return fail(VL_ERR_HIP, "lookup prove: %s", hipGetErrorString(e));
   const int32_t* st = reinterpret_cast<const int32_t*>(oh + st_off);
   for (uint64_t k = 0; k < n; ++k) {

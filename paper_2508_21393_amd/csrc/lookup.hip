@@ -13,8 +13,8 @@
 //
 //   lookup_hist_kernel   multiplicities (atomic counts) and the membership
 //                        check of every entry
-//   lookup_table_kernel  Tb = T + beta, B = 1/Tb (chunked batch inversion),
-//                        m in the field, partial sums of B m
+//   lookup_inv_kernel    Tb = T + beta, B = 1/Tb (chunked batch inversion)
+//   lookup_mult_kernel   m in the field, partial sums of B m
 //   lookup_prep_kernel   Sb = S + beta and A = B[row of the entry]
 //   lookup_start_kernel  the constant K of the high rounds, the status
 //   lookup_sweep/chal    the first rounds across the GPU, then a one-block
@@ -237,12 +237,42 @@ __global__ void __launch_bounds__(256) lookup_hist_kernel(const LookupJob* __res
   else *reinterpret_cast<volatile int32_t*>(J.flag) = 1;
 }
 
-// Table rows: Tb_j = t0 + j + gamma tb_j + beta, B_j = 1/Tb_j by a batch
-// inversion over each thread's kLookupInvChunk rows (prefix products, one
-// inversion, back-substitution), M'_j = c2 m_j, and per block the sum of
-// B_j M'_j.  A zero Tb_j (beta at a pole, probability N/p) sets the flag.
-__global__ void __launch_bounds__(256) lookup_table_kernel(const LookupJob* __restrict__ jobs, uint32_t n_jobs,
-                                                           uint32_t n_blocks) {
+// Table rows, in two kernels with the same chunks of kLookupInvChunk rows
+// per thread.  lookup_inv_kernel: Tb_j = t0 + j + gamma tb_j + beta and
+// B_j = 1/Tb_j by a batch inversion over the chunk (prefix products, one
+// inversion, back-substitution); it reads no count, so it runs beside the
+// count kernel.  A zero Tb_j (beta at a pole, probability N/p) sets the
+// flag.  lookup_mult_kernel, after the counts: M'_j = c2 m_j and per block
+// the sum of B_j M'_j.
+__global__ void __launch_bounds__(256) lookup_inv_kernel(const LookupJob* __restrict__ jobs, uint32_t n_jobs,
+                                                         uint32_t n_blocks) {
+  const uint32_t blk = blockIdx.x;
+  if (blk >= n_blocks) return;
+  const LookupJob& J = jobs[lk_find([&](uint32_t k) { return jobs[k].tab_begin; }, n_jobs, blk)];
+  const uint64_t N = 1ull << J.nL;
+  const uint64_t ch = (uint64_t)(blk - J.tab_begin) * 256 + threadIdx.x;
+  const uint64_t j0 = ch * kLookupInvChunk, j1 = min(j0 + kLookupInvChunk, N);
+  if (j0 >= N) return;
+  const Fr gamma = lk_fr(J.gamma), beta = lk_fr(J.beta);
+  Fr acc = fr_R();
+  for (uint64_t j = j0; j < j1; ++j) {
+    const Fr tb = compress_mont(J.t0 + (int64_t)j, J.tb ? J.tb[j] : 0, J.tb != nullptr, gamma, beta);
+    if (fr_is_zero(tb)) *reinterpret_cast<volatile int32_t*>(J.flag) = 1;
+    store_sol(J.T, N, j, tb);
+    store_sol(J.B, N, j, acc);      // prefix product, replaced below
+    acc = fr_mul(acc, tb);
+  }
+  Fr inv = fr_inv_mont(acc);
+  for (uint64_t jj = j1; jj > j0; --jj) {
+    const uint64_t j = jj - 1;
+    const Fr b = fr_mul(inv, load_sol(J.B, N, j));
+    inv = fr_mul(inv, load_sol(J.T, N, j));
+    store_sol(J.B, N, j, b);
+  }
+}
+
+__global__ void __launch_bounds__(256) lookup_mult_kernel(const LookupJob* __restrict__ jobs, uint32_t n_jobs,
+                                                          uint32_t n_blocks) {
   const uint32_t blk = blockIdx.x;
   if (blk >= n_blocks) return;
   const LookupJob& J = jobs[lk_find([&](uint32_t k) { return jobs[k].tab_begin; }, n_jobs, blk)];
@@ -253,26 +283,13 @@ __global__ void __launch_bounds__(256) lookup_table_kernel(const LookupJob* __re
 #pragma unroll
   for (int k = 0; k < 4; ++k) g[k] = fr_zero();
   if (j0 < N) {
-    const Fr gamma = lk_fr(J.gamma), beta = lk_fr(J.beta), c2r2 = fr_mul(lk_fr(J.c2), fr_R2());
-    Fr acc = fr_R();
+    const Fr c2r2 = fr_mul(lk_fr(J.c2), fr_R2());
     for (uint64_t j = j0; j < j1; ++j) {
-      const Fr tb = compress_mont(J.t0 + (int64_t)j, J.tb ? J.tb[j] : 0, J.tb != nullptr, gamma, beta);
-      if (fr_is_zero(tb)) *reinterpret_cast<volatile int32_t*>(J.flag) = 1;
-      store_sol(J.T, N, j, tb);
-      store_sol(J.B, N, j, acc);      // prefix product, replaced below
-      acc = fr_mul(acc, tb);
-    }
-    Fr inv = fr_inv_mont(acc);
-    for (uint64_t jj = j1; jj > j0; --jj) {
-      const uint64_t j = jj - 1;
-      const Fr b = fr_mul(inv, load_sol(J.B, N, j));
-      inv = fr_mul(inv, load_sol(J.T, N, j));
-      store_sol(J.B, N, j, b);
       Fr m = fr_zero();
       m.w[0] = J.cnt[j];
       m = fr_mul(c2r2, m);            // c2 m in Montgomery form (c2 R^2 times the count)
       store_sol(J.M, N, j, m);
-      g[0] = fr_add(g[0], fr_mul(b, m));
+      g[0] = fr_add(g[0], fr_mul(load_sol(J.B, N, j), m));
     }
   }
   lk_block_out(g, J.kpart + (uint64_t)(blk - J.tab_begin) * 32);
@@ -484,9 +501,15 @@ hipError_t launch_lookup_hist(const LookupJob* jobs, uint32_t n_jobs, uint32_t n
   return hipGetLastError();
 }
 
-hipError_t launch_lookup_table(const LookupJob* jobs, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s) {
+hipError_t launch_lookup_inv(const LookupJob* jobs, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s) {
   if (n_blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(lookup_table_kernel, dim3(n_blocks), dim3(256), 0, s, jobs, n_jobs, n_blocks);
+  hipLaunchKernelGGL(lookup_inv_kernel, dim3(n_blocks), dim3(256), 0, s, jobs, n_jobs, n_blocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_lookup_mult(const LookupJob* jobs, uint32_t n_jobs, uint32_t n_blocks, hipStream_t s) {
+  if (n_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(lookup_mult_kernel, dim3(n_blocks), dim3(256), 0, s, jobs, n_jobs, n_blocks);
   return hipGetLastError();
 }
 

@@ -174,8 +174,9 @@ struct StageEvents {
 hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipStream_t s,
                         hipStream_t s2, StageEvents* ev = nullptr, const void* blob_src_dev = nullptr,
                         hipStream_t s3 = nullptr);
-// the calling stream's internal side stream (one per device and caller
-// stream, kept for the process)
+// the calling stream's internal rounds and side streams (one each per
+// device and caller stream, kept for the process)
+hipError_t rounds_stream_for(hipStream_t s, hipStream_t* out);
 hipError_t side_stream_for(hipStream_t s, hipStream_t* out);
 // whether a segment's contraction kinds are split over two streams
 bool fork_contractions(const Segment& G);
