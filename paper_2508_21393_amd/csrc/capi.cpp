@@ -491,6 +491,7 @@ void Builder::contract(const void* M, int dtype, int nd, uint64_t ld, bool rows,
   const uint32_t out_waves = (n_out + 64 * opl - 1) / (64 * opl);
   // chunk: about T.lane_macs multiply-adds per lane and task
   uint64_t chunk = std::max<uint64_t>(64, T.lane_macs / (8ull * nd * opl));
+  if (rows && !wide && opl > 1) chunk *= T.rows16_scale;
   chunk = std::min<uint64_t>(chunk, kMaxChunk);
   // the vector rows kernels of wide entries keep no high-word accumulators:
   // a chunk holds at most kWideSpill rows
@@ -1191,6 +1192,13 @@ Tuning tuning_for(const vl_prove_opts* o) {
   // made their throughput depend on how the runtime happened to map streams
   // to queues (one proof's rounds kernel holding up another's contractions)
   t.contract_streams = (o && !o->async) ? 2 : 1;
+  // the int16 contractions over rows write 48 bytes of chunk sums per output
+  // and chunk (about a tenth of their matrix bytes at 256-row chunks), which
+  // the finish pass reads back: with several proofs of a large batch in
+  // flight the GPU is bound by HBM, and chunks kRows16LongChunks times longer
+  // gave more throughput (plan_groups keeps short chunks for small calls); a
+  // lone blocking call needs the tasks of short chunks more than the bytes
+  if (!t.per_instance && o && o->async && !(o->tuning && o->tuning->lane_macs)) t.rows16_scale = kRows16LongChunks;
   if (o) apply_tuning(t, o->tuning);
   return t;
 }
@@ -1273,6 +1281,16 @@ static std::vector<uint64_t> segment_cuts(const std::vector<uint64_t>& order, co
 // one region of pinned host memory (out: its device-side address; proofs at
 // their final offsets, then statuses, then digests) that the kernels write
 // directly.  ws == nullptr plans for sizing only.
+// matrix bytes a group's contractions stream (C once, every A and B once)
+static double group_bytes(const vl_group& g) {
+  double b = (double)g.prods[0].D0 * g.prods[0].D2 * (double)esize(g.dtype_c);
+  for (uint32_t k = 0; k < g.n_prods; ++k) {
+    const vl_product& p = g.prods[k];
+    b += (double)p.D1 * ((double)p.D0 * esize(p.dtype_a) + (double)p.D2 * esize(p.dtype_b));
+  }
+  return b;
+}
+
 void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, uint64_t g1,
                  uint64_t seed, uint8_t* ws, bool async, uint8_t* proofs_dev, const uint64_t* offsets,
                  int32_t* status_dev, uint8_t* digests_dev, uint8_t* out, const Challenges* given) {
@@ -1280,7 +1298,17 @@ void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, 
   P.persistent = T.persistent;
   P.fork = !T.persistent && T.contract_streams == 2;
   const uint64_t blob = blob_bound(groups + g0, g1 - g0);
-  Builder B(P, T, reinterpret_cast<uint64_t>(ws), blob);
+  // long int16 row chunks only for calls that stream enough matrix bytes to
+  // keep the GPU's tasks plentiful at that length (a 7B-class block streams
+  // 3.8 GB; the per-layer requests of a proof server, well under 1 GB, lost
+  // 12% of their throughput with them)
+  Tuning TT = T;
+  if (TT.rows16_scale > 1) {
+    double call_bytes = 0;
+    for (uint64_t i = g0; i < g1; ++i) call_bytes += group_bytes(groups[i]);
+    if (call_bytes < kRows16LongMinBytes) TT.rows16_scale = 1;
+  }
+  Builder B(P, TT, reinterpret_cast<uint64_t>(ws), blob);
   P.n_err = (uint32_t)(g1 - g0);
   const uint64_t n = g1 - g0;
   // challenges: given, computed with the groups' jobs below (ws), or for
@@ -1307,13 +1335,8 @@ void plan_groups(Plan& P, const Tuning& T, const vl_group* groups, uint64_t g0, 
   for (uint64_t i = 0; i < n; ++i) order[i] = i;
   std::vector<double> chain(n), bytes(n);
   for (uint64_t i = 0; i < n; ++i) {
-    const vl_group& g = groups[g0 + i];
-    chain[i] = rounds_us(g);
-    bytes[i] = (double)g.prods[0].D0 * g.prods[0].D2 * (double)esize(g.dtype_c);
-    for (uint32_t k = 0; k < g.n_prods; ++k) {
-      const vl_product& p = g.prods[k];
-      bytes[i] += (double)p.D1 * ((double)p.D0 * esize(p.dtype_a) + (double)p.D2 * esize(p.dtype_b));
-    }
+    chain[i] = rounds_us(groups[g0 + i]);
+    bytes[i] = group_bytes(groups[g0 + i]);
   }
   std::stable_sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) { return chain[a] > chain[b]; });
   const uint32_t nseg = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(T.segments, n));

@@ -93,6 +93,10 @@ struct MatSweep {
   uint32_t job;               // index in the launch's RoundsJob array
   uint32_t block_begin;       // prefix sum of sweep blocks within the launch
 };
+// int16 row contractions of large asynchronous calls: chunk factor, and the
+// matrix bytes a call must stream to use it
+constexpr uint32_t kRows16LongChunks = 16;
+constexpr double kRows16LongMinBytes = 1e9;
 
 // The sumcheck rounds of one group, run by one workgroup.
 struct RoundsJob {

@@ -47,6 +47,7 @@ struct Tuning {
   bool persistent = false;        // rounds launched first, waiting on readiness counters
   uint32_t spin_limit = 1u << 24; // persistent mode: polls before VL_ERR_TIMEOUT
   uint32_t contract_streams = 1;  // 2: large contraction kinds split over two streams
+  uint32_t rows16_scale = 1;      // chunk length factor of the int16 vector rows kernels
 };
 
 // Jobs of one pipeline segment: its groups' contractions, finish jobs and

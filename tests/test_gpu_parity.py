@@ -353,6 +353,32 @@ def test_full_size_config_matches_oracle(B, cfg):
         assert dg.hex() == rec["state"], g.name
 
 
+def test_async_full_size_cfg4_long_row_chunks(B):
+    # an asynchronous call on a batch that streams over 1 GB (the 7B block,
+    # 3.8 GB) contracts its int16 matrices over rows in chunks 16 times
+    # longer than a blocking call does (fewer chunk sums for the finish
+    # pass); its proofs must still be the oracle's bytes
+    import torch
+    _say("cfg4 async: generating")
+    w = workloads.make_config("cfg4", device="cuda")
+    gold = golden("cfg4")
+    gs = [device_group(g, B) for g in w.groups]
+    total = sum(B.proof_size(g) for g in gs)
+    async_ws = B.workspace_size(gs, 1, async_=True)
+    # an explicit lane_macs keeps the short chunks: more room for chunk sums
+    assert async_ws < B.workspace_size(gs, 1, async_=True, tuning_=B.tuning(lane_macs=8192))
+    proofs = torch.zeros(total, dtype=torch.uint8, device="cuda")
+    status = torch.full((len(gs),), -1, dtype=torch.int32, device="cuda")
+    ws = torch.empty(async_ws, dtype=torch.uint8, device="cuda")
+    _say(f"cfg4 async: proving {len(gs)} groups")
+    offs = B.sumcheck_matmul_prove_async(gs, w.seed, proofs, status, ws, mode=1)
+    torch.cuda.synchronize()
+    assert status.cpu().tolist() == [0] * len(gs)
+    raw = proofs.cpu().numpy().tobytes()
+    for i, (g, rec) in enumerate(zip(w.groups, gold["groups"])):
+        assert sha(raw[offs[i]:offs[i + 1]]) == rec["proof_sha256"], g.name
+
+
 # ------------------------------------------------------------ graph mode ---
 @pytest.mark.parametrize("segments", [1, 3])
 def test_prove_graph_replays_match_eager(B, segments):
