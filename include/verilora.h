@@ -122,7 +122,10 @@ typedef struct {
  * default.  No value changes any result: they only decide how the
  * contractions are cut into wave tasks and how a batched call is pipelined. */
 typedef struct {
-  uint32_t lane_macs;      /* multiply-adds per lane and contraction task          */
+  uint32_t lane_macs;      /* multiply-adds per lane and contraction task (default
+                              8192; when left 0, asynchronous calls and graphs
+                              whose groups stream 1 GB or more of matrices cut
+                              int16 contractions over rows 16 times longer)      */
   uint32_t min_tasks;      /* halve a contraction's chunk until it has this many
                               wave tasks (chunks stay >= 256 entries)               */
   uint32_t segments;       /* batched mode: pipeline segments, 1..8; the rounds of
