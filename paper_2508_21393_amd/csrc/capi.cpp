@@ -1128,7 +1128,7 @@ hipError_t enqueue_plan(const Plan& P, const BlobLayout& L, uint8_t* dblob, hipS
       VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_hist(lj, nl, P.lk_hist_blocks, s));
       VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_inv(lj, nl, P.lk_tab_blocks, s));
     }
-    VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_mult(lj, nl, P.lk_tab_blocks, s));
+    VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_mult(lj, nl, P.lk_mult_blocks, s));
     VL_STAGE(ev, VL_STAGE_FINISH, s, launch_lookup_prep(lj, nl, P.lk_prep_blocks, s));
     if (eq_side) {
       const hipError_t e = hipStreamWaitEvent(s, fork.ev[4 * nseg + 3], 0);

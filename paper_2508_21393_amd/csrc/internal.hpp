@@ -234,8 +234,10 @@ struct LookupJob {
   uint32_t wide;
   uint32_t hist_begin;        // block prefixes: histogram launch (D entries),
   uint32_t prep_begin;        // preparation launch (padded entries),
-  uint32_t tab_begin;         // table launch (chunks of table rows)
-  uint32_t nkparts;           // table-launch blocks (partials of sum_j B_j m_j)
+  uint32_t tab_begin;         // inversion launch (chunks of table rows)
+  uint32_t mult_begin;        // multiplicity launch (one table row per thread)
+  uint32_t nkparts;           // multiplicity-launch blocks (partials of sum_j B_j m_j)
+  uint32_t pad2_;
   uint32_t* cnt;              // N counts, zeroed by the plan
   uint32_t* A;                // ld 2^(nH + nL)
   uint32_t* S;

@@ -133,7 +133,7 @@ void plan_lookup(Builder& B, const vl_lookup& L, const LookupChallenges& ch, uin
   B.eq_job(ch.u, j.E, nullptr, 0, false, false, &am);
   B.eq_job(std::vector<Fr>(ch.u.begin() + nH, ch.u.end()), j.EL, nullptr, 0, false, false, &c1);
   const uint64_t chunks = (N + kLookupInvChunk - 1) / kLookupInvChunk;
-  j.nkparts = (uint32_t)((chunks + 255) / 256);
+  j.nkparts = (uint32_t)((N + 255) / 256);
   j.kpart = B.dev<uint32_t>(B.take(128ull * j.nkparts));
   j.io = B.dev<uint32_t>(B.take(4 * kLkIoWords));
   j.flag = flag;
@@ -145,7 +145,9 @@ void plan_lookup(Builder& B, const vl_lookup& L, const LookupChallenges& ch, uin
   j.prep_begin = B.P.lk_prep_blocks;
   B.P.lk_prep_blocks += (uint32_t)((Dp + 255) / 256);
   j.tab_begin = B.P.lk_tab_blocks;
-  B.P.lk_tab_blocks += j.nkparts;
+  B.P.lk_tab_blocks += (uint32_t)((chunks + 255) / 256);
+  j.mult_begin = B.P.lk_mult_blocks;
+  B.P.lk_mult_blocks += j.nkparts;
   uint32_t wide = 0;
   while (wide < n && wide < kLookupMaxWide && (Dp >> (wide + 1)) >= kLookupWidePairs) ++wide;
   j.wide = wide;

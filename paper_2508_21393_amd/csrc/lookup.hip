@@ -237,13 +237,13 @@ __global__ void __launch_bounds__(256) lookup_hist_kernel(const LookupJob* __res
   else *reinterpret_cast<volatile int32_t*>(J.flag) = 1;
 }
 
-// Table rows, in two kernels with the same chunks of kLookupInvChunk rows
-// per thread.  lookup_inv_kernel: Tb_j = t0 + j + gamma tb_j + beta and
+// Table rows, in two kernels.  lookup_inv_kernel, kLookupInvChunk rows per
+// thread: Tb_j = t0 + j + gamma tb_j + beta and
 // B_j = 1/Tb_j by a batch inversion over the chunk (prefix products, one
 // inversion, back-substitution); it reads no count, so it runs beside the
 // count kernel.  A zero Tb_j (beta at a pole, probability N/p) sets the
-// flag.  lookup_mult_kernel, after the counts: M'_j = c2 m_j and per block
-// the sum of B_j M'_j.
+// flag.  lookup_mult_kernel, after the counts, one row per thread:
+// M'_j = c2 m_j and per block the sum of B_j M'_j.
 __global__ void __launch_bounds__(256) lookup_inv_kernel(const LookupJob* __restrict__ jobs, uint32_t n_jobs,
                                                          uint32_t n_blocks) {
   const uint32_t blk = blockIdx.x;
@@ -275,24 +275,20 @@ __global__ void __launch_bounds__(256) lookup_mult_kernel(const LookupJob* __res
                                                           uint32_t n_blocks) {
   const uint32_t blk = blockIdx.x;
   if (blk >= n_blocks) return;
-  const LookupJob& J = jobs[lk_find([&](uint32_t k) { return jobs[k].tab_begin; }, n_jobs, blk)];
+  const LookupJob& J = jobs[lk_find([&](uint32_t k) { return jobs[k].mult_begin; }, n_jobs, blk)];
   const uint64_t N = 1ull << J.nL;
-  const uint64_t ch = (uint64_t)(blk - J.tab_begin) * 256 + threadIdx.x;
-  const uint64_t j0 = ch * kLookupInvChunk, j1 = min(j0 + kLookupInvChunk, N);
+  const uint64_t j = (uint64_t)(blk - J.mult_begin) * 256 + threadIdx.x;
   Fr g[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) g[k] = fr_zero();
-  if (j0 < N) {
-    const Fr c2r2 = fr_mul(lk_fr(J.c2), fr_R2());
-    for (uint64_t j = j0; j < j1; ++j) {
-      Fr m = fr_zero();
-      m.w[0] = J.cnt[j];
-      m = fr_mul(c2r2, m);            // c2 m in Montgomery form (c2 R^2 times the count)
-      store_sol(J.M, N, j, m);
-      g[0] = fr_add(g[0], fr_mul(load_sol(J.B, N, j), m));
-    }
+  if (j < N) {
+    Fr m = fr_zero();
+    m.w[0] = J.cnt[j];
+    m = fr_mul(fr_mul(lk_fr(J.c2), fr_R2()), m);   // c2 m in Montgomery form (c2 R^2 times the count)
+    store_sol(J.M, N, j, m);
+    g[0] = fr_mul(load_sol(J.B, N, j), m);
   }
-  lk_block_out(g, J.kpart + (uint64_t)(blk - J.tab_begin) * 32);
+  lk_block_out(g, J.kpart + (uint64_t)(blk - J.mult_begin) * 32);
 }
 
 // Entries: Sb_i = x_i + gamma y_i + beta and A_i = B_{x_i - t0} (padding

@@ -95,7 +95,7 @@ struct Plan {
   // launches, wide rounds, the one-workgroup rounds
   std::vector<LookupJob> lookups;
   std::vector<std::pair<uint32_t*, uint64_t>> lookup_zero;
-  uint32_t lk_hist_blocks = 0, lk_prep_blocks = 0, lk_tab_blocks = 0;
+  uint32_t lk_hist_blocks = 0, lk_prep_blocks = 0, lk_tab_blocks = 0, lk_mult_blocks = 0;
   std::vector<std::vector<LookupSweep>> lk_wide[2];   // per round: jobs binding a high [0] / low [1] bit
   std::vector<uint32_t> lk_wide_blocks[2];
 };
